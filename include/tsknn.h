@@ -1,0 +1,185 @@
+/*
+ * tsknn — exact k-nearest-neighbour scan over multi-dimensional time series
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bachmann & Freytag, "An Analytical Approach to Improving Time
+ * Warping on Multidimensional Time Series" (arXiv 1811.11076).
+ *   - Distances (Sec. 2.1): DTW = the smallest sum of squared Euclidean point
+ *     distances along a warping path (no final square root); DK (dog-keeper,
+ *     discrete Frechet) = the smallest maximum Euclidean point distance along
+ *     a warping path.
+ *   - Sakoe-Chiba band (Sec. 2.2) optional for both.
+ *   - k-NN query (Sec. 1): the k database series closest to each query.
+ *   - Pruning: DTW uses LB_Box (Sec. 3, eq. (1)); DK uses the greedy upper
+ *     bound of Alg. 1 to seed the threshold (Sec. 4.4) and the sparse-DK
+ *     semantics of Alg. 3 (cells above the threshold are dead).
+ *   Results are exact: identical to evaluating every pair with the full DP
+ *   and sorting by (distance, id).
+ *
+ * Conventions for every call:
+ *   - Return value: TSK_OK (0) or one of the TSK_ERR_* codes below.  On
+ *     error no output is written and tsk_last_error() describes the cause.
+ *     No C++ exception crosses this boundary.
+ *   - All argument validation happens before any device work.
+ *   - "_dev" pointers are device memory on the current HIP device; "_host"
+ *     pointers are host memory.  The caller owns every buffer it passes.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on that stream unless stated otherwise.
+ *   - Series values are float32, array-of-structs [length][dim], several
+ *     series concatenated; offsets (int64, n+1 entries, offsets[0] == 0,
+ *     strictly increasing) delimit series i as rows offsets[i]..offsets[i+1]-1.
+ *     Lengths must be in [1, TSK_MAX_LEN]; dim in [1, TSK_MAX_DIM].
+ *   - Non-finite series values are undefined behaviour.
+ */
+#ifndef TSKNN_H
+#define TSKNN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSK_VERSION_MAJOR 0
+#define TSK_VERSION_MINOR 1
+
+#define TSK_MAX_DIM 8
+#define TSK_MAX_LEN 4096
+#define TSK_MAX_K 64
+
+enum {
+    TSK_OK = 0,
+    TSK_ERR_INVALID_ARG = 1,
+    TSK_ERR_OOM = 2,
+    TSK_ERR_DEVICE = 3,
+    TSK_ERR_UNSUPPORTED = 4,
+    TSK_ERR_IO = 5,
+    TSK_ERR_CANCELLED = 6
+};
+
+/* Distance (Sec. 2.1). */
+enum { TSK_DTW = 0, TSK_DK = 1 };
+
+/* Sakoe-Chiba band (Sec. 2.2).  For a pair of lengths (m, n) with
+ * L = max(m, n) the half-width is w = r (TSK_BAND_ABS) or
+ * w = floor(frac * L) (TSK_BAND_FRAC), and cell (i, j) is inside iff
+ *   |i (n-1) - j (m-1)| (L-1) <= w (m-1) (n-1),
+ * which is |i - j| <= w for equal lengths; every cell is inside when m == 1
+ * or n == 1.  TSK_BAND_NONE: no band. */
+enum { TSK_BAND_NONE = 0, TSK_BAND_ABS = 1, TSK_BAND_FRAC = 2 };
+typedef struct {
+    int32_t mode;
+    int32_t r;
+    float frac;
+} tsk_band;
+
+/* Candidate order for a query.  The order never changes the result, only
+ * how early the threshold falls (and so how much work is pruned). */
+enum { TSK_ORDER_PLAIN = 0, TSK_ORDER_GIVEN = 1 };
+
+typedef struct tsk_index tsk_index;
+
+/* Per-call counters (all int64) and device times.  Counts are over all
+ * (query, candidate) pairs of the call. */
+typedef struct {
+    int64_t pairs;          /* n_queries * n_series */
+    int64_t seed_pairs;     /* pairs evaluated by the threshold-seeding pass */
+    int64_t bound_pruned;   /* pairs discarded by a bound before any DP */
+    int64_t dp_started;     /* pairs whose DP began */
+    int64_t dp_completed;   /* DPs that ended with a value <= threshold */
+    int64_t dp_abandoned;   /* DPs stopped early (value > threshold) */
+    int64_t dp_cells;       /* DP cells evaluated (lane-cells, dead ones too) */
+    int64_t bound_steps;    /* greedy-bound moves + LB_Box terms */
+    int64_t fallback_pairs; /* pairs that left the fast DP for the general one */
+    float ms_total;         /* device time of the whole call */
+    float ms_seed, ms_bound, ms_dp, ms_final;
+} tsk_stats;
+
+typedef struct {
+    int64_t size;                  /* sizeof(tsk_query_opts) */
+    int32_t order;                 /* TSK_ORDER_PLAIN or TSK_ORDER_GIVEN */
+    int32_t seed_count;            /* candidates per query used to seed the
+                                      threshold (0 = library default) */
+    const int32_t *order_dev;      /* TSK_ORDER_GIVEN: [n_queries][n_series]
+                                      candidate ids, each row a permutation;
+                                      the first seed_count entries form the
+                                      seed set and survivors are processed in
+                                      this order */
+    int32_t use_graph;             /* reserved (0) */
+    int32_t dp_kernel;             /* 0 auto, 1 force the general DP */
+} tsk_query_opts;
+
+typedef struct {
+    int64_t size;                  /* sizeof(tsk_index_opts) */
+    int64_t reserved;
+} tsk_index_opts;
+
+/* Library version. */
+int tsk_version(int *major, int *minor);
+
+/* Text of the last error on the calling thread; valid until the next tsk_*
+ * call on that thread.  Never NULL. */
+const char *tsk_last_error(void);
+
+/* Builds a read-only index over n_series database series (Sec. 1: the
+ * database the k-NN query scans).  values_dev: [offsets_host[n]][dim] float32
+ * device AoS; offsets_host: n+1 int64 host offsets.  The library copies the
+ * data into its own device layouts (an AoS copy and 64-series struct-of-arrays
+ * tiles), so the caller may free its buffers once the stream has completed.
+ * *out receives an index owned by the caller (free with tsk_index_free).
+ * Errors: INVALID_ARG (null pointers, n < 1, bad offsets), UNSUPPORTED
+ * (dim or a length outside the supported range), OOM, DEVICE. */
+int tsk_index_build(const float *values_dev, const int64_t *offsets_host, int64_t n_series,
+                    int32_t dim, const tsk_index_opts *opts, void *hip_stream, tsk_index **out);
+
+/* Frees an index and its device memory after synchronising its stream.
+ * NULL is accepted. */
+int tsk_index_free(tsk_index *index);
+
+/* Number of series and dimensionality of an index. */
+int tsk_index_info(const tsk_index *index, int64_t *n_series, int32_t *dim);
+
+/* Exact k-NN query (Sec. 1; pruning of Sec. 3 and Sec. 4).  For every query
+ * q the k database series with the smallest (distance, id) are written to
+ * out_ids_dev[q*k .. q*k+k-1] (int64 ids, ascending) and out_dist_dev (float32:
+ * DTW sums, or DK as the correctly rounded sqrt of the squared DK).  Ranks
+ * without a finite distance (k > n_series, or an infeasible band) get
+ * (-1, +inf).  q_values_dev / q_offsets_host: the queries, as for an index.
+ * opts may be NULL.  stats_host (nullable): if given, the call synchronises
+ * the stream and fills the counters.  The index is only read; calls on one
+ * index must not overlap in time (the per-index workspace is shared).
+ * Errors: INVALID_ARG, UNSUPPORTED (k > TSK_MAX_K, dim mismatch), OOM, DEVICE. */
+int tsk_knn_query(const tsk_index *index, const float *q_values_dev, const int64_t *q_offsets_host,
+                  int64_t n_queries, int32_t k, int32_t dist, tsk_band band,
+                  const tsk_query_opts *opts, int64_t *out_ids_dev, float *out_dist_dev,
+                  tsk_stats *stats_host, void *hip_stream);
+
+/* Full-DP distance of every (query, database series) pair with no pruning
+ * (Sec. 2.1 definitions through the same DP kernels as the k-NN path):
+ * out_keys_dev[q * n_series + c] = DTW, or the SQUARED DK (float32).  Used
+ * to check the DP against an independent implementation. */
+int tsk_pair_distances(const tsk_index *index, const float *q_values_dev,
+                       const int64_t *q_offsets_host, int64_t n_queries, int32_t dist,
+                       tsk_band band, float *out_keys_dev, void *hip_stream);
+
+/* Per-pair bounds through the same kernels as the k-NN path, with no
+ * threshold (no early return):
+ *   out_lb_dev[q*N + c]  = LB_Box with the query's band envelope and the
+ *                          candidate's points (eq. (1) with the roles of
+ *                          the two series exchanged), summed over the
+ *                          candidate's points in order in float32;
+ *   out_ub_dev[q*N + c]  = the greedy path bound of Alg. 1: for TSK_DK the
+ *                          maximum squared cost along the greedy path, for
+ *                          TSK_DTW the float32 sum of costs along it;
+ *   out_steps_dev[q*N+c] = number of greedy moves (int32).
+ * Any output pointer may be NULL. */
+int tsk_pair_bounds(const tsk_index *index, const float *q_values_dev,
+                    const int64_t *q_offsets_host, int64_t n_queries, int32_t dist,
+                    tsk_band band, float *out_lb_dev, float *out_ub_dev,
+                    int32_t *out_steps_dev, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSKNN_H */

@@ -1,0 +1,154 @@
+"""Seeded synthetic inputs: multi-dimensional time series for the k-NN scan.
+
+This module holds no part of the method's arithmetic (no distances, bounds or
+DP).  It is the one module that both the oracle-side tests and the GPU path
+use to obtain identical inputs.
+
+Two families stand in for the paper's RAM/CBF generators and UCI/ECG data sets
+(Sec. 5), which are not available:
+
+* Gaussian random walks: x_0 = e_0, x_t = x_{t-1} + e_t, e_t ~ N(0, I_d).
+* Class-warp series: C prototypes (random walks of length L_p).  A member of
+  class c is the prototype under a random monotone piecewise-linear time warp
+  (8 equal output segments, slopes U[0.8, 1.2] renormalised so that the warp
+  maps [0, 1] onto [0, 1], i.e. at most 20 % local stretch), sampled by linear
+  interpolation at m points, plus N(0, 0.1^2) noise.  Database member i has
+  class i mod C; query classes are uniform.
+
+Every draw comes from numpy's PCG64 seeded by SeedSequence([1811, cfg, stream,
+chunk]) with fixed chunks of CHUNK series, so a given (cfg, stream) always
+yields the same values however the caller slices it.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BASE_SEED = 1811
+STREAMS = {"proto": 0, "db": 1, "query": 2, "train": 3, "aux": 4}
+CHUNK = 2048
+N_SEGMENTS = 8
+SLOPE_LO, SLOPE_HI = 0.8, 1.2
+NOISE_SIGMA = 0.1
+
+
+def _rng(cfg_id: int, stream: str, index: int) -> np.random.Generator:
+    ss = np.random.SeedSequence([BASE_SEED, int(cfg_id), STREAMS[stream], int(index)])
+    return np.random.Generator(np.random.PCG64(ss))
+
+
+def random_walks(n: int, length: int, d: int, cfg_id: int, stream: str,
+                 start: int = 0) -> np.ndarray:
+    """Series start..start+n-1 of a random-walk stream, float32 [n, length, d]."""
+    out = np.empty((n, length, d), dtype=np.float32)
+    first_chunk = start // CHUNK
+    last_chunk = (start + n - 1) // CHUNK if n > 0 else first_chunk - 1
+    for ch in range(first_chunk, last_chunk + 1):
+        rng = _rng(cfg_id, stream, ch)
+        steps = rng.standard_normal((CHUNK, length, d))
+        walks = np.cumsum(steps, axis=1)
+        lo = max(start, ch * CHUNK)
+        hi = min(start + n, (ch + 1) * CHUNK)
+        out[lo - start:hi - start] = walks[lo - ch * CHUNK:hi - ch * CHUNK]
+    return out
+
+
+def _warp_positions(slopes: np.ndarray, m: int, proto_len: int) -> np.ndarray:
+    """Sample positions (float64, [cnt, m]) on the prototype axis for each warp."""
+    cnt = slopes.shape[0]
+    knots_y = np.concatenate([np.zeros((cnt, 1)), np.cumsum(slopes, axis=1)], axis=1)
+    knots_y /= knots_y[:, -1:]
+    knots_x = np.linspace(0.0, 1.0, N_SEGMENTS + 1)
+    u = np.linspace(0.0, 1.0, m) if m > 1 else np.zeros(1)
+    seg = np.minimum((u * N_SEGMENTS).astype(np.int64), N_SEGMENTS - 1)
+    frac = (u - knots_x[seg]) * N_SEGMENTS
+    y0 = np.take_along_axis(knots_y, np.broadcast_to(seg, (cnt, m)), axis=1)
+    y1 = np.take_along_axis(knots_y, np.broadcast_to(seg + 1, (cnt, m)), axis=1)
+    w = y0 + (y1 - y0) * frac
+    return w * (proto_len - 1)
+
+
+def _interp(protos: np.ndarray, cls: np.ndarray, pos: np.ndarray) -> np.ndarray:
+    """Linear interpolation of protos[cls[r]] at positions pos[r, :] -> [cnt, m, d]."""
+    proto_len = protos.shape[1]
+    p0 = np.clip(np.floor(pos).astype(np.int64), 0, proto_len - 1)
+    p1 = np.minimum(p0 + 1, proto_len - 1)
+    f = (pos - p0)[..., None]
+    a = protos[cls[:, None], p0]
+    b = protos[cls[:, None], p1]
+    return a + (b - a) * f
+
+
+class ClassWarp:
+    """Class-warp generator for one configuration id."""
+
+    def __init__(self, cfg_id: int, n_classes: int, proto_len: int, d: int):
+        self.cfg_id = cfg_id
+        self.n_classes = n_classes
+        self.proto_len = proto_len
+        self.d = d
+        rng = _rng(cfg_id, "proto", 0)
+        steps = rng.standard_normal((n_classes, proto_len, d))
+        self.protos = np.cumsum(steps, axis=1)  # float64
+
+    def members(self, n: int, stream: str, start: int = 0,
+                length: int | tuple[int, int] = 256, class_mode: str = "mod"):
+        """Members start..start+n-1 of a stream.
+
+        length: an int (all equal) or (lo, hi) for lengths uniform in {lo..hi}.
+        class_mode: "mod" (class = index mod C) or "uniform" (drawn).
+        Returns (values float32 [sum(len), d], offsets int64 [n+1], labels int64 [n]).
+        """
+        chunks = []
+        lens_all = []
+        labels_all = []
+        first_chunk = start // CHUNK
+        last_chunk = (start + n - 1) // CHUNK if n > 0 else first_chunk - 1
+        for ch in range(first_chunk, last_chunk + 1):
+            rng = _rng(self.cfg_id, stream, ch)
+            idx = np.arange(ch * CHUNK, (ch + 1) * CHUNK)
+            if isinstance(length, tuple):
+                lens = rng.integers(length[0], length[1] + 1, size=CHUNK)
+            else:
+                lens = np.full(CHUNK, int(length))
+            if class_mode == "uniform":
+                cls = rng.integers(0, self.n_classes, size=CHUNK)
+            else:
+                cls = idx % self.n_classes
+            slopes = rng.uniform(SLOPE_LO, SLOPE_HI, size=(CHUNK, N_SEGMENTS))
+            noise_seed = rng.integers(0, 2**63 - 1)
+            lo = max(start, ch * CHUNK)
+            hi = min(start + n, (ch + 1) * CHUNK)
+            sel = slice(lo - ch * CHUNK, hi - ch * CHUNK)
+            nrng = np.random.Generator(np.random.PCG64(noise_seed))
+            lens_c, cls_c, slopes_c = lens[sel], cls[sel], slopes[sel]
+            # noise for the whole chunk is drawn in one fixed order, then sliced
+            total = int(lens.sum())
+            noise = nrng.standard_normal((total, self.d)) * NOISE_SIGMA
+            noff = np.concatenate([[0], np.cumsum(lens)])
+            for ulen in np.unique(lens_c):
+                rows = np.nonzero(lens_c == ulen)[0]
+                pos = _warp_positions(slopes_c[rows], int(ulen), self.proto_len)
+                vals = _interp(self.protos, cls_c[rows], pos)
+                r_chunk = rows + sel.start
+                gather = noff[r_chunk][:, None] + np.arange(int(ulen))[None, :]
+                vals += noise[gather]
+                chunks.append((rows + (lo - start), vals))
+            lens_all.append(lens_c)
+            labels_all.append(cls_c)
+        lens_all = np.concatenate(lens_all) if lens_all else np.zeros(0, np.int64)
+        labels = np.concatenate(labels_all) if labels_all else np.zeros(0, np.int64)
+        offsets = np.zeros(n + 1, dtype=np.int64)
+        offsets[1:] = np.cumsum(lens_all)
+        values = np.empty((int(offsets[-1]), self.d), dtype=np.float32)
+        for rows, vals in chunks:
+            ulen = vals.shape[1]
+            gather = offsets[rows][:, None] + np.arange(ulen)[None, :]
+            values[gather] = vals
+        return values, offsets, labels.astype(np.int64)
+
+
+def flat_equal(arr: np.ndarray):
+    """[n, L, d] -> (values [n*L, d], offsets [n+1])."""
+    n, length, d = arr.shape
+    return (np.ascontiguousarray(arr.reshape(n * length, d)),
+            np.arange(n + 1, dtype=np.int64) * length)

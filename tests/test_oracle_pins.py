@@ -1,0 +1,405 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test compares the oracle with something other than itself: hand-worked
+examples from the definitions (tests/golden), brute-force enumeration of all
+warping paths, closed forms, the bound chains and identities stated in the
+paper, and invariants (identity, symmetry, triangle inequality).
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")
+INF = float("inf")
+
+
+def _val(x):
+    return INF if x == "inf" else float(x)
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)["examples"]
+
+
+@pytest.mark.parametrize("ex", _golden(), ids=lambda e: e["name"])
+def test_hand_examples(ex):
+    S = np.array(ex["S"], np.float32)
+    T = np.array(ex["T"], np.float32)
+    w = ex["w"]
+    if "dtw" in ex:
+        assert O.dtw_f32(S, T, w) == _val(ex["dtw"])
+        assert O.dtw_f64(S, T, w) == _val(ex["dtw"])
+    if "dk_sq" in ex:
+        assert O.dk_sq_f32(S, T, w) == _val(ex["dk_sq"])
+    if "gdk_sq" in ex:
+        v, steps = O.gdk_sq_f32(S, T, w)
+        assert v == ex["gdk_sq"] and steps == ex["gdk_steps"]
+    if "greedy_sum" in ex:
+        assert O.greedy_sum_f32(S, T, w)[0] == ex["greedy_sum"]
+    if "lb_box_paper" in ex:
+        assert O.lb_box_f32(S, T, w) == ex["lb_box_paper"]
+        assert O.lb_box_f64(S, T, w) == ex["lb_box_paper"]
+    if "lb_sigmamin" in ex:
+        assert O.lb_sigmamin_f64(S, T, w) == ex["lb_sigmamin"]
+    if "envelope_of_T_lo" in ex:
+        lo, hi = O.envelope(T, S.shape[0], w)
+        assert np.array_equal(lo, np.array(ex["envelope_of_T_lo"], np.float32))
+        assert np.array_equal(hi, np.array(ex["envelope_of_T_hi"], np.float32))
+
+
+# ------------------------------------------------------------------ cost
+def test_cost_identity_symmetry_1d(rng):
+    for d in (1, 2, 3, 6, 8):
+        for _ in range(50):
+            s = rng.normal(size=d).astype(np.float32) * 10
+            t = rng.normal(size=d).astype(np.float32) * 10
+            assert O.cost_f32(s, s) == 0.0
+            assert O.cost_f32(s, t) == O.cost_f32(t, s)  # fl(a-b) = -fl(b-a)
+            exact = float(np.sum((s.astype(np.float64) - t.astype(np.float64)) ** 2))
+            assert abs(O.cost_f32(s, t) - exact) <= 4e-7 * exact + 1e-30
+    # d = 1: (s - t)^2 rounded once after the rounded difference
+    for _ in range(200):
+        s, t = rng.normal(size=2).astype(np.float32) * 100
+        e = np.float32(s - t)
+        assert O.cost_f32([s], [t]) == float(np.float32(e * e))
+
+
+# ------------------------------------------------------------------ brute force paths
+def _small_pairs(rng, count=60):
+    for _ in range(count):
+        m = int(rng.integers(1, 8))
+        n = int(rng.integers(1, 8))
+        d = int(rng.integers(1, 4))
+        S = rng.normal(size=(m, d)).astype(np.float32)
+        T = rng.normal(size=(n, d)).astype(np.float32)
+        yield S, T
+
+
+@pytest.mark.parametrize("band", [None, 0, 1, 2, 0.3])
+def test_dp_equals_path_enumeration(rng, band):
+    """The DP equals the minimum over every warping path (Sec. 2.1)."""
+    for S, T in _small_pairs(rng):
+        w = O.band_w(band, S.shape[0], T.shape[0])
+        s64, s32, mx, count = O.enumerate_paths(S, T, w)
+        if count == 0:
+            assert O.dtw_f32(S, T, w) == INF and O.dk_sq_f32(S, T, w) == INF
+            continue
+        assert O.dtw_f64(S, T, w) == pytest.approx(s64, rel=1e-12)
+        assert O.dtw_f32(S, T, w) == s32  # same rounding chain, bit for bit
+        assert O.dk_sq_f32(S, T, w) == mx  # max/min only select: exact
+
+
+def test_path_count_is_delannoy():
+    # unbanded m x n grid: central Delannoy numbers on the diagonal
+    S = np.zeros((8, 1), np.float32)
+    assert O.enumerate_paths(S, S)[3] == 48639   # D(7)
+    assert O.enumerate_paths(S[:7], S[:7])[3] == 8989
+    assert O.enumerate_paths(S[:3], S[:3])[3] == 13
+
+
+# ------------------------------------------------------------------ closed forms
+def test_zero_band_is_euclidean(rng):
+    """w = 0 and m = n leave only the diagonal path: DTW is the squared
+    Euclidean distance of the stacked series, DK the largest point cost."""
+    for _ in range(30):
+        L = int(rng.integers(1, 40))
+        d = int(rng.integers(1, 5))
+        S = rng.normal(size=(L, d)).astype(np.float32)
+        T = rng.normal(size=(L, d)).astype(np.float32)
+        sq = np.sum((S.astype(np.float64) - T.astype(np.float64)) ** 2, axis=1)
+        assert O.dtw_f64(S, T, 0) == pytest.approx(float(sq.sum()), rel=1e-12)
+        assert O.dk_sq_f32(S, T, 0) == pytest.approx(float(sq.max()), rel=1e-6)
+        assert O.dtw_f32(S, T, 0) == pytest.approx(float(sq.sum()), rel=1e-5)
+
+
+def test_single_point_query(rng):
+    """m = 1: the only path visits every point of T."""
+    for _ in range(30):
+        n = int(rng.integers(1, 30))
+        d = int(rng.integers(1, 4))
+        S = rng.normal(size=(1, d)).astype(np.float32)
+        T = rng.normal(size=(n, d)).astype(np.float32)
+        sq = np.sum((S.astype(np.float64) - T.astype(np.float64)) ** 2, axis=1)
+        assert O.dtw_f64(S, T) == pytest.approx(float(sq.sum()), rel=1e-12)
+        assert O.dk_sq_f32(S, T) == pytest.approx(float(sq.max()), rel=1e-6)
+        assert O.dtw_f64(T, S) == pytest.approx(float(sq.sum()), rel=1e-12)
+
+
+def test_identity_and_symmetry(rng):
+    for _ in range(40):
+        m = int(rng.integers(1, 30))
+        n = int(rng.integers(1, 30))
+        d = int(rng.integers(1, 4))
+        S = rng.normal(size=(m, d)).astype(np.float32)
+        T = rng.normal(size=(n, d)).astype(np.float32)
+        for band in (None, 2, 0.2):
+            w = O.band_w(band, m, n)
+            assert O.dtw_f32(S, S, O.band_w(band, m, m)) == 0.0
+            assert O.dk_sq_f32(S, S, O.band_w(band, m, m)) == 0.0
+            # transposed DP takes the min of the same three values
+            assert O.dtw_f32(S, T, w) == O.dtw_f32(T, S, w)
+            assert O.dk_sq_f32(S, T, w) == O.dk_sq_f32(T, S, w)
+
+
+def test_band_monotone_and_full(rng):
+    for _ in range(20):
+        L = int(rng.integers(2, 30))
+        S = rng.normal(size=(L, 3)).astype(np.float32)
+        T = rng.normal(size=(L, 3)).astype(np.float32)
+        prev_t, prev_k = INF, INF
+        for w in range(0, L + 1):
+            t, k = O.dtw_f64(S, T, w), O.dk_sq_f32(S, T, w)
+            assert t <= prev_t and k <= prev_k
+            prev_t, prev_k = t, k
+        assert O.dtw_f32(S, T, L - 1) == O.dtw_f32(S, T, -1)
+        assert O.dk_sq_f32(S, T, L - 1) == O.dk_sq_f32(S, T, -1)
+
+
+def test_band_rule():
+    # equal lengths: |i - j| <= w exactly
+    for L in (2, 5, 17):
+        for w in range(0, L):
+            for i, j in itertools.product(range(L), range(L)):
+                assert O.band_ok(i, j, L, L, w) == (abs(i - j) <= w)
+    # length-1 series: everything allowed
+    assert all(O.band_ok(0, j, 1, 9, 0) for j in range(9))
+    # fractional width uses floor(frac * L)
+    assert O.band_w(0.1, 256, 256) == 25 and O.band_w(0.1, 512, 512) == 51
+    assert O.band_w(0.1, 64, 1024) == 102
+
+
+def test_slanted_band_feasible_for_uneven_lengths(rng):
+    """Every length pair of the uneven-length workload has a path in band."""
+    for _ in range(40):
+        m = int(rng.integers(64, 1025))
+        n = int(rng.integers(64, 1025))
+        w = O.band_w(0.1, m, n)
+        S = np.zeros((m, 1), np.float32)
+        T = np.zeros((n, 1), np.float32)
+        assert O.dk_sq_f32(S, T, w) == 0.0
+
+
+# ------------------------------------------------------------------ DK extras
+def test_dk_sqrt_domain(rng):
+    """sqrt is monotone: the DP on sqrt'ed costs ends in sqrtf(DK^2)."""
+    for S, T in _small_pairs(rng, 100):
+        assert O.dk_unsq_f32(S, T) == float(np.sqrt(np.float32(O.dk_sq_f32(S, T))))
+
+
+def test_dk_triangle_inequality(rng):
+    """DK is a metric (Sec. 6), up to fp32 rounding of the costs."""
+    for _ in range(200):
+        d = int(rng.integers(1, 4))
+        A, B, C = (rng.normal(size=(int(rng.integers(1, 12)), d)).astype(np.float32) for _ in range(3))
+        ab = math.sqrt(O.dk_sq_f32(A, B))
+        bc = math.sqrt(O.dk_sq_f32(B, C))
+        ac = math.sqrt(O.dk_sq_f32(A, C))
+        assert ac <= (ab + bc) * (1 + 1e-6) + 1e-12
+
+
+def test_dk_corner_bound(rng):
+    for S, T in _small_pairs(rng, 100):
+        dk = O.dk_sq_f32(S, T)
+        assert dk >= O.cost_f32(S[0], T[0]) and dk >= O.cost_f32(S[-1], T[-1])
+
+
+# ------------------------------------------------------------------ bounds
+@pytest.mark.parametrize("band", [None, 0, 1, 3, 0.25])
+def test_lb_chain(rng, band):
+    """LB_Box <= LB_Sigma-min <= DTW (Sec. 3), and the fp32 LB_Box summed in
+    series order never exceeds the fp32 DTW, in either orientation."""
+    for _ in range(60):
+        m = int(rng.integers(1, 25))
+        n = m if band is not None and not isinstance(band, float) else int(rng.integers(1, 25))
+        d = int(rng.integers(1, 5))
+        S = rng.normal(size=(m, d)).astype(np.float32)
+        T = rng.normal(size=(n, d)).astype(np.float32)
+        w = O.band_w(band, m, n)
+        dtw64 = O.dtw_f64(S, T, w)
+        if dtw64 == INF:
+            continue
+        lb64 = O.lb_box_f64(S, T, w)
+        smin = O.lb_sigmamin_f64(S, T, w)
+        assert lb64 <= smin * (1 + 1e-12) + 1e-12
+        assert smin <= dtw64 * (1 + 1e-12) + 1e-12
+        dtw32 = O.dtw_f32(S, T, w)
+        assert O.lb_box_f32(S, T, w) <= dtw32
+        assert O.lb_box_qenv_f32(S, T, w) <= dtw32
+        # exchanging the roles of the two series is the same bound as the
+        # query-envelope orientation
+        assert O.lb_box_qenv_f32(S, T, w) == O.lb_box_f32(T, S, w)
+
+
+def test_lb_box_is_sum_of_keogh(rng):
+    """eq. (1): LB_Box = sum over dimensions of LB_Keogh; d = 1 identical."""
+    for _ in range(40):
+        L = int(rng.integers(1, 30))
+        d = int(rng.integers(1, 6))
+        w = int(rng.integers(0, 6))
+        S = rng.normal(size=(L, d)).astype(np.float32)
+        T = rng.normal(size=(L, d)).astype(np.float32)
+        total = sum(O.lb_keogh_f64(S, T, w, k) for k in range(d))
+        assert O.lb_box_f64(S, T, w) == pytest.approx(total, rel=1e-12, abs=1e-12)
+        if d == 1:
+            assert O.lb_box_f64(S, T, w) == O.lb_keogh_f64(S, T, w, 0)
+
+
+def test_lb_box_zero_band_equals_dtw(rng):
+    """w = 0: each box is the point itself, LB_Box = DTW bit for bit."""
+    for _ in range(40):
+        L = int(rng.integers(1, 40))
+        d = int(rng.integers(1, 5))
+        S = rng.normal(size=(L, d)).astype(np.float32)
+        T = rng.normal(size=(L, d)).astype(np.float32)
+        assert O.lb_box_f32(S, T, 0) == O.dtw_f32(S, T, 0)
+
+
+def test_envelope_bruteforce(rng):
+    for _ in range(20):
+        n = int(rng.integers(1, 30))
+        m = int(rng.integers(1, 30))
+        w = int(rng.integers(0, 5))
+        T = rng.normal(size=(n, 2)).astype(np.float32)
+        lo, hi = O.envelope(T, m, w)
+        for i in range(m):
+            cols = [j for j in range(n) if O.band_ok(i, j, m, n, w)]
+            if cols:
+                assert np.array_equal(lo[i], T[cols].min(0)) and np.array_equal(hi[i], T[cols].max(0))
+
+
+# ------------------------------------------------------------------ greedy bounds
+def test_greedy_upper_bounds(rng):
+    """Alg. 1 returns an upper bound of DK (Sec. 4.1) in at most m+n-2 moves;
+    the summing walk is an upper bound of DTW."""
+    for band in (None, 2, 0.3):
+        for _ in range(80):
+            m = int(rng.integers(1, 30))
+            n = int(rng.integers(1, 30))
+            d = int(rng.integers(1, 4))
+            S = rng.normal(size=(m, d)).astype(np.float32)
+            T = rng.normal(size=(n, d)).astype(np.float32)
+            w = O.band_w(band, m, n)
+            g, steps = O.gdk_sq_f32(S, T, w)
+            assert g >= O.dk_sq_f32(S, T, w)
+            assert steps <= m + n - 2
+            gs, _ = O.greedy_sum_f32(S, T, w)
+            assert gs >= O.dtw_f32(S, T, w)
+            if m == 1 or n == 1 or w == 0 and m == n:
+                assert g == O.dk_sq_f32(S, T, w)
+                assert gs == O.dtw_f32(S, T, w)
+
+
+def test_greedy_early_return(rng):
+    for _ in range(100):
+        S = rng.normal(size=(20, 3)).astype(np.float32)
+        T = rng.normal(size=(25, 3)).astype(np.float32)
+        full, _ = O.gdk_sq_f32(S, T)
+        eps = float(rng.uniform(0, full * 1.2))
+        v, _ = O.gdk_sq_f32(S, T, eps=eps)
+        if full > eps:
+            assert v > eps
+        else:
+            assert v == full
+
+
+# ------------------------------------------------------------------ sparse DK (Alg. 3)
+def test_sparse_dk_equals_dense(rng):
+    """Alg. 3 returns DK when DK <= eps and +inf otherwise (Sec. 4.2)."""
+    for band in (None, 3):
+        for _ in range(150):
+            m = int(rng.integers(1, 30))
+            n = int(rng.integers(1, 30))
+            S = rng.normal(size=(m, 3)).astype(np.float32)
+            T = rng.normal(size=(n, 3)).astype(np.float32)
+            w = O.band_w(band, m, n)
+            dk = O.dk_sq_f32(S, T, w)
+            assert O.sparse_dk_sq_f32(S, T, w)[0] == dk
+            for eps in (dk, dk * 0.999, dk * 1.5, float(rng.uniform(0, 10))):
+                v, cells = O.sparse_dk_sq_f32(S, T, w, eps)
+                assert v == (dk if dk <= eps else INF)
+                assert cells <= m * n
+
+
+def test_sparse_dk_visits_few_cells_on_similar_series(rng):
+    # a tight threshold keeps the visited set close to the warping path
+    base = np.cumsum(rng.normal(size=(200, 3)), axis=0).astype(np.float32)
+    other = (base + rng.normal(scale=0.05, size=base.shape)).astype(np.float32)
+    dk = O.dk_sq_f32(base, other)
+    v, cells = O.sparse_dk_sq_f32(base, other, eps=dk)
+    assert v == dk and cells < 0.05 * 200 * 200
+
+
+# ------------------------------------------------------------------ k-NN
+def _db(rng, N, lens, d):
+    L = rng.integers(lens[0], lens[1] + 1, size=N)
+    off = np.concatenate([[0], np.cumsum(L)]).astype(np.int64)
+    vals = np.cumsum(rng.normal(size=(int(off[-1]), d)), axis=0).astype(np.float32)
+    return vals, off
+
+
+@pytest.mark.parametrize("dist,band", [("dk", None), ("dtw", None), ("dtw", 3), ("dtw", 0.15),
+                                       ("dk", 0.2)])
+def test_knn_scan_equals_brute(rng, dist, band):
+    """The paper's pruned scan (Sec. 4.4 / LB_Box + DTW) equals the plain
+    definition: full DP for every pair and a (distance, id) sort."""
+    db, dbo = _db(rng, 300, (5, 40), 3)
+    qs, qo = _db(rng, 7, (5, 40), 3)
+    for k in (1, 5, 17):
+        ids_b, keys_b = O.knn_brute(db, dbo, qs, qo, k, dist, band)
+        ids_s, keys_s, st = O.knn_scan(db, dbo, qs, qo, k, dist, band)
+        assert np.array_equal(ids_b, ids_s)
+        assert np.array_equal(keys_b, keys_s)
+        if dist == "dtw" and band is not None:
+            assert st[:, 0].sum() > 0  # LB_Box prunes something
+
+
+def test_knn_ties_and_padding():
+    # identical candidates: ties resolved by id; k > N padded with (-1, inf)
+    T = np.ones((4, 2), np.float32)
+    db = np.concatenate([T, T, T + 1, T]).astype(np.float32)
+    dbo = np.array([0, 4, 8, 12, 16], np.int64)
+    qs = T.copy()
+    qo = np.array([0, 4], np.int64)
+    for dist in ("dk", "dtw"):
+        ids, keys = O.knn_brute(db, dbo, qs, qo, 6, dist)
+        assert ids.tolist() == [[0, 1, 3, 2, -1, -1]]
+        assert keys[0, 4] == INF and keys[0, 0] == 0.0
+        ids2, keys2, _ = O.knn_scan(db, dbo, qs, qo, 6, dist)
+        assert np.array_equal(ids, ids2) and np.array_equal(keys, keys2)
+
+
+def test_knn_permutation_invariance(rng):
+    db, dbo = _db(rng, 120, (8, 20), 2)
+    qs, qo = _db(rng, 3, (8, 20), 2)
+    perm = rng.permutation(120)
+    lens = np.diff(dbo)
+    series = [db[dbo[i]:dbo[i + 1]] for i in range(120)]
+    db2 = np.concatenate([series[p] for p in perm]).astype(np.float32)
+    dbo2 = np.concatenate([[0], np.cumsum(lens[perm])]).astype(np.int64)
+    for dist in ("dk", "dtw"):
+        ids, keys = O.knn_brute(db, dbo, qs, qo, 4, dist)
+        ids2, keys2 = O.knn_brute(db2, dbo2, qs, qo, 4, dist)
+        assert np.array_equal(keys, keys2)
+        # ids agree wherever the key is unique among the candidates
+        assert np.array_equal(perm[ids2], ids)
+
+
+def test_fp32_dtw_close_to_fp64():
+    """fp32 accumulation stays within 1e-5 relative of fp64 at length 1024."""
+    r = np.random.default_rng(7)
+    worst = 0.0
+    for _ in range(4):
+        base = np.cumsum(r.normal(size=(1024, 3)), axis=0)
+        S = (base + r.normal(scale=0.1, size=base.shape)).astype(np.float32)
+        T = (base + r.normal(scale=0.1, size=base.shape)).astype(np.float32)
+        for w in (102, -1):
+            a, b = O.dtw_f32(S, T, w), O.dtw_f64(S, T, w)
+            worst = max(worst, abs(a - b) / b)
+    assert worst < 1e-5
