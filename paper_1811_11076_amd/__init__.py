@@ -1,0 +1,141 @@
+"""Exact k-NN over multi-dimensional time series on MI355X (gfx950).
+
+Python face of the C-ABI in ``include/tsknn.h``: torch supplies device
+memory and the current stream; every step of the scan runs in the HIP
+library.  Importing the package does not load the library; the first Index
+does, and raises if it has not been built (there is no CPU fallback).
+
+    idx = Index(db_values_cuda_f32[sum_len, d], db_offsets_int64[n+1])
+    ids, dist, stats = idx.knn(q_values, q_offsets, k=10, distance="dk",
+                               band=0.1, stats=True)
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+__all__ = ["Index", "TskError", "version"]
+
+TskError = _lib.TskError
+
+
+def version():
+    lib = _lib.load()
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _lib.check(lib.tsk_version(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _offsets(off) -> np.ndarray:
+    if hasattr(off, "detach"):
+        off = off.detach().cpu().numpy()
+    return np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+
+
+def _values(v, dim=None):
+    torch = _torch()
+    if not isinstance(v, torch.Tensor) or not v.is_cuda:
+        raise TypeError("series values must be a CUDA (HIP) torch tensor")
+    if v.dtype != torch.float32:
+        raise TypeError("series values must be float32")
+    if v.dim() == 1:
+        v = v[:, None]
+    if dim is not None and v.shape[1] != dim:
+        raise ValueError(f"dimension {v.shape[1]} does not match the index ({dim})")
+    return v.contiguous()
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+_DIST = {"dtw": _lib.TSK_DTW, "dk": _lib.TSK_DK}
+
+
+class Index:
+    """Read-only device index over database series (C: tsk_index_build)."""
+
+    def __init__(self, values, offsets):
+        self._lib = _lib.load()
+        v = _values(values)
+        off = _offsets(offsets)
+        self.n = int(off.shape[0] - 1)
+        self.dim = int(v.shape[1])
+        self._h = ctypes.c_void_p()
+        _lib.check(self._lib.tsk_index_build(
+            ctypes.c_void_p(v.data_ptr()), off.ctypes.data_as(ctypes.c_void_p), self.n, self.dim,
+            None, _stream(), ctypes.byref(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.tsk_index_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def knn(self, queries, q_offsets, k: int, distance: str = "dk", band=None, order=None,
+            seed_count: int = 0, stats: bool = False):
+        """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
+        float32 [nq, k], stats dict or None); DK distances are unsquared."""
+        torch = _torch()
+        qv = _values(queries, self.dim)
+        qo = _offsets(q_offsets)
+        nq = int(qo.shape[0] - 1)
+        ids = torch.empty((nq, k), dtype=torch.int64, device=qv.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=qv.device)
+        opts = _lib.QueryOpts()
+        opts.size = ctypes.sizeof(_lib.QueryOpts)
+        opts.seed_count = int(seed_count)
+        if order is not None:
+            if order.dtype != torch.int32 or not order.is_cuda or tuple(order.shape) != (nq, self.n):
+                raise ValueError("order must be a CUDA int32 tensor [n_queries, n_series]")
+            order = order.contiguous()
+            opts.order = _lib.TSK_ORDER_GIVEN
+            opts.order_dev = order.data_ptr()
+        st = _lib.Stats() if stats else None
+        _lib.check(self._lib.tsk_knn_query(
+            self._h, ctypes.c_void_p(qv.data_ptr()), qo.ctypes.data_as(ctypes.c_void_p), nq, int(k),
+            _DIST[distance], _lib.band_struct(band), ctypes.byref(opts),
+            ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
+            ctypes.byref(st) if st is not None else None, _stream()))
+        return ids, dist, (st.as_dict() if st is not None else None)
+
+    def pair_distances(self, queries, q_offsets, distance: str = "dk", band=None):
+        """Full-DP key of every (query, series) pair (C: tsk_pair_distances);
+        DK keys are squared."""
+        torch = _torch()
+        qv = _values(queries, self.dim)
+        qo = _offsets(q_offsets)
+        nq = int(qo.shape[0] - 1)
+        out = torch.empty((nq, self.n), dtype=torch.float32, device=qv.device)
+        _lib.check(self._lib.tsk_pair_distances(
+            self._h, ctypes.c_void_p(qv.data_ptr()), qo.ctypes.data_as(ctypes.c_void_p), nq,
+            _DIST[distance], _lib.band_struct(band), ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def pair_bounds(self, queries, q_offsets, distance: str = "dk", band=None):
+        """(lb, greedy value, greedy moves) of every pair (C: tsk_pair_bounds)."""
+        torch = _torch()
+        qv = _values(queries, self.dim)
+        qo = _offsets(q_offsets)
+        nq = int(qo.shape[0] - 1)
+        lb = torch.empty((nq, self.n), dtype=torch.float32, device=qv.device)
+        ub = torch.empty((nq, self.n), dtype=torch.float32, device=qv.device)
+        steps = torch.empty((nq, self.n), dtype=torch.int32, device=qv.device)
+        _lib.check(self._lib.tsk_pair_bounds(
+            self._h, ctypes.c_void_p(qv.data_ptr()), qo.ctypes.data_as(ctypes.c_void_p), nq,
+            _DIST[distance], _lib.band_struct(band), ctypes.c_void_p(lb.data_ptr()),
+            ctypes.c_void_p(ub.data_ptr()), ctypes.c_void_p(steps.data_ptr()), _stream()))
+        return lb, ub, steps

@@ -1,0 +1,104 @@
+"""ctypes view of the C-ABI in include/tsknn.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from .build import lib_path
+
+TSK_OK = 0
+TSK_ERR_INVALID_ARG = 1
+TSK_ERR_OOM = 2
+TSK_ERR_DEVICE = 3
+TSK_ERR_UNSUPPORTED = 4
+TSK_ERR_IO = 5
+TSK_ERR_CANCELLED = 6
+
+TSK_DTW, TSK_DK = 0, 1
+TSK_BAND_NONE, TSK_BAND_ABS, TSK_BAND_FRAC = 0, 1, 2
+TSK_ORDER_PLAIN, TSK_ORDER_GIVEN = 0, 1
+
+_ERRNAMES = {1: "INVALID_ARG", 2: "OOM", 3: "DEVICE", 4: "UNSUPPORTED", 5: "IO", 6: "CANCELLED"}
+
+
+class TskError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tsknn error {_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Band(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("r", ctypes.c_int32), ("frac", ctypes.c_float)]
+
+
+class QueryOpts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int64), ("order", ctypes.c_int32), ("seed_count", ctypes.c_int32),
+                ("order_dev", ctypes.c_void_p), ("use_graph", ctypes.c_int32),
+                ("dp_kernel", ctypes.c_int32)]
+
+
+class IndexOpts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int64), ("reserved", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int64), ("seed_pairs", ctypes.c_int64),
+                ("bound_pruned", ctypes.c_int64), ("dp_started", ctypes.c_int64),
+                ("dp_completed", ctypes.c_int64), ("dp_abandoned", ctypes.c_int64),
+                ("dp_cells", ctypes.c_int64), ("bound_steps", ctypes.c_int64),
+                ("fallback_pairs", ctypes.c_int64), ("ms_total", ctypes.c_float),
+                ("ms_seed", ctypes.c_float), ("ms_bound", ctypes.c_float),
+                ("ms_dp", ctypes.c_float), ("ms_final", ctypes.c_float)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+
+SIGNATURES = {
+    "tsk_version": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "tsk_last_error": (ctypes.c_char_p, []),
+    "tsk_index_build": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp, ctypes.POINTER(_vp)]),
+    "tsk_index_free": (ctypes.c_int, [_vp]),
+    "tsk_index_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
+    "tsk_knn_query": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, Band, _vp, _vp, _vp, _vp,
+                                     _vp]),
+    "tsk_pair_distances": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp]),
+    "tsk_pair_bounds": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def load():
+    """Loads libtsknn.so from the package directory; raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"the HIP library {path} is not built; run "
+                           "`python -m paper_1811_11076_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int):
+    if rc != TSK_OK:
+        raise TskError(rc, load().tsk_last_error().decode(errors="replace"))
+
+
+def band_struct(band) -> Band:
+    if band is None:
+        return Band(TSK_BAND_NONE, 0, 0.0)
+    if isinstance(band, float):
+        return Band(TSK_BAND_FRAC, 0, band)
+    return Band(TSK_BAND_ABS, int(band), 0.0)

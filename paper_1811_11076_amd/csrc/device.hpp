@@ -37,6 +37,35 @@ __device__ __forceinline__ void load_point(const float *__restrict__ p, float (&
         v[k] = p[k];
 }
 
+// Correctly rounded fp32 square root.  The hardware/library square root is
+// taken as a first guess r, then corrected with Tuckerman's rounding test: the
+// midpoints between r and its fp32 neighbours have at most 25 significant
+// bits, so their squares are exact in fp64 and comparing x with them decides
+// whether r, or a neighbour, is the nearest fp32 value to sqrt(x).  (x cannot
+// equal a midpoint's square: that square needs more than 24 bits.)
+__device__ __forceinline__ float sqrt_rn_f32(float x)
+{
+    if (!(x > 0.0f) || x == __builtin_huge_valf())
+        return x == 0.0f ? x : (x > 0.0f ? x : __builtin_nanf(""));
+    float r = __builtin_sqrtf(x);
+    const double xd = (double)x;
+#pragma unroll
+    for (int it = 0; it < 3; ++it) {
+        // r > 0 and finite: the fp32 neighbours are one bit pattern apart
+        const float lo = __uint_as_float(__float_as_uint(r) - 1u);
+        const float hi = __uint_as_float(__float_as_uint(r) + 1u);
+        const double mlo = 0.5 * ((double)r + (double)lo);
+        const double mhi = 0.5 * ((double)r + (double)hi);
+        if (xd < mlo * mlo)
+            r = lo;
+        else if (xd > mhi * mhi)
+            r = hi;
+        else
+            break;
+    }
+    return r;
+}
+
 __device__ __forceinline__ float min3f(float a, float b, float c)
 {
     return fminf(fminf(a, b), c);

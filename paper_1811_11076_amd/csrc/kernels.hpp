@@ -1,0 +1,726 @@
+// tsknn device kernels for gfx950 (wave64).
+#pragma once
+
+#include "device.hpp"
+
+namespace tsk {
+
+enum { DIST_DTW = 0, DIST_DK = 1 };
+
+// Counter slots (device u64), mirrored by tsk_stats.
+enum {
+    C_PAIRS = 0,
+    C_SEED_PAIRS,
+    C_BOUND_PRUNED,
+    C_DP_STARTED,
+    C_DP_COMPLETED,
+    C_DP_ABANDONED,
+    C_DP_CELLS,
+    C_BOUND_STEPS,
+    C_FALLBACK,
+    C_LATE_PRUNED,
+    C_NUM
+};
+
+struct BandArgs {
+    int mode, r;
+    float frac;
+};
+
+__device__ __forceinline__ Band pair_band(const BandArgs &ba, int m, int n)
+{
+    return make_band(m, n, band_w(ba.mode, ba.r, ba.frac, m, n));
+}
+
+// Wave-wide sum of a per-lane counter, added once per wave.
+__device__ __forceinline__ void wave_count(unsigned long long *ctr, unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v)
+        atomicAdd(ctr, v);
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ------------------------------------------------------------------ fills
+// Plain fill kernels (no hipMemsetAsync, so the sequence stays capturable).
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------------ index pack
+// AoS [sum len][D] -> 64-series struct-of-arrays tiles: tile t holds series
+// 64t..64t+63 as [pos][dim][lane] with pos < the tile's longest length, so a
+// wave whose lane l handles series 64t+l reads 256 contiguous bytes per
+// (pos, dim).  Slots past a series' end hold 0 and are never read.
+template <int D>
+__global__ void k_pack_soa(const float *__restrict__ aos, const int64_t *__restrict__ off,
+                           const int32_t *__restrict__ len, int64_t N,
+                           const int64_t *__restrict__ tile_off, const int32_t *__restrict__ tile_len,
+                           float *__restrict__ soa)
+{
+    const int64_t t = blockIdx.x;
+    const int64_t cnt = (int64_t)tile_len[t] * D * 64;
+    float *dst = soa + tile_off[t];
+    for (int64_t idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
+        const int lane = (int)(idx & 63);
+        const int dim = (int)((idx >> 6) % D);
+        const int64_t pos = (idx >> 6) / D;
+        const int64_t s = t * 64 + lane;
+        float v = 0.0f;
+        if (s < N && pos < len[s])
+            v = aos[(off[s] + pos) * D + dim];
+        dst[idx] = v;
+    }
+}
+
+// ------------------------------------------------------------------ query envelope
+// Envelope of the query for candidates of length n (Sec. 2.3 / Sec. 3 boxes,
+// with the query in the role of the enveloped series): for every candidate
+// point j, the per-dimension [min, max] of the query points i that the band
+// lets align with j.  Brute-force window; an empty window gives
+// [+inf, -inf].  env: [q][j][2][D].
+template <int D>
+__global__ void k_env(const float *__restrict__ qv, const int64_t *__restrict__ qoff, int nq, int n,
+                      BandArgs ba, float *__restrict__ env)
+{
+    const int q = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq || j >= n)
+        return;
+    const int m = (int)(qoff[q + 1] - qoff[q]);
+    const float *Q = qv + qoff[q] * D;
+    const Band b = pair_band(ba, m, n);
+    int lo, hi;
+    band_rows(b, j, m, lo, hi);
+    float mn[D], mx[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        mn[k] = tsk_inf();
+        mx[k] = -tsk_inf();
+    }
+    for (int i = lo; i <= hi; ++i) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float v = Q[i * D + k];
+            mn[k] = fminf(mn[k], v);
+            mx[k] = fmaxf(mx[k], v);
+        }
+    }
+    float *e = env + ((int64_t)q * n + j) * 2 * D;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        e[k] = mn[k];
+        e[D + k] = mx[k];
+    }
+}
+
+// Squared distance of x to the box [lo, hi] (Sec. 3: sum over dimensions of
+// the squared interval distances), same fp32 order as the point cost; an
+// empty box gives +inf.
+template <int D>
+__device__ __forceinline__ float box_term(const float (&x)[D], const float *lo, const float *hi)
+{
+    float acc = 0.0f;
+    bool empty = false;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        empty |= lo[k] > hi[k];
+        float e = 0.0f;
+        if (x[k] < lo[k])
+            e = lo[k] - x[k];
+        else if (x[k] > hi[k])
+            e = x[k] - hi[k];
+        acc = (k == 0) ? e * e : __builtin_fmaf(e, e, acc);
+    }
+    return empty ? tsk_inf() : acc;
+}
+
+// ------------------------------------------------------------------ greedy walk
+// Alg. 1 (Sec. 4.1): from (0,0) step to the cheapest of (i+1,j), (i+1,j+1),
+// (i,j+1) (ties to the first listed; off-matrix or out-of-band moves +inf)
+// until (m-1, n-1).  DIST_DK keeps the running maximum (the greedy DK upper
+// bound, squared domain); DIST_DTW sums along the path in path order (an
+// upper bound of the fp32 DTW, used to seed its threshold).  Returns as soon
+// as the value exceeds eps; eps is lowered from *tau (nullable) every 8
+// moves.  *completed says whether the walk reached the corner.
+template <int D, int DIST>
+__device__ float greedy_walk(const float *__restrict__ q, int m, const float *__restrict__ c, int n,
+                             const Band &band, float eps, const uint32_t *tau, int &steps_out,
+                             bool &completed)
+{
+    float qi[D], qi1[D], cj[D], cj1[D];
+    load_point<D>(q, qi);
+    load_point<D>(c, cj);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        qi1[k] = 0.0f;
+        cj1[k] = 0.0f;
+    }
+    float g = point_cost<D>(qi, cj);
+    int i = 0, j = 0, steps = 0;
+    completed = false;
+    if (g > eps) {
+        steps_out = 0;
+        return g;
+    }
+    if (m > 1)
+        load_point<D>(q + D, qi1);
+    if (n > 1)
+        load_point<D>(c + D, cj1);
+    while (i < m - 1 || j < n - 1) {
+        const bool di = i + 1 < m, dj = j + 1 < n;
+        float c_dn = tsk_inf(), c_dg = tsk_inf(), c_rt = tsk_inf();
+        if (di && band_ok(band, i + 1, j))
+            c_dn = point_cost<D>(qi1, cj);
+        if (di && dj && band_ok(band, i + 1, j + 1))
+            c_dg = point_cost<D>(qi1, cj1);
+        if (dj && band_ok(band, i, j + 1))
+            c_rt = point_cost<D>(qi, cj1);
+        int mv;
+        float cst;
+        if (c_dn <= c_dg && c_dn <= c_rt) {
+            mv = 0;
+            cst = c_dn;
+        } else if (c_dg <= c_rt) {
+            mv = 1;
+            cst = c_dg;
+        } else {
+            mv = 2;
+            cst = c_rt;
+        }
+        ++steps;
+        if (cst == tsk_inf()) {
+            g = tsk_inf();
+            steps_out = steps;
+            return g;
+        }
+        g = DIST == DIST_DK ? fmaxf(g, cst) : cst + g;
+        if (mv != 2) {
+            ++i;
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                qi[k] = qi1[k];
+            if (i + 1 < m)
+                load_point<D>(q + (int64_t)(i + 1) * D, qi1);
+        }
+        if (mv != 0) {
+            ++j;
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                cj[k] = cj1[k];
+            if (j + 1 < n)
+                load_point<D>(c + (int64_t)(j + 1) * D, cj1);
+        }
+        if (tau && (steps & 7) == 0)
+            eps = fminf(eps, bits_f(load_relaxed_u32(tau)));
+        if (g > eps) {
+            steps_out = steps;
+            return g;
+        }
+    }
+    steps_out = steps;
+    completed = true;
+    return g;
+}
+
+// ------------------------------------------------------------------ seed pass
+// Threshold seed (Sec. 4.4, first loop, generalised to k): the greedy bound
+// of the first S candidates of each query (in the query's candidate order)
+// is computed in full; the k-th smallest of them bounds the k-th smallest
+// distance from above and becomes the query's starting threshold.
+template <int D, int DIST>
+__global__ void k_seed(const float *__restrict__ qv, const int64_t *__restrict__ qoff, int nq,
+                       const float *__restrict__ aos, const int64_t *__restrict__ off,
+                       const int32_t *__restrict__ len, int64_t N, const int32_t *__restrict__ order,
+                       int S, int k, BandArgs ba, unsigned long long *seedslots, uint32_t *tau,
+                       unsigned long long *ctr)
+{
+    const int q = blockIdx.y;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long steps_cnt = 0, pairs = 0;
+    if (q < nq && p < S) {
+        const int c = order ? order[(int64_t)q * N + p] : p;
+        const int m = (int)(qoff[q + 1] - qoff[q]);
+        const int n = len[c];
+        const Band b = pair_band(ba, m, n);
+        int steps;
+        bool done;
+        const float g = greedy_walk<D, DIST>(qv + qoff[q] * D, m, aos + off[c] * D, n, b, tsk_inf(),
+                                             nullptr, steps, done);
+        if (done && g != tsk_inf()) {
+            topk_insert(seedslots + (int64_t)q * k, k, make_key(g, (uint32_t)c));
+            tau_from_slots(seedslots + (int64_t)q * k, k, tau + q);
+        }
+        steps_cnt = steps;
+        pairs = 1;
+    }
+    wave_count(ctr + C_BOUND_STEPS, steps_cnt);
+    wave_count(ctr + C_SEED_PAIRS, pairs);
+}
+
+// ------------------------------------------------------------------ bound pass
+// One lane per candidate (64-series SoA tiles, coalesced), a group of
+// queries per block.
+//   DTW: LB_Box with the query's envelope around each candidate point (eq. (1)
+//        with the two series' roles exchanged), fp32, summed over the
+//        candidate's points in order; stops once the partial sum exceeds the
+//        threshold (terms are >= 0).
+//   DK:  every path starts at (0,0) and ends at (m-1,n-1), so
+//        max(c(0,0), c(m-1,n-1)) <= squared DK; pairs passing it run the
+//        greedy walk of Alg. 1 with early return at the running threshold,
+//        and a completed walk lowers that threshold (Sec. 4.4).
+// lbv[q][c] receives the bound if the pair survives (<= threshold), else
+// +inf.  DEBUG mode: no threshold, writes lb / greedy value / moves instead.
+struct BoundArgs {
+    const float *qv;
+    const int64_t *qoff;
+    int nq;
+    int qgroup;
+    const float *soa;
+    const int64_t *tile_off;
+    const float *aos;
+    const int64_t *off;
+    const int32_t *len;
+    int64_t N;
+    int k;
+    BandArgs ba;
+    const float *env; // [nq][env_n][2][D] or null
+    int env_n;
+    uint32_t *tau;
+    unsigned long long *ubslots;
+    float *lbv;
+    unsigned long long *ctr;
+    // debug outputs (DEBUG mode)
+    float *dbg_lb;
+    float *dbg_ub;
+    int32_t *dbg_steps;
+};
+
+template <int D, int DIST, bool DEBUG>
+__global__ __launch_bounds__(256) void k_bounds(BoundArgs a)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q0 = blockIdx.y * a.qgroup;
+    const int q1 = min(a.nq, q0 + a.qgroup);
+    const bool valid = c < a.N;
+    const int64_t tile = c >> 6;
+    const int lane = (int)(c & 63);
+    const int n = valid ? a.len[c] : 1;
+    const float *tb = valid ? a.soa + a.tile_off[tile] + lane : a.soa;
+    unsigned long long pruned = 0, steps_cnt = 0, pairs = 0;
+
+    float c0[D], cl[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        c0[k] = valid ? tb[(0 * D + k) * 64] : 0.0f;
+        cl[k] = valid ? tb[((int64_t)(n - 1) * D + k) * 64] : 0.0f;
+    }
+
+    for (int q = q0; q < q1; ++q) {
+        if (!valid)
+            continue;
+        ++pairs;
+        const int m = (int)(a.qoff[q + 1] - a.qoff[q]);
+        const float *Q = a.qv + a.qoff[q] * D;
+        const Band b = pair_band(a.ba, m, n);
+        float tq = DEBUG ? tsk_inf() : bits_f(load_relaxed_u32(a.tau + q));
+        float lb;
+        if (DIST == DIST_DK) {
+            float qa[D], qz[D];
+            load_point<D>(Q, qa);
+            load_point<D>(Q + (int64_t)(m - 1) * D, qz);
+            lb = fmaxf(point_cost<D>(qa, c0), point_cost<D>(qz, cl));
+            if (DEBUG || lb <= tq) {
+                int steps;
+                bool done;
+                const float g = greedy_walk<D, DIST_DK>(Q, m, a.aos + a.off[c] * D, n, b, tq,
+                                                        DEBUG ? nullptr : a.tau + q, steps, done);
+                steps_cnt += steps;
+                if (DEBUG) {
+                    if (a.dbg_ub)
+                        a.dbg_ub[(int64_t)q * a.N + c] = g;
+                    if (a.dbg_steps)
+                        a.dbg_steps[(int64_t)q * a.N + c] = steps;
+                } else if (done && g != tsk_inf() && g <= bits_f(load_relaxed_u32(a.tau + q))) {
+                    topk_insert(a.ubslots + (int64_t)q * a.k, a.k, make_key(g, (uint32_t)c));
+                    tau_from_slots(a.ubslots + (int64_t)q * a.k, a.k, a.tau + q);
+                }
+            }
+        } else {
+            // LB_Box, candidate points against the query envelope.
+            float acc = 0.0f;
+            if (a.env && n == a.env_n) {
+                const float *E = a.env + (int64_t)q * a.env_n * 2 * D;
+                for (int j = 0; j < n; ++j) {
+                    float x[D];
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        x[k] = tb[((int64_t)j * D + k) * 64];
+                    acc = box_term<D>(x, E + (int64_t)j * 2 * D, E + (int64_t)j * 2 * D + D) + acc;
+                    if (!DEBUG && acc > tq)
+                        break;
+                }
+            } else {
+                for (int j = 0; j < n; ++j) {
+                    float x[D], lo[D], hi[D];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        x[k] = tb[((int64_t)j * D + k) * 64];
+                        lo[k] = tsk_inf();
+                        hi[k] = -tsk_inf();
+                    }
+                    int ilo, ihi;
+                    band_rows(b, j, m, ilo, ihi);
+                    for (int i = ilo; i <= ihi; ++i) {
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            const float v = Q[(int64_t)i * D + k];
+                            lo[k] = fminf(lo[k], v);
+                            hi[k] = fmaxf(hi[k], v);
+                        }
+                    }
+                    acc = box_term<D>(x, lo, hi) + acc;
+                    if (!DEBUG && acc > tq)
+                        break;
+                }
+            }
+            steps_cnt += n;
+            lb = acc;
+            if (DEBUG) {
+                int steps;
+                bool done;
+                const float g = greedy_walk<D, DIST_DTW>(Q, m, a.aos + a.off[c] * D, n, b, tsk_inf(),
+                                                         nullptr, steps, done);
+                if (a.dbg_ub)
+                    a.dbg_ub[(int64_t)q * a.N + c] = g;
+                if (a.dbg_steps)
+                    a.dbg_steps[(int64_t)q * a.N + c] = steps;
+            }
+        }
+        if (DEBUG) {
+            if (a.dbg_lb)
+                a.dbg_lb[(int64_t)q * a.N + c] = lb;
+        } else {
+            tq = bits_f(load_relaxed_u32(a.tau + q));
+            const bool keep = lb <= tq;
+            a.lbv[(int64_t)q * a.N + c] = keep ? lb : tsk_inf();
+            pruned += keep ? 0 : 1;
+        }
+    }
+    if (!DEBUG) {
+        wave_count(a.ctr + C_BOUND_PRUNED, pruned);
+        wave_count(a.ctr + C_PAIRS, pairs);
+    }
+    wave_count(a.ctr + C_BOUND_STEPS, steps_cnt);
+}
+
+// ------------------------------------------------------------------ compaction
+// Survivors of one query, in the query's candidate order, re-checked against
+// the current threshold: surv[q][0..cnt).  One block of 256 per query.
+__global__ __launch_bounds__(256) void k_compact(const float *__restrict__ lbv, int64_t N,
+                                                 const int32_t *__restrict__ order,
+                                                 const uint32_t *__restrict__ tau,
+                                                 int32_t *__restrict__ surv, int32_t *__restrict__ cnt,
+                                                 int32_t *__restrict__ max_cnt,
+                                                 unsigned long long *ctr)
+{
+    const int q = blockIdx.x;
+    __shared__ int wave_tot[4];
+    __shared__ int base_s;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const float tq = bits_f(tau[q]);
+    if (threadIdx.x == 0)
+        base_s = 0;
+    __syncthreads();
+    unsigned long long late = 0;
+    for (int64_t p0 = 0; p0 < N; p0 += 256) {
+        const int64_t p = p0 + threadIdx.x;
+        int c = -1;
+        bool keep = false;
+        if (p < N) {
+            c = order ? order[(int64_t)q * N + p] : (int)p;
+            const float lb = lbv[(int64_t)q * N + c];
+            keep = lb <= tq;
+            late += (lb != tsk_inf() && !keep) ? 1 : 0;
+        }
+        const unsigned long long bal = __ballot(keep);
+        const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0)
+            wave_tot[wv] = __popcll(bal);
+        __syncthreads();
+        int off = base_s;
+        for (int w = 0; w < wv; ++w)
+            off += wave_tot[w];
+        if (keep)
+            surv[(int64_t)q * N + off + rank] = c;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            base_s += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+        __syncthreads();
+    }
+    wave_count(ctr + C_BOUND_PRUNED, late);
+    if (threadIdx.x == 0) {
+        cnt[q] = base_s;
+        atomicMax(max_cnt, base_s);
+    }
+}
+
+// ------------------------------------------------------------------ general DP
+// One wave per pair: the quadratic DP of Sec. 2.1 (DTW: cost + min of the
+// three predecessors; DK: max(cost, min)), with D(-1,-1) = 0 and every other
+// outside cell +inf, restricted to the band.  Rows are processed in strips
+// of 256 (4 consecutive rows per lane); inside a strip lane l works on column
+// s - l at step s (a skewed wavefront), receiving the row below from lane
+// l-1 of the previous step; the strip's top row is handed to the next strip
+// through a per-wave buffer.
+// Dead cells (value > tau) become +inf (the sparse-DK semantics of Alg. 3;
+// for DTW the same holds because values only grow along a path).  With
+// sigma(i, j) = j + floor(i / 4) a path moves sigma by 0, 1 or 2 per move,
+// so it cannot skip two consecutive steps of a strip: when two consecutive
+// steps are all dead and no live input from the strip below is still
+// pending, the rest of the strip is dead, and if it handed no live value up
+// the whole pair is > tau (abandoned).  Returns the value, or +inf if > tau.
+template <int D, int DIST>
+__device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *__restrict__ cp, int n,
+                              const Band &band, const uint32_t *tau_ptr, float *__restrict__ tbuf,
+                              unsigned long long &cells)
+{
+    const int lane = threadIdx.x & 63;
+    const float tau = tau_ptr ? bits_f(load_relaxed_u32(tau_ptr)) : tsk_inf();
+    float result = tsk_inf();
+    int in_max = -1;  // largest column with a live value in the strip input
+    int js_prev = 0;  // first column of the previous strip
+    float *tb_in = tbuf, *tb_out = tbuf + n;
+    for (int base = 0; base < m; base += 256) {
+        if (base > 0 && in_max < 0)
+            break;
+        const bool last_strip = base + 256 >= m;
+        float qr[4][D];
+        int jlo[4], jhi[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = base + 4 * lane + r;
+            if (i < m) {
+                load_point<D>(qp + (int64_t)i * D, qr[r]);
+                band_cols(band, i, n, jlo[r], jhi[r]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    qr[r][k] = 0.0f;
+                jlo[r] = n;
+                jhi[r] = -1;
+            }
+        }
+        int js, je, tmp;
+        band_cols(band, base, n, js, tmp);
+        band_cols(band, min(base + 255, m - 1), n, tmp, je);
+        if (js > je)
+            break;
+        int out_max = -1;
+        float Dp[4] = {tsk_inf(), tsk_inf(), tsk_inf(), tsk_inf()};
+        // lane 0's first cell (base, js) has the lower-left predecessor
+        // (base-1, js-1), which a band can leave inside and finite; the
+        // previous strip wrote it iff js-1 is within its columns
+        float recv_prev = tsk_inf(), my_top = tsk_inf();
+        if (lane == 0 && base > 0 && js - 1 >= js_prev && js - 1 <= in_max)
+            recv_prev = tb_in[js - 1];
+        bool alive_prev = true;
+        const int nsteps = je - js + 64;
+        for (int s = 0; s < nsteps; ++s) {
+            const int j = js + s - lane;
+            float recv = __shfl_up(my_top, 1, 64);
+            if (lane == 0)
+                recv = (base > 0 && j <= in_max) ? tb_in[j] : tsk_inf();
+            const bool jv = j >= 0 && j < n;
+            float cv[D];
+            if (jv)
+                load_point<D>(cp + (int64_t)j * D, cv);
+            else {
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    cv[k] = 0.0f;
+            }
+            float down = recv, diag = recv_prev;
+            bool any = false;
+            float Dc[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = base + 4 * lane + r;
+                const bool ok = jv && j >= jlo[r] && j <= jhi[r];
+                float pred = min3f(diag, down, Dp[r]);
+                if (i == 0 && j == 0)
+                    pred = 0.0f;
+                const float cst = point_cost<D>(qr[r], cv);
+                float v = DIST == DIST_DK ? fmaxf(cst, pred) : cst + pred;
+                v = (ok && v <= tau) ? v : tsk_inf();
+                diag = Dp[r];
+                down = v;
+                Dc[r] = v;
+                any |= v != tsk_inf();
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                Dp[r] = Dc[r];
+            recv_prev = recv;
+            my_top = Dc[3];
+            if (!last_strip && lane == 63 && jv) {
+                tb_out[j] = Dc[3];
+                if (Dc[3] != tsk_inf())
+                    out_max = j;
+            }
+            if (last_strip && j == n - 1) {
+                const int rr = m - 1 - base - 4 * lane;
+                if (rr >= 0 && rr < 4)
+                    result = Dc[rr];
+            }
+            cells += 4;
+            const bool alive_now = __ballot(any) != 0ull;
+            if (!alive_now && !alive_prev && js + s > in_max)
+                break;
+            alive_prev = alive_now;
+        }
+        in_max = __shfl(out_max, 63, 64);
+        js_prev = js;
+        float *t = tb_in;
+        tb_in = tb_out;
+        tb_out = t;
+        __threadfence_block();
+        if (last_strip)
+            break;
+    }
+    return wave_min(result);
+}
+
+struct DpArgs {
+    const float *qv;
+    const int64_t *qoff;
+    int nq;
+    const float *aos;
+    const int64_t *off;
+    const int32_t *len;
+    int64_t N;
+    int k;
+    BandArgs ba;
+    uint32_t *tau;
+    const float *lbv;
+    const int32_t *surv;
+    const int32_t *surv_cnt;
+    const int32_t *max_cnt;
+    unsigned long long *resslots;
+    unsigned long long *work;
+    float *tbuf;
+    int tb_stride;
+    unsigned long long *ctr;
+    float *out_all; // ALLPAIRS: [nq][N]
+};
+
+template <int D, int DIST, bool ALLPAIRS>
+__global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    float *tb = a.tbuf + gw * a.tb_stride;
+    unsigned long long cells = 0, started = 0, completed = 0, abandoned = 0, late = 0;
+    const int64_t total = ALLPAIRS ? (int64_t)a.nq * a.N : (int64_t)a.nq * (int64_t)(*a.max_cnt);
+    for (;;) {
+        unsigned long long t = 0;
+        if (lane == 0)
+            t = atomicAdd(a.work, 1ull);
+        t = __shfl(t, 0, 64);
+        if ((int64_t)t >= total)
+            break;
+        int q, c;
+        if (ALLPAIRS) {
+            q = (int)(t / a.N);
+            c = (int)(t % a.N);
+        } else {
+            q = (int)(t % a.nq);
+            const int r = (int)(t / a.nq);
+            if (r >= a.surv_cnt[q])
+                continue;
+            c = a.surv[(int64_t)q * a.N + r];
+            if (a.lbv[(int64_t)q * a.N + c] > bits_f(load_relaxed_u32(a.tau + q))) {
+                ++late;
+                continue;
+            }
+        }
+        const int m = (int)(a.qoff[q + 1] - a.qoff[q]);
+        const int n = a.len[c];
+        const Band b = pair_band(a.ba, m, n);
+        const float res = dp_wave_pair<D, DIST>(a.qv + a.qoff[q] * D, m, a.aos + a.off[c] * D, n, b,
+                                                ALLPAIRS ? nullptr : a.tau + q, tb, cells);
+        if (ALLPAIRS) {
+            if (lane == 0)
+                a.out_all[t] = res;
+        } else {
+            ++started;
+            if (res != tsk_inf()) {
+                ++completed;
+                if (lane == 0 && res <= bits_f(load_relaxed_u32(a.tau + q))) {
+                    topk_insert(a.resslots + (int64_t)q * a.k, a.k, make_key(res, (uint32_t)c));
+                    tau_from_slots(a.resslots + (int64_t)q * a.k, a.k, a.tau + q);
+                }
+            } else {
+                ++abandoned;
+            }
+        }
+    }
+    if (lane == 0) {
+        if (cells)
+            atomicAdd(a.ctr + C_DP_CELLS, cells * 64ull);
+        if (!ALLPAIRS) {
+            if (started)
+                atomicAdd(a.ctr + C_DP_STARTED, started);
+            if (completed)
+                atomicAdd(a.ctr + C_DP_COMPLETED, completed);
+            if (abandoned)
+                atomicAdd(a.ctr + C_DP_ABANDONED, abandoned);
+            if (late)
+                atomicAdd(a.ctr + C_BOUND_PRUNED, late);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ finalize
+// Slots -> (id, distance) rows, ascending; DK distances are the correctly
+// rounded square root of the squared key; empty ranks -> (-1, +inf).
+template <int DIST>
+__global__ void k_finalize(const unsigned long long *__restrict__ resslots, int nq, int k,
+                           int64_t *__restrict__ out_ids, float *__restrict__ out_dist)
+{
+    const int q = blockIdx.x;
+    const int r = threadIdx.x;
+    if (q >= nq || r >= k)
+        return;
+    const unsigned long long key = resslots[(int64_t)q * k + r];
+    int64_t id = -1;
+    float dist = tsk_inf();
+    if (key != TSK_KEY_EMPTY) {
+        id = (int64_t)(uint32_t)(key & 0xFFFFFFFFull);
+        const float v = bits_f((uint32_t)(key >> 32));
+        dist = DIST == DIST_DK ? sqrt_rn_f32(v) : v;
+    }
+    out_ids[(int64_t)q * k + r] = id;
+    out_dist[(int64_t)q * k + r] = dist;
+}
+
+} // namespace tsk

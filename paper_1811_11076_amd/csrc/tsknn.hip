@@ -1,0 +1,734 @@
+// tsknn: host runtime and C-ABI for the exact k-NN scan (arXiv 1811.11076)
+// on gfx950.  All arithmetic of the method runs in the kernels of
+// kernels.hpp; this file validates arguments, owns device memory and
+// sequences launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "tsknn.h"
+
+using namespace tsk;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int set_err(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            (void)hipGetLastError();                                                               \
+            return set_err(e_ == hipErrorOutOfMemory ? TSK_ERR_OOM : TSK_ERR_DEVICE, "%s: %s",     \
+                           #expr, hipGetErrorString(e_));                                          \
+        }                                                                                          \
+    } while (0)
+
+#define TSK_TRY(expr)                                                                              \
+    do {                                                                                           \
+        int rc_ = (expr);                                                                          \
+        if (rc_ != TSK_OK)                                                                         \
+            return rc_;                                                                            \
+    } while (0)
+
+// ------------------------------------------------------------------ device buffers
+template <typename T> struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0; // elements
+    int ensure(size_t n)
+    {
+        if (n <= cap && p)
+            return TSK_OK;
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+            cap = 0;
+        }
+        size_t want = std::max<size_t>(n, 1);
+        hipError_t e = hipMalloc((void **)&p, want * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return set_err(e == hipErrorOutOfMemory ? TSK_ERR_OOM : TSK_ERR_DEVICE,
+                           "hipMalloc of %zu bytes: %s", want * sizeof(T), hipGetErrorString(e));
+        }
+        cap = want;
+        return TSK_OK;
+    }
+    void release()
+    {
+        if (p)
+            (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+struct Workspace {
+    DevBuf<uint32_t> tau;
+    DevBuf<unsigned long long> seedslots, ubslots, resslots;
+    DevBuf<float> lbv;
+    DevBuf<int32_t> surv, surv_cnt, max_cnt;
+    DevBuf<unsigned long long> ctr, work;
+    DevBuf<int64_t> qoff;
+    DevBuf<float> env;
+    DevBuf<float> tbuf;
+    std::vector<int64_t> h_qoff;
+    void release()
+    {
+        tau.release();
+        seedslots.release();
+        ubslots.release();
+        resslots.release();
+        lbv.release();
+        surv.release();
+        surv_cnt.release();
+        max_cnt.release();
+        ctr.release();
+        work.release();
+        qoff.release();
+        env.release();
+        tbuf.release();
+    }
+};
+
+struct tsk_index {
+    int device = 0;
+    int dim = 0;
+    int64_t n = 0;
+    int64_t total = 0;
+    int32_t min_len = 0, max_len = 0;
+    int n_cu = 256;
+    std::vector<int64_t> h_off;
+    std::vector<int32_t> h_len;
+    float *aos = nullptr;
+    int64_t *off = nullptr;
+    int32_t *len = nullptr;
+    int64_t n_tiles = 0;
+    float *soa = nullptr;
+    int64_t *tile_off = nullptr;
+    int32_t *tile_len = nullptr;
+    hipStream_t last_stream = nullptr;
+    Workspace ws;
+    std::mutex mu;
+};
+
+// ------------------------------------------------------------------ dispatch
+template <template <int> class F, typename... A> static void dispatch_d(int d, A &&...args)
+{
+    switch (d) {
+    case 1: F<1>::run(args...); break;
+    case 2: F<2>::run(args...); break;
+    case 3: F<3>::run(args...); break;
+    case 4: F<4>::run(args...); break;
+    case 5: F<5>::run(args...); break;
+    case 6: F<6>::run(args...); break;
+    case 7: F<7>::run(args...); break;
+    case 8: F<8>::run(args...); break;
+    default: break;
+    }
+}
+
+static int grid_for(int64_t n, int block, int cap = 1 << 16)
+{
+    int64_t g = (n + block - 1) / block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+static void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+}
+
+static void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+}
+
+template <int D> struct PackLaunch {
+    static void run(tsk_index *ix, const float *, hipStream_t s)
+    {
+        hipLaunchKernelGGL(k_pack_soa<D>, dim3((unsigned)ix->n_tiles), dim3(256), 0, s, ix->aos,
+                           ix->off, ix->len, ix->n, ix->tile_off, ix->tile_len, ix->soa);
+    }
+};
+
+// ------------------------------------------------------------------ validation helpers
+static int check_series(const int64_t *off, int64_t n, const char *what, int32_t *min_len,
+                        int32_t *max_len)
+{
+    if (!off)
+        return set_err(TSK_ERR_INVALID_ARG, "%s offsets are NULL", what);
+    if (n < 1)
+        return set_err(TSK_ERR_INVALID_ARG, "%s count must be >= 1", what);
+    if (n > INT32_MAX)
+        return set_err(TSK_ERR_UNSUPPORTED, "%s count above 2^31-1", what);
+    if (off[0] != 0)
+        return set_err(TSK_ERR_INVALID_ARG, "%s offsets[0] must be 0", what);
+    int32_t mn = INT32_MAX, mx = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t L = off[i + 1] - off[i];
+        if (L < 1)
+            return set_err(TSK_ERR_INVALID_ARG, "%s %lld has length %lld (must be >= 1)", what,
+                           (long long)i, (long long)L);
+        if (L > TSK_MAX_LEN)
+            return set_err(TSK_ERR_UNSUPPORTED, "%s %lld has length %lld > %d", what, (long long)i,
+                           (long long)L, TSK_MAX_LEN);
+        mn = std::min<int32_t>(mn, (int32_t)L);
+        mx = std::max<int32_t>(mx, (int32_t)L);
+    }
+    if (min_len)
+        *min_len = mn;
+    if (max_len)
+        *max_len = mx;
+    return TSK_OK;
+}
+
+static int check_band(tsk_band b)
+{
+    if (b.mode != TSK_BAND_NONE && b.mode != TSK_BAND_ABS && b.mode != TSK_BAND_FRAC)
+        return set_err(TSK_ERR_INVALID_ARG, "band.mode %d is not NONE/ABS/FRAC", b.mode);
+    if (b.mode == TSK_BAND_ABS && b.r < 0)
+        return set_err(TSK_ERR_INVALID_ARG, "band.r must be >= 0");
+    if (b.mode == TSK_BAND_FRAC && !(b.frac >= 0.0f && std::isfinite(b.frac)))
+        return set_err(TSK_ERR_INVALID_ARG, "band.frac must be finite and >= 0");
+    return TSK_OK;
+}
+
+static int check_device(const tsk_index *ix)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != ix->device)
+        return set_err(TSK_ERR_INVALID_ARG, "current device %d differs from the index's device %d",
+                       dev, ix->device);
+    return TSK_OK;
+}
+
+// ------------------------------------------------------------------ C-ABI
+extern "C" int tsk_version(int *major, int *minor)
+{
+    if (major)
+        *major = TSK_VERSION_MAJOR;
+    if (minor)
+        *minor = TSK_VERSION_MINOR;
+    return TSK_OK;
+}
+
+extern "C" const char *tsk_last_error(void) { return g_err.c_str(); }
+
+extern "C" int tsk_index_info(const tsk_index *ix, int64_t *n_series, int32_t *dim)
+{
+    if (!ix)
+        return set_err(TSK_ERR_INVALID_ARG, "index is NULL");
+    if (n_series)
+        *n_series = ix->n;
+    if (dim)
+        *dim = ix->dim;
+    return TSK_OK;
+}
+
+static void free_index_memory(tsk_index *ix)
+{
+    if (ix->aos) (void)hipFree(ix->aos);
+    if (ix->off) (void)hipFree(ix->off);
+    if (ix->len) (void)hipFree(ix->len);
+    if (ix->soa) (void)hipFree(ix->soa);
+    if (ix->tile_off) (void)hipFree(ix->tile_off);
+    if (ix->tile_len) (void)hipFree(ix->tile_len);
+    ix->ws.release();
+}
+
+extern "C" int tsk_index_free(tsk_index *ix)
+{
+    if (!ix)
+        return TSK_OK;
+    (void)hipDeviceSynchronize();
+    free_index_memory(ix);
+    delete ix;
+    return TSK_OK;
+}
+
+static int index_build_impl(tsk_index *ix, const float *values_dev, hipStream_t s)
+{
+    const int D = ix->dim;
+    HIP_TRY(hipMalloc((void **)&ix->aos, std::max<int64_t>(1, ix->total * D) * sizeof(float)));
+    HIP_TRY(hipMalloc((void **)&ix->off, (ix->n + 1) * sizeof(int64_t)));
+    HIP_TRY(hipMalloc((void **)&ix->len, ix->n * sizeof(int32_t)));
+    HIP_TRY(hipMemcpyAsync(ix->aos, values_dev, ix->total * D * sizeof(float),
+                           hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ix->off, ix->h_off.data(), (ix->n + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ix->len, ix->h_len.data(), ix->n * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s));
+    ix->n_tiles = (ix->n + 63) / 64;
+    std::vector<int64_t> toff(ix->n_tiles + 1, 0);
+    std::vector<int32_t> tlen(ix->n_tiles, 0);
+    for (int64_t t = 0; t < ix->n_tiles; ++t) {
+        int32_t mx = 0;
+        for (int64_t c = t * 64; c < std::min<int64_t>(ix->n, t * 64 + 64); ++c)
+            mx = std::max(mx, ix->h_len[c]);
+        tlen[t] = mx;
+        toff[t + 1] = toff[t] + (int64_t)mx * D * 64;
+    }
+    HIP_TRY(hipMalloc((void **)&ix->soa, std::max<int64_t>(1, toff.back()) * sizeof(float)));
+    HIP_TRY(hipMalloc((void **)&ix->tile_off, toff.size() * sizeof(int64_t)));
+    HIP_TRY(hipMalloc((void **)&ix->tile_len, tlen.size() * sizeof(int32_t)));
+    HIP_TRY(hipMemcpyAsync(ix->tile_off, toff.data(), toff.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ix->tile_len, tlen.data(), tlen.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s));
+    dispatch_d<PackLaunch>(D, ix, values_dev, s);
+    HIP_TRY(hipGetLastError());
+    // the host vectors feeding the async copies live in the index; wait so
+    // the caller may release its input as soon as this call returns
+    HIP_TRY(hipStreamSynchronize(s));
+    return TSK_OK;
+}
+
+extern "C" int tsk_index_build(const float *values_dev, const int64_t *offsets_host,
+                               int64_t n_series, int32_t dim, const tsk_index_opts *opts,
+                               void *hip_stream, tsk_index **out)
+{
+    g_err.clear();
+    if (!out)
+        return set_err(TSK_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!values_dev)
+        return set_err(TSK_ERR_INVALID_ARG, "values_dev is NULL");
+    if (dim < 1 || dim > TSK_MAX_DIM)
+        return set_err(TSK_ERR_UNSUPPORTED, "dim %d outside [1, %d]", dim, TSK_MAX_DIM);
+    if (opts && opts->size != (int64_t)sizeof(tsk_index_opts))
+        return set_err(TSK_ERR_INVALID_ARG, "opts->size mismatch");
+    int32_t mn = 0, mx = 0;
+    TSK_TRY(check_series(offsets_host, n_series, "series", &mn, &mx));
+    int dev = 0, ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return set_err(TSK_ERR_DEVICE, "no HIP device available");
+    }
+    HIP_TRY(hipGetDevice(&dev));
+    tsk_index *ix = new (std::nothrow) tsk_index();
+    if (!ix)
+        return set_err(TSK_ERR_OOM, "host allocation failed");
+    ix->device = dev;
+    ix->dim = dim;
+    ix->n = n_series;
+    ix->total = offsets_host[n_series];
+    ix->min_len = mn;
+    ix->max_len = mx;
+    ix->h_off.assign(offsets_host, offsets_host + n_series + 1);
+    ix->h_len.resize(n_series);
+    for (int64_t i = 0; i < n_series; ++i)
+        ix->h_len[i] = (int32_t)(offsets_host[i + 1] - offsets_host[i]);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        ix->n_cu = std::max(1, prop.multiProcessorCount);
+    int rc = index_build_impl(ix, values_dev, (hipStream_t)hip_stream);
+    if (rc != TSK_OK) {
+        free_index_memory(ix);
+        delete ix;
+        return rc;
+    }
+    *out = ix;
+    return TSK_OK;
+}
+
+// ------------------------------------------------------------------ query plumbing
+struct QueryPlan {
+    int D;
+    int dist;
+    int k;
+    BandArgs ba;
+    int64_t nq, N;
+    int64_t chunk;
+    int seed;
+    const int32_t *order;
+    bool env_ok;
+};
+
+template <int D> struct EnvLaunch {
+    static void run(tsk_index *ix, const float *qv, int nq, BandArgs ba, hipStream_t s)
+    {
+        const int n = ix->max_len;
+        hipLaunchKernelGGL(k_env<D>, dim3((n + 63) / 64, nq), dim3(64), 0, s, qv, ix->ws.qoff.p, nq,
+                           n, ba, ix->ws.env.p);
+    }
+};
+
+template <int D> struct SeedLaunch {
+    static void run(tsk_index *ix, const float *qv, int nq, const QueryPlan &P,
+                    const int32_t *order, hipStream_t s)
+    {
+        if (P.seed <= 0)
+            return;
+        dim3 grid((P.seed + 63) / 64, nq);
+        if (P.dist == DIST_DK)
+            hipLaunchKernelGGL((k_seed<D, DIST_DK>), grid, dim3(64), 0, s, qv, ix->ws.qoff.p, nq,
+                               ix->aos, ix->off, ix->len, ix->n, order, P.seed, P.k, P.ba,
+                               ix->ws.seedslots.p, ix->ws.tau.p, ix->ws.ctr.p);
+        else
+            hipLaunchKernelGGL((k_seed<D, DIST_DTW>), grid, dim3(64), 0, s, qv, ix->ws.qoff.p, nq,
+                               ix->aos, ix->off, ix->len, ix->n, order, P.seed, P.k, P.ba,
+                               ix->ws.seedslots.p, ix->ws.tau.p, ix->ws.ctr.p);
+    }
+};
+
+static BoundArgs bound_args(tsk_index *ix, const float *qv, int nq, const QueryPlan &P)
+{
+    BoundArgs a;
+    a.qv = qv;
+    a.qoff = ix->ws.qoff.p;
+    a.nq = nq;
+    a.qgroup = 4;
+    a.soa = ix->soa;
+    a.tile_off = ix->tile_off;
+    a.aos = ix->aos;
+    a.off = ix->off;
+    a.len = ix->len;
+    a.N = ix->n;
+    a.k = P.k;
+    a.ba = P.ba;
+    a.env = P.env_ok ? ix->ws.env.p : nullptr;
+    a.env_n = ix->max_len;
+    a.tau = ix->ws.tau.p;
+    a.ubslots = ix->ws.ubslots.p;
+    a.lbv = ix->ws.lbv.p;
+    a.ctr = ix->ws.ctr.p;
+    a.dbg_lb = nullptr;
+    a.dbg_ub = nullptr;
+    a.dbg_steps = nullptr;
+    return a;
+}
+
+template <int D> struct BoundLaunch {
+    static void run(const BoundArgs &a, int dist, bool debug, hipStream_t s)
+    {
+        dim3 grid((unsigned)((a.N + 255) / 256), (unsigned)((a.nq + a.qgroup - 1) / a.qgroup));
+        if (dist == DIST_DK) {
+            if (debug)
+                hipLaunchKernelGGL((k_bounds<D, DIST_DK, true>), grid, dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_bounds<D, DIST_DK, false>), grid, dim3(256), 0, s, a);
+        } else {
+            if (debug)
+                hipLaunchKernelGGL((k_bounds<D, DIST_DTW, true>), grid, dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_bounds<D, DIST_DTW, false>), grid, dim3(256), 0, s, a);
+        }
+    }
+};
+
+static DpArgs dp_args(tsk_index *ix, const float *qv, int nq, const QueryPlan &P)
+{
+    DpArgs a;
+    a.qv = qv;
+    a.qoff = ix->ws.qoff.p;
+    a.nq = nq;
+    a.aos = ix->aos;
+    a.off = ix->off;
+    a.len = ix->len;
+    a.N = ix->n;
+    a.k = P.k;
+    a.ba = P.ba;
+    a.tau = ix->ws.tau.p;
+    a.lbv = ix->ws.lbv.p;
+    a.surv = ix->ws.surv.p;
+    a.surv_cnt = ix->ws.surv_cnt.p;
+    a.max_cnt = ix->ws.max_cnt.p;
+    a.resslots = ix->ws.resslots.p;
+    a.work = ix->ws.work.p;
+    a.tbuf = ix->ws.tbuf.p;
+    a.tb_stride = 2 * ix->max_len;
+    a.ctr = ix->ws.ctr.p;
+    a.out_all = nullptr;
+    return a;
+}
+
+static int dp_blocks(const tsk_index *ix) { return ix->n_cu * 4; }
+
+template <int D> struct DpLaunch {
+    static void run(const DpArgs &a, int dist, bool allpairs, int blocks, hipStream_t s)
+    {
+        dim3 grid(blocks), block(256);
+        if (dist == DIST_DK) {
+            if (allpairs)
+                hipLaunchKernelGGL((k_dp_wave<D, DIST_DK, true>), grid, block, 0, s, a);
+            else
+                hipLaunchKernelGGL((k_dp_wave<D, DIST_DK, false>), grid, block, 0, s, a);
+        } else {
+            if (allpairs)
+                hipLaunchKernelGGL((k_dp_wave<D, DIST_DTW, true>), grid, block, 0, s, a);
+            else
+                hipLaunchKernelGGL((k_dp_wave<D, DIST_DTW, false>), grid, block, 0, s, a);
+        }
+    }
+};
+
+static int check_queries(const tsk_index *ix, const float *qv, const int64_t *qoff, int64_t nq,
+                         int32_t dist, tsk_band band)
+{
+    if (!ix)
+        return set_err(TSK_ERR_INVALID_ARG, "index is NULL");
+    if (!qv)
+        return set_err(TSK_ERR_INVALID_ARG, "q_values_dev is NULL");
+    TSK_TRY(check_series(qoff, nq, "query", nullptr, nullptr));
+    if (dist != TSK_DTW && dist != TSK_DK)
+        return set_err(TSK_ERR_INVALID_ARG, "dist %d is not TSK_DTW/TSK_DK", dist);
+    TSK_TRY(check_band(band));
+    TSK_TRY(check_device(ix));
+    return TSK_OK;
+}
+
+// Workspace for a chunk of nq queries; sizes follow the index.
+static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env)
+{
+    Workspace &w = ix->ws;
+    const int64_t N = ix->n;
+    TSK_TRY(w.tau.ensure(nq));
+    TSK_TRY(w.seedslots.ensure(nq * k));
+    TSK_TRY(w.ubslots.ensure(nq * k));
+    TSK_TRY(w.resslots.ensure(nq * k));
+    TSK_TRY(w.lbv.ensure(nq * N));
+    TSK_TRY(w.surv.ensure(nq * N));
+    TSK_TRY(w.surv_cnt.ensure(nq));
+    TSK_TRY(w.max_cnt.ensure(1));
+    TSK_TRY(w.ctr.ensure(C_NUM));
+    TSK_TRY(w.work.ensure(4));
+    TSK_TRY(w.qoff.ensure(nq + 1));
+    if (need_env)
+        TSK_TRY(w.env.ensure(nq * (int64_t)ix->max_len * 2 * ix->dim));
+    TSK_TRY(w.tbuf.ensure((size_t)dp_blocks(ix) * 4 * 2 * ix->max_len));
+    return TSK_OK;
+}
+
+// Relative query offsets of queries [q0, q0+nq) to the device.
+static int upload_qoff(tsk_index *ix, const int64_t *qoff, int64_t q0, int64_t nq, hipStream_t s)
+{
+    ix->ws.h_qoff.assign(qoff + q0, qoff + q0 + nq + 1);
+    HIP_TRY(hipMemcpyAsync(ix->ws.qoff.p, ix->ws.h_qoff.data(), (nq + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    return TSK_OK;
+}
+
+static int64_t chunk_queries(const tsk_index *ix, int64_t nq)
+{
+    const int64_t budget = (int64_t)1 << 28; // (query, candidate) entries per chunk
+    return std::max<int64_t>(1, std::min<int64_t>(nq, budget / std::max<int64_t>(1, ix->n)));
+}
+
+extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
+                             const int64_t *q_offsets_host, int64_t n_queries, int32_t k,
+                             int32_t dist, tsk_band band, const tsk_query_opts *opts,
+                             int64_t *out_ids_dev, float *out_dist_dev, tsk_stats *stats_host,
+                             void *hip_stream)
+{
+    g_err.clear();
+    TSK_TRY(check_queries(cix, q_values_dev, q_offsets_host, n_queries, dist, band));
+    if (k < 1)
+        return set_err(TSK_ERR_INVALID_ARG, "k must be >= 1");
+    if (k > TSK_MAX_K)
+        return set_err(TSK_ERR_UNSUPPORTED, "k %d > %d", k, TSK_MAX_K);
+    if (!out_ids_dev || !out_dist_dev)
+        return set_err(TSK_ERR_INVALID_ARG, "output pointers are NULL");
+    tsk_query_opts o;
+    memset(&o, 0, sizeof(o));
+    if (opts) {
+        if (opts->size != (int64_t)sizeof(tsk_query_opts))
+            return set_err(TSK_ERR_INVALID_ARG, "opts->size mismatch");
+        o = *opts;
+    }
+    if (o.order != TSK_ORDER_PLAIN && o.order != TSK_ORDER_GIVEN)
+        return set_err(TSK_ERR_INVALID_ARG, "opts->order %d unknown", o.order);
+    if (o.order == TSK_ORDER_GIVEN && !o.order_dev)
+        return set_err(TSK_ERR_INVALID_ARG, "TSK_ORDER_GIVEN needs order_dev");
+    if (o.seed_count < 0)
+        return set_err(TSK_ERR_INVALID_ARG, "seed_count must be >= 0");
+    tsk_index *ix = const_cast<tsk_index *>(cix);
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    QueryPlan P;
+    P.D = ix->dim;
+    P.dist = dist;
+    P.k = k;
+    P.ba = BandArgs{band.mode, band.r, band.frac};
+    P.nq = n_queries;
+    P.N = ix->n;
+    P.chunk = chunk_queries(ix, n_queries);
+    const int default_seed = 256;
+    P.seed = (int)std::min<int64_t>(ix->n, o.seed_count > 0 ? o.seed_count : default_seed);
+    P.env_ok = (dist == TSK_DTW) && ix->min_len == ix->max_len;
+
+    TSK_TRY(ensure_ws(ix, P.chunk, k, P.env_ok));
+    Workspace &W = ix->ws;
+
+    hipEvent_t ev[6] = {};
+    const bool timed = stats_host != nullptr;
+    if (timed)
+        for (auto &e : ev)
+            HIP_TRY(hipEventCreate(&e));
+    float ms[5] = {0, 0, 0, 0, 0};
+
+    fill_u64(W.ctr.p, 0ull, C_NUM, s);
+    for (int64_t q0 = 0; q0 < n_queries; q0 += P.chunk) {
+        const int nq = (int)std::min<int64_t>(P.chunk, n_queries - q0);
+        const int32_t *order = o.order == TSK_ORDER_GIVEN ? o.order_dev + q0 * ix->n : nullptr;
+        TSK_TRY(upload_qoff(ix, q_offsets_host, q0, nq, s));
+        const float *qv = q_values_dev; // offsets are absolute into q_values_dev
+        if (timed)
+            HIP_TRY(hipEventRecord(ev[0], s));
+        fill_u32(W.tau.p, TSK_INF_BITS, nq, s);
+        fill_u64(W.seedslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
+        fill_u64(W.ubslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
+        fill_u64(W.resslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
+        fill_u32((uint32_t *)W.max_cnt.p, 0u, 1, s);
+        fill_u64(W.work.p, 0ull, 4, s);
+        if (P.env_ok)
+            dispatch_d<EnvLaunch>(P.D, ix, qv, nq, P.ba, s);
+        dispatch_d<SeedLaunch>(P.D, ix, qv, nq, P, order, s);
+        if (timed)
+            HIP_TRY(hipEventRecord(ev[1], s));
+        BoundArgs ba = bound_args(ix, qv, nq, P);
+        dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
+        hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, order, W.tau.p,
+                           W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
+        if (timed)
+            HIP_TRY(hipEventRecord(ev[2], s));
+        DpArgs da = dp_args(ix, qv, nq, P);
+        dispatch_d<DpLaunch>(P.D, da, dist, false, dp_blocks(ix), s);
+        if (timed)
+            HIP_TRY(hipEventRecord(ev[3], s));
+        if (dist == TSK_DK)
+            hipLaunchKernelGGL(k_finalize<DIST_DK>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq, k,
+                               out_ids_dev + q0 * k, out_dist_dev + q0 * k);
+        else
+            hipLaunchKernelGGL(k_finalize<DIST_DTW>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq, k,
+                               out_ids_dev + q0 * k, out_dist_dev + q0 * k);
+        HIP_TRY(hipGetLastError());
+        if (timed) {
+            HIP_TRY(hipEventRecord(ev[4], s));
+            HIP_TRY(hipEventSynchronize(ev[4]));
+            float t;
+            HIP_TRY(hipEventElapsedTime(&t, ev[0], ev[1]));
+            ms[1] += t;
+            HIP_TRY(hipEventElapsedTime(&t, ev[1], ev[2]));
+            ms[2] += t;
+            HIP_TRY(hipEventElapsedTime(&t, ev[2], ev[3]));
+            ms[3] += t;
+            HIP_TRY(hipEventElapsedTime(&t, ev[3], ev[4]));
+            ms[4] += t;
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    if (timed) {
+        unsigned long long c[C_NUM];
+        HIP_TRY(hipMemcpyAsync(c, W.ctr.p, sizeof(c), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (auto &e : ev)
+            (void)hipEventDestroy(e);
+        memset(stats_host, 0, sizeof(*stats_host));
+        stats_host->pairs = (int64_t)c[C_PAIRS];
+        stats_host->seed_pairs = (int64_t)c[C_SEED_PAIRS];
+        stats_host->bound_pruned = (int64_t)c[C_BOUND_PRUNED];
+        stats_host->dp_started = (int64_t)c[C_DP_STARTED];
+        stats_host->dp_completed = (int64_t)c[C_DP_COMPLETED];
+        stats_host->dp_abandoned = (int64_t)c[C_DP_ABANDONED];
+        stats_host->dp_cells = (int64_t)c[C_DP_CELLS];
+        stats_host->bound_steps = (int64_t)c[C_BOUND_STEPS];
+        stats_host->fallback_pairs = (int64_t)c[C_FALLBACK];
+        stats_host->ms_seed = ms[1];
+        stats_host->ms_bound = ms[2];
+        stats_host->ms_dp = ms[3];
+        stats_host->ms_final = ms[4];
+        stats_host->ms_total = ms[1] + ms[2] + ms[3] + ms[4];
+    }
+    return TSK_OK;
+}
+
+extern "C" int tsk_pair_distances(const tsk_index *cix, const float *q_values_dev,
+                                  const int64_t *q_offsets_host, int64_t n_queries, int32_t dist,
+                                  tsk_band band, float *out_keys_dev, void *hip_stream)
+{
+    g_err.clear();
+    TSK_TRY(check_queries(cix, q_values_dev, q_offsets_host, n_queries, dist, band));
+    if (!out_keys_dev)
+        return set_err(TSK_ERR_INVALID_ARG, "out_keys_dev is NULL");
+    tsk_index *ix = const_cast<tsk_index *>(cix);
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    QueryPlan P;
+    memset(&P, 0, sizeof(P));
+    P.D = ix->dim;
+    P.dist = dist;
+    P.k = 1;
+    P.ba = BandArgs{band.mode, band.r, band.frac};
+    const int64_t chunk = chunk_queries(ix, n_queries);
+    TSK_TRY(ensure_ws(ix, chunk, 1, false));
+    for (int64_t q0 = 0; q0 < n_queries; q0 += chunk) {
+        const int nq = (int)std::min<int64_t>(chunk, n_queries - q0);
+        TSK_TRY(upload_qoff(ix, q_offsets_host, q0, nq, s));
+        fill_u64(ix->ws.work.p, 0ull, 4, s);
+        fill_u64(ix->ws.ctr.p, 0ull, C_NUM, s);
+        DpArgs da = dp_args(ix, q_values_dev, nq, P);
+        da.out_all = out_keys_dev + q0 * ix->n;
+        dispatch_d<DpLaunch>(P.D, da, dist, true, dp_blocks(ix), s);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return TSK_OK;
+}
+
+extern "C" int tsk_pair_bounds(const tsk_index *cix, const float *q_values_dev,
+                               const int64_t *q_offsets_host, int64_t n_queries, int32_t dist,
+                               tsk_band band, float *out_lb_dev, float *out_ub_dev,
+                               int32_t *out_steps_dev, void *hip_stream)
+{
+    g_err.clear();
+    TSK_TRY(check_queries(cix, q_values_dev, q_offsets_host, n_queries, dist, band));
+    tsk_index *ix = const_cast<tsk_index *>(cix);
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    QueryPlan P;
+    memset(&P, 0, sizeof(P));
+    P.D = ix->dim;
+    P.dist = dist;
+    P.k = 1;
+    P.ba = BandArgs{band.mode, band.r, band.frac};
+    P.env_ok = (dist == TSK_DTW) && ix->min_len == ix->max_len;
+    const int64_t chunk = chunk_queries(ix, n_queries);
+    TSK_TRY(ensure_ws(ix, chunk, 1, P.env_ok));
+    for (int64_t q0 = 0; q0 < n_queries; q0 += chunk) {
+        const int nq = (int)std::min<int64_t>(chunk, n_queries - q0);
+        TSK_TRY(upload_qoff(ix, q_offsets_host, q0, nq, s));
+        fill_u64(ix->ws.ctr.p, 0ull, C_NUM, s);
+        if (P.env_ok)
+            dispatch_d<EnvLaunch>(P.D, ix, q_values_dev, nq, P.ba, s);
+        BoundArgs ba = bound_args(ix, q_values_dev, nq, P);
+        ba.dbg_lb = out_lb_dev ? out_lb_dev + q0 * ix->n : nullptr;
+        ba.dbg_ub = out_ub_dev ? out_ub_dev + q0 * ix->n : nullptr;
+        ba.dbg_steps = out_steps_dev ? out_steps_dev + q0 * ix->n : nullptr;
+        dispatch_d<BoundLaunch>(P.D, ba, dist, true, s);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return TSK_OK;
+}

@@ -1,0 +1,107 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1811_11076_amd import _lib
+from paper_1811_11076_amd.build import lib_path
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsknn.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(tsk_[a-z_]+)\s*\(", text)))
+
+
+needs_lib = pytest.mark.skipif(not os.path.exists(lib_path()),
+                               reason="libtsknn.so not built (run the package build)")
+
+
+@needs_lib
+def test_exports_every_declared_symbol():
+    lib = ctypes.CDLL(lib_path())
+    names = _declared()
+    assert "tsk_knn_query" in names and "tsk_index_build" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding's table covers the header
+    assert set(_lib.SIGNATURES) == set(names)
+
+
+@needs_lib
+def test_version_and_error_text():
+    lib = _lib.load()
+    a, b = ctypes.c_int(), ctypes.c_int()
+    assert lib.tsk_version(ctypes.byref(a), ctypes.byref(b)) == 0
+    assert (a.value, b.value) == (0, 1)
+    assert isinstance(lib.tsk_last_error(), bytes)
+
+
+@needs_lib
+def test_build_rejects_bad_arguments_before_device_work():
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    off = np.array([0, 4, 8], np.int64)
+    offp = off.ctypes.data_as(ctypes.c_void_p)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    # null output
+    assert lib.tsk_index_build(fake, offp, 2, 3, None, None, None) == _lib.TSK_ERR_INVALID_ARG
+    # null values
+    assert lib.tsk_index_build(None, offp, 2, 3, None, None, ctypes.byref(out)) == _lib.TSK_ERR_INVALID_ARG
+    # unsupported dimension
+    assert lib.tsk_index_build(fake, offp, 2, 0, None, None, ctypes.byref(out)) == _lib.TSK_ERR_UNSUPPORTED
+    assert lib.tsk_index_build(fake, offp, 2, 9, None, None, ctypes.byref(out)) == _lib.TSK_ERR_UNSUPPORTED
+    # zero-length series
+    bad = np.array([0, 4, 4], np.int64)
+    assert lib.tsk_index_build(fake, bad.ctypes.data_as(ctypes.c_void_p), 2, 3, None, None,
+                               ctypes.byref(out)) == _lib.TSK_ERR_INVALID_ARG
+    assert b"length 0" in lib.tsk_last_error()
+    # too long
+    long_ = np.array([0, 5000], np.int64)
+    assert lib.tsk_index_build(fake, long_.ctypes.data_as(ctypes.c_void_p), 1, 3, None, None,
+                               ctypes.byref(out)) == _lib.TSK_ERR_UNSUPPORTED
+    # offsets[0] != 0 and empty database
+    shifted = np.array([1, 4], np.int64)
+    assert lib.tsk_index_build(fake, shifted.ctypes.data_as(ctypes.c_void_p), 1, 3, None, None,
+                               ctypes.byref(out)) == _lib.TSK_ERR_INVALID_ARG
+    assert lib.tsk_index_build(fake, offp, 0, 3, None, None, ctypes.byref(out)) == _lib.TSK_ERR_INVALID_ARG
+    assert out.value is None
+
+
+@needs_lib
+def test_build_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    off = np.array([0, 4], np.int64)
+    rc = lib.tsk_index_build(ctypes.c_void_p(0x1000), off.ctypes.data_as(ctypes.c_void_p), 1, 3,
+                             None, None, ctypes.byref(out))
+    assert rc == _lib.TSK_ERR_DEVICE
+    assert out.value is None
+
+
+@needs_lib
+def test_query_rejects_null_index():
+    lib = _lib.load()
+    off = np.array([0, 4], np.int64)
+    rc = lib.tsk_knn_query(None, ctypes.c_void_p(0x1000), off.ctypes.data_as(ctypes.c_void_p), 1, 5,
+                           1, _lib.band_struct(None), None, ctypes.c_void_p(0x2000),
+                           ctypes.c_void_p(0x3000), None, None)
+    assert rc == _lib.TSK_ERR_INVALID_ARG
+    assert lib.tsk_index_free(None) == 0
+
+
+def test_binding_refuses_without_library(monkeypatch, tmp_path):
+    import paper_1811_11076_amd._lib as L
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "lib_path", lambda: str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        L.load()

@@ -1,0 +1,165 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Bit-exact: k-NN ids, squared DK keys, DK distances (fp32 sqrt), fp32 DTW
+keys (the oracle's fp32 mirror arithmetic), LB_Box, greedy bounds and move
+counts.  DTW also within 1e-5 relative of the fp64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_cases import assert_same_knn, classwarp, ragged_walks, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print(f"\n[gpu] {torch.cuda.get_device_name(0)}", flush=True)
+
+
+def _index(vals, off):
+    from paper_1811_11076_amd import Index
+    return Index(to_dev(vals), off)
+
+
+PAIR_CASES = [
+    # (name, seed, Q, N, lens, d)
+    ("ragged_small", 1, 3, 70, (1, 40), 3),
+    ("multistrip", 2, 2, 20, (250, 600), 2),
+    ("d1", 3, 2, 30, (10, 80), 1),
+    ("d6", 4, 2, 30, (10, 80), 6),
+    ("d8", 5, 2, 30, (10, 80), 8),
+    ("equal64", 6, 3, 100, (64, 64), 3),
+]
+BANDS = [None, 3, 0.2]
+
+
+@pytest.mark.parametrize("case", PAIR_CASES, ids=lambda c: c[0])
+@pytest.mark.parametrize("band", BANDS, ids=lambda b: f"band{b}")
+def test_pair_distances(case, band):
+    name, seed, Q, N, lens, d = case
+    print(f"[case] pair_distances {name} band={band}", flush=True)
+    db, dbo = ragged_walks(seed, N, lens, d)
+    qs, qo = ragged_walks(seed + 100, Q, lens, d)
+    idx = _index(db, dbo)
+    for dist in ("dk", "dtw"):
+        got = idx.pair_distances(to_dev(qs), qo, dist, band).cpu().numpy()
+        ref = O.pair_keys(db, dbo, qs, qo, dist, band)
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (dist, np.argwhere(got != ref)[:5])
+        if dist == "dtw":
+            for q in range(Q):
+                for c in range(0, N, max(1, N // 10)):
+                    w = O.band_w(band, qo[q + 1] - qo[q], dbo[c + 1] - dbo[c])
+                    ref64 = O.dtw_f64(qs[qo[q]:qo[q + 1]], db[dbo[c]:dbo[c + 1]], w)
+                    if np.isfinite(ref64) and ref64 > 0:
+                        assert abs(got[q, c] - ref64) <= 1e-5 * ref64
+                    else:
+                        assert got[q, c] == ref64
+    idx.close()
+
+
+@pytest.mark.parametrize("case", PAIR_CASES[:2] + PAIR_CASES[5:], ids=lambda c: c[0])
+@pytest.mark.parametrize("band", BANDS, ids=lambda b: f"band{b}")
+def test_pair_bounds(case, band):
+    name, seed, Q, N, lens, d = case
+    print(f"[case] pair_bounds {name} band={band}", flush=True)
+    db, dbo = ragged_walks(seed, N, lens, d)
+    qs, qo = ragged_walks(seed + 100, Q, lens, d)
+    idx = _index(db, dbo)
+    for dist in ("dk", "dtw"):
+        lb, ub, steps = (t.cpu().numpy() for t in idx.pair_bounds(to_dev(qs), qo, dist, band))
+        for q in range(Q):
+            S = qs[qo[q]:qo[q + 1]]
+            for c in range(N):
+                T = db[dbo[c]:dbo[c + 1]]
+                w = O.band_w(band, S.shape[0], T.shape[0])
+                if dist == "dk":
+                    corner = max(O.cost_f32(S[0], T[0]), O.cost_f32(S[-1], T[-1]))
+                    assert lb[q, c] == np.float32(corner)
+                    v, st = O.gdk_sq_f32(S, T, w)
+                else:
+                    assert lb[q, c] == np.float32(O.lb_box_qenv_f32(S, T, w)), (q, c)
+                    v, st = O.greedy_sum_f32(S, T, w)
+                assert ub[q, c] == np.float32(v) and steps[q, c] == st, (dist, q, c, ub[q, c], v)
+    idx.close()
+
+
+KNN_CASES = [
+    # (name, seed, Q, N, lens, d, k)
+    ("tiny_k_gt_n", 10, 2, 5, (3, 12), 2, 8),
+    ("ragged", 11, 5, 300, (5, 60), 3, 7),
+    ("multistrip", 12, 2, 40, (200, 520), 3, 3),
+    ("equal", 13, 4, 500, (50, 50), 3, 10),
+    ("d6", 14, 3, 200, (20, 40), 6, 5),
+]
+
+
+@pytest.mark.parametrize("case", KNN_CASES, ids=lambda c: c[0])
+@pytest.mark.parametrize("band", BANDS, ids=lambda b: f"band{b}")
+def test_knn_small(case, band):
+    name, seed, Q, N, lens, d, k = case
+    print(f"[case] knn {name} band={band}", flush=True)
+    db, dbo = ragged_walks(seed, N, lens, d)
+    qs, qo = ragged_walks(seed + 100, Q, lens, d)
+    idx = _index(db, dbo)
+    for dist in ("dk", "dtw"):
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, k, dist, band)
+        ids, dst, st = idx.knn(to_dev(qs), qo, k, dist, band, stats=True)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
+        assert st["pairs"] == Q * N
+    idx.close()
+
+
+def test_knn_cfg1_full():
+    """Random walks, 1 query x 1000 series, length 64, d = 3, k = 1, unbanded."""
+    from paper_1811_11076_amd import synth
+    print("[case] knn cfg1", flush=True)
+    db, dbo = synth.flat_equal(synth.random_walks(1000, 64, 3, 1, "db"))
+    qs, qo = synth.flat_equal(synth.random_walks(1, 64, 3, 1, "query"))
+    idx = _index(db, dbo)
+    for dist in ("dk", "dtw"):
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 1, dist, None)
+        ids, dst, _ = idx.knn(to_dev(qs), qo, 1, dist, None)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
+    idx.close()
+
+
+def test_knn_ties_and_order():
+    """Duplicated series tie; ties go to the lower id; a given candidate
+    order changes nothing."""
+    import torch
+    print("[case] knn ties/order", flush=True)
+    db, dbo = ragged_walks(21, 50, (10, 30), 3)
+    series = [db[dbo[i]:dbo[i + 1]] for i in range(50)]
+    series += series[:20]  # ids 50..69 duplicate 0..19
+    dbo2 = np.concatenate([[0], np.cumsum([len(s) for s in series])]).astype(np.int64)
+    db2 = np.concatenate(series).astype(np.float32)
+    qs = np.concatenate([series[3], series[7]]).astype(np.float32)
+    qo = np.array([0, len(series[3]), len(series[3]) + len(series[7])], np.int64)
+    idx = _index(db2, dbo2)
+    perm = torch.stack([torch.randperm(70, generator=torch.Generator().manual_seed(s)) for s in (1, 2)])
+    perm = perm.to(torch.int32).cuda()
+    for dist in ("dk", "dtw"):
+        ref_ids, ref_keys = O.knn_brute(db2, dbo2, qs, qo, 6, dist, 4)
+        assert ref_ids[0, 0] == 3 and ref_ids[0, 1] == 53
+        ids, dst, _ = idx.knn(to_dev(qs), qo, 6, dist, 4)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
+        ids, dst, _ = idx.knn(to_dev(qs), qo, 6, dist, 4, order=perm, seed_count=9)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
+    idx.close()
+
+
+def test_knn_classwarp_reduced():
+    """Class-warp series (10 classes, length 256, d = 3), 12 queries x 3000."""
+    print("[case] knn classwarp reduced", flush=True)
+    db, dbo, qs, qo = classwarp(2, 10, 256, 3, 3000, 12)
+    idx = _index(db, dbo)
+    for dist, band in (("dk", None), ("dtw", 0.1)):
+        ref_ids, ref_keys, _ = O.knn_scan(db, dbo, qs, qo, 10, dist, band)
+        ids, dst, st = idx.knn(to_dev(qs), qo, 10, dist, band, stats=True)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
+        print(f"  {dist}: {st}", flush=True)
+    idx.close()
