@@ -91,8 +91,13 @@ typedef struct {
     int64_t dp_cells;       /* DP cells evaluated (lane-cells, dead ones too) */
     int64_t bound_steps;    /* greedy-bound moves + LB_Box terms */
     int64_t fallback_pairs; /* pairs that left the fast DP for the general one */
+    int64_t dp_valid_cells; /* DP cells inside the matrix and the band */
+    int64_t calls;          /* calls accumulated (tsk_index_profile) */
     float ms_total;         /* device time of the whole call */
-    float ms_seed, ms_bound, ms_dp, ms_final;
+    float ms_seed;          /* envelope + threshold seed kernels */
+    float ms_bound;         /* bound pass + survivor compaction */
+    float ms_dp;            /* DP kernels */
+    float ms_final;         /* output kernel */
 } tsk_stats;
 
 typedef struct {
@@ -107,6 +112,10 @@ typedef struct {
                                       this order */
     int32_t use_graph;             /* reserved (0) */
     int32_t dp_kernel;             /* 0 auto, 1 force the general DP */
+    int32_t profile;               /* 1: record per-stage HIP events on the
+                                      stream and add this call's counters to
+                                      the index's profile, without any
+                                      synchronisation (tsk_index_profile) */
 } tsk_query_opts;
 
 typedef struct {
@@ -153,6 +162,12 @@ int tsk_knn_query(const tsk_index *index, const float *q_values_dev, const int64
                   int64_t n_queries, int32_t k, int32_t dist, tsk_band band,
                   const tsk_query_opts *opts, int64_t *out_ids_dev, float *out_dist_dev,
                   tsk_stats *stats_host, void *hip_stream);
+
+/* Reads (and with reset != 0 clears) the profile accumulated by calls made
+ * with opts->profile = 1 on this index: counters summed over those calls and
+ * per-stage device milliseconds measured by HIP events recorded on each
+ * call's stream.  Synchronises with those events.  Errors: INVALID_ARG. */
+int tsk_index_profile(tsk_index *index, tsk_stats *out, int32_t reset);
 
 /* Full-DP distance of every (query, database series) pair with no pruning
  * (Sec. 2.1 definitions through the same DP kernels as the k-NN path):

@@ -86,7 +86,7 @@ class Index:
             pass
 
     def knn(self, queries, q_offsets, k: int, distance: str = "dk", band=None, order=None,
-            seed_count: int = 0, stats: bool = False):
+            seed_count: int = 0, stats: bool = False, profile: bool = False):
         """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
         float32 [nq, k], stats dict or None); DK distances are unsquared."""
         torch = _torch()
@@ -98,6 +98,7 @@ class Index:
         opts = _lib.QueryOpts()
         opts.size = ctypes.sizeof(_lib.QueryOpts)
         opts.seed_count = int(seed_count)
+        opts.profile = 1 if profile else 0
         if order is not None:
             if order.dtype != torch.int32 or not order.is_cuda or tuple(order.shape) != (nq, self.n):
                 raise ValueError("order must be a CUDA int32 tensor [n_queries, n_series]")
@@ -111,6 +112,13 @@ class Index:
             ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
             ctypes.byref(st) if st is not None else None, _stream()))
         return ids, dist, (st.as_dict() if st is not None else None)
+
+    def profile(self, reset: bool = False) -> dict:
+        """Counters and stage times accumulated by knn(..., profile=True)
+        calls (C: tsk_index_profile); synchronises."""
+        st = _lib.Stats()
+        _lib.check(self._lib.tsk_index_profile(self._h, ctypes.byref(st), 1 if reset else 0))
+        return st.as_dict()
 
     def pair_distances(self, queries, q_offsets, distance: str = "dk", band=None):
         """Full-DP key of every (query, series) pair (C: tsk_pair_distances);

@@ -34,7 +34,7 @@ class Band(ctypes.Structure):
 class QueryOpts(ctypes.Structure):
     _fields_ = [("size", ctypes.c_int64), ("order", ctypes.c_int32), ("seed_count", ctypes.c_int32),
                 ("order_dev", ctypes.c_void_p), ("use_graph", ctypes.c_int32),
-                ("dp_kernel", ctypes.c_int32)]
+                ("dp_kernel", ctypes.c_int32), ("profile", ctypes.c_int32)]
 
 
 class IndexOpts(ctypes.Structure):
@@ -46,7 +46,8 @@ class Stats(ctypes.Structure):
                 ("bound_pruned", ctypes.c_int64), ("dp_started", ctypes.c_int64),
                 ("dp_completed", ctypes.c_int64), ("dp_abandoned", ctypes.c_int64),
                 ("dp_cells", ctypes.c_int64), ("bound_steps", ctypes.c_int64),
-                ("fallback_pairs", ctypes.c_int64), ("ms_total", ctypes.c_float),
+                ("fallback_pairs", ctypes.c_int64), ("dp_valid_cells", ctypes.c_int64),
+                ("calls", ctypes.c_int64), ("ms_total", ctypes.c_float),
                 ("ms_seed", ctypes.c_float), ("ms_bound", ctypes.c_float),
                 ("ms_dp", ctypes.c_float), ("ms_final", ctypes.c_float)]
 
@@ -66,6 +67,7 @@ SIGNATURES = {
     "tsk_index_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
     "tsk_knn_query": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, Band, _vp, _vp, _vp, _vp,
                                      _vp]),
+    "tsk_index_profile": (ctypes.c_int, [_vp, _vp, _i32]),
     "tsk_pair_distances": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp]),
     "tsk_pair_bounds": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp, _vp, _vp]),
 }

@@ -19,6 +19,7 @@ enum {
     C_BOUND_STEPS,
     C_FALLBACK,
     C_LATE_PRUNED,
+    C_VALID_CELLS,
     C_NUM
 };
 
@@ -64,6 +65,13 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+__global__ void k_add_u64(unsigned long long *dst, const unsigned long long *src, int n)
+{
+    const int i = threadIdx.x;
+    if (i < n)
+        dst[i] += src[i];
 }
 
 // ------------------------------------------------------------------ index pack
@@ -502,7 +510,7 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ lbv, 
 template <int D, int DIST>
 __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *__restrict__ cp, int n,
                               const Band &band, const uint32_t *tau_ptr, float *__restrict__ tbuf,
-                              unsigned long long &cells)
+                              unsigned long long &cells, unsigned long long &valid)
 {
     const int lane = threadIdx.x & 63;
     const float tau = tau_ptr ? bits_f(load_relaxed_u32(tau_ptr)) : tsk_inf();
@@ -572,6 +580,7 @@ __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *
                 const float cst = point_cost<D>(qr[r], cv);
                 float v = DIST == DIST_DK ? fmaxf(cst, pred) : cst + pred;
                 v = (ok && v <= tau) ? v : tsk_inf();
+                valid += __popcll(__ballot(ok));
                 diag = Dp[r];
                 down = v;
                 Dc[r] = v;
@@ -639,7 +648,7 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
     const int lane = threadIdx.x & 63;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     float *tb = a.tbuf + gw * a.tb_stride;
-    unsigned long long cells = 0, started = 0, completed = 0, abandoned = 0, late = 0;
+    unsigned long long cells = 0, valid = 0, started = 0, completed = 0, abandoned = 0, late = 0;
     const int64_t total = ALLPAIRS ? (int64_t)a.nq * a.N : (int64_t)a.nq * (int64_t)(*a.max_cnt);
     for (;;) {
         unsigned long long t = 0;
@@ -667,7 +676,7 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
         const int n = a.len[c];
         const Band b = pair_band(a.ba, m, n);
         const float res = dp_wave_pair<D, DIST>(a.qv + a.qoff[q] * D, m, a.aos + a.off[c] * D, n, b,
-                                                ALLPAIRS ? nullptr : a.tau + q, tb, cells);
+                                                ALLPAIRS ? nullptr : a.tau + q, tb, cells, valid);
         if (ALLPAIRS) {
             if (lane == 0)
                 a.out_all[t] = res;
@@ -687,6 +696,8 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
     if (lane == 0) {
         if (cells)
             atomicAdd(a.ctr + C_DP_CELLS, cells * 64ull);
+        if (valid)
+            atomicAdd(a.ctr + C_VALID_CELLS, valid);
         if (!ALLPAIRS) {
             if (started)
                 atomicAdd(a.ctr + C_DP_STARTED, started);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -129,7 +130,54 @@ struct tsk_index {
     hipStream_t last_stream = nullptr;
     Workspace ws;
     std::mutex mu;
+    // profile accumulated by calls with opts->profile = 1
+    std::vector<std::array<hipEvent_t, 5>> ev_pool;
+    size_t ev_used = 0;
+    DevBuf<unsigned long long> prof_ctr;
+    int64_t prof_calls = 0;
 };
+
+static int take_events(tsk_index *ix, hipEvent_t **out)
+{
+    if (ix->ev_used == ix->ev_pool.size()) {
+        std::array<hipEvent_t, 5> e;
+        for (auto &x : e)
+            HIP_TRY(hipEventCreate(&x));
+        ix->ev_pool.push_back(e);
+    }
+    *out = ix->ev_pool[ix->ev_used++].data();
+    return TSK_OK;
+}
+
+static void stats_from(tsk_stats *st, const unsigned long long *c)
+{
+    st->pairs = (int64_t)c[C_PAIRS];
+    st->seed_pairs = (int64_t)c[C_SEED_PAIRS];
+    st->bound_pruned = (int64_t)c[C_BOUND_PRUNED];
+    st->dp_started = (int64_t)c[C_DP_STARTED];
+    st->dp_completed = (int64_t)c[C_DP_COMPLETED];
+    st->dp_abandoned = (int64_t)c[C_DP_ABANDONED];
+    st->dp_cells = (int64_t)c[C_DP_CELLS];
+    st->bound_steps = (int64_t)c[C_BOUND_STEPS];
+    st->fallback_pairs = (int64_t)c[C_FALLBACK];
+    st->dp_valid_cells = (int64_t)c[C_VALID_CELLS];
+}
+
+// Sums the stage times of event sets [from, to) of the pool (synchronising).
+static int sum_events(tsk_index *ix, size_t from, size_t to, float ms[5])
+{
+    for (size_t i = from; i < to; ++i) {
+        hipEvent_t *e = ix->ev_pool[i].data();
+        HIP_TRY(hipEventSynchronize(e[4]));
+        for (int st = 0; st < 4; ++st) {
+            float t = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&t, e[st], e[st + 1]));
+            ms[st + 1] += t;
+        }
+    }
+    ms[0] = ms[1] + ms[2] + ms[3] + ms[4];
+    return TSK_OK;
+}
 
 // ------------------------------------------------------------------ dispatch
 template <template <int> class F, typename... A> static void dispatch_d(int d, A &&...args)
@@ -255,6 +303,11 @@ static void free_index_memory(tsk_index *ix)
     if (ix->tile_off) (void)hipFree(ix->tile_off);
     if (ix->tile_len) (void)hipFree(ix->tile_len);
     ix->ws.release();
+    ix->prof_ctr.release();
+    for (auto &e : ix->ev_pool)
+        for (auto &x : e)
+            (void)hipEventDestroy(x);
+    ix->ev_pool.clear();
 }
 
 extern "C" int tsk_index_free(tsk_index *ix)
@@ -581,12 +634,11 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
     TSK_TRY(ensure_ws(ix, P.chunk, k, P.env_ok));
     Workspace &W = ix->ws;
 
-    hipEvent_t ev[6] = {};
-    const bool timed = stats_host != nullptr;
-    if (timed)
-        for (auto &e : ev)
-            HIP_TRY(hipEventCreate(&e));
-    float ms[5] = {0, 0, 0, 0, 0};
+    const bool profile = o.profile != 0;
+    const bool timed = stats_host != nullptr || profile;
+    if (profile)
+        TSK_TRY(ix->prof_ctr.ensure(C_NUM));
+    const size_t ev_first = ix->ev_used;
 
     fill_u64(W.ctr.p, 0ull, C_NUM, s);
     for (int64_t q0 = 0; q0 < n_queries; q0 += P.chunk) {
@@ -594,8 +646,11 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         const int32_t *order = o.order == TSK_ORDER_GIVEN ? o.order_dev + q0 * ix->n : nullptr;
         TSK_TRY(upload_qoff(ix, q_offsets_host, q0, nq, s));
         const float *qv = q_values_dev; // offsets are absolute into q_values_dev
-        if (timed)
+        hipEvent_t *ev = nullptr;
+        if (timed) {
+            TSK_TRY(take_events(ix, &ev));
             HIP_TRY(hipEventRecord(ev[0], s));
+        }
         fill_u32(W.tau.p, TSK_INF_BITS, nq, s);
         fill_u64(W.seedslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
         fill_u64(W.ubslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
@@ -623,43 +678,63 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         else
             hipLaunchKernelGGL(k_finalize<DIST_DTW>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq, k,
                                out_ids_dev + q0 * k, out_dist_dev + q0 * k);
-        HIP_TRY(hipGetLastError());
-        if (timed) {
+        if (timed)
             HIP_TRY(hipEventRecord(ev[4], s));
-            HIP_TRY(hipEventSynchronize(ev[4]));
-            float t;
-            HIP_TRY(hipEventElapsedTime(&t, ev[0], ev[1]));
-            ms[1] += t;
-            HIP_TRY(hipEventElapsedTime(&t, ev[1], ev[2]));
-            ms[2] += t;
-            HIP_TRY(hipEventElapsedTime(&t, ev[2], ev[3]));
-            ms[3] += t;
-            HIP_TRY(hipEventElapsedTime(&t, ev[3], ev[4]));
-            ms[4] += t;
-        }
+        HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipGetLastError());
-    if (timed) {
+    if (profile) {
+        hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, s, ix->prof_ctr.p, W.ctr.p, (int)C_NUM);
+        ix->prof_calls += 1;
+    }
+    if (stats_host) {
         unsigned long long c[C_NUM];
         HIP_TRY(hipMemcpyAsync(c, W.ctr.p, sizeof(c), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        for (auto &e : ev)
-            (void)hipEventDestroy(e);
+        float ms[5] = {0, 0, 0, 0, 0};
+        TSK_TRY(sum_events(ix, ev_first, ix->ev_used, ms));
+        if (!profile)
+            ix->ev_used = ev_first; // these events are not part of a profile
         memset(stats_host, 0, sizeof(*stats_host));
-        stats_host->pairs = (int64_t)c[C_PAIRS];
-        stats_host->seed_pairs = (int64_t)c[C_SEED_PAIRS];
-        stats_host->bound_pruned = (int64_t)c[C_BOUND_PRUNED];
-        stats_host->dp_started = (int64_t)c[C_DP_STARTED];
-        stats_host->dp_completed = (int64_t)c[C_DP_COMPLETED];
-        stats_host->dp_abandoned = (int64_t)c[C_DP_ABANDONED];
-        stats_host->dp_cells = (int64_t)c[C_DP_CELLS];
-        stats_host->bound_steps = (int64_t)c[C_BOUND_STEPS];
-        stats_host->fallback_pairs = (int64_t)c[C_FALLBACK];
+        stats_from(stats_host, c);
+        stats_host->calls = 1;
+        stats_host->ms_total = ms[0];
         stats_host->ms_seed = ms[1];
         stats_host->ms_bound = ms[2];
         stats_host->ms_dp = ms[3];
         stats_host->ms_final = ms[4];
-        stats_host->ms_total = ms[1] + ms[2] + ms[3] + ms[4];
+    }
+    return TSK_OK;
+}
+
+extern "C" int tsk_index_profile(tsk_index *ix, tsk_stats *out, int32_t reset)
+{
+    g_err.clear();
+    if (!ix || !out)
+        return set_err(TSK_ERR_INVALID_ARG, "index and out must be non-NULL");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    memset(out, 0, sizeof(*out));
+    float ms[5] = {0, 0, 0, 0, 0};
+    TSK_TRY(sum_events(ix, 0, ix->ev_used, ms));
+    if (ix->prof_ctr.p) {
+        unsigned long long c[C_NUM];
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(c, ix->prof_ctr.p, sizeof(c), hipMemcpyDeviceToHost));
+        stats_from(out, c);
+    }
+    out->calls = ix->prof_calls;
+    out->ms_total = ms[0];
+    out->ms_seed = ms[1];
+    out->ms_bound = ms[2];
+    out->ms_dp = ms[3];
+    out->ms_final = ms[4];
+    if (reset) {
+        ix->ev_used = 0;
+        ix->prof_calls = 0;
+        if (ix->prof_ctr.p) {
+            fill_u64(ix->prof_ctr.p, 0ull, C_NUM, nullptr);
+            HIP_TRY(hipDeviceSynchronize());
+        }
     }
     return TSK_OK;
 }
