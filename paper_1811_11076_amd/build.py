@@ -19,8 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtsknn.so")
 ARCH = os.environ.get("TSK_ARCH", "gfx950")
 
-SOURCES = ["tsknn.hip"]
-DEPS = ["device.hpp", "kernels.hpp"]
+SOURCES = ["tsknn.hip", "k_band.hip", "k_tube.hip", "k_wave.hip"]
 
 
 def lib_path() -> str:
@@ -34,15 +33,36 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def _flags() -> list[str]:
+    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall",
+            "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES] + (extra or [])
+    """Compiles every source to an object in parallel, then links the .so."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    tag = "%d" % os.getpid()
+
+    def compile_one(src):
+        obj = os.path.join(objdir, src.replace(".hip", "") + "." + tag + ".o")
+        cmd = [hipcc()] + _flags() + (extra or []) + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
+    tmp = LIB + ".tmp" + tag
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
+    for o in objs:
+        os.remove(o)
     os.replace(tmp, LIB)
     return LIB
 

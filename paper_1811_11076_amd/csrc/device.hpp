@@ -66,6 +66,15 @@ __device__ __forceinline__ float sqrt_rn_f32(float x)
     return r;
 }
 
+// Wave-uniform copy of lane 0's value (readfirstlane keeps the result in
+// SGPRs, so loops and addresses that depend on it stay uniform).
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 __device__ __forceinline__ float min3f(float a, float b, float c)
 {
     return fminf(fminf(a, b), c);

@@ -53,21 +53,21 @@ __device__ __forceinline__ float wave_min(float v)
 
 // ------------------------------------------------------------------ fills
 // Plain fill kernels (no hipMemsetAsync, so the sequence stays capturable).
-__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
+static __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
 
-__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n)
+static __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
 
-__global__ void k_add_u64(unsigned long long *dst, const unsigned long long *src, int n)
+static __global__ void k_add_u64(unsigned long long *dst, const unsigned long long *src, int n)
 {
     const int i = threadIdx.x;
     if (i < n)
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(256) void k_bounds(BoundArgs a)
 // ------------------------------------------------------------------ compaction
 // Survivors of one query, in the query's candidate order, re-checked against
 // the current threshold: surv[q][0..cnt).  One block of 256 per query.
-__global__ __launch_bounds__(256) void k_compact(const float *__restrict__ lbv, int64_t N,
+static __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ lbv, int64_t N,
                                                  const int32_t *__restrict__ order,
                                                  const uint32_t *__restrict__ tau,
                                                  int32_t *__restrict__ surv, int32_t *__restrict__ cnt,
@@ -639,28 +639,46 @@ struct DpArgs {
     float *tbuf;
     int tb_stride;
     unsigned long long *ctr;
-    float *out_all; // ALLPAIRS: [nq][N]
+    float *out_all;     // ALLPAIRS: [nq][N]
+    const int2 *fb;     // FALLBACK: (query, candidate) list
+    const unsigned long long *fb_count;
 };
 
-template <int D, int DIST, bool ALLPAIRS>
+enum { DPW_SURV = 0, DPW_ALLPAIRS = 1, DPW_FALLBACK = 2 };
+
+// MODE: DPW_SURV walks the compacted survivors (query-interleaved ranks),
+// DPW_ALLPAIRS every pair with no threshold (tsk_pair_distances),
+// DPW_FALLBACK the pairs the lane-per-pair kernels handed over.
+template <int D, int DIST, int MODE>
 __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
 {
+    constexpr bool ALLPAIRS = MODE == DPW_ALLPAIRS;
     const int lane = threadIdx.x & 63;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     float *tb = a.tbuf + gw * a.tb_stride;
     unsigned long long cells = 0, valid = 0, started = 0, completed = 0, abandoned = 0, late = 0;
-    const int64_t total = ALLPAIRS ? (int64_t)a.nq * a.N : (int64_t)a.nq * (int64_t)(*a.max_cnt);
+    const int64_t total = ALLPAIRS ? (int64_t)a.nq * a.N
+                          : MODE == DPW_FALLBACK ? (int64_t)(*a.fb_count)
+                                                 : (int64_t)a.nq * (int64_t)(*a.max_cnt);
     for (;;) {
         unsigned long long t = 0;
         if (lane == 0)
             t = atomicAdd(a.work, 1ull);
-        t = __shfl(t, 0, 64);
+        t = uniform_u64(t);
         if ((int64_t)t >= total)
             break;
         int q, c;
         if (ALLPAIRS) {
             q = (int)(t / a.N);
             c = (int)(t % a.N);
+        } else if (MODE == DPW_FALLBACK) {
+            const int2 item = a.fb[t];
+            q = item.x;
+            c = item.y;
+            if (a.lbv[(int64_t)q * a.N + c] > bits_f(load_relaxed_u32(a.tau + q))) {
+                ++late;
+                continue;
+            }
         } else {
             q = (int)(t % a.nq);
             const int r = (int)(t / a.nq);
@@ -681,7 +699,7 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
             if (lane == 0)
                 a.out_all[t] = res;
         } else {
-            ++started;
+            started += MODE == DPW_SURV ? 1 : 0; // fallback pairs were counted when started
             if (res != tsk_inf()) {
                 ++completed;
                 if (lane == 0 && res <= bits_f(load_relaxed_u32(a.tau + q))) {

@@ -1,0 +1,404 @@
+// Lane-per-pair DP kernels for the common shapes (gfx950, wave64).
+//
+// A wave takes 64 surviving candidates of ONE query and runs their DPs in
+// lockstep, one candidate per lane, column by column over the candidate.
+// Pairs a kernel cannot represent exactly are appended to a fallback list
+// and finished by the general wave-per-pair DP (k_dp_wave).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace tsk {
+
+// Rows of padding (+inf points) around each staged query.
+constexpr int QPAD = 128;
+
+// Read-only memory seen through the constant address space: uniform loads
+// from it become scalar (SMEM) loads into SGPRs.  Only used for buffers that
+// earlier kernels wrote (the scalar cache is invalidated at kernel start).
+typedef __attribute__((address_space(4))) const float cfloat;
+
+template <int D> struct PadDim {
+    static constexpr int value = D <= 4 ? 4 : 8;
+};
+
+struct FastArgs {
+    const int64_t *qoff;
+    int nq;
+    const float *aos;
+    const int64_t *off;
+    const int32_t *len;
+    int64_t N;
+    int k;
+    BandArgs ba;
+    uint32_t *tau;
+    const float *lbv;
+    const int32_t *surv;
+    const int32_t *surv_cnt;
+    const int32_t *max_cnt;
+    unsigned long long *resslots;
+    unsigned long long *work; // [0] task counter, [1] fallback count
+    int2 *fb;                 // fallback (query, candidate) list
+    const float *qpad;        // [nq][qrows][DP]: query rows at QPAD.., +inf around
+    int qrows;
+    unsigned long long *ctr;
+};
+
+// Staged query: rows -QPAD .. m-1+QPAD of every query, points padded to DP
+// floats, rows outside the query set to +inf (a point at infinity has an
+// infinite cost to every finite point, so such cells never hold a finite
+// value).
+template <int D>
+__global__ void k_qpad(const float *__restrict__ qv, const int64_t *__restrict__ qoff, int nq,
+                       int qrows, float *__restrict__ qpad)
+{
+    constexpr int DP = PadDim<D>::value;
+    const int q = blockIdx.y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq || r >= qrows)
+        return;
+    const int m = (int)(qoff[q + 1] - qoff[q]);
+    const int row = r - QPAD;
+    float *dst = qpad + ((int64_t)q * qrows + r) * DP;
+#pragma unroll
+    for (int k = 0; k < DP; ++k) {
+        float v = tsk_inf();
+        if (row >= 0 && row < m && k < D)
+            v = qv[(qoff[q] + row) * D + k];
+        dst[k] = (k < D || row < 0 || row >= m) ? v : 0.0f;
+    }
+}
+
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// One fast-kernel task: the 64-candidate chunk r of query q.  Fills c (-1 if
+// none), act (lane runs the fast DP), and handles late pruning / fallback.
+struct Chunk {
+    int q, m, c;
+    bool act;
+};
+
+__device__ __forceinline__ bool next_chunk(const FastArgs &a, int64_t total, Chunk &ch,
+                                           unsigned long long &late)
+{
+    for (;;) {
+        unsigned long long t = 0;
+        if (threadIdx.x == 0)
+            t = atomicAdd(a.work, 1ull);
+        t = uniform_u64(t);
+        if ((int64_t)t >= total)
+            return false;
+        const int q = uniform_i((int)(t % (unsigned long long)a.nq));
+        const int r = (int)(t / (unsigned long long)a.nq);
+        const int cnt = a.surv_cnt[q];
+        const int base = r * 64;
+        if (base >= cnt)
+            continue;
+        ch.q = q;
+        ch.m = uniform_i((int)(a.qoff[q + 1] - a.qoff[q]));
+        ch.c = -1;
+        ch.act = false;
+        const int idx = base + (int)threadIdx.x;
+        if (idx < cnt) {
+            const int c = a.surv[(int64_t)q * a.N + idx];
+            if (a.lbv[(int64_t)q * a.N + c] > bits_f(load_relaxed_u32(a.tau + q)))
+                ++late;
+            else {
+                ch.c = c;
+                ch.act = true;
+            }
+        }
+        return true;
+    }
+}
+
+__device__ __forceinline__ void push_fallback(const FastArgs &a, int q, int c)
+{
+    const unsigned long long slot = atomicAdd(a.work + 1, 1ull);
+    a.fb[slot] = make_int2(q, c);
+}
+
+__device__ __forceinline__ void finish_lane(const FastArgs &a, int q, int c, float res,
+                                            unsigned long long &completed)
+{
+    if (res != tsk_inf() && res <= bits_f(load_relaxed_u32(a.tau + q))) {
+        ++completed;
+        topk_insert(a.resslots + (int64_t)q * a.k, a.k, make_key(res, (uint32_t)c));
+        tau_from_slots(a.resslots + (int64_t)q * a.k, a.k, a.tau + q);
+    }
+}
+
+// ------------------------------------------------------------------ banded, equal lengths
+// Pairs with n == m and band half-width w (2w+1 <= W; no band = w of m-1).
+// Each lane keeps the band part of the current column in W registers:
+// slot k of column j holds D(j - w + k, j).  Because the band moves down by
+// one row per column, the lower-left predecessor of slot k is slot k of the
+// previous column and the left predecessor is slot k+1, so the column is
+// updated in place in ascending k (Sec. 2.1 recurrence; Sec. 2.2 band).
+// Slots beyond 2w and rows outside the query read +inf query points, so
+// they never hold a finite value.  The query rows are the same for the
+// whole wave (scalar loads); the candidate point is per lane.  Every path
+// visits every column, so a column whose values all exceed tau ends the
+// lane's pair (checked every 8 columns).
+template <int D, int DIST, int W, int KMASK>
+__global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restrict__ qpad)
+{
+    // W slots per column; slots below KMASK are always inside the band for
+    // the pairs this instantiation serves (2w+1 >= KMASK), slots from KMASK
+    // up are masked against 2w+1 at run time.
+    constexpr int DP = PadDim<D>::value;
+    constexpr int G = 8;
+    static_assert(W % G == 0, "W must be a multiple of 8");
+    unsigned long long started = 0, completed = 0, abandoned = 0, late = 0, fallback = 0;
+    unsigned long long cells = 0, valid = 0;
+    const int64_t total = (int64_t)a.nq * ((*a.max_cnt + 63) / 64);
+    Chunk ch;
+    while (next_chunk(a, total, ch, late)) {
+        const int q = ch.q, m = ch.m;
+        int w = band_w(a.ba.mode, a.ba.r, a.ba.frac, m, m);
+        if (w < 0 || w > m - 1)
+            w = m - 1;
+        w = uniform_i(w);
+        bool act = ch.act;
+        if (act && (a.len[ch.c] != m || 2 * w + 1 > W || 2 * w + 1 < KMASK)) {
+            push_fallback(a, q, ch.c);
+            ++fallback;
+            act = false;
+        }
+        const unsigned long long act_mask = __ballot(act);
+        if (act_mask == 0ull)
+            continue;
+        started += act ? 1 : 0;
+        const int wact = 2 * w + 1;
+        const float *cp = a.aos + a.off[act ? ch.c : 0] * D;
+        const int nl = act ? m : a.len[0]; // idle lanes read candidate 0 in bounds
+        // slot k of column j reads query row j - w + k, staged at qpad row
+        // QPAD + j - w + k (QPAD >= W keeps every slot inside the buffer)
+        cfloat *qbase = (cfloat *)qpad + ((int64_t)q * a.qrows + QPAD - w) * DP;
+        float Dv[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            Dv[k] = (k == w) ? 0.0f : tsk_inf(); // D(-1,-1) = 0 sits in slot w of column -1
+        bool alive = act;
+        float tau = bits_f(load_relaxed_u32(a.tau + q));
+        int j = 0;
+        float cv[D];
+        load_point<D>(cp, cv);
+        for (; j < m; ++j) {
+            float cn[D];
+            load_point<D>(cp + (int64_t)min(j + 1, nl - 1) * D, cn);
+            cfloat *qrow = qbase + (int64_t)j * DP;
+            // an opaque copy: the per-slot masks are rebuilt in SALU each
+            // column instead of being hoisted (W live masks would spill)
+            int wl = wact;
+            asm volatile("" : "+s"(wl));
+            float down = tsk_inf();
+            // Query rows go through SGPRs in groups of G slots: the loads of
+            // group g+1 are issued before group g is computed; the scheduling
+            // barriers keep a whole column of rows from being hoisted.
+            float qc[G][D], qn[G][D];
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+#pragma unroll
+                for (int e = 0; e < D; ++e)
+                    qc[u][e] = qrow[u * DP + e];
+#pragma unroll
+            for (int g = 0; g < W / G; ++g) {
+                if (g + 1 < W / G) {
+#pragma unroll
+                    for (int u = 0; u < G; ++u)
+#pragma unroll
+                        for (int e = 0; e < D; ++e)
+                            qn[u][e] = qrow[((g + 1) * G + u) * DP + e];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    const int k = g * G + u;
+                    float cst = point_cost<D>(qc[u], cv);
+                    if (k >= KMASK)
+                        cst = k < wl ? cst : tsk_inf();
+                    const float left = (k + 1 < W) ? Dv[k + 1] : tsk_inf();
+                    const float pred = min3f(down, Dv[k], left);
+                    const float v = DIST == DIST_DK ? fmaxf(cst, pred) : cst + pred;
+                    Dv[k] = v;
+                    down = v;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < G; ++u)
+#pragma unroll
+                    for (int e = 0; e < D; ++e)
+                        qc[u][e] = qn[u][e];
+            }
+#pragma unroll
+            for (int e = 0; e < D; ++e)
+                cv[e] = cn[e];
+            const int h = min(j + w, m - 1) - max(j - w, 0) + 1;
+            valid += (unsigned long long)h * __popcll(__ballot(alive));
+            cells += W;
+            if ((j & 7) == 7) {
+                float cm = Dv[0];
+#pragma unroll
+                for (int k = 1; k < W; ++k)
+                    cm = fminf(cm, Dv[k]);
+                tau = bits_f(load_relaxed_u32(a.tau + q));
+                alive = alive && cm <= tau;
+                if (__ballot(alive) == 0ull) {
+                    ++j;
+                    break;
+                }
+            }
+        }
+        float res = tsk_inf();
+        if (j >= m) {
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                res = (k == w) ? Dv[k] : res;
+        }
+        if (act) {
+            if (!alive)
+                res = tsk_inf();
+            if (res == tsk_inf())
+                ++abandoned;
+            finish_lane(a, q, ch.c, res, completed);
+        }
+    }
+    wave_count(a.ctr + C_DP_STARTED, started);
+    wave_count(a.ctr + C_DP_COMPLETED, completed);
+    wave_count(a.ctr + C_DP_ABANDONED, abandoned);
+    wave_count(a.ctr + C_BOUND_PRUNED, late);
+    wave_count(a.ctr + C_FALLBACK, fallback);
+    if (threadIdx.x == 0) {
+        atomicAdd(a.ctr + C_DP_CELLS, cells * 64ull);
+        atomicAdd(a.ctr + C_VALID_CELLS, valid);
+    }
+}
+
+// ------------------------------------------------------------------ sparse DK tube
+// Unbanded DK with the sparse-DK semantics of Alg. 3 (Sec. 4.2): a cell above
+// tau is dead (+inf), and a pair with no live cell left in a column is > tau.
+// Each lane keeps a window of W consecutive rows [lo, lo+W) of the current
+// column.  Cells below lo are dead (nothing below a dead prefix can come
+// back: every predecessor is lower or to the left), so after each column lo
+// moves up past up to two leading dead slots.  Cells above the window are
+// reached only through the window's top slot (same column, or the previous
+// column's top when lo did not move), so as long as the top slot stays dead
+// the window holds every live cell and the result is exact; a live top slot
+// sends the pair to the general DP.  Query rows come from LDS (per lane
+// addresses), the candidate point is per lane.
+template <int D, int W>
+__global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
+{
+    constexpr int DP = PadDim<D>::value;
+    extern __shared__ float qs[];
+    unsigned long long started = 0, completed = 0, abandoned = 0, late = 0, fallback = 0;
+    unsigned long long cells = 0, valid = 0;
+    const int64_t total = (int64_t)a.nq * ((*a.max_cnt + 63) / 64);
+    int staged = -1;
+    Chunk ch;
+    while (next_chunk(a, total, ch, late)) {
+        const int q = ch.q, m = ch.m;
+        if (q != staged) {
+            // query rows 0 .. m-1+W (those past m-1 are +inf)
+            __syncthreads();
+            const float4 *src = reinterpret_cast<const float4 *>(a.qpad + ((int64_t)q * a.qrows + QPAD) * DP);
+            float4 *dst = reinterpret_cast<float4 *>(qs);
+            const int n4 = (m + W) * DP / 4;
+            for (int i = threadIdx.x; i < n4; i += 64)
+                dst[i] = src[i];
+            __syncthreads();
+            staged = q;
+        }
+        const bool act = ch.act;
+        const int n = act ? a.len[ch.c] : 1;
+        started += act ? 1 : 0;
+        const float *cp = a.aos + a.off[act ? ch.c : 0] * D;
+        int nmax = n;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            nmax = max(nmax, __shfl_xor(nmax, o, 64));
+        float Dv[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            Dv[k] = tsk_inf();
+        int lo = 0;
+        bool running = act, over = false;
+        float res = tsk_inf();
+        float tau = bits_f(load_relaxed_u32(a.tau + q));
+        for (int j = 0; j < nmax; ++j) {
+            if (__ballot(running) == 0ull)
+                break;
+            if ((j & 7) == 0)
+                tau = bits_f(load_relaxed_u32(a.tau + q));
+            float cv[D];
+            load_point<D>(cp + (int64_t)min(j, n - 1) * D, cv);
+            float down = tsk_inf();
+            float diag = (j == 0) ? 0.0f : tsk_inf(); // D(-1,-1) = 0 feeds (0,0)
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const float *qr = qs + (lo + k) * DP;
+                float qq[D];
+#pragma unroll
+                for (int e = 0; e < D; ++e)
+                    qq[e] = qr[e];
+                const float cst = point_cost<D>(qq, cv);
+                const float old = Dv[k];
+                float v = fmaxf(cst, min3f(down, old, diag));
+                v = v <= tau ? v : tsk_inf();
+                diag = old;
+                Dv[k] = v;
+                down = v;
+                any |= v != tsk_inf();
+            }
+            cells += W;
+            valid += __popcll(__ballot(running)) * (unsigned long long)W;
+            if (running) {
+                if (j == n - 1) {
+                    const int slot = m - 1 - lo;
+#pragma unroll
+                    for (int k = 0; k < W; ++k)
+                        res = (k == slot) ? Dv[k] : res;
+                    running = false;
+                } else if (!any) {
+                    running = false;
+                } else if (Dv[W - 1] != tsk_inf()) {
+                    over = true;
+                    running = false;
+                }
+            }
+            // drop up to two leading dead slots (finished lanes keep lo)
+            int s = Dv[0] != tsk_inf() ? 0 : (Dv[1] != tsk_inf() ? 1 : 2);
+            s = running ? s : 0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const float d1 = (k + 1 < W) ? Dv[k + 1] : tsk_inf();
+                const float d2 = (k + 2 < W) ? Dv[k + 2] : tsk_inf();
+                Dv[k] = s == 0 ? Dv[k] : (s == 1 ? d1 : d2);
+            }
+            lo += s;
+        }
+        if (act) {
+            if (over) {
+                push_fallback(a, q, ch.c);
+                ++fallback;
+            } else {
+                if (res == tsk_inf())
+                    ++abandoned;
+                finish_lane(a, q, ch.c, res, completed);
+            }
+        }
+    }
+    wave_count(a.ctr + C_DP_STARTED, started);
+    wave_count(a.ctr + C_DP_COMPLETED, completed);
+    wave_count(a.ctr + C_DP_ABANDONED, abandoned);
+    wave_count(a.ctr + C_BOUND_PRUNED, late);
+    wave_count(a.ctr + C_FALLBACK, fallback);
+    if (threadIdx.x == 0) {
+        atomicAdd(a.ctr + C_DP_CELLS, cells * 64ull);
+        atomicAdd(a.ctr + C_VALID_CELLS, valid);
+    }
+}
+
+} // namespace tsk

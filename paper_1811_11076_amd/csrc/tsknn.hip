@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "kernels.hpp"
+#include "launch.hpp"
 #include "tsknn.h"
 
 using namespace tsk;
@@ -92,6 +92,8 @@ struct Workspace {
     DevBuf<int64_t> qoff;
     DevBuf<float> env;
     DevBuf<float> tbuf;
+    DevBuf<float> qpad;
+    DevBuf<int2> fb;
     std::vector<int64_t> h_qoff;
     void release()
     {
@@ -108,6 +110,8 @@ struct Workspace {
         qoff.release();
         env.release();
         tbuf.release();
+        qpad.release();
+        fb.release();
     }
 };
 
@@ -513,28 +517,84 @@ static DpArgs dp_args(tsk_index *ix, const float *qv, int nq, const QueryPlan &P
     a.tb_stride = 2 * ix->max_len;
     a.ctr = ix->ws.ctr.p;
     a.out_all = nullptr;
+    a.fb = ix->ws.fb.p;
+    a.fb_count = ix->ws.work.p + 1;
     return a;
 }
 
 static int dp_blocks(const tsk_index *ix) { return ix->n_cu * 4; }
 
-template <int D> struct DpLaunch {
-    static void run(const DpArgs &a, int dist, bool allpairs, int blocks, hipStream_t s)
+// Which lane-per-pair kernel serves a call (0 = none: everything goes to the
+// general DP).
+enum { FAST_NONE = 0, FAST_BAND, FAST_TUBE32 };
+
+static FastArgs fast_args(tsk_index *ix, int nq, const QueryPlan &P, int qrows)
+{
+    FastArgs a;
+    a.qoff = ix->ws.qoff.p;
+    a.nq = nq;
+    a.aos = ix->aos;
+    a.off = ix->off;
+    a.len = ix->len;
+    a.N = ix->n;
+    a.k = P.k;
+    a.ba = P.ba;
+    a.tau = ix->ws.tau.p;
+    a.lbv = ix->ws.lbv.p;
+    a.surv = ix->ws.surv.p;
+    a.surv_cnt = ix->ws.surv_cnt.p;
+    a.max_cnt = ix->ws.max_cnt.p;
+    a.resslots = ix->ws.resslots.p;
+    a.work = ix->ws.work.p;
+    a.fb = ix->ws.fb.p;
+    a.qpad = ix->ws.qpad.p;
+    a.qrows = qrows;
+    a.ctr = ix->ws.ctr.p;
+    return a;
+}
+
+template <int D> struct QpadLaunch {
+    static void run(const float *qv, const int64_t *qoff, int nq, int qrows, float *qpad,
+                    hipStream_t s)
     {
-        dim3 grid(blocks), block(256);
-        if (dist == DIST_DK) {
-            if (allpairs)
-                hipLaunchKernelGGL((k_dp_wave<D, DIST_DK, true>), grid, block, 0, s, a);
-            else
-                hipLaunchKernelGGL((k_dp_wave<D, DIST_DK, false>), grid, block, 0, s, a);
-        } else {
-            if (allpairs)
-                hipLaunchKernelGGL((k_dp_wave<D, DIST_DTW, true>), grid, block, 0, s, a);
-            else
-                hipLaunchKernelGGL((k_dp_wave<D, DIST_DTW, false>), grid, block, 0, s, a);
-        }
+        hipLaunchKernelGGL(k_qpad<D>, dim3((qrows + 63) / 64, nq), dim3(64), 0, s, qv, qoff, nq,
+                           qrows, qpad);
     }
 };
+
+// Picks the lane-per-pair kernel from the call's shape (per-pair exceptions
+// are handed to the general DP inside the kernels).
+static int pick_fast(const tsk_index *ix, int dist, const tsk_band &band, int32_t qmin, int32_t qmax,
+                     int dp_kernel, int *wsel)
+{
+    *wsel = -1;
+    if (dp_kernel == 1)
+        return FAST_NONE;
+    const int DP = ix->dim <= 4 ? 4 : 8;
+    if (dist == TSK_DK && band.mode == TSK_BAND_NONE) {
+        if ((size_t)(qmax + 32) * DP * sizeof(float) <= 64 * 1024)
+            return FAST_TUBE32;
+        return FAST_NONE;
+    }
+    // banded (or unbanded short) equal-length pairs
+    if (qmin != qmax || ix->min_len != ix->max_len || ix->min_len != qmin)
+        return FAST_NONE;
+    const int m = qmin;
+    int w;
+    if (band.mode == TSK_BAND_ABS)
+        w = band.r;
+    else if (band.mode == TSK_BAND_FRAC)
+        w = (int)std::floor((double)band.frac * (double)m);
+    else
+        w = m - 1;
+    w = std::min(w, m - 1);
+    for (int i = 0; i < N_BAND_WS; ++i)
+        if (2 * w + 1 <= BAND_WS[i]) {
+            *wsel = i;
+            return FAST_BAND;
+        }
+    return FAST_NONE;
+}
 
 static int check_queries(const tsk_index *ix, const float *qv, const int64_t *qoff, int64_t nq,
                          int32_t dist, tsk_band band)
@@ -570,6 +630,7 @@ static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env)
     if (need_env)
         TSK_TRY(w.env.ensure(nq * (int64_t)ix->max_len * 2 * ix->dim));
     TSK_TRY(w.tbuf.ensure((size_t)dp_blocks(ix) * 4 * 2 * ix->max_len));
+    TSK_TRY(w.fb.ensure(nq * N));
     return TSK_OK;
 }
 
@@ -668,8 +729,30 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
                            W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
         if (timed)
             HIP_TRY(hipEventRecord(ev[2], s));
+        int32_t qmin = INT32_MAX, qmax = 0;
+        for (int i = 0; i < nq; ++i) {
+            const int32_t L = (int32_t)(q_offsets_host[q0 + i + 1] - q_offsets_host[q0 + i]);
+            qmin = std::min(qmin, L);
+            qmax = std::max(qmax, L);
+        }
+        int wsel = -1;
+        const int fast = pick_fast(ix, dist, band, qmin, qmax, o.dp_kernel, &wsel);
         DpArgs da = dp_args(ix, qv, nq, P);
-        dispatch_d<DpLaunch>(P.D, da, dist, false, dp_blocks(ix), s);
+        if (fast != FAST_NONE) {
+            const int DP = P.D <= 4 ? 4 : 8;
+            const int qrows = qmax + 2 * QPAD;
+            TSK_TRY(W.qpad.ensure((size_t)nq * qrows * DP));
+            dispatch_d<QpadLaunch>(P.D, qv, W.qoff.p, nq, qrows, W.qpad.p, s);
+            FastArgs fa = fast_args(ix, nq, P, qrows);
+            if (fast == FAST_TUBE32)
+                launch_tube(P.D, fa, ix->n_cu * 8, qmax, s);
+            else
+                launch_band(P.D, dist, wsel, fa, ix->n_cu * 8, s);
+            da.work = W.work.p + 2;
+            launch_dp_wave(P.D, dist, DPW_FALLBACK, da, dp_blocks(ix), s);
+        } else {
+            launch_dp_wave(P.D, dist, DPW_SURV, da, dp_blocks(ix), s);
+        }
         if (timed)
             HIP_TRY(hipEventRecord(ev[3], s));
         if (dist == TSK_DK)
@@ -765,7 +848,7 @@ extern "C" int tsk_pair_distances(const tsk_index *cix, const float *q_values_de
         fill_u64(ix->ws.ctr.p, 0ull, C_NUM, s);
         DpArgs da = dp_args(ix, q_values_dev, nq, P);
         da.out_all = out_keys_dev + q0 * ix->n;
-        dispatch_d<DpLaunch>(P.D, da, dist, true, dp_blocks(ix), s);
+        launch_dp_wave(P.D, dist, DPW_ALLPAIRS, da, dp_blocks(ix), s);
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(s));

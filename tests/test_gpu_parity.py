@@ -163,3 +163,70 @@ def test_knn_classwarp_reduced():
         assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
         print(f"  {dist}: {st}", flush=True)
     idx.close()
+
+
+@pytest.mark.parametrize("w", [3, 12, 20, 30, 45, 60])
+def test_knn_band_kernel_widths(w):
+    """Equal lengths, one band width per lane-per-pair window size (2w+1 of
+    7, 25, 41, 61, 91, 121 slots), both distances, against the oracle."""
+    print(f"[case] knn band widths w={w}", flush=True)
+    db, dbo = ragged_walks(40 + w, 150, (128, 128), 3)
+    qs, qo = ragged_walks(140 + w, 3, (128, 128), 3)
+    idx = _index(db, dbo)
+    for dist in ("dk", "dtw"):
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 6, dist, w)
+        ids, dst, st = idx.knn(to_dev(qs), qo, 6, dist, w, stats=True)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
+        assert st["fallback_pairs"] == 0
+    idx.close()
+
+
+def test_knn_tube_overflow_goes_to_general_dp():
+    """k = N keeps every DK cell alive, so every tube outgrows its window and
+    the pair is finished by the general DP; results stay exact."""
+    print("[case] knn tube overflow", flush=True)
+    db, dbo = ragged_walks(51, 40, (60, 90), 2)
+    qs, qo = ragged_walks(52, 2, (60, 90), 2)
+    idx = _index(db, dbo)
+    ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 40, "dk", None)
+    ids, dst, st = idx.knn(to_dev(qs), qo, 40, "dk", None, stats=True)
+    assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
+    assert st["fallback_pairs"] > 0
+    # short queries fit the window: no fallback
+    db2, dbo2 = ragged_walks(53, 40, (10, 30), 2)
+    qs2, qo2 = ragged_walks(54, 2, (10, 30), 2)
+    idx2 = _index(db2, dbo2)
+    ref_ids, ref_keys = O.knn_brute(db2, dbo2, qs2, qo2, 40, "dk", None)
+    ids, dst, st = idx2.knn(to_dev(qs2), qo2, 40, "dk", None, stats=True)
+    assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
+    assert st["fallback_pairs"] == 0
+    idx.close()
+    idx2.close()
+
+
+def test_knn_general_dp_forced_equals_fast():
+    """dp_kernel = 1 (general DP only) and the default give identical rows."""
+    import ctypes
+    from paper_1811_11076_amd import _lib
+    print("[case] knn general vs fast", flush=True)
+    db, dbo, qs, qo = classwarp(2, 10, 256, 3, 2000, 6)
+    idx = _index(db, dbo)
+    for dist, band in (("dk", None), ("dtw", 0.1)):
+        a_ids, a_d, _ = idx.knn(to_dev(qs), qo, 10, dist, band)
+        lib = _lib.load()
+        opts = _lib.QueryOpts()
+        opts.size = ctypes.sizeof(_lib.QueryOpts)
+        opts.dp_kernel = 1
+        import torch
+        ids = torch.empty((6, 10), dtype=torch.int64, device="cuda")
+        dd = torch.empty((6, 10), dtype=torch.float32, device="cuda")
+        qv = to_dev(qs)
+        _lib.check(lib.tsk_knn_query(idx._h, ctypes.c_void_p(qv.data_ptr()),
+                                     qo.ctypes.data_as(ctypes.c_void_p), 6, 10,
+                                     _lib.TSK_DK if dist == "dk" else _lib.TSK_DTW,
+                                     _lib.band_struct(band), ctypes.byref(opts),
+                                     ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dd.data_ptr()),
+                                     None, None))
+        torch.cuda.synchronize()
+        assert torch.equal(ids, a_ids) and torch.equal(dd.view(torch.int32), a_d.view(torch.int32))
+    idx.close()
