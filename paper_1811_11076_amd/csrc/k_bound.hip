@@ -1,0 +1,109 @@
+// Bound-pass kernels (k_bound_dk, k_bound_lb, k_seed_ring) and launchers.
+#include "launch.hpp"
+
+namespace tsk {
+
+namespace {
+template <int D> void bound_dk_d(int qg, const BoundArgs &a, int maxm, hipStream_t s)
+{
+    constexpr int DP = PadDim<D>::value;
+    dim3 grid((unsigned)((a.N + 255) / 256), (unsigned)((a.nq + qg - 1) / qg));
+    const size_t lds = (size_t)qg * maxm * DP * sizeof(float);
+    if (qg == 4)
+        hipLaunchKernelGGL((k_bound_dk<D, 4>), grid, dim3(256), lds, s, a, maxm);
+    else
+        hipLaunchKernelGGL((k_bound_dk<D, 1>), grid, dim3(256), lds, s, a, maxm);
+}
+
+template <int D> void bound_lb_d(const BoundArgs &a, bool debug, hipStream_t s)
+{
+    constexpr int QG = 8;
+    dim3 grid((unsigned)((a.N + 255) / 256), (unsigned)((a.nq + QG - 1) / QG));
+    if (debug)
+        hipLaunchKernelGGL((k_bound_lb<D, QG, true>), grid, dim3(256), 0, s, a, a.env);
+    else
+        hipLaunchKernelGGL((k_bound_lb<D, QG, false>), grid, dim3(256), 0, s, a, a.env);
+}
+
+template <int D>
+void seed_ring_d(int dist, const SeedRingArgs &r, hipStream_t s)
+{
+    constexpr int DP = PadDim<D>::value;
+    dim3 grid((r.S - r.P0 + 63) / 64, r.nq);
+    const size_t lds = (size_t)r.maxm * DP * sizeof(float);
+    if (dist == DIST_DK)
+        hipLaunchKernelGGL((k_seed_ring<D, DIST_DK>), grid, dim3(64), lds, s, r.qv, r.qoff, r.nq,
+                           r.aos, r.off, r.len, r.N, r.order, r.P0, r.S, r.k, r.ba, r.seedslots,
+                           r.tau, r.ctr, r.dbg_ub, r.dbg_steps);
+    else
+        hipLaunchKernelGGL((k_seed_ring<D, DIST_DTW>), grid, dim3(64), lds, s, r.qv, r.qoff, r.nq,
+                           r.aos, r.off, r.len, r.N, r.order, r.P0, r.S, r.k, r.ba, r.seedslots,
+                           r.tau, r.ctr, r.dbg_ub, r.dbg_steps);
+}
+template <int D> void corner_d(const BoundArgs &a, hipStream_t s)
+{
+    constexpr int QG = 8;
+    dim3 grid((unsigned)((a.N + 255) / 256), (unsigned)((a.nq + QG - 1) / QG));
+    hipLaunchKernelGGL((k_corner<D, QG>), grid, dim3(256), 0, s, a);
+}
+
+template <int D>
+void walk_d(const FastArgs &a, const float *qv, unsigned long long *ubslots, int blocks, int maxm,
+            hipStream_t s)
+{
+    constexpr int DP = PadDim<D>::value;
+    const size_t lds = (size_t)maxm * DP * sizeof(float);
+    hipLaunchKernelGGL((k_walk_dk<D>), dim3(blocks), dim3(64), lds, s, a, qv, ubslots);
+}
+} // namespace
+
+#define TSK_SWITCH_D(D_, CALL)                                                                     \
+    switch (D_) {                                                                                  \
+    case 1: CALL(1); break;                                                                        \
+    case 2: CALL(2); break;                                                                        \
+    case 3: CALL(3); break;                                                                        \
+    case 4: CALL(4); break;                                                                        \
+    case 5: CALL(5); break;                                                                        \
+    case 6: CALL(6); break;                                                                        \
+    case 7: CALL(7); break;                                                                        \
+    case 8: CALL(8); break;                                                                        \
+    default: break;                                                                                \
+    }
+
+void launch_bound_dk(int D, int qg, const BoundArgs &a, int maxm, hipStream_t s)
+{
+#define CALL(d) bound_dk_d<d>(qg, a, maxm, s)
+    TSK_SWITCH_D(D, CALL)
+#undef CALL
+}
+
+void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s)
+{
+#define CALL(d) bound_lb_d<d>(a, debug, s)
+    TSK_SWITCH_D(D, CALL)
+#undef CALL
+}
+
+void launch_corner(int D, const BoundArgs &a, hipStream_t s)
+{
+#define CALL(d) corner_d<d>(a, s)
+    TSK_SWITCH_D(D, CALL)
+#undef CALL
+}
+
+void launch_walk_dk(int D, const FastArgs &a, const float *qv, unsigned long long *ubslots,
+                    int blocks, int maxm, hipStream_t s)
+{
+#define CALL(d) walk_d<d>(a, qv, ubslots, blocks, maxm, s)
+    TSK_SWITCH_D(D, CALL)
+#undef CALL
+}
+
+void launch_seed_ring(int D, int dist, const SeedRingArgs &r, hipStream_t s)
+{
+#define CALL(d) seed_ring_d<d>(dist, r, s)
+    TSK_SWITCH_D(D, CALL)
+#undef CALL
+}
+
+} // namespace tsk

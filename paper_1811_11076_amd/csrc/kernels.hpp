@@ -665,7 +665,7 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
         if (lane == 0)
             t = atomicAdd(a.work, 1ull);
         t = uniform_u64(t);
-        if ((int64_t)t >= total)
+        if (t >= (unsigned long long)total)
             break;
         int q, c;
         if (ALLPAIRS) {

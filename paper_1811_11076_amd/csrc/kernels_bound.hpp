@@ -1,0 +1,414 @@
+// Bound-pass kernels tuned for gfx950: LB_Box for DTW and the greedy bound
+// of Alg. 1 for DK, one lane per candidate.
+#pragma once
+
+#include "kernels_fast.hpp"
+
+namespace tsk {
+
+// Greedy walk of Alg. 1 (Sec. 4.1), same moves, tie order and value as
+// greedy_walk(), with the query read from LDS (row stride DP floats) and the
+// candidate streamed through a 4-point register ring so that the loads are
+// issued several moves before their use.
+template <int D, int DIST>
+__device__ float greedy_walk_ring(const float *qs, int m, const float *__restrict__ c, int n,
+                                  const Band &band, float eps, const uint32_t *tau, int &steps_out,
+                                  bool &completed)
+{
+    constexpr int DP = PadDim<D>::value;
+    float q0[D], q1[D], q2[D];
+    float r0[D], r1[D], r2[D], r3[D];
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        q0[e] = qs[e];
+        q1[e] = qs[min(1, m - 1) * DP + e];
+        q2[e] = qs[min(2, m - 1) * DP + e];
+        r0[e] = c[e];
+        r1[e] = c[(int64_t)min(1, n - 1) * D + e];
+        r2[e] = c[(int64_t)min(2, n - 1) * D + e];
+        r3[e] = c[(int64_t)min(3, n - 1) * D + e];
+    }
+    float g = point_cost<D>(q0, r0);
+    int i = 0, j = 0, steps = 0;
+    completed = false;
+    if (g > eps) {
+        steps_out = 0;
+        return g;
+    }
+    while (i < m - 1 || j < n - 1) {
+        const bool di = i + 1 < m, dj = j + 1 < n;
+        float c_dn = tsk_inf(), c_dg = tsk_inf(), c_rt = tsk_inf();
+        if (di && band_ok(band, i + 1, j))
+            c_dn = point_cost<D>(q1, r0);
+        if (di && dj && band_ok(band, i + 1, j + 1))
+            c_dg = point_cost<D>(q1, r1);
+        if (dj && band_ok(band, i, j + 1))
+            c_rt = point_cost<D>(q0, r1);
+        int mv;
+        float cst;
+        if (c_dn <= c_dg && c_dn <= c_rt) {
+            mv = 0;
+            cst = c_dn;
+        } else if (c_dg <= c_rt) {
+            mv = 1;
+            cst = c_dg;
+        } else {
+            mv = 2;
+            cst = c_rt;
+        }
+        ++steps;
+        if (cst == tsk_inf()) {
+            steps_out = steps;
+            return tsk_inf();
+        }
+        g = DIST == DIST_DK ? fmaxf(g, cst) : cst + g;
+        if (mv != 2) {
+            ++i;
+            const int ni = min(i + 2, m - 1);
+#pragma unroll
+            for (int e = 0; e < D; ++e) {
+                q0[e] = q1[e];
+                q1[e] = q2[e];
+                q2[e] = qs[ni * DP + e];
+            }
+        }
+        if (mv != 0) {
+            ++j;
+            const int64_t nj = min(j + 3, n - 1);
+#pragma unroll
+            for (int e = 0; e < D; ++e) {
+                r0[e] = r1[e];
+                r1[e] = r2[e];
+                r2[e] = r3[e];
+                r3[e] = c[nj * D + e];
+            }
+        }
+        if (tau && (steps & 7) == 0)
+            eps = fminf(eps, bits_f(load_relaxed_u32(tau)));
+        if (g > eps) {
+            steps_out = steps;
+            return g;
+        }
+    }
+    steps_out = steps;
+    completed = true;
+    return g;
+}
+
+// Inserts the lanes' keys that can still matter into a query's top-k slots.
+// If more than k lanes of the wave want to insert, only the wave's k
+// smallest keys can be among the query's k smallest, so the others skip
+// the atomics.
+__device__ __forceinline__ void wave_topk_insert(unsigned long long *slots, int k, bool want,
+                                                 unsigned long long key, uint32_t *tau)
+{
+    const unsigned long long mask = __ballot(want);
+    if (mask == 0ull)
+        return;
+    if (__popcll(mask) > k) {
+        // every lane walks the same list, so the shuffles are uniform
+        int rank = 0;
+        unsigned long long rest = mask;
+        while (rest) {
+            const int l = __ffsll((long long)rest) - 1;
+            rest &= rest - 1;
+            const unsigned long long other = __shfl(key, l, 64);
+            rank += other < key ? 1 : 0;
+        }
+        want = want && rank < k;
+    }
+    if (want) {
+        topk_insert(slots, k, key);
+        tau_from_slots(slots, k, tau);
+    }
+}
+
+// DK bound pass: corner bound for every pair, then the greedy walk for the
+// pairs it does not prune (Sec. 4.4's first loop, with early return at the
+// running threshold).  Block: 256 candidates x a group of QG queries staged
+// in LDS.
+template <int D, int QG>
+__global__ __launch_bounds__(256) void k_bound_dk(BoundArgs a, int maxm)
+{
+    constexpr int DP = PadDim<D>::value;
+    extern __shared__ float qs[];
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q0 = blockIdx.y * QG;
+    const int nqg = min(QG, a.nq - q0);
+    // stage the group's queries: qs[g][row][DP]
+    for (int g = 0; g < nqg; ++g) {
+        const int q = q0 + g;
+        const int m = (int)(a.qoff[q + 1] - a.qoff[q]);
+        const float *src = a.qv + a.qoff[q] * D;
+        for (int t = threadIdx.x; t < m * DP; t += blockDim.x) {
+            const int row = t / DP, e = t % DP;
+            qs[(g * maxm + row) * DP + e] = e < D ? src[row * D + e] : 0.0f;
+        }
+    }
+    __syncthreads();
+    const bool valid = c < a.N;
+    const int64_t tile = c >> 6;
+    const int lane = (int)(c & 63);
+    const int n = valid ? a.len[c] : 1;
+    const float *tb = valid ? a.soa + a.tile_off[tile] + lane : a.soa;
+    const float *cp = a.aos + a.off[valid ? c : 0] * D;
+    float c0[D], cl[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        c0[k] = valid ? tb[(0 * D + k) * 64] : 0.0f;
+        cl[k] = valid ? tb[((int64_t)(n - 1) * D + k) * 64] : 0.0f;
+    }
+    unsigned long long pruned = 0, steps_cnt = 0, pairs = 0;
+    for (int g = 0; g < nqg; ++g) {
+        const int q = q0 + g;
+        const int m = (int)(a.qoff[q + 1] - a.qoff[q]);
+        const float *Q = qs + g * maxm * DP;
+        float qa[D], qz[D];
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            qa[e] = Q[e];
+            qz[e] = Q[(m - 1) * DP + e];
+        }
+        const float lb = fmaxf(point_cost<D>(qa, c0), point_cost<D>(qz, cl));
+        float tq = bits_f(load_relaxed_u32(a.tau + q));
+        bool want = false;
+        float gval = tsk_inf();
+        if (valid && lb <= tq) {
+            const Band b = pair_band(a.ba, m, n);
+            int steps;
+            bool done;
+            gval = greedy_walk_ring<D, DIST_DK>(Q, m, cp, n, b, tq, a.tau + q, steps, done);
+            steps_cnt += steps;
+            want = done && gval != tsk_inf() && gval <= bits_f(load_relaxed_u32(a.tau + q));
+        }
+        wave_topk_insert(a.ubslots + (int64_t)q * a.k, a.k, want, make_key(gval, (uint32_t)c),
+                         a.tau + q);
+        if (valid) {
+            ++pairs;
+            tq = bits_f(load_relaxed_u32(a.tau + q));
+            const bool keep = lb <= tq;
+            a.lbv[(int64_t)q * a.N + c] = keep ? lb : tsk_inf();
+            pruned += keep ? 0 : 1;
+        }
+    }
+    wave_count(a.ctr + C_BOUND_PRUNED, pruned);
+    wave_count(a.ctr + C_PAIRS, pairs);
+    wave_count(a.ctr + C_BOUND_STEPS, steps_cnt);
+}
+
+// DTW bound pass for an index of equal-length series: LB_Box of every
+// (query, candidate) pair with the query's envelope around each candidate
+// point (eq. (1), roles exchanged), fp32, summed over the candidate's
+// points in order.  Each candidate point is loaded once (coalesced SoA) and
+// scored against the QG queries of the block; the envelopes are wave-uniform
+// and arrive through scalar loads.
+template <int D, int QG, bool DEBUG>
+__global__ __launch_bounds__(256) void k_bound_lb(BoundArgs a, const float *__restrict__ env)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q0 = blockIdx.y * QG;
+    const int nqg = min(QG, a.nq - q0);
+    const bool valid = c < a.N;
+    const int64_t tile = c >> 6;
+    const int lane = (int)(c & 63);
+    const int n = a.env_n; // every series has this length
+    const float *tb = valid ? a.soa + a.tile_off[tile] + lane : a.soa;
+    cfloat *E = (cfloat *)env + (int64_t)q0 * n * 2 * D;
+    float acc[QG];
+#pragma unroll
+    for (int g = 0; g < QG; ++g)
+        acc[g] = 0.0f;
+    for (int j = 0; j < n; ++j) {
+        float x[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            x[k] = tb[((int64_t)j * D + k) * 64];
+#pragma unroll
+        for (int g = 0; g < QG; ++g) {
+            // groups past the last query reuse query q0's envelope; their sums
+            // are never written
+            const int gg = g < nqg ? g : 0;
+            cfloat *e = E + ((int64_t)gg * n + j) * 2 * D;
+            float t = 0.0f;
+            bool empty = false;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const float lo = e[k], hi = e[D + k];
+                empty |= lo > hi;
+                // distance to [lo, hi]: lo - x below, x - hi above, 0 inside
+                const float d = fmaxf(fmaxf(lo - x[k], x[k] - hi), 0.0f);
+                t = (k == 0) ? d * d : __builtin_fmaf(d, d, t);
+            }
+            acc[g] = (empty ? tsk_inf() : t) + acc[g];
+        }
+    }
+    unsigned long long pruned = 0, pairs = 0;
+    if (DEBUG) {
+        if (valid)
+#pragma unroll
+            for (int g = 0; g < QG; ++g)
+                if (g < nqg)
+                    a.dbg_lb[(int64_t)(q0 + g) * a.N + c] = acc[g];
+        return;
+    }
+    if (valid) {
+#pragma unroll
+        for (int g = 0; g < QG; ++g) {
+            if (g < nqg) {
+                const int q = q0 + g;
+                const bool keep = acc[g] <= bits_f(load_relaxed_u32(a.tau + q));
+                a.lbv[(int64_t)q * a.N + c] = keep ? acc[g] : tsk_inf();
+                pruned += keep ? 0 : 1;
+                ++pairs;
+            }
+        }
+    }
+    wave_count(a.ctr + C_BOUND_PRUNED, pruned);
+    wave_count(a.ctr + C_PAIRS, pairs);
+    wave_count(a.ctr + C_BOUND_STEPS, valid ? (unsigned long long)n * nqg : 0ull);
+}
+
+// DK corner pass: every warping path starts at (0,0) and ends at (m-1,n-1),
+// so max(c(0,0), c(m-1,n-1)) <= squared DK.  One lane per candidate, a
+// group of QG queries per block (their end points via scalar loads); lbv gets
+// the bound if it does not exceed the running threshold, else +inf.
+template <int D, int QG>
+__global__ __launch_bounds__(256) void k_corner(BoundArgs a)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q0 = blockIdx.y * QG;
+    const int nqg = min(QG, a.nq - q0);
+    if (c >= a.N)
+        return;
+    const int64_t tile = c >> 6;
+    const int lane = (int)(c & 63);
+    const int n = a.len[c];
+    const float *tb = a.soa + a.tile_off[tile] + lane;
+    float c0[D], cl[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        c0[k] = tb[(0 * D + k) * 64];
+        cl[k] = tb[((int64_t)(n - 1) * D + k) * 64];
+    }
+    unsigned long long pruned = 0;
+    for (int g = 0; g < nqg; ++g) {
+        const int q = q0 + g;
+        const int64_t o0 = a.qoff[q], o1 = a.qoff[q + 1];
+        cfloat *Q = (cfloat *)a.qv;
+        float qa[D], qz[D];
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            qa[e] = Q[o0 * D + e];
+            qz[e] = Q[(o1 - 1) * D + e];
+        }
+        const float lb = fmaxf(point_cost<D>(qa, c0), point_cost<D>(qz, cl));
+        const bool keep = lb <= bits_f(load_relaxed_u32(a.tau + q));
+        a.lbv[(int64_t)q * a.N + c] = keep ? lb : tsk_inf();
+        pruned += keep ? 0 : 1;
+    }
+    wave_count(a.ctr + C_BOUND_PRUNED, pruned);
+    wave_count(a.ctr + C_PAIRS, (unsigned long long)nqg);
+}
+
+// DK greedy pass over the compacted survivors (Sec. 4.4, first loop): a wave
+// takes 64 survivors of one query (query staged in LDS) and walks Alg. 1 on
+// each with early return at the running threshold; completed walks lower the
+// threshold through the query's upper-bound slots.
+template <int D>
+__global__ __launch_bounds__(64) void k_walk_dk(FastArgs a, const float *__restrict__ qv,
+                                                 unsigned long long *ubslots)
+{
+    constexpr int DP = PadDim<D>::value;
+    extern __shared__ float qs[];
+    unsigned long long steps_cnt = 0, late = 0;
+    const int64_t total = (int64_t)a.nq * ((*a.max_cnt + 63) / 64);
+    int staged = -1;
+    Chunk ch;
+    while (next_chunk(a, total, ch, late)) {
+        const int q = ch.q, m = ch.m;
+        if (q != staged) {
+            __syncthreads();
+            const float *src = qv + a.qoff[q] * D;
+            for (int t = threadIdx.x; t < m * DP; t += 64) {
+                const int row = t / DP, e = t % DP;
+                qs[t] = e < D ? src[row * D + e] : 0.0f;
+            }
+            __syncthreads();
+            staged = q;
+        }
+        bool want = false;
+        float g = tsk_inf();
+        if (ch.act) {
+            const int n = a.len[ch.c];
+            const Band b = pair_band(a.ba, m, n);
+            int steps;
+            bool done;
+            const float tq = bits_f(load_relaxed_u32(a.tau + q));
+            g = greedy_walk_ring<D, DIST_DK>(qs, m, a.aos + a.off[ch.c] * D, n, b, tq, a.tau + q,
+                                             steps, done);
+            steps_cnt += steps;
+            want = done && g != tsk_inf() && g <= bits_f(load_relaxed_u32(a.tau + q));
+        }
+        wave_topk_insert(ubslots + (int64_t)q * a.k, a.k, want,
+                         make_key(g, (uint32_t)(ch.act ? ch.c : 0)), a.tau + q);
+    }
+    wave_count(a.ctr + C_BOUND_STEPS, steps_cnt);
+}
+
+// Threshold seed with the LDS query and the prefetching walk (see k_seed).
+template <int D, int DIST>
+__global__ __launch_bounds__(64) void k_seed_ring(const float *__restrict__ qv,
+                                                  const int64_t *__restrict__ qoff, int nq,
+                                                  const float *__restrict__ aos,
+                                                  const int64_t *__restrict__ off,
+                                                  const int32_t *__restrict__ len, int64_t N,
+                                                  const int32_t *__restrict__ order, int P0, int S,
+                                                  int k, BandArgs ba, unsigned long long *seedslots,
+                                                  uint32_t *tau, unsigned long long *ctr,
+                                                  float *dbg_ub, int32_t *dbg_steps)
+{
+    // Candidates P0..S-1 of the query's order.  P0 == 0: full walks (no
+    // threshold yet); P0 > 0: early return at the running threshold set by
+    // the first part.  dbg_ub != null: write every walk's value and move
+    // count ([q][p]) and insert nothing (tsk_pair_bounds).
+    constexpr int DP = PadDim<D>::value;
+    extern __shared__ float qs[];
+    const int q = blockIdx.y;
+    const int m = (int)(qoff[q + 1] - qoff[q]);
+    const float *src = qv + qoff[q] * D;
+    for (int t = threadIdx.x; t < m * DP; t += blockDim.x) {
+        const int row = t / DP, e = t % DP;
+        qs[t] = e < D ? src[row * D + e] : 0.0f;
+    }
+    __syncthreads();
+    const int p = P0 + blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long steps_cnt = 0, pairs = 0;
+    bool want = false;
+    float g = tsk_inf();
+    int c = 0;
+    if (p < S) {
+        c = order ? order[(int64_t)q * N + p] : p;
+        const int n = len[c];
+        const Band b = pair_band(ba, m, n);
+        int steps;
+        bool done;
+        const bool early = P0 > 0 && !dbg_ub;
+        const float eps = early ? bits_f(load_relaxed_u32(tau + q)) : tsk_inf();
+        g = greedy_walk_ring<D, DIST>(qs, m, aos + off[c] * D, n, b, eps, early ? tau + q : nullptr,
+                                      steps, done);
+        want = done && g != tsk_inf() && g <= bits_f(load_relaxed_u32(tau + q));
+        steps_cnt = steps;
+        pairs = 1;
+        if (dbg_ub) {
+            dbg_ub[(int64_t)q * N + p] = g;
+            dbg_steps[(int64_t)q * N + p] = steps;
+        }
+    }
+    if (dbg_ub)
+        return;
+    wave_topk_insert(seedslots + (int64_t)q * k, k, want, make_key(g, (uint32_t)c), tau + q);
+    wave_count(ctr + C_BOUND_STEPS, steps_cnt);
+    wave_count(ctr + C_SEED_PAIRS, pairs);
+}
+
+} // namespace tsk

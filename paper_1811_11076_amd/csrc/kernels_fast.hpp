@@ -86,7 +86,8 @@ __device__ __forceinline__ bool next_chunk(const FastArgs &a, int64_t total, Chu
         if (threadIdx.x == 0)
             t = atomicAdd(a.work, 1ull);
         t = uniform_u64(t);
-        if ((int64_t)t >= total)
+        // unsigned: a counter value can never pass as a negative index
+        if (t >= (unsigned long long)total)
             return false;
         const int q = uniform_i((int)(t % (unsigned long long)a.nq));
         const int r = (int)(t / (unsigned long long)a.nq);

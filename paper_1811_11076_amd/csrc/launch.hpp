@@ -2,7 +2,7 @@
 // the library builds in parallel.
 #pragma once
 
-#include "kernels_fast.hpp"
+#include "kernels_bound.hpp"
 
 namespace tsk {
 
@@ -12,6 +12,31 @@ namespace tsk {
 constexpr int BAND_WS[] = {16, 32, 56, 64, 104, 128};
 constexpr int N_BAND_WS = 6;
 
+struct SeedRingArgs {
+    const float *qv;
+    const int64_t *qoff;
+    int nq;
+    int maxm;
+    const float *aos;
+    const int64_t *off;
+    const int32_t *len;
+    int64_t N;
+    const int32_t *order;
+    int P0, S, k;
+    BandArgs ba;
+    unsigned long long *seedslots;
+    uint32_t *tau;
+    unsigned long long *ctr;
+    float *dbg_ub;      // debug: per-pair walk value, or null
+    int32_t *dbg_steps; // debug: per-pair move count
+};
+
+void launch_bound_dk(int D, int qg, const BoundArgs &a, int maxm, hipStream_t s);
+void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s);
+void launch_seed_ring(int D, int dist, const SeedRingArgs &r, hipStream_t s);
+void launch_corner(int D, const BoundArgs &a, hipStream_t s);
+void launch_walk_dk(int D, const FastArgs &a, const float *qv, unsigned long long *ubslots,
+                    int blocks, int maxm, hipStream_t s);
 void launch_band(int D, int dist, int wsel, const FastArgs &a, int blocks, hipStream_t s);
 void launch_tube(int D, const FastArgs &a, int blocks, int maxm, hipStream_t s);
 void launch_dp_wave(int D, int dist, int mode, const DpArgs &a, int blocks, hipStream_t s);

@@ -625,7 +625,7 @@ static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env)
     TSK_TRY(w.surv_cnt.ensure(nq));
     TSK_TRY(w.max_cnt.ensure(1));
     TSK_TRY(w.ctr.ensure(C_NUM));
-    TSK_TRY(w.work.ensure(4));
+    TSK_TRY(w.work.ensure(8));
     TSK_TRY(w.qoff.ensure(nq + 1));
     if (need_env)
         TSK_TRY(w.env.ensure(nq * (int64_t)ix->max_len * 2 * ix->dim));
@@ -688,7 +688,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
     P.nq = n_queries;
     P.N = ix->n;
     P.chunk = chunk_queries(ix, n_queries);
-    const int default_seed = 256;
+    const int default_seed = 1024;
     P.seed = (int)std::min<int64_t>(ix->n, o.seed_count > 0 ? o.seed_count : default_seed);
     P.env_ok = (dist == TSK_DTW) && ix->min_len == ix->max_len;
 
@@ -717,24 +717,53 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         fill_u64(W.ubslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
         fill_u64(W.resslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
         fill_u32((uint32_t *)W.max_cnt.p, 0u, 1, s);
-        fill_u64(W.work.p, 0ull, 4, s);
-        if (P.env_ok)
-            dispatch_d<EnvLaunch>(P.D, ix, qv, nq, P.ba, s);
-        dispatch_d<SeedLaunch>(P.D, ix, qv, nq, P, order, s);
-        if (timed)
-            HIP_TRY(hipEventRecord(ev[1], s));
-        BoundArgs ba = bound_args(ix, qv, nq, P);
-        dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
-        hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, order, W.tau.p,
-                           W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
-        if (timed)
-            HIP_TRY(hipEventRecord(ev[2], s));
+        fill_u64(W.work.p, 0ull, 8, s); // every task / list counter of the call
         int32_t qmin = INT32_MAX, qmax = 0;
         for (int i = 0; i < nq; ++i) {
             const int32_t L = (int32_t)(q_offsets_host[q0 + i + 1] - q_offsets_host[q0 + i]);
             qmin = std::min(qmin, L);
             qmax = std::max(qmax, L);
         }
+        const size_t qrow_bytes = (size_t)(P.D <= 4 ? 4 : 8) * sizeof(float);
+        const size_t lds_cap = 64 * 1024;
+        if (P.env_ok)
+            dispatch_d<EnvLaunch>(P.D, ix, qv, nq, P.ba, s);
+        const bool lds_query = (size_t)qmax * qrow_bytes <= lds_cap && o.dp_kernel != 1;
+        if (P.seed > 0 && lds_query) {
+            // a first slice of full walks sets a threshold; the rest of the
+            // seed set returns early against it
+            const int s1 = std::min(P.seed, 64);
+            SeedRingArgs r{qv, W.qoff.p, nq, qmax, ix->aos, ix->off, ix->len, ix->n, order,
+                           0, s1, k, P.ba, W.seedslots.p, W.tau.p, W.ctr.p, nullptr, nullptr};
+            launch_seed_ring(P.D, dist, r, s);
+            if (P.seed > s1) {
+                r.P0 = s1;
+                r.S = P.seed;
+                launch_seed_ring(P.D, dist, r, s);
+            }
+        } else {
+            dispatch_d<SeedLaunch>(P.D, ix, qv, nq, P, order, s);
+        }
+        if (timed)
+            HIP_TRY(hipEventRecord(ev[1], s));
+        BoundArgs ba = bound_args(ix, qv, nq, P);
+        const bool dk_split = dist == TSK_DK && lds_query;
+        if (dk_split)
+            launch_corner(P.D, ba, s);
+        else if (dist == TSK_DTW && P.env_ok && o.dp_kernel != 1)
+            launch_bound_lb(P.D, ba, false, s);
+        else
+            dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
+        hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, order, W.tau.p,
+                           W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
+        if (dk_split) {
+            // greedy bound (Alg. 1) of every survivor of the corner bound
+            FastArgs wa = fast_args(ix, nq, P, 0);
+            wa.work = W.work.p + 4;
+            launch_walk_dk(P.D, wa, qv, W.ubslots.p, ix->n_cu * 8, qmax, s);
+        }
+        if (timed)
+            HIP_TRY(hipEventRecord(ev[2], s));
         int wsel = -1;
         const int fast = pick_fast(ix, dist, band, qmin, qmax, o.dp_kernel, &wsel);
         DpArgs da = dp_args(ix, qv, nq, P);
@@ -844,7 +873,7 @@ extern "C" int tsk_pair_distances(const tsk_index *cix, const float *q_values_de
     for (int64_t q0 = 0; q0 < n_queries; q0 += chunk) {
         const int nq = (int)std::min<int64_t>(chunk, n_queries - q0);
         TSK_TRY(upload_qoff(ix, q_offsets_host, q0, nq, s));
-        fill_u64(ix->ws.work.p, 0ull, 4, s);
+        fill_u64(ix->ws.work.p, 0ull, 8, s);
         fill_u64(ix->ws.ctr.p, 0ull, C_NUM, s);
         DpArgs da = dp_args(ix, q_values_dev, nq, P);
         da.out_all = out_keys_dev + q0 * ix->n;
@@ -884,7 +913,21 @@ extern "C" int tsk_pair_bounds(const tsk_index *cix, const float *q_values_dev,
         ba.dbg_lb = out_lb_dev ? out_lb_dev + q0 * ix->n : nullptr;
         ba.dbg_ub = out_ub_dev ? out_ub_dev + q0 * ix->n : nullptr;
         ba.dbg_steps = out_steps_dev ? out_steps_dev + q0 * ix->n : nullptr;
+        // the k-NN path's kernels where they apply (LB_Box of equal-length
+        // indexes, LDS walks), the general bound kernel for the rest
         dispatch_d<BoundLaunch>(P.D, ba, dist, true, s);
+        if (dist == TSK_DTW && P.env_ok && ba.dbg_lb)
+            launch_bound_lb(P.D, ba, true, s);
+        int32_t qmax = 0;
+        for (int i = 0; i < nq; ++i)
+            qmax = std::max<int32_t>(qmax, (int32_t)(q_offsets_host[q0 + i + 1] - q_offsets_host[q0 + i]));
+        const size_t qrow_bytes = (size_t)(P.D <= 4 ? 4 : 8) * sizeof(float);
+        if (ba.dbg_ub && ba.dbg_steps && (size_t)qmax * qrow_bytes <= 64 * 1024) {
+            SeedRingArgs r{q_values_dev, ix->ws.qoff.p, nq, qmax, ix->aos, ix->off, ix->len, ix->n,
+                           nullptr, 0, (int)std::min<int64_t>(ix->n, INT32_MAX), 1, P.ba,
+                           ix->ws.seedslots.p, ix->ws.tau.p, ix->ws.ctr.p, ba.dbg_ub, ba.dbg_steps};
+            launch_seed_ring(P.D, dist, r, s);
+        }
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(s));
