@@ -116,6 +116,16 @@ typedef struct {
                                       stream and add this call's counters to
                                       the index's profile, without any
                                       synchronisation (tsk_index_profile) */
+    int32_t walk_pass;             /* DK: greedy walks (Alg. 1) over the
+                                      survivors of the corner bound before
+                                      the DP: -1 auto, 0 off, 1 on */
+    int32_t task_size;             /* survivors per wave task of the sparse-DK
+                                      kernel (0 = library default) */
+    int32_t tube_rows;             /* rows per lane window of the sparse-DK
+                                      kernel: 16 or 32 (0 = library default,
+                                      16);
+                                      pairs whose live cells outgrow it finish
+                                      in the general DP */
 } tsk_query_opts;
 
 typedef struct {

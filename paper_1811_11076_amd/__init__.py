@@ -86,7 +86,8 @@ class Index:
             pass
 
     def knn(self, queries, q_offsets, k: int, distance: str = "dk", band=None, order=None,
-            seed_count: int = 0, stats: bool = False, profile: bool = False):
+            seed_count: int = 0, stats: bool = False, profile: bool = False,
+            walk_pass: int = -1, task_size: int = 0, tube_rows: int = 0):
         """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
         float32 [nq, k], stats dict or None); DK distances are unsquared."""
         torch = _torch()
@@ -99,6 +100,9 @@ class Index:
         opts.size = ctypes.sizeof(_lib.QueryOpts)
         opts.seed_count = int(seed_count)
         opts.profile = 1 if profile else 0
+        opts.walk_pass = int(walk_pass)
+        opts.task_size = int(task_size)
+        opts.tube_rows = int(tube_rows)
         if order is not None:
             if order.dtype != torch.int32 or not order.is_cuda or tuple(order.shape) != (nq, self.n):
                 raise ValueError("order must be a CUDA int32 tensor [n_queries, n_series]")

@@ -34,7 +34,9 @@ class Band(ctypes.Structure):
 class QueryOpts(ctypes.Structure):
     _fields_ = [("size", ctypes.c_int64), ("order", ctypes.c_int32), ("seed_count", ctypes.c_int32),
                 ("order_dev", ctypes.c_void_p), ("use_graph", ctypes.c_int32),
-                ("dp_kernel", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("dp_kernel", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("walk_pass", ctypes.c_int32), ("task_size", ctypes.c_int32),
+                ("tube_rows", ctypes.c_int32)]
 
 
 class IndexOpts(ctypes.Structure):

@@ -4,17 +4,6 @@
 namespace tsk {
 
 namespace {
-template <int D> void bound_dk_d(int qg, const BoundArgs &a, int maxm, hipStream_t s)
-{
-    constexpr int DP = PadDim<D>::value;
-    dim3 grid((unsigned)((a.N + 255) / 256), (unsigned)((a.nq + qg - 1) / qg));
-    const size_t lds = (size_t)qg * maxm * DP * sizeof(float);
-    if (qg == 4)
-        hipLaunchKernelGGL((k_bound_dk<D, 4>), grid, dim3(256), lds, s, a, maxm);
-    else
-        hipLaunchKernelGGL((k_bound_dk<D, 1>), grid, dim3(256), lds, s, a, maxm);
-}
-
 template <int D> void bound_lb_d(const BoundArgs &a, bool debug, hipStream_t s)
 {
     constexpr int QG = 8;
@@ -30,16 +19,23 @@ void seed_ring_d(int dist, const SeedRingArgs &r, hipStream_t s)
 {
     constexpr int DP = PadDim<D>::value;
     dim3 grid((r.S - r.P0 + 63) / 64, r.nq);
-    const size_t lds = (size_t)r.maxm * DP * sizeof(float);
+    const size_t lds = walk_lds_bytes(D, r.maxm);
     if (dist == DIST_DK)
         hipLaunchKernelGGL((k_seed_ring<D, DIST_DK>), grid, dim3(64), lds, s, r.qv, r.qoff, r.nq,
-                           r.aos, r.off, r.len, r.N, r.order, r.P0, r.S, r.k, r.ba, r.seedslots,
+                           r.aos, r.off, r.len, r.N, r.order, r.P0, r.S, r.maxm, r.k, r.ba, r.seedslots,
                            r.tau, r.ctr, r.dbg_ub, r.dbg_steps);
     else
         hipLaunchKernelGGL((k_seed_ring<D, DIST_DTW>), grid, dim3(64), lds, s, r.qv, r.qoff, r.nq,
-                           r.aos, r.off, r.len, r.N, r.order, r.P0, r.S, r.k, r.ba, r.seedslots,
+                           r.aos, r.off, r.len, r.N, r.order, r.P0, r.S, r.maxm, r.k, r.ba, r.seedslots,
                            r.tau, r.ctr, r.dbg_ub, r.dbg_steps);
 }
+template <int D> void seed_diag_d(const SeedRingArgs &r, hipStream_t s)
+{
+    dim3 grid((r.S + 63) / 64, r.nq);
+    hipLaunchKernelGGL((k_seed_diag<D>), grid, dim3(64), 0, s, r.qv, r.qoff, r.nq, r.aos, r.off,
+                       r.len, r.N, r.order, r.S, r.k, r.seedslots, r.tau, r.ctr);
+}
+
 template <int D> void corner_d(const BoundArgs &a, hipStream_t s)
 {
     constexpr int QG = 8;
@@ -51,9 +47,8 @@ template <int D>
 void walk_d(const FastArgs &a, const float *qv, unsigned long long *ubslots, int blocks, int maxm,
             hipStream_t s)
 {
-    constexpr int DP = PadDim<D>::value;
-    const size_t lds = (size_t)maxm * DP * sizeof(float);
-    hipLaunchKernelGGL((k_walk_dk<D>), dim3(blocks), dim3(64), lds, s, a, qv, ubslots);
+    const size_t lds = walk_lds_bytes(D, maxm);
+    hipLaunchKernelGGL((k_walk_dk<D>), dim3(blocks), dim3(64), lds, s, a, qv, ubslots, maxm);
 }
 } // namespace
 
@@ -70,16 +65,16 @@ void walk_d(const FastArgs &a, const float *qv, unsigned long long *ubslots, int
     default: break;                                                                                \
     }
 
-void launch_bound_dk(int D, int qg, const BoundArgs &a, int maxm, hipStream_t s)
+void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s)
 {
-#define CALL(d) bound_dk_d<d>(qg, a, maxm, s)
+#define CALL(d) bound_lb_d<d>(a, debug, s)
     TSK_SWITCH_D(D, CALL)
 #undef CALL
 }
 
-void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s)
+void launch_seed_diag(int D, const SeedRingArgs &r, hipStream_t s)
 {
-#define CALL(d) bound_lb_d<d>(a, debug, s)
+#define CALL(d) seed_diag_d<d>(r, s)
     TSK_SWITCH_D(D, CALL)
 #undef CALL
 }

@@ -4,25 +4,28 @@
 namespace tsk {
 
 namespace {
-template <int D> void tube_d(const FastArgs &a, int blocks, int maxm, hipStream_t s)
+template <int D> void tube_d(const FastArgs &a, int rows, int blocks, int maxm, hipStream_t s)
 {
     constexpr int DP = PadDim<D>::value;
     const size_t lds = (size_t)(maxm + 32) * DP * sizeof(float);
-    hipLaunchKernelGGL((k_dp_tube<D, 32>), dim3(blocks), dim3(64), lds, s, a);
+    if (rows == 16)
+        hipLaunchKernelGGL((k_dp_tube<D, 16>), dim3(blocks), dim3(64), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_dp_tube<D, 32>), dim3(blocks), dim3(64), lds, s, a);
 }
 } // namespace
 
-void launch_tube(int D, const FastArgs &a, int blocks, int maxm, hipStream_t s)
+void launch_tube(int D, const FastArgs &a, int rows, int blocks, int maxm, hipStream_t s)
 {
     switch (D) {
-    case 1: tube_d<1>(a, blocks, maxm, s); break;
-    case 2: tube_d<2>(a, blocks, maxm, s); break;
-    case 3: tube_d<3>(a, blocks, maxm, s); break;
-    case 4: tube_d<4>(a, blocks, maxm, s); break;
-    case 5: tube_d<5>(a, blocks, maxm, s); break;
-    case 6: tube_d<6>(a, blocks, maxm, s); break;
-    case 7: tube_d<7>(a, blocks, maxm, s); break;
-    case 8: tube_d<8>(a, blocks, maxm, s); break;
+    case 1: tube_d<1>(a, rows, blocks, maxm, s); break;
+    case 2: tube_d<2>(a, rows, blocks, maxm, s); break;
+    case 3: tube_d<3>(a, rows, blocks, maxm, s); break;
+    case 4: tube_d<4>(a, rows, blocks, maxm, s); break;
+    case 5: tube_d<5>(a, rows, blocks, maxm, s); break;
+    case 6: tube_d<6>(a, rows, blocks, maxm, s); break;
+    case 7: tube_d<7>(a, rows, blocks, maxm, s); break;
+    case 8: tube_d<8>(a, rows, blocks, maxm, s); break;
     default: break;
     }
 }

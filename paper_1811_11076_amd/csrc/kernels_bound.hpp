@@ -7,84 +7,112 @@
 namespace tsk {
 
 // Greedy walk of Alg. 1 (Sec. 4.1), same moves, tie order and value as
-// greedy_walk(), with the query read from LDS (row stride DP floats) and the
-// candidate streamed through a 4-point register ring so that the loads are
-// issued several moves before their use.
-template <int D, int DIST>
+// greedy_walk().  Latency layout for gfx950: the query comes from LDS (row
+// stride DP floats); the candidate goes through a lane-private LDS ring of
+// 16 points (slot = point mod 16) that always holds points [jb, jb+16) with
+// jb = 8 * floor(j / 8).  Each time j enters a new block of 8, the 8 points
+// loaded into registers one block earlier are written to the ring and the
+// next 8 are requested, so global loads are waited on once per 8 advances
+// and long after they were issued.  The points at j, j+1, j+2 (and i, i+1,
+// i+2) sit in registers, the third one read from LDS one move before use.
+// The running threshold is re-read every 8 moves and used 8 moves later.
+template <int D, int DIST, bool BANDED>
 __device__ float greedy_walk_ring(const float *qs, int m, const float *__restrict__ c, int n,
-                                  const Band &band, float eps, const uint32_t *tau, int &steps_out,
-                                  bool &completed)
+                                  float *ring, const Band &band, float eps, const uint32_t *tau,
+                                  int &steps_out, bool &completed)
 {
     constexpr int DP = PadDim<D>::value;
+    constexpr int RB = 8; // block of points
     float q0[D], q1[D], q2[D];
-    float r0[D], r1[D], r2[D], r3[D];
+    float r0[D], r1[D], r2[D];
+    float pf[RB][D];
 #pragma unroll
     for (int e = 0; e < D; ++e) {
         q0[e] = qs[e];
         q1[e] = qs[min(1, m - 1) * DP + e];
         q2[e] = qs[min(2, m - 1) * DP + e];
-        r0[e] = c[e];
-        r1[e] = c[(int64_t)min(1, n - 1) * D + e];
-        r2[e] = c[(int64_t)min(2, n - 1) * D + e];
-        r3[e] = c[(int64_t)min(3, n - 1) * D + e];
+    }
+    // ring <- points 0..15, registers <- points 16..23 (indices clamped)
+#pragma unroll
+    for (int t = 0; t < 2 * RB; ++t)
+#pragma unroll
+        for (int e = 0; e < D; ++e)
+            ring[t * DP + e] = c[(int64_t)min(t, n - 1) * D + e];
+#pragma unroll
+    for (int t = 0; t < RB; ++t)
+#pragma unroll
+        for (int e = 0; e < D; ++e)
+            pf[t][e] = c[(int64_t)min(2 * RB + t, n - 1) * D + e];
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        r0[e] = ring[0 * DP + e];
+        r1[e] = ring[1 * DP + e];
+        r2[e] = ring[2 * DP + e];
     }
     float g = point_cost<D>(q0, r0);
-    int i = 0, j = 0, steps = 0;
+    int i = 0, j = 0, jb = 0, steps = 0;
     completed = false;
     if (g > eps) {
         steps_out = 0;
         return g;
     }
+    uint32_t tau_next = tau ? load_relaxed_u32(tau) : TSK_INF_BITS;
     while (i < m - 1 || j < n - 1) {
         const bool di = i + 1 < m, dj = j + 1 < n;
-        float c_dn = tsk_inf(), c_dg = tsk_inf(), c_rt = tsk_inf();
-        if (di && band_ok(band, i + 1, j))
-            c_dn = point_cost<D>(q1, r0);
-        if (di && dj && band_ok(band, i + 1, j + 1))
-            c_dg = point_cost<D>(q1, r1);
-        if (dj && band_ok(band, i, j + 1))
-            c_rt = point_cost<D>(q0, r1);
-        int mv;
-        float cst;
-        if (c_dn <= c_dg && c_dn <= c_rt) {
-            mv = 0;
-            cst = c_dn;
-        } else if (c_dg <= c_rt) {
-            mv = 1;
-            cst = c_dg;
-        } else {
-            mv = 2;
-            cst = c_rt;
+        bool ok_dn = di, ok_dg = di && dj, ok_rt = dj;
+        if (BANDED) {
+            ok_dn = ok_dn && band_ok(band, i + 1, j);
+            ok_dg = ok_dg && band_ok(band, i + 1, j + 1);
+            ok_rt = ok_rt && band_ok(band, i, j + 1);
         }
+        const float c_dn = ok_dn ? point_cost<D>(q1, r0) : tsk_inf();
+        const float c_dg = ok_dg ? point_cost<D>(q1, r1) : tsk_inf();
+        const float c_rt = ok_rt ? point_cost<D>(q0, r1) : tsk_inf();
+        // first strict minimum in the order (i+1,j), (i+1,j+1), (i,j+1)
+        const bool pick_dn = c_dn <= c_dg && c_dn <= c_rt;
+        const bool pick_dg = !pick_dn && c_dg <= c_rt;
+        const float cst = pick_dn ? c_dn : (pick_dg ? c_dg : c_rt);
         ++steps;
         if (cst == tsk_inf()) {
             steps_out = steps;
             return tsk_inf();
         }
         g = DIST == DIST_DK ? fmaxf(g, cst) : cst + g;
-        if (mv != 2) {
-            ++i;
-            const int ni = min(i + 2, m - 1);
+        const bool adv_i = pick_dn || pick_dg;
+        const bool adv_j = !pick_dn;
+        i += adv_i ? 1 : 0;
+        j += adv_j ? 1 : 0;
+        if (j >= jb + RB) {
+            // points jb+16 .. jb+23 replace jb .. jb+7 in the ring
+            jb += RB;
 #pragma unroll
-            for (int e = 0; e < D; ++e) {
-                q0[e] = q1[e];
-                q1[e] = q2[e];
-                q2[e] = qs[ni * DP + e];
-            }
-        }
-        if (mv != 0) {
-            ++j;
-            const int64_t nj = min(j + 3, n - 1);
+            for (int t = 0; t < RB; ++t)
 #pragma unroll
-            for (int e = 0; e < D; ++e) {
-                r0[e] = r1[e];
-                r1[e] = r2[e];
-                r2[e] = r3[e];
-                r3[e] = c[nj * D + e];
-            }
+                for (int e = 0; e < D; ++e)
+                    ring[((jb + RB + t) & (2 * RB - 1)) * DP + e] = pf[t][e];
+#pragma unroll
+            for (int t = 0; t < RB; ++t)
+#pragma unroll
+                for (int e = 0; e < D; ++e)
+                    pf[t][e] = c[(int64_t)min(jb + 2 * RB + t, n - 1) * D + e];
         }
-        if (tau && (steps & 7) == 0)
-            eps = fminf(eps, bits_f(load_relaxed_u32(tau)));
+        const int ni = min(i + 2, m - 1);
+        const int nj = min(j + 2, n - 1) & (2 * RB - 1);
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            const float qn = qs[ni * DP + e];
+            const float rn = ring[nj * DP + e];
+            q0[e] = adv_i ? q1[e] : q0[e];
+            q1[e] = adv_i ? q2[e] : q1[e];
+            q2[e] = adv_i ? qn : q2[e];
+            r0[e] = adv_j ? r1[e] : r0[e];
+            r1[e] = adv_j ? r2[e] : r1[e];
+            r2[e] = adv_j ? rn : r2[e];
+        }
+        if (tau && (steps & 7) == 0) {
+            eps = fminf(eps, bits_f(tau_next));
+            tau_next = load_relaxed_u32(tau);
+        }
         if (g > eps) {
             steps_out = steps;
             return g;
@@ -93,6 +121,19 @@ __device__ float greedy_walk_ring(const float *qs, int m, const float *__restric
     steps_out = steps;
     completed = true;
     return g;
+}
+
+// The walk with the band test only where a band exists.
+template <int D, int DIST>
+__device__ float greedy_walk_lds(const float *qs, int m, const float *__restrict__ c, int n,
+                                 float *ring, const Band &band, float eps, const uint32_t *tau,
+                                 int &steps_out, bool &completed)
+{
+    if (band.all)
+        return greedy_walk_ring<D, DIST, false>(qs, m, c, n, ring, band, eps, tau, steps_out,
+                                                completed);
+    return greedy_walk_ring<D, DIST, true>(qs, m, c, n, ring, band, eps, tau, steps_out,
+                                           completed);
 }
 
 // Inserts the lanes' keys that can still matter into a query's top-k slots.
@@ -121,79 +162,6 @@ __device__ __forceinline__ void wave_topk_insert(unsigned long long *slots, int 
         topk_insert(slots, k, key);
         tau_from_slots(slots, k, tau);
     }
-}
-
-// DK bound pass: corner bound for every pair, then the greedy walk for the
-// pairs it does not prune (Sec. 4.4's first loop, with early return at the
-// running threshold).  Block: 256 candidates x a group of QG queries staged
-// in LDS.
-template <int D, int QG>
-__global__ __launch_bounds__(256) void k_bound_dk(BoundArgs a, int maxm)
-{
-    constexpr int DP = PadDim<D>::value;
-    extern __shared__ float qs[];
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int q0 = blockIdx.y * QG;
-    const int nqg = min(QG, a.nq - q0);
-    // stage the group's queries: qs[g][row][DP]
-    for (int g = 0; g < nqg; ++g) {
-        const int q = q0 + g;
-        const int m = (int)(a.qoff[q + 1] - a.qoff[q]);
-        const float *src = a.qv + a.qoff[q] * D;
-        for (int t = threadIdx.x; t < m * DP; t += blockDim.x) {
-            const int row = t / DP, e = t % DP;
-            qs[(g * maxm + row) * DP + e] = e < D ? src[row * D + e] : 0.0f;
-        }
-    }
-    __syncthreads();
-    const bool valid = c < a.N;
-    const int64_t tile = c >> 6;
-    const int lane = (int)(c & 63);
-    const int n = valid ? a.len[c] : 1;
-    const float *tb = valid ? a.soa + a.tile_off[tile] + lane : a.soa;
-    const float *cp = a.aos + a.off[valid ? c : 0] * D;
-    float c0[D], cl[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        c0[k] = valid ? tb[(0 * D + k) * 64] : 0.0f;
-        cl[k] = valid ? tb[((int64_t)(n - 1) * D + k) * 64] : 0.0f;
-    }
-    unsigned long long pruned = 0, steps_cnt = 0, pairs = 0;
-    for (int g = 0; g < nqg; ++g) {
-        const int q = q0 + g;
-        const int m = (int)(a.qoff[q + 1] - a.qoff[q]);
-        const float *Q = qs + g * maxm * DP;
-        float qa[D], qz[D];
-#pragma unroll
-        for (int e = 0; e < D; ++e) {
-            qa[e] = Q[e];
-            qz[e] = Q[(m - 1) * DP + e];
-        }
-        const float lb = fmaxf(point_cost<D>(qa, c0), point_cost<D>(qz, cl));
-        float tq = bits_f(load_relaxed_u32(a.tau + q));
-        bool want = false;
-        float gval = tsk_inf();
-        if (valid && lb <= tq) {
-            const Band b = pair_band(a.ba, m, n);
-            int steps;
-            bool done;
-            gval = greedy_walk_ring<D, DIST_DK>(Q, m, cp, n, b, tq, a.tau + q, steps, done);
-            steps_cnt += steps;
-            want = done && gval != tsk_inf() && gval <= bits_f(load_relaxed_u32(a.tau + q));
-        }
-        wave_topk_insert(a.ubslots + (int64_t)q * a.k, a.k, want, make_key(gval, (uint32_t)c),
-                         a.tau + q);
-        if (valid) {
-            ++pairs;
-            tq = bits_f(load_relaxed_u32(a.tau + q));
-            const bool keep = lb <= tq;
-            a.lbv[(int64_t)q * a.N + c] = keep ? lb : tsk_inf();
-            pruned += keep ? 0 : 1;
-        }
-    }
-    wave_count(a.ctr + C_BOUND_PRUNED, pruned);
-    wave_count(a.ctr + C_PAIRS, pairs);
-    wave_count(a.ctr + C_BOUND_STEPS, steps_cnt);
 }
 
 // DTW bound pass for an index of equal-length series: LB_Box of every
@@ -316,10 +284,12 @@ __global__ __launch_bounds__(256) void k_corner(BoundArgs a)
 // threshold through the query's upper-bound slots.
 template <int D>
 __global__ __launch_bounds__(64) void k_walk_dk(FastArgs a, const float *__restrict__ qv,
-                                                 unsigned long long *ubslots)
+                                                 unsigned long long *ubslots, int maxm)
 {
     constexpr int DP = PadDim<D>::value;
     extern __shared__ float qs[];
+    // LDS: the query (maxm rows), then one 16-point candidate ring per lane
+    float *ring = qs + maxm * DP + threadIdx.x * 16 * DP;
     unsigned long long steps_cnt = 0, late = 0;
     const int64_t total = (int64_t)a.nq * ((*a.max_cnt + 63) / 64);
     int staged = -1;
@@ -344,8 +314,8 @@ __global__ __launch_bounds__(64) void k_walk_dk(FastArgs a, const float *__restr
             int steps;
             bool done;
             const float tq = bits_f(load_relaxed_u32(a.tau + q));
-            g = greedy_walk_ring<D, DIST_DK>(qs, m, a.aos + a.off[ch.c] * D, n, b, tq, a.tau + q,
-                                             steps, done);
+            g = greedy_walk_lds<D, DIST_DK>(qs, m, a.aos + a.off[ch.c] * D, n, ring, b, tq,
+                                             a.tau + q, steps, done);
             steps_cnt += steps;
             want = done && g != tsk_inf() && g <= bits_f(load_relaxed_u32(a.tau + q));
         }
@@ -353,6 +323,48 @@ __global__ __launch_bounds__(64) void k_walk_dk(FastArgs a, const float *__restr
                          make_key(g, (uint32_t)(ch.act ? ch.c : 0)), a.tau + q);
     }
     wave_count(a.ctr + C_BOUND_STEPS, steps_cnt);
+}
+
+// DTW threshold seed for equal lengths: the diagonal path (i, i) is a
+// warping path inside every band, and with monotone rounding its fp32 sum in
+// path order is >= the fp32 DTW, so the k-th smallest diagonal sum over the
+// first S candidates of each query bounds the k-th smallest DTW from above.
+// No sequential walk: one lane per candidate, query rows wave-uniform
+// (scalar loads), candidate rows per lane.  Candidates whose length differs
+// from the query's are skipped.
+template <int D>
+__global__ __launch_bounds__(64) void k_seed_diag(const float *__restrict__ qv,
+                                                  const int64_t *__restrict__ qoff, int nq,
+                                                  const float *__restrict__ aos,
+                                                  const int64_t *__restrict__ off,
+                                                  const int32_t *__restrict__ len, int64_t N,
+                                                  const int32_t *__restrict__ order, int S, int k,
+                                                  unsigned long long *seedslots, uint32_t *tau,
+                                                  unsigned long long *ctr)
+{
+    const int q = blockIdx.y;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t o0 = qoff[q];
+    const int m = (int)(qoff[q + 1] - o0);
+    cfloat *Q = (cfloat *)qv + o0 * D;
+    int c = 0;
+    bool ok = false;
+    if (p < S) {
+        c = order ? order[(int64_t)q * N + p] : p;
+        ok = len[c] == m;
+    }
+    const float *cp = aos + off[ok ? c : 0] * D;
+    float ub = 0.0f;
+    for (int i = 0; i < m; ++i) {
+        float qq[D], cc[D];
+#pragma unroll
+        for (int e = 0; e < D; ++e)
+            qq[e] = Q[(int64_t)i * D + e];
+        load_point<D>(cp + (int64_t)(ok ? i : 0) * D, cc);
+        ub = point_cost<D>(qq, cc) + ub;
+    }
+    wave_topk_insert(seedslots + (int64_t)q * k, k, ok, make_key(ub, (uint32_t)c), tau + q);
+    wave_count(ctr + C_SEED_PAIRS, ok ? 1ull : 0ull);
 }
 
 // Threshold seed with the LDS query and the prefetching walk (see k_seed).
@@ -363,18 +375,20 @@ __global__ __launch_bounds__(64) void k_seed_ring(const float *__restrict__ qv,
                                                   const int64_t *__restrict__ off,
                                                   const int32_t *__restrict__ len, int64_t N,
                                                   const int32_t *__restrict__ order, int P0, int S,
-                                                  int k, BandArgs ba, unsigned long long *seedslots,
+                                                  int maxm, int k, BandArgs ba,
+                                                  unsigned long long *seedslots,
                                                   uint32_t *tau, unsigned long long *ctr,
                                                   float *dbg_ub, int32_t *dbg_steps)
 {
-    // Candidates P0..S-1 of the query's order.  P0 == 0: full walks (no
-    // threshold yet); P0 > 0: early return at the running threshold set by
-    // the first part.  dbg_ub != null: write every walk's value and move
-    // count ([q][p]) and insert nothing (tsk_pair_bounds).
+    // Candidates P0..S-1 of the query's order.  dbg_ub != null: write every
+    // walk's value and move count ([q][p]) and insert nothing
+    // (tsk_pair_bounds).
     constexpr int DP = PadDim<D>::value;
     extern __shared__ float qs[];
     const int q = blockIdx.y;
     const int m = (int)(qoff[q + 1] - qoff[q]);
+    // LDS: the query (maxm rows), then one 16-point candidate ring per lane
+    float *ring = qs + maxm * DP + threadIdx.x * 16 * DP;
     const float *src = qv + qoff[q] * D;
     for (int t = threadIdx.x; t < m * DP; t += blockDim.x) {
         const int row = t / DP, e = t % DP;
@@ -392,10 +406,12 @@ __global__ __launch_bounds__(64) void k_seed_ring(const float *__restrict__ qv,
         const Band b = pair_band(ba, m, n);
         int steps;
         bool done;
-        const bool early = P0 > 0 && !dbg_ub;
+        // walks of the first 64 candidates are complete; the others return
+        // early against the threshold those set
+        const bool early = p >= 64 && !dbg_ub;
         const float eps = early ? bits_f(load_relaxed_u32(tau + q)) : tsk_inf();
-        g = greedy_walk_ring<D, DIST>(qs, m, aos + off[c] * D, n, b, eps, early ? tau + q : nullptr,
-                                      steps, done);
+        g = greedy_walk_lds<D, DIST>(qs, m, aos + off[c] * D, n, ring, b, eps,
+                                      early ? tau + q : nullptr, steps, done);
         want = done && g != tsk_inf() && g <= bits_f(load_relaxed_u32(tau + q));
         steps_cnt = steps;
         pairs = 1;

@@ -41,6 +41,7 @@ struct FastArgs {
     int2 *fb;                 // fallback (query, candidate) list
     const float *qpad;        // [nq][qrows][DP]: query rows at QPAD.., +inf around
     int qrows;
+    int task;                 // survivors per wave task (k_dp_tube)
     unsigned long long *ctr;
 };
 
@@ -279,15 +280,18 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
 // ------------------------------------------------------------------ sparse DK tube
 // Unbanded DK with the sparse-DK semantics of Alg. 3 (Sec. 4.2): a cell above
 // tau is dead (+inf), and a pair with no live cell left in a column is > tau.
-// Each lane keeps a window of W consecutive rows [lo, lo+W) of the current
+// Each lane keeps a window of W consecutive rows [lo, lo+W) of its current
 // column.  Cells below lo are dead (nothing below a dead prefix can come
 // back: every predecessor is lower or to the left), so after each column lo
 // moves up past up to two leading dead slots.  Cells above the window are
 // reached only through the window's top slot (same column, or the previous
 // column's top when lo did not move), so as long as the top slot stays dead
 // the window holds every live cell and the result is exact; a live top slot
-// sends the pair to the general DP.  Query rows come from LDS (per lane
-// addresses), the candidate point is per lane.
+// sends the pair to the general DP.
+// A wave takes a chunk of up to a.task survivors of one query (query rows in
+// LDS).  Lanes advance independently, each on its own pair and column; a
+// lane whose pair ends takes the chunk's next survivor, so the wave stays
+// busy until the chunk drains.
 template <int D, int W>
 __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
 {
@@ -295,42 +299,76 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
     extern __shared__ float qs[];
     unsigned long long started = 0, completed = 0, abandoned = 0, late = 0, fallback = 0;
     unsigned long long cells = 0, valid = 0;
-    const int64_t total = (int64_t)a.nq * ((*a.max_cnt + 63) / 64);
+    const int T = a.task;
+    const int64_t total = (int64_t)a.nq * ((*a.max_cnt + T - 1) / T);
+    const int lane = threadIdx.x;
     int staged = -1;
-    Chunk ch;
-    while (next_chunk(a, total, ch, late)) {
-        const int q = ch.q, m = ch.m;
+    for (;;) {
+        unsigned long long t = 0;
+        if (lane == 0)
+            t = atomicAdd(a.work, 1ull);
+        t = uniform_u64(t);
+        if (t >= (unsigned long long)total)
+            break;
+        const int q = uniform_i((int)(t % (unsigned long long)a.nq));
+        const int base = (int)(t / (unsigned long long)a.nq) * T;
+        const int cnt = a.surv_cnt[q];
+        if (base >= cnt)
+            continue;
+        const int end = uniform_i(min(base + T, cnt));
+        const int m = uniform_i((int)(a.qoff[q + 1] - a.qoff[q]));
         if (q != staged) {
             // query rows 0 .. m-1+W (those past m-1 are +inf)
             __syncthreads();
-            const float4 *src = reinterpret_cast<const float4 *>(a.qpad + ((int64_t)q * a.qrows + QPAD) * DP);
+            const float4 *src =
+                reinterpret_cast<const float4 *>(a.qpad + ((int64_t)q * a.qrows + QPAD) * DP);
             float4 *dst = reinterpret_cast<float4 *>(qs);
             const int n4 = (m + W) * DP / 4;
-            for (int i = threadIdx.x; i < n4; i += 64)
+            for (int i = lane; i < n4; i += 64)
                 dst[i] = src[i];
             __syncthreads();
             staged = q;
         }
-        const bool act = ch.act;
-        const int n = act ? a.len[ch.c] : 1;
-        started += act ? 1 : 0;
-        const float *cp = a.aos + a.off[act ? ch.c : 0] * D;
-        int nmax = n;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
-            nmax = max(nmax, __shfl_xor(nmax, o, 64));
+        float tau = bits_f(load_relaxed_u32(a.tau + q));
+        int next = base;
+        bool running = false;
+        int c = 0, n = 1, j = 0, lo = 0;
+        const float *cp = a.aos;
         float Dv[W];
 #pragma unroll
         for (int k = 0; k < W; ++k)
             Dv[k] = tsk_inf();
-        int lo = 0;
-        bool running = act, over = false;
-        float res = tsk_inf();
-        float tau = bits_f(load_relaxed_u32(a.tau + q));
-        for (int j = 0; j < nmax; ++j) {
-            if (__ballot(running) == 0ull)
-                break;
-            if ((j & 7) == 0)
+        for (int it = 0;; ++it) {
+            // idle lanes take the chunk's next survivors
+            const unsigned long long need = __ballot(!running);
+            if (need != 0ull && next < end) {
+                const int rank = __popcll(need & ((1ull << lane) - 1ull));
+                const int idx = next + rank;
+                if (!running && idx < end) {
+                    const int cc = a.surv[(int64_t)q * a.N + idx];
+                    if (a.lbv[(int64_t)q * a.N + cc] > tau) {
+                        ++late;
+                    } else {
+                        c = cc;
+                        n = a.len[c];
+                        cp = a.aos + a.off[c] * D;
+                        j = 0;
+                        lo = 0;
+#pragma unroll
+                        for (int k = 0; k < W; ++k)
+                            Dv[k] = tsk_inf();
+                        running = true;
+                        ++started;
+                    }
+                }
+                next = uniform_i(min(end, next + (int)__popcll(need)));
+            }
+            if (__ballot(running) == 0ull) {
+                if (next >= end)
+                    break;
+                continue;
+            }
+            if ((it & 7) == 0)
                 tau = bits_f(load_relaxed_u32(a.tau + q));
             float cv[D];
             load_point<D>(cp + (int64_t)min(j, n - 1) * D, cv);
@@ -358,37 +396,34 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
             if (running) {
                 if (j == n - 1) {
                     const int slot = m - 1 - lo;
+                    float res = tsk_inf();
 #pragma unroll
                     for (int k = 0; k < W; ++k)
                         res = (k == slot) ? Dv[k] : res;
+                    if (res == tsk_inf())
+                        ++abandoned;
+                    finish_lane(a, q, c, res, completed);
                     running = false;
                 } else if (!any) {
+                    ++abandoned;
                     running = false;
                 } else if (Dv[W - 1] != tsk_inf()) {
-                    over = true;
+                    push_fallback(a, q, c);
+                    ++fallback;
                     running = false;
                 }
             }
-            // drop up to two leading dead slots (finished lanes keep lo)
-            int s = Dv[0] != tsk_inf() ? 0 : (Dv[1] != tsk_inf() ? 1 : 2);
-            s = running ? s : 0;
+            // drop up to two leading dead slots (idle lanes keep lo)
+            int sh = Dv[0] != tsk_inf() ? 0 : (Dv[1] != tsk_inf() ? 1 : 2);
+            sh = running ? sh : 0;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 const float d1 = (k + 1 < W) ? Dv[k + 1] : tsk_inf();
                 const float d2 = (k + 2 < W) ? Dv[k + 2] : tsk_inf();
-                Dv[k] = s == 0 ? Dv[k] : (s == 1 ? d1 : d2);
+                Dv[k] = sh == 0 ? Dv[k] : (sh == 1 ? d1 : d2);
             }
-            lo += s;
-        }
-        if (act) {
-            if (over) {
-                push_fallback(a, q, ch.c);
-                ++fallback;
-            } else {
-                if (res == tsk_inf())
-                    ++abandoned;
-                finish_lane(a, q, ch.c, res, completed);
-            }
+            lo += sh;
+            j += running ? 1 : 0;
         }
     }
     wave_count(a.ctr + C_DP_STARTED, started);

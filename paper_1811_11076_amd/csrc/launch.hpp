@@ -31,14 +31,22 @@ struct SeedRingArgs {
     int32_t *dbg_steps; // debug: per-pair move count
 };
 
-void launch_bound_dk(int D, int qg, const BoundArgs &a, int maxm, hipStream_t s);
+// LDS of the 64-lane greedy-walk kernels: the query, then a 16-point ring
+// per lane.
+inline size_t walk_lds_bytes(int D, int maxm)
+{
+    const int DP = D <= 4 ? 4 : 8;
+    return (size_t)(maxm + 64 * 16) * DP * sizeof(float);
+}
+
 void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s);
 void launch_seed_ring(int D, int dist, const SeedRingArgs &r, hipStream_t s);
 void launch_corner(int D, const BoundArgs &a, hipStream_t s);
+void launch_seed_diag(int D, const SeedRingArgs &r, hipStream_t s);
 void launch_walk_dk(int D, const FastArgs &a, const float *qv, unsigned long long *ubslots,
                     int blocks, int maxm, hipStream_t s);
 void launch_band(int D, int dist, int wsel, const FastArgs &a, int blocks, hipStream_t s);
-void launch_tube(int D, const FastArgs &a, int blocks, int maxm, hipStream_t s);
+void launch_tube(int D, const FastArgs &a, int rows, int blocks, int maxm, hipStream_t s);
 void launch_dp_wave(int D, int dist, int mode, const DpArgs &a, int blocks, hipStream_t s);
 
 } // namespace tsk

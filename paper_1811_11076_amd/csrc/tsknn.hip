@@ -549,6 +549,7 @@ static FastArgs fast_args(tsk_index *ix, int nq, const QueryPlan &P, int qrows)
     a.fb = ix->ws.fb.p;
     a.qpad = ix->ws.qpad.p;
     a.qrows = qrows;
+    a.task = 64;
     a.ctr = ix->ws.ctr.p;
     return a;
 }
@@ -665,6 +666,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "output pointers are NULL");
     tsk_query_opts o;
     memset(&o, 0, sizeof(o));
+    o.walk_pass = -1;
     if (opts) {
         if (opts->size != (int64_t)sizeof(tsk_query_opts))
             return set_err(TSK_ERR_INVALID_ARG, "opts->size mismatch");
@@ -676,6 +678,12 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "TSK_ORDER_GIVEN needs order_dev");
     if (o.seed_count < 0)
         return set_err(TSK_ERR_INVALID_ARG, "seed_count must be >= 0");
+    if (o.walk_pass < -1 || o.walk_pass > 1)
+        return set_err(TSK_ERR_INVALID_ARG, "walk_pass must be -1, 0 or 1");
+    if (o.task_size < 0 || o.task_size > (1 << 20))
+        return set_err(TSK_ERR_INVALID_ARG, "task_size out of range");
+    if (o.tube_rows != 0 && o.tube_rows != 16 && o.tube_rows != 32)
+        return set_err(TSK_ERR_INVALID_ARG, "tube_rows must be 0, 16 or 32");
     tsk_index *ix = const_cast<tsk_index *>(cix);
     std::lock_guard<std::mutex> lock(ix->mu);
     hipStream_t s = (hipStream_t)hip_stream;
@@ -688,7 +696,10 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
     P.nq = n_queries;
     P.N = ix->n;
     P.chunk = chunk_queries(ix, n_queries);
-    const int default_seed = 1024;
+    // seed sizes: the greedy DK seed is a latency-bound walk (a few hundred
+    // candidates give a tight threshold); the diagonal DTW seed is a cheap
+    // parallel sum, so it takes more candidates
+    const int default_seed = dist == TSK_DK ? 512 : 1024;
     P.seed = (int)std::min<int64_t>(ix->n, o.seed_count > 0 ? o.seed_count : default_seed);
     P.env_ok = (dist == TSK_DTW) && ix->min_len == ix->max_len;
 
@@ -728,19 +739,19 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         const size_t lds_cap = 64 * 1024;
         if (P.env_ok)
             dispatch_d<EnvLaunch>(P.D, ix, qv, nq, P.ba, s);
-        const bool lds_query = (size_t)qmax * qrow_bytes <= lds_cap && o.dp_kernel != 1;
-        if (P.seed > 0 && lds_query) {
-            // a first slice of full walks sets a threshold; the rest of the
-            // seed set returns early against it
-            const int s1 = std::min(P.seed, 64);
-            SeedRingArgs r{qv, W.qoff.p, nq, qmax, ix->aos, ix->off, ix->len, ix->n, order,
-                           0, s1, k, P.ba, W.seedslots.p, W.tau.p, W.ctr.p, nullptr, nullptr};
-            launch_seed_ring(P.D, dist, r, s);
-            if (P.seed > s1) {
-                r.P0 = s1;
-                r.S = P.seed;
-                launch_seed_ring(P.D, dist, r, s);
-            }
+        const bool lds_query = walk_lds_bytes(P.D, qmax) <= lds_cap && o.dp_kernel != 1;
+        (void)qrow_bytes;
+        SeedRingArgs seed_args{qv, W.qoff.p, nq, qmax, ix->aos, ix->off, ix->len, ix->n, order,
+                               0, P.seed, k, P.ba, W.seedslots.p, W.tau.p, W.ctr.p, nullptr,
+                               nullptr};
+        if (P.seed > 0 && dist == TSK_DTW && qmin == qmax && ix->min_len == ix->max_len &&
+            ix->min_len == qmin && o.dp_kernel != 1) {
+            // equal lengths: diagonal-path sums seed the DTW threshold
+            launch_seed_diag(P.D, seed_args, s);
+        } else if (P.seed > 0 && lds_query) {
+            // the first 64 candidates walk to the end and set a threshold;
+            // the rest of the seed set returns early against it
+            launch_seed_ring(P.D, dist, seed_args, s);
         } else {
             dispatch_d<SeedLaunch>(P.D, ix, qv, nq, P, order, s);
         }
@@ -756,7 +767,10 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
         hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, order, W.tau.p,
                            W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
-        if (dk_split) {
+        // the greedy pass over the corner survivors costs more than the DP
+        // work its tighter threshold saves on the class-warp workloads, so
+        // it runs only on request
+        if (dk_split && o.walk_pass == 1) {
             // greedy bound (Alg. 1) of every survivor of the corner bound
             FastArgs wa = fast_args(ix, nq, P, 0);
             wa.work = W.work.p + 4;
@@ -773,8 +787,12 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             TSK_TRY(W.qpad.ensure((size_t)nq * qrows * DP));
             dispatch_d<QpadLaunch>(P.D, qv, W.qoff.p, nq, qrows, W.qpad.p, s);
             FastArgs fa = fast_args(ix, nq, P, qrows);
-            if (fast == FAST_TUBE32)
-                launch_tube(P.D, fa, ix->n_cu * 8, qmax, s);
+            if (fast == FAST_TUBE32) {
+                fa.task = o.task_size > 0 ? o.task_size : 64;
+                // 16-row windows: the live tube of near neighbours is a few
+                // rows wide; the rare wider ones finish in the general DP
+                launch_tube(P.D, fa, o.tube_rows == 32 ? 32 : 16, ix->n_cu * 8, qmax, s);
+            }
             else
                 launch_band(P.D, dist, wsel, fa, ix->n_cu * 8, s);
             da.work = W.work.p + 2;
@@ -921,8 +939,7 @@ extern "C" int tsk_pair_bounds(const tsk_index *cix, const float *q_values_dev,
         int32_t qmax = 0;
         for (int i = 0; i < nq; ++i)
             qmax = std::max<int32_t>(qmax, (int32_t)(q_offsets_host[q0 + i + 1] - q_offsets_host[q0 + i]));
-        const size_t qrow_bytes = (size_t)(P.D <= 4 ? 4 : 8) * sizeof(float);
-        if (ba.dbg_ub && ba.dbg_steps && (size_t)qmax * qrow_bytes <= 64 * 1024) {
+        if (ba.dbg_ub && ba.dbg_steps && walk_lds_bytes(P.D, qmax) <= 64 * 1024) {
             SeedRingArgs r{q_values_dev, ix->ws.qoff.p, nq, qmax, ix->aos, ix->off, ix->len, ix->n,
                            nullptr, 0, (int)std::min<int64_t>(ix->n, INT32_MAX), 1, P.ba,
                            ix->ws.seedslots.p, ix->ws.tau.p, ix->ws.ctr.p, ba.dbg_ub, ba.dbg_steps};

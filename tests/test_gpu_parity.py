@@ -181,27 +181,42 @@ def test_knn_band_kernel_widths(w):
     idx.close()
 
 
-def test_knn_tube_overflow_goes_to_general_dp():
+@pytest.mark.parametrize("rows", [16, 32])
+def test_knn_tube_overflow_goes_to_general_dp(rows):
     """k = N keeps every DK cell alive, so every tube outgrows its window and
     the pair is finished by the general DP; results stay exact."""
-    print("[case] knn tube overflow", flush=True)
+    print(f"[case] knn tube overflow rows={rows}", flush=True)
     db, dbo = ragged_walks(51, 40, (60, 90), 2)
     qs, qo = ragged_walks(52, 2, (60, 90), 2)
     idx = _index(db, dbo)
     ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 40, "dk", None)
-    ids, dst, st = idx.knn(to_dev(qs), qo, 40, "dk", None, stats=True)
+    ids, dst, st = idx.knn(to_dev(qs), qo, 40, "dk", None, stats=True, tube_rows=rows)
     assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
     assert st["fallback_pairs"] > 0
-    # short queries fit the window: no fallback
-    db2, dbo2 = ragged_walks(53, 40, (10, 30), 2)
-    qs2, qo2 = ragged_walks(54, 2, (10, 30), 2)
+    # queries no taller than the window never overflow it
+    db2, dbo2 = ragged_walks(53, 40, (5, 40), 2)
+    qs2, qo2 = ragged_walks(54, 2, (5, rows), 2)
     idx2 = _index(db2, dbo2)
     ref_ids, ref_keys = O.knn_brute(db2, dbo2, qs2, qo2, 40, "dk", None)
-    ids, dst, st = idx2.knn(to_dev(qs2), qo2, 40, "dk", None, stats=True)
+    ids, dst, st = idx2.knn(to_dev(qs2), qo2, 40, "dk", None, stats=True, tube_rows=rows)
     assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
     assert st["fallback_pairs"] == 0
     idx.close()
     idx2.close()
+
+
+@pytest.mark.parametrize("walk,task,seed", [(1, 128, 64), (0, 32, 0), (1, 256, 3000)])
+def test_knn_dk_pipeline_options(walk, task, seed):
+    """The DK bound-stage options (greedy pass over survivors, task size,
+    seed size) change work, never results."""
+    print(f"[case] knn dk options walk={walk} task={task} seed={seed}", flush=True)
+    db, dbo, qs, qo = classwarp(2, 10, 256, 3, 2000, 5)
+    idx = _index(db, dbo)
+    ref_ids, ref_keys, _ = O.knn_scan(db, dbo, qs, qo, 10, "dk", None)
+    ids, dst, _ = idx.knn(to_dev(qs), qo, 10, "dk", None, walk_pass=walk, task_size=task,
+                          seed_count=seed)
+    assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
+    idx.close()
 
 
 def test_knn_general_dp_forced_equals_fast():
