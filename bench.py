@@ -41,6 +41,29 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_BPS = 8.0e12
 
 
+def load_traffic(kernel, workload):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's reading), or
+    None if there is none for this kernel and workload or the kernel sources
+    changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    rec = data.get(f"{kernel}|{workload}")
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for name in rec["sources"]:
+        with open(os.path.join(ROOT, name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def make_data(w):
     from paper_1811_11076_amd import synth
     if w["gen"] == "randomwalk":
@@ -53,21 +76,33 @@ def make_data(w):
     return db, dbo, qs, qo
 
 
-def stage_roofline(prof, dist, d):
-    """Algorithmic work and rate of each stage of one distance's profile."""
+def kernel_rooflines(prof, dist, d, fast_kernel):
+    """Per-kernel device time (HIP events around each kernel on its launch
+    stream, averaged per call) and algorithmic work of one distance's
+    profile.  Work units: DP = in-band in-matrix cells of live pairs, 2d+2
+    ops each; LB_Box = terms, 4d+1 ops each; corner bound = 2 point costs per
+    pair (4d+1 ops); greedy seed = moves (~6d+4 ops)."""
     calls = max(1, prof["calls"])
-    out = {}
-    # DP: valid (in-matrix, in-band) cells x (d subs + d mul/fma + min3 + add/max)
-    ops = prof["dp_valid_cells"] * (2 * d + 2)
-    out["dp"] = dict(ms=prof["ms_dp"] / calls, ops=ops / calls, unit_ops=2 * d + 2,
-                     units=prof["dp_valid_cells"] / calls)
-    # bound pass: LB_Box terms (4d + 1 ops each) or greedy moves (3 costs ~ 6d, + 4)
-    per = (4 * d + 1) if dist == "dtw" else (6 * d + 4)
-    out["bound"] = dict(ms=(prof["ms_seed"] + prof["ms_bound"]) / calls,
-                        ops=prof["bound_steps"] * per / calls, unit_ops=per,
-                        units=prof["bound_steps"] / calls)
+    cell_ops = 2 * d + 2
+    fast_cells = prof["dp_valid_cells"] - prof["dp_valid_cells_general"]
+    out = {
+        fast_kernel: dict(ms=prof["ms_dp_fast"] / calls, units=fast_cells / calls,
+                          unit_ops=cell_ops),
+        "k_dp_wave": dict(ms=prof["ms_dp_general"] / calls,
+                          units=prof["dp_valid_cells_general"] / calls, unit_ops=cell_ops),
+    }
+    if dist == "dtw":
+        out["k_bound_lb"] = dict(ms=prof["ms_bound_kernel"] / calls,
+                                 units=prof["bound_steps"] / calls, unit_ops=4 * d + 1)
+        out["k_seed_diag"] = dict(ms=prof["ms_seed"] / calls, units=0, unit_ops=0)
+    else:
+        out["k_corner"] = dict(ms=prof["ms_bound_kernel"] / calls, units=prof["pairs"] / calls,
+                               unit_ops=4 * d + 1)
+        out["k_seed_ring"] = dict(ms=prof["ms_seed"] / calls, units=prof["bound_steps"] / calls,
+                                  unit_ops=6 * d + 4)
     for v in out.values():
-        v["achieved_ops"] = v["ops"] / (v["ms"] * 1e-3) if v["ms"] > 0 else 0.0
+        v["ops"] = v["units"] * v["unit_ops"]
+        v["tops"] = v["ops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0
     return out
 
 
@@ -98,7 +133,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-queries", type=int, default=16)
+    ap.add_argument("--cpu-queries", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -147,15 +182,15 @@ def main():
     dk_ms = prof_dk["ms_total"] / max(1, prof_dk["calls"])
     dtw_ms = prof_dtw["ms_total"] / max(1, prof_dtw["calls"])
 
-    stages = {"dk": stage_roofline(prof_dk, "dk", w["d"]),
-              "dtw": stage_roofline(prof_dtw, "dtw", w["d"])}
-    dist_dom, stage_dom = max(((dd, ss) for dd in stages for ss in stages[dd]),
-                              key=lambda x: stages[x[0]][x[1]]["ms"])
-    dom = stages[dist_dom][stage_dom]
-    kernel = {"dp": "k_dp_wave", "bound": "k_seed+k_bounds+k_compact"}[stage_dom]
-    roof = {"bound": "alu", "kernel": f"{kernel} ({dist_dom})",
-            "achieved": dom["achieved_ops"] / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-            "unit": "TOP/s", "frac": dom["achieved_ops"] / VALU_PEAK_OPS, "traffic": None,
+    kern = {"dk": kernel_rooflines(prof_dk, "dk", w["d"], "k_dp_tube"),
+            "dtw": kernel_rooflines(prof_dtw, "dtw", w["d"], "k_dp_band")}
+    dist_dom, kname = max(((dd, kk) for dd in kern for kk in kern[dd]),
+                          key=lambda x: kern[x[0]][x[1]]["ms"])
+    dom = kern[dist_dom][kname]
+    roof = {"bound": "alu", "kernel": f"{kname} ({dist_dom})",
+            "achieved": dom["tops"], "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+            "frac": dom["tops"] * 1e12 / VALU_PEAK_OPS,
+            "traffic": load_traffic(kname, args.workload),
             "ms_per_launch": dom["ms"], "algorithmic_ops_per_launch": dom["ops"],
             "per_unit_ops": dom["unit_ops"], "units_per_launch": dom["units"]}
 
@@ -168,11 +203,13 @@ def main():
                    "dtw_band": w["dtw_band"], "order": "plain"},
         "roofline": roof,
         "dk": {"pairs_per_s": pairs / (dk_ms * 1e-3), "device_ms": dk_ms,
-               "stages_ms": {s: v["ms"] for s, v in stages["dk"].items()},
+               "kernels": {k: {"ms": round(v["ms"], 4), "TOP/s": round(v["tops"], 3)}
+                           for k, v in kern["dk"].items()},
                "dp_started": prof_dk["dp_started"] / max(1, prof_dk["calls"]),
                "dp_valid_cells": prof_dk["dp_valid_cells"] / max(1, prof_dk["calls"])},
         "dtw": {"pairs_per_s": pairs / (dtw_ms * 1e-3), "device_ms": dtw_ms,
-                "stages_ms": {s: v["ms"] for s, v in stages["dtw"].items()},
+                "kernels": {k: {"ms": round(v["ms"], 4), "TOP/s": round(v["tops"], 3)}
+                            for k, v in kern["dtw"].items()},
                 "dp_started": prof_dtw["dp_started"] / max(1, prof_dtw["calls"]),
                 "dp_valid_cells": prof_dtw["dp_valid_cells"] / max(1, prof_dtw["calls"])},
         "dk_vs_dtw_speedup": dtw_ms / dk_ms if dk_ms > 0 else None,

@@ -98,6 +98,10 @@ typedef struct {
     float ms_bound;         /* bound pass + survivor compaction */
     float ms_dp;            /* DP kernels */
     float ms_final;         /* output kernel */
+    float ms_bound_kernel;  /* the bound kernel alone (LB_Box or corner) */
+    float ms_dp_fast;       /* the lane-per-pair DP kernel alone */
+    float ms_dp_general;    /* the general (fallback) DP kernel alone */
+    int64_t dp_valid_cells_general; /* of dp_valid_cells: general DP's share */
 } tsk_stats;
 
 typedef struct {

@@ -51,7 +51,9 @@ class Stats(ctypes.Structure):
                 ("fallback_pairs", ctypes.c_int64), ("dp_valid_cells", ctypes.c_int64),
                 ("calls", ctypes.c_int64), ("ms_total", ctypes.c_float),
                 ("ms_seed", ctypes.c_float), ("ms_bound", ctypes.c_float),
-                ("ms_dp", ctypes.c_float), ("ms_final", ctypes.c_float)]
+                ("ms_dp", ctypes.c_float), ("ms_final", ctypes.c_float),
+                ("ms_bound_kernel", ctypes.c_float), ("ms_dp_fast", ctypes.c_float),
+                ("ms_dp_general", ctypes.c_float), ("dp_valid_cells_general", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

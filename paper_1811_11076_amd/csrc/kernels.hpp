@@ -20,6 +20,7 @@ enum {
     C_FALLBACK,
     C_LATE_PRUNED,
     C_VALID_CELLS,
+    C_VALID_GEN, // valid cells of the general DP (also counted in C_VALID_CELLS)
     C_NUM
 };
 
@@ -714,8 +715,10 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
     if (lane == 0) {
         if (cells)
             atomicAdd(a.ctr + C_DP_CELLS, cells * 64ull);
-        if (valid)
+        if (valid) {
             atomicAdd(a.ctr + C_VALID_CELLS, valid);
+            atomicAdd(a.ctr + C_VALID_GEN, valid);
+        }
         if (!ALLPAIRS) {
             if (started)
                 atomicAdd(a.ctr + C_DP_STARTED, started);

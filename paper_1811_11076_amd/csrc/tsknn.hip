@@ -115,6 +115,11 @@ struct Workspace {
     }
 };
 
+// Stage marks recorded per chunk when timing: start, after seed, after the
+// bound kernel, after compaction (+ walks), after query staging, after the
+// fast DP, after the general DP, after the output kernel.
+constexpr int NEV = 8;
+
 struct tsk_index {
     int device = 0;
     int dim = 0;
@@ -135,7 +140,7 @@ struct tsk_index {
     Workspace ws;
     std::mutex mu;
     // profile accumulated by calls with opts->profile = 1
-    std::vector<std::array<hipEvent_t, 5>> ev_pool;
+    std::vector<std::array<hipEvent_t, NEV>> ev_pool;
     size_t ev_used = 0;
     DevBuf<unsigned long long> prof_ctr;
     int64_t prof_calls = 0;
@@ -144,7 +149,7 @@ struct tsk_index {
 static int take_events(tsk_index *ix, hipEvent_t **out)
 {
     if (ix->ev_used == ix->ev_pool.size()) {
-        std::array<hipEvent_t, 5> e;
+        std::array<hipEvent_t, NEV> e;
         for (auto &x : e)
             HIP_TRY(hipEventCreate(&x));
         ix->ev_pool.push_back(e);
@@ -165,22 +170,37 @@ static void stats_from(tsk_stats *st, const unsigned long long *c)
     st->bound_steps = (int64_t)c[C_BOUND_STEPS];
     st->fallback_pairs = (int64_t)c[C_FALLBACK];
     st->dp_valid_cells = (int64_t)c[C_VALID_CELLS];
+    st->dp_valid_cells_general = (int64_t)c[C_VALID_GEN];
 }
 
-// Sums the stage times of event sets [from, to) of the pool (synchronising).
-static int sum_events(tsk_index *ix, size_t from, size_t to, float ms[5])
+// Stage times of event sets [from, to) of the pool (synchronising):
+// t[i] = sum of elapsed(mark i, mark i+1).
+static int sum_events(tsk_index *ix, size_t from, size_t to, float t[NEV - 1])
 {
+    for (int i = 0; i < NEV - 1; ++i)
+        t[i] = 0.0f;
     for (size_t i = from; i < to; ++i) {
         hipEvent_t *e = ix->ev_pool[i].data();
-        HIP_TRY(hipEventSynchronize(e[4]));
-        for (int st = 0; st < 4; ++st) {
-            float t = 0.0f;
-            HIP_TRY(hipEventElapsedTime(&t, e[st], e[st + 1]));
-            ms[st + 1] += t;
+        HIP_TRY(hipEventSynchronize(e[NEV - 1]));
+        for (int st = 0; st < NEV - 1; ++st) {
+            float x = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&x, e[st], e[st + 1]));
+            t[st] += x;
         }
     }
-    ms[0] = ms[1] + ms[2] + ms[3] + ms[4];
     return TSK_OK;
+}
+
+static void stats_times(tsk_stats *st, const float t[NEV - 1])
+{
+    st->ms_seed = t[0];
+    st->ms_bound_kernel = t[1];
+    st->ms_bound = t[1] + t[2];
+    st->ms_dp_fast = t[4];
+    st->ms_dp_general = t[5];
+    st->ms_dp = t[3] + t[4] + t[5];
+    st->ms_final = t[6];
+    st->ms_total = t[0] + t[1] + t[2] + t[3] + t[4] + t[5] + t[6];
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -755,8 +775,12 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         } else {
             dispatch_d<SeedLaunch>(P.D, ix, qv, nq, P, order, s);
         }
-        if (timed)
-            HIP_TRY(hipEventRecord(ev[1], s));
+#define TSK_MARK(i)                                                                                \
+    do {                                                                                           \
+        if (timed)                                                                                 \
+            HIP_TRY(hipEventRecord(ev[i], s));                                                     \
+    } while (0)
+        TSK_MARK(1);
         BoundArgs ba = bound_args(ix, qv, nq, P);
         const bool dk_split = dist == TSK_DK && lds_query;
         if (dk_split)
@@ -765,6 +789,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             launch_bound_lb(P.D, ba, false, s);
         else
             dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
+        TSK_MARK(2);
         hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, order, W.tau.p,
                            W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
         // the greedy pass over the corner survivors costs more than the DP
@@ -776,8 +801,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             wa.work = W.work.p + 4;
             launch_walk_dk(P.D, wa, qv, W.ubslots.p, ix->n_cu * 8, qmax, s);
         }
-        if (timed)
-            HIP_TRY(hipEventRecord(ev[2], s));
+        TSK_MARK(3);
         int wsel = -1;
         const int fast = pick_fast(ix, dist, band, qmin, qmax, o.dp_kernel, &wsel);
         DpArgs da = dp_args(ix, qv, nq, P);
@@ -786,6 +810,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             const int qrows = qmax + 2 * QPAD;
             TSK_TRY(W.qpad.ensure((size_t)nq * qrows * DP));
             dispatch_d<QpadLaunch>(P.D, qv, W.qoff.p, nq, qrows, W.qpad.p, s);
+            TSK_MARK(4);
             FastArgs fa = fast_args(ix, nq, P, qrows);
             if (fast == FAST_TUBE32) {
                 fa.task = o.task_size > 0 ? o.task_size : 64;
@@ -795,21 +820,23 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             }
             else
                 launch_band(P.D, dist, wsel, fa, ix->n_cu * 8, s);
+            TSK_MARK(5);
             da.work = W.work.p + 2;
             launch_dp_wave(P.D, dist, DPW_FALLBACK, da, dp_blocks(ix), s);
         } else {
+            TSK_MARK(4);
+            TSK_MARK(5);
             launch_dp_wave(P.D, dist, DPW_SURV, da, dp_blocks(ix), s);
         }
-        if (timed)
-            HIP_TRY(hipEventRecord(ev[3], s));
+        TSK_MARK(6);
         if (dist == TSK_DK)
             hipLaunchKernelGGL(k_finalize<DIST_DK>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq, k,
                                out_ids_dev + q0 * k, out_dist_dev + q0 * k);
         else
             hipLaunchKernelGGL(k_finalize<DIST_DTW>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq, k,
                                out_ids_dev + q0 * k, out_dist_dev + q0 * k);
-        if (timed)
-            HIP_TRY(hipEventRecord(ev[4], s));
+        TSK_MARK(7);
+#undef TSK_MARK
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipGetLastError());
@@ -821,18 +848,14 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         unsigned long long c[C_NUM];
         HIP_TRY(hipMemcpyAsync(c, W.ctr.p, sizeof(c), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        float ms[5] = {0, 0, 0, 0, 0};
-        TSK_TRY(sum_events(ix, ev_first, ix->ev_used, ms));
+        float t[NEV - 1];
+        TSK_TRY(sum_events(ix, ev_first, ix->ev_used, t));
         if (!profile)
             ix->ev_used = ev_first; // these events are not part of a profile
         memset(stats_host, 0, sizeof(*stats_host));
         stats_from(stats_host, c);
         stats_host->calls = 1;
-        stats_host->ms_total = ms[0];
-        stats_host->ms_seed = ms[1];
-        stats_host->ms_bound = ms[2];
-        stats_host->ms_dp = ms[3];
-        stats_host->ms_final = ms[4];
+        stats_times(stats_host, t);
     }
     return TSK_OK;
 }
@@ -844,8 +867,8 @@ extern "C" int tsk_index_profile(tsk_index *ix, tsk_stats *out, int32_t reset)
         return set_err(TSK_ERR_INVALID_ARG, "index and out must be non-NULL");
     std::lock_guard<std::mutex> lock(ix->mu);
     memset(out, 0, sizeof(*out));
-    float ms[5] = {0, 0, 0, 0, 0};
-    TSK_TRY(sum_events(ix, 0, ix->ev_used, ms));
+    float t[NEV - 1];
+    TSK_TRY(sum_events(ix, 0, ix->ev_used, t));
     if (ix->prof_ctr.p) {
         unsigned long long c[C_NUM];
         HIP_TRY(hipDeviceSynchronize());
@@ -853,11 +876,7 @@ extern "C" int tsk_index_profile(tsk_index *ix, tsk_stats *out, int32_t reset)
         stats_from(out, c);
     }
     out->calls = ix->prof_calls;
-    out->ms_total = ms[0];
-    out->ms_seed = ms[1];
-    out->ms_bound = ms[2];
-    out->ms_dp = ms[3];
-    out->ms_final = ms[4];
+    stats_times(out, t);
     if (reset) {
         ix->ev_used = 0;
         ix->prof_calls = 0;
