@@ -33,6 +33,10 @@ WORKLOADS = {
                                           L=256, d=3, k=10, dk_band=None, dtw_band=0.1),
     "randomwalk-q1-n1000-L64-d3": dict(cfg_id=1, gen="randomwalk", Q=1, N=1000, L=64, d=3, k=1,
                                        dk_band=None, dtw_band=None),
+    # uneven lengths: members of length U{64..1024} from 50 prototypes of length 1024
+    "classwarp-q1024-n100000-L64to1024-d3": dict(cfg_id=3, gen="classwarp", classes=50, Q=1024,
+                                                 N=100000, L=1024, lengths=(64, 1024), d=3,
+                                                 k=10, dk_band=None, dtw_band=0.1),
 }
 DEFAULT = "classwarp-q100-n20000-L256-d3"
 
@@ -71,8 +75,9 @@ def make_data(w):
         qs, qo = synth.flat_equal(synth.random_walks(w["Q"], w["L"], w["d"], w["cfg_id"], "query"))
     else:
         g = synth.ClassWarp(w["cfg_id"], w["classes"], w["L"], w["d"])
-        db, dbo, _ = g.members(w["N"], "db", length=w["L"])
-        qs, qo, _ = g.members(w["Q"], "query", length=w["L"], class_mode="uniform")
+        length = w.get("lengths", w["L"])
+        db, dbo, _ = g.members(w["N"], "db", length=length)
+        qs, qo, _ = g.members(w["Q"], "query", length=length, class_mode="uniform")
     return db, dbo, qs, qo
 
 

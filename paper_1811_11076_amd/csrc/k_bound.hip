@@ -17,7 +17,6 @@ template <int D> void bound_lb_d(const BoundArgs &a, bool debug, hipStream_t s)
 template <int D>
 void seed_ring_d(int dist, const SeedRingArgs &r, hipStream_t s)
 {
-    constexpr int DP = PadDim<D>::value;
     dim3 grid((r.S - r.P0 + 63) / 64, r.nq);
     const size_t lds = walk_lds_bytes(D, r.maxm);
     if (dist == DIST_DK)

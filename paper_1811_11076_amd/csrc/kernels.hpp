@@ -445,8 +445,14 @@ __global__ __launch_bounds__(256) void k_bounds(BoundArgs a)
 // ------------------------------------------------------------------ compaction
 // Survivors of one query, in the query's candidate order, re-checked against
 // the current threshold: surv[q][0..cnt).  One block of 256 per query.
+// Candidate order: order[q][p] if given, else perm[p] (length-sorted
+// positions) if given, else p.  lbv is indexed by candidate id, except after
+// the length-bucket bound pass, which writes it by position (then perm maps
+// positions to ids and inv ids to positions).
 static __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ lbv, int64_t N,
                                                  const int32_t *__restrict__ order,
+                                                 const int32_t *__restrict__ perm,
+                                                 const int32_t *__restrict__ inv,
                                                  const uint32_t *__restrict__ tau,
                                                  int32_t *__restrict__ surv, int32_t *__restrict__ cnt,
                                                  int32_t *__restrict__ max_cnt,
@@ -466,8 +472,15 @@ static __global__ __launch_bounds__(256) void k_compact(const float *__restrict_
         int c = -1;
         bool keep = false;
         if (p < N) {
-            c = order ? order[(int64_t)q * N + p] : (int)p;
-            const float lb = lbv[(int64_t)q * N + c];
+            int64_t li;
+            if (order) {
+                c = order[(int64_t)q * N + p];
+                li = inv ? inv[c] : c;
+            } else {
+                c = perm ? perm[p] : (int)p;
+                li = p;
+            }
+            const float lb = lbv[(int64_t)q * N + li];
             keep = lb <= tq;
             late += (lb != tsk_inf() && !keep) ? 1 : 0;
         }
@@ -632,6 +645,7 @@ struct DpArgs {
     BandArgs ba;
     uint32_t *tau;
     const float *lbv;
+    const int32_t *lb_inv; // lbv index of a candidate id (null: the id itself)
     const int32_t *surv;
     const int32_t *surv_cnt;
     const int32_t *max_cnt;
@@ -676,7 +690,7 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
             const int2 item = a.fb[t];
             q = item.x;
             c = item.y;
-            if (a.lbv[(int64_t)q * a.N + c] > bits_f(load_relaxed_u32(a.tau + q))) {
+            if (a.lbv[(int64_t)q * a.N + (a.lb_inv ? a.lb_inv[c] : c)] > bits_f(load_relaxed_u32(a.tau + q))) {
                 ++late;
                 continue;
             }
@@ -686,7 +700,7 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
             if (r >= a.surv_cnt[q])
                 continue;
             c = a.surv[(int64_t)q * a.N + r];
-            if (a.lbv[(int64_t)q * a.N + c] > bits_f(load_relaxed_u32(a.tau + q))) {
+            if (a.lbv[(int64_t)q * a.N + (a.lb_inv ? a.lb_inv[c] : c)] > bits_f(load_relaxed_u32(a.tau + q))) {
                 ++late;
                 continue;
             }

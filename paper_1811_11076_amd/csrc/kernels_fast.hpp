@@ -33,6 +33,7 @@ struct FastArgs {
     BandArgs ba;
     uint32_t *tau;
     const float *lbv;
+    const int32_t *lb_inv; // lbv index of a candidate id (null: the id itself)
     const int32_t *surv;
     const int32_t *surv_cnt;
     const int32_t *max_cnt;
@@ -103,7 +104,7 @@ __device__ __forceinline__ bool next_chunk(const FastArgs &a, int64_t total, Chu
         const int idx = base + (int)threadIdx.x;
         if (idx < cnt) {
             const int c = a.surv[(int64_t)q * a.N + idx];
-            if (a.lbv[(int64_t)q * a.N + c] > bits_f(load_relaxed_u32(a.tau + q)))
+            if (a.lbv[(int64_t)q * a.N + (a.lb_inv ? a.lb_inv[c] : c)] > bits_f(load_relaxed_u32(a.tau + q)))
                 ++late;
             else {
                 ch.c = c;
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
                 const int idx = next + rank;
                 if (!running && idx < end) {
                     const int cc = a.surv[(int64_t)q * a.N + idx];
-                    if (a.lbv[(int64_t)q * a.N + cc] > tau) {
+                    if (a.lbv[(int64_t)q * a.N + (a.lb_inv ? a.lb_inv[cc] : cc)] > tau) {
                         ++late;
                     } else {
                         c = cc;

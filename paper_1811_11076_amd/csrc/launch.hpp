@@ -3,6 +3,7 @@
 #pragma once
 
 #include "kernels_bound.hpp"
+#include "kernels_lbu.hpp"
 
 namespace tsk {
 
@@ -48,5 +49,11 @@ void launch_walk_dk(int D, const FastArgs &a, const float *qv, unsigned long lon
 void launch_band(int D, int dist, int wsel, const FastArgs &a, int blocks, hipStream_t s);
 void launch_tube(int D, const FastArgs &a, int rows, int blocks, int maxm, hipStream_t s);
 void launch_dp_wave(int D, int dist, int mode, const DpArgs &a, int blocks, hipStream_t s);
+void launch_qtable(int D, const float *qv, const int64_t *qoff, int nq, const int64_t *tab_off,
+                   float *tab, hipStream_t s);
+void launch_bound_lbu(int D, const BoundArgs &a, const BucketArgs &bk, const float *tab,
+                      const int64_t *tab_off, int qg, bool debug, hipStream_t s);
+void launch_pack_bucket(int D, const float *aos, const int64_t *off, const BucketArgs &bk,
+                        float *soa, hipStream_t s);
 
 } // namespace tsk

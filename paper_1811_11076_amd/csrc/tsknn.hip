@@ -94,7 +94,9 @@ struct Workspace {
     DevBuf<float> tbuf;
     DevBuf<float> qpad;
     DevBuf<int2> fb;
-    std::vector<int64_t> h_qoff;
+    DevBuf<float> qtab;       // per-query sparse tables (length buckets)
+    DevBuf<int64_t> qtab_off; // their offsets (floats)
+    std::vector<int64_t> h_qoff, h_qtab;
     void release()
     {
         tau.release();
@@ -112,6 +114,8 @@ struct Workspace {
         tbuf.release();
         qpad.release();
         fb.release();
+        qtab.release();
+        qtab_off.release();
     }
 };
 
@@ -136,6 +140,14 @@ struct tsk_index {
     float *soa = nullptr;
     int64_t *tile_off = nullptr;
     int32_t *tile_len = nullptr;
+    // length buckets (only when the series differ in length): ids sorted by
+    // (length, id), tiles of <= 64 series of one length, SoA per tile
+    bool bucketed = false;
+    int32_t *perm = nullptr, *inv = nullptr;
+    int32_t *bt_pos = nullptr, *bt_cnt = nullptr, *bt_len = nullptr;
+    int64_t *bt_off = nullptr;
+    float *bsoa = nullptr;
+    int64_t n_btiles = 0;
     hipStream_t last_stream = nullptr;
     Workspace ws;
     std::mutex mu;
@@ -326,6 +338,10 @@ static void free_index_memory(tsk_index *ix)
     if (ix->soa) (void)hipFree(ix->soa);
     if (ix->tile_off) (void)hipFree(ix->tile_off);
     if (ix->tile_len) (void)hipFree(ix->tile_len);
+    for (int32_t *p : {ix->perm, ix->inv, ix->bt_pos, ix->bt_cnt, ix->bt_len})
+        if (p) (void)hipFree(p);
+    if (ix->bt_off) (void)hipFree(ix->bt_off);
+    if (ix->bsoa) (void)hipFree(ix->bsoa);
     ix->ws.release();
     ix->prof_ctr.release();
     for (auto &e : ix->ev_pool)
@@ -342,6 +358,19 @@ extern "C" int tsk_index_free(tsk_index *ix)
     free_index_memory(ix);
     delete ix;
     return TSK_OK;
+}
+
+static BucketArgs bucket_args(const tsk_index *ix)
+{
+    BucketArgs b;
+    b.perm = ix->perm;
+    b.tpos = ix->bt_pos;
+    b.tcnt = ix->bt_cnt;
+    b.tlen = ix->bt_len;
+    b.toff = ix->bt_off;
+    b.soa = ix->bsoa;
+    b.n_tiles = ix->n_btiles;
+    return b;
 }
 
 static int index_build_impl(tsk_index *ix, const float *values_dev, hipStream_t s)
@@ -375,6 +404,55 @@ static int index_build_impl(tsk_index *ix, const float *values_dev, hipStream_t 
                            hipMemcpyHostToDevice, s));
     dispatch_d<PackLaunch>(D, ix, values_dev, s);
     HIP_TRY(hipGetLastError());
+    std::vector<int32_t> perm, inv, bpos, bcnt, blen;
+    std::vector<int64_t> boff;
+    if (ix->min_len != ix->max_len) {
+        // length buckets for the bound pass of uneven-length DTW
+        perm.resize(ix->n);
+        for (int64_t i = 0; i < ix->n; ++i)
+            perm[i] = (int32_t)i;
+        std::stable_sort(perm.begin(), perm.end(),
+                         [&](int32_t a, int32_t b) { return ix->h_len[a] < ix->h_len[b]; });
+        inv.resize(ix->n);
+        for (int64_t p = 0; p < ix->n; ++p)
+            inv[perm[p]] = (int32_t)p;
+        boff.push_back(0);
+        for (int64_t p = 0; p < ix->n;) {
+            const int32_t L = ix->h_len[perm[p]];
+            int64_t e = p;
+            while (e < ix->n && e - p < 64 && ix->h_len[perm[e]] == L)
+                ++e;
+            bpos.push_back((int32_t)p);
+            bcnt.push_back((int32_t)(e - p));
+            blen.push_back(L);
+            boff.push_back(boff.back() + (int64_t)L * D * 64);
+            p = e;
+        }
+        ix->n_btiles = (int64_t)bpos.size();
+        const size_t nt = (size_t)ix->n_btiles;
+        HIP_TRY(hipMalloc((void **)&ix->perm, ix->n * sizeof(int32_t)));
+        HIP_TRY(hipMalloc((void **)&ix->inv, ix->n * sizeof(int32_t)));
+        HIP_TRY(hipMalloc((void **)&ix->bt_pos, nt * sizeof(int32_t)));
+        HIP_TRY(hipMalloc((void **)&ix->bt_cnt, nt * sizeof(int32_t)));
+        HIP_TRY(hipMalloc((void **)&ix->bt_len, nt * sizeof(int32_t)));
+        HIP_TRY(hipMalloc((void **)&ix->bt_off, (nt + 1) * sizeof(int64_t)));
+        HIP_TRY(hipMalloc((void **)&ix->bsoa, boff.back() * sizeof(float)));
+        HIP_TRY(hipMemcpyAsync(ix->perm, perm.data(), ix->n * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ix->inv, inv.data(), ix->n * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ix->bt_pos, bpos.data(), nt * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ix->bt_cnt, bcnt.data(), nt * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ix->bt_len, blen.data(), nt * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ix->bt_off, boff.data(), (nt + 1) * sizeof(int64_t),
+                               hipMemcpyHostToDevice, s));
+        ix->bucketed = true;
+        launch_pack_bucket(D, ix->aos, ix->off, bucket_args(ix), ix->bsoa, s);
+        HIP_TRY(hipGetLastError());
+    }
     // the host vectors feeding the async copies live in the index; wait so
     // the caller may release its input as soon as this call returns
     HIP_TRY(hipStreamSynchronize(s));
@@ -528,6 +606,7 @@ static DpArgs dp_args(tsk_index *ix, const float *qv, int nq, const QueryPlan &P
     a.ba = P.ba;
     a.tau = ix->ws.tau.p;
     a.lbv = ix->ws.lbv.p;
+    a.lb_inv = nullptr;
     a.surv = ix->ws.surv.p;
     a.surv_cnt = ix->ws.surv_cnt.p;
     a.max_cnt = ix->ws.max_cnt.p;
@@ -561,6 +640,7 @@ static FastArgs fast_args(tsk_index *ix, int nq, const QueryPlan &P, int qrows)
     a.ba = P.ba;
     a.tau = ix->ws.tau.p;
     a.lbv = ix->ws.lbv.p;
+    a.lb_inv = nullptr;
     a.surv = ix->ws.surv.p;
     a.surv_cnt = ix->ws.surv_cnt.p;
     a.max_cnt = ix->ws.max_cnt.p;
@@ -661,6 +741,23 @@ static int upload_qoff(tsk_index *ix, const int64_t *qoff, int64_t q0, int64_t n
     ix->ws.h_qoff.assign(qoff + q0, qoff + q0 + nq + 1);
     HIP_TRY(hipMemcpyAsync(ix->ws.qoff.p, ix->ws.h_qoff.data(), (nq + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
+    return TSK_OK;
+}
+
+// Sparse tables of a chunk's queries for the length-bucket bound pass.
+static int build_qtables(tsk_index *ix, const float *qv, const int64_t *qoff_host, int64_t q0,
+                         int nq, hipStream_t s)
+{
+    const int DP = ix->dim <= 4 ? 4 : 8;
+    std::vector<int64_t> &h = ix->ws.h_qtab;
+    h.assign(nq + 1, 0);
+    for (int i = 0; i < nq; ++i)
+        h[i + 1] = h[i] + qtable_floats((int)(qoff_host[q0 + i + 1] - qoff_host[q0 + i]), DP);
+    TSK_TRY(ix->ws.qtab.ensure(h[nq]));
+    TSK_TRY(ix->ws.qtab_off.ensure(nq + 1));
+    HIP_TRY(hipMemcpyAsync(ix->ws.qtab_off.p, h.data(), (nq + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    launch_qtable(ix->dim, qv, ix->ws.qoff.p, nq, ix->ws.qtab_off.p, ix->ws.qtab.p, s);
     return TSK_OK;
 }
 
@@ -783,14 +880,21 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         TSK_MARK(1);
         BoundArgs ba = bound_args(ix, qv, nq, P);
         const bool dk_split = dist == TSK_DK && lds_query;
-        if (dk_split)
+        // uneven lengths: LB_Box per length bucket, lbv by sorted position
+        const bool lbu = dist == TSK_DTW && !P.env_ok && ix->bucketed && o.dp_kernel != 1;
+        if (dk_split) {
             launch_corner(P.D, ba, s);
-        else if (dist == TSK_DTW && P.env_ok && o.dp_kernel != 1)
+        } else if (dist == TSK_DTW && P.env_ok && o.dp_kernel != 1) {
             launch_bound_lb(P.D, ba, false, s);
-        else
+        } else if (lbu) {
+            TSK_TRY(build_qtables(ix, qv, q_offsets_host, q0, nq, s));
+            launch_bound_lbu(P.D, ba, bucket_args(ix), W.qtab.p, W.qtab_off.p, 4, false, s);
+        } else {
             dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
+        }
         TSK_MARK(2);
-        hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, order, W.tau.p,
+        hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, order,
+                           lbu ? ix->perm : nullptr, lbu ? ix->inv : nullptr, W.tau.p,
                            W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
         // the greedy pass over the corner survivors costs more than the DP
         // work its tighter threshold saves on the class-warp workloads, so
@@ -805,6 +909,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         int wsel = -1;
         const int fast = pick_fast(ix, dist, band, qmin, qmax, o.dp_kernel, &wsel);
         DpArgs da = dp_args(ix, qv, nq, P);
+        da.lb_inv = lbu ? ix->inv : nullptr;
         if (fast != FAST_NONE) {
             const int DP = P.D <= 4 ? 4 : 8;
             const int qrows = qmax + 2 * QPAD;
@@ -812,6 +917,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             dispatch_d<QpadLaunch>(P.D, qv, W.qoff.p, nq, qrows, W.qpad.p, s);
             TSK_MARK(4);
             FastArgs fa = fast_args(ix, nq, P, qrows);
+            fa.lb_inv = lbu ? ix->inv : nullptr;
             if (fast == FAST_TUBE32) {
                 fa.task = o.task_size > 0 ? o.task_size : 64;
                 // 16-row windows: the live tube of near neighbours is a few
@@ -955,6 +1061,10 @@ extern "C" int tsk_pair_bounds(const tsk_index *cix, const float *q_values_dev,
         dispatch_d<BoundLaunch>(P.D, ba, dist, true, s);
         if (dist == TSK_DTW && P.env_ok && ba.dbg_lb)
             launch_bound_lb(P.D, ba, true, s);
+        if (dist == TSK_DTW && !P.env_ok && ix->bucketed && ba.dbg_lb) {
+            TSK_TRY(build_qtables(ix, q_values_dev, q_offsets_host, q0, nq, s));
+            launch_bound_lbu(P.D, ba, bucket_args(ix), ix->ws.qtab.p, ix->ws.qtab_off.p, 4, true, s);
+        }
         int32_t qmax = 0;
         for (int i = 0; i < nq; ++i)
             qmax = std::max<int32_t>(qmax, (int32_t)(q_offsets_host[q0 + i + 1] - q_offsets_host[q0 + i]));

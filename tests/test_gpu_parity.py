@@ -33,6 +33,8 @@ PAIR_CASES = [
     ("d6", 4, 2, 30, (10, 80), 6),
     ("d8", 5, 2, 30, (10, 80), 8),
     ("equal64", 6, 3, 100, (64, 64), 3),
+    # ~100 series per length: length buckets split into several tiles
+    ("buckets", 7, 3, 400, (20, 23), 3),
 ]
 BANDS = [None, 3, 0.2]
 
@@ -156,6 +158,21 @@ def test_knn_classwarp_reduced():
     """Class-warp series (10 classes, length 256, d = 3), 12 queries x 3000."""
     print("[case] knn classwarp reduced", flush=True)
     db, dbo, qs, qo = classwarp(2, 10, 256, 3, 3000, 12)
+    idx = _index(db, dbo)
+    for dist, band in (("dk", None), ("dtw", 0.1)):
+        ref_ids, ref_keys, _ = O.knn_scan(db, dbo, qs, qo, 10, dist, band)
+        ids, dst, st = idx.knn(to_dev(qs), qo, 10, dist, band, stats=True)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
+        print(f"  {dist}: {st}", flush=True)
+    idx.close()
+
+
+def test_knn_classwarp_uneven_reduced():
+    """The uneven-length class-warp generator (50 classes, prototypes of
+    length 1024, members of length U{64..1024}, d = 3), 6 queries x 1500:
+    slanted 10 % band for DTW (length-bucket LB_Box), unbanded DK."""
+    print("[case] knn classwarp uneven reduced", flush=True)
+    db, dbo, qs, qo = classwarp(3, 50, (64, 1024), 3, 1500, 6, proto_len=1024)
     idx = _index(db, dbo)
     for dist, band in (("dk", None), ("dtw", 0.1)):
         ref_ids, ref_keys, _ = O.knn_scan(db, dbo, qs, qo, 10, dist, band)
