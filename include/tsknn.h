@@ -75,9 +75,13 @@ typedef struct {
 
 /* Candidate order for a query.  The order never changes the result, only
  * how early the threshold falls (and so how much work is pruned). */
-enum { TSK_ORDER_PLAIN = 0, TSK_ORDER_GIVEN = 1 };
+enum { TSK_ORDER_PLAIN = 0, TSK_ORDER_GIVEN = 1, TSK_ORDER_LEARNED = 2 };
 
 typedef struct tsk_index tsk_index;
+
+/* Encoder that predicts distances for TSK_ORDER_LEARNED (not part of the
+ * paper's method: it only reorders candidates, so results never change). */
+typedef struct tsk_model tsk_model;
 
 /* Per-call counters (all int64) and device times.  Counts are over all
  * (query, candidate) pairs of the call. */
@@ -102,11 +106,13 @@ typedef struct {
     float ms_dp_fast;       /* the lane-per-pair DP kernel alone */
     float ms_dp_general;    /* the general (fallback) DP kernel alone */
     int64_t dp_valid_cells_general; /* of dp_valid_cells: general DP's share */
+    float ms_order;         /* TSK_ORDER_LEARNED: query embedding, scores and
+                               per-query candidate order */
 } tsk_stats;
 
 typedef struct {
     int64_t size;                  /* sizeof(tsk_query_opts) */
-    int32_t order;                 /* TSK_ORDER_PLAIN or TSK_ORDER_GIVEN */
+    int32_t order;                 /* TSK_ORDER_PLAIN, _GIVEN or _LEARNED */
     int32_t seed_count;            /* candidates per query used to seed the
                                       threshold (0 = library default) */
     const int32_t *order_dev;      /* TSK_ORDER_GIVEN: [n_queries][n_series]
@@ -130,6 +136,11 @@ typedef struct {
                                       16);
                                       pairs whose live cells outgrow it finish
                                       in the general DP */
+    const tsk_model *model;        /* TSK_ORDER_LEARNED: the encoder; each
+                                      query's candidates are taken in
+                                      ascending embedding distance.  The
+                                      index caches the candidates' embeddings
+                                      for the model's current parameters */
 } tsk_query_opts;
 
 typedef struct {
@@ -206,6 +217,84 @@ int tsk_pair_bounds(const tsk_index *index, const float *q_values_dev,
                     const int64_t *q_offsets_host, int64_t n_queries, int32_t dist,
                     tsk_band band, float *out_lb_dev, float *out_ub_dev,
                     int32_t *out_steps_dev, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Learned candidate ordering.  An MLP encoder maps a series, resampled to
+ * `points` points by linear interpolation at t_k = k (L-1) / (points-1),
+ * to an embedding: (points * dim) -> hidden -> hidden -> embed, ReLU on the
+ * hidden layers, bfloat16 weights and layer inputs (nearest-even rounding of
+ * fp32 master values where the products read them), fp32 accumulation and
+ * biases.  The distance of two series is predicted as the Euclidean distance
+ * of their embeddings; training fits it to DK distances by mean squared
+ * error with Adam.  Parameters are laid out flat in this order:
+ * W1 [hidden][points*dim], b1 [hidden], W2 [hidden][hidden], b2 [hidden],
+ * W3 [embed][hidden], b3 [embed] (row-major).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t size;    /* sizeof(tsk_mlp_shape) */
+    int32_t dim;     /* series dimensionality (1..TSK_MAX_DIM) */
+    int32_t points;  /* resampled points (2..256; 32 by default if 0) */
+    int32_t hidden;  /* hidden width (multiple of 32, <= 1024; 256 if 0) */
+    int32_t embed;   /* embedding width (multiple of 32, <= 256; 64 if 0) */
+} tsk_mlp_shape;
+
+typedef struct {
+    int64_t size;    /* sizeof(tsk_train_opts) */
+    int32_t epochs;  /* passes over the pairs (>= 1) */
+    int32_t batch;   /* pairs per step (1..65536) */
+    float lr;        /* Adam step size (> 0) */
+    float beta1, beta2, eps; /* 0 selects 0.9, 0.999, 1e-8 */
+    uint64_t seed;   /* order of the pairs in each epoch (splitmix64 stream) */
+} tsk_train_opts;
+
+/* Creates an encoder on the current device: He-uniform weights
+ * (U(-sqrt(6/fan_in), sqrt(6/fan_in)) from a splitmix64 stream seeded with
+ * `seed`), zero biases, zero Adam state.  *out is owned by the caller.
+ * Errors: INVALID_ARG, UNSUPPORTED (shape out of range), OOM, DEVICE. */
+int tsk_model_create(const tsk_mlp_shape *shape, uint64_t seed, tsk_model **out);
+
+/* Frees an encoder (NULL accepted) after synchronising the device. */
+int tsk_model_free(tsk_model *model);
+
+/* Shape and parameter count of an encoder (outputs nullable). */
+int tsk_model_info(const tsk_model *model, tsk_mlp_shape *shape, int64_t *n_params);
+
+/* Copies the fp32 master parameters to host memory [n_params] (flat layout
+ * above), or replaces them from host memory (also clearing the Adam state
+ * and step count).  n must equal the parameter count.  Synchronous. */
+int tsk_model_get_params(const tsk_model *model, float *out_host, int64_t n);
+int tsk_model_set_params(tsk_model *model, const float *in_host, int64_t n);
+
+/* Embeddings of n series given as for tsk_index_build: out_dev receives
+ * [n][embed] float32.  Asynchronous on the stream. */
+int tsk_model_embed(tsk_model *model, const float *values_dev, const int64_t *offsets_host,
+                    int64_t n_series, float *out_dev, void *hip_stream);
+
+/* Loss and parameter gradient of one batch of pairs (a_host[i], b_host[i])
+ * of the given series with target distances target_host[i] (the forward and
+ * backward passes of one training step, without the update).  out_loss_host
+ * and out_grad_host ([n_params], nullable) are host outputs; synchronous.
+ * Errors: INVALID_ARG (ids outside [0, n_series), n_pairs < 1), OOM, DEVICE. */
+int tsk_model_batch_grad(tsk_model *model, const float *values_dev, const int64_t *offsets_host,
+                         int64_t n_series, const int32_t *a_host, const int32_t *b_host,
+                         const float *target_host, int64_t n_pairs, float *out_loss_host,
+                         float *out_grad_host, void *hip_stream);
+
+/* Trains on n_pairs pairs of the given series: every epoch takes the pairs
+ * in a fresh shuffled order, in batches of opts->batch, each batch one
+ * forward, backward and Adam step on the device.  out_epoch_loss_host
+ * (nullable, [epochs]) receives each epoch's mean batch loss.  Synchronous.
+ * Errors: INVALID_ARG, OOM, DEVICE. */
+int tsk_model_train(tsk_model *model, const float *values_dev, const int64_t *offsets_host,
+                    int64_t n_series, const int32_t *a_host, const int32_t *b_host,
+                    const float *target_host, int64_t n_pairs, const tsk_train_opts *opts,
+                    float *out_epoch_loss_host, void *hip_stream);
+
+/* Writes / reads an encoder (shape, fp32 master parameters) to / from a
+ * binary file.  Errors: IO (cannot open, short read, bad header), plus those
+ * of tsk_model_create for load. */
+int tsk_model_save(const tsk_model *model, const char *path);
+int tsk_model_load(const char *path, tsk_model **out);
 
 #ifdef __cplusplus
 }

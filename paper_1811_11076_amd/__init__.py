@@ -17,7 +17,7 @@ import numpy as np
 
 from . import _lib
 
-__all__ = ["Index", "TskError", "version"]
+__all__ = ["Index", "Model", "TskError", "version"]
 
 TskError = _lib.TskError
 
@@ -87,9 +87,11 @@ class Index:
 
     def knn(self, queries, q_offsets, k: int, distance: str = "dk", band=None, order=None,
             seed_count: int = 0, stats: bool = False, profile: bool = False,
-            walk_pass: int = -1, task_size: int = 0, tube_rows: int = 0):
+            walk_pass: int = -1, task_size: int = 0, tube_rows: int = 0, model=None):
         """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
-        float32 [nq, k], stats dict or None); DK distances are unsquared."""
+        float32 [nq, k], stats dict or None); DK distances are unsquared.
+        order: None (plain), a CUDA int32 [nq, n] permutation per query, or
+        "learned" with model= a Model (candidates by embedding distance)."""
         torch = _torch()
         qv = _values(queries, self.dim)
         qo = _offsets(q_offsets)
@@ -103,7 +105,12 @@ class Index:
         opts.walk_pass = int(walk_pass)
         opts.task_size = int(task_size)
         opts.tube_rows = int(tube_rows)
-        if order is not None:
+        if isinstance(order, str):
+            if order != "learned" or model is None:
+                raise ValueError('order="learned" needs model=')
+            opts.order = _lib.TSK_ORDER_LEARNED
+            opts.model = model._h.value
+        elif order is not None:
             if order.dtype != torch.int32 or not order.is_cuda or tuple(order.shape) != (nq, self.n):
                 raise ValueError("order must be a CUDA int32 tensor [n_queries, n_series]")
             order = order.contiguous()
@@ -151,3 +158,108 @@ class Index:
             _DIST[distance], _lib.band_struct(band), ctypes.c_void_p(lb.data_ptr()),
             ctypes.c_void_p(ub.data_ptr()), ctypes.c_void_p(steps.data_ptr()), _stream()))
         return lb, ub, steps
+
+
+class Model:
+    """Encoder for the learned candidate order (C: tsk_model_*).  Predicts
+    DK distances as Euclidean distances of embeddings; only reorders the
+    scan, never changes its results."""
+
+    def __init__(self, dim: int, points: int = 32, hidden: int = 256, embed: int = 64,
+                 seed: int = 0, _handle=None):
+        self._lib = _lib.load()
+        self._h = ctypes.c_void_p()
+        if _handle is not None:
+            self._h = _handle
+        else:
+            sh = _lib.MlpShape(ctypes.sizeof(_lib.MlpShape), dim, points, hidden, embed)
+            _lib.check(self._lib.tsk_model_create(ctypes.byref(sh), ctypes.c_uint64(seed),
+                                                  ctypes.byref(self._h)))
+        sh = _lib.MlpShape()
+        n = ctypes.c_int64()
+        _lib.check(self._lib.tsk_model_info(self._h, ctypes.byref(sh), ctypes.byref(n)))
+        self.dim, self.points, self.hidden, self.embed = sh.dim, sh.points, sh.hidden, sh.embed
+        self.n_params = n.value
+
+    @classmethod
+    def load(cls, path: str) -> "Model":
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().tsk_model_load(path.encode(), ctypes.byref(h)))
+        return cls(0, _handle=h)
+
+    def save(self, path: str):
+        _lib.check(self._lib.tsk_model_save(self._h, path.encode()))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.tsk_model_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        _lib.check(self._lib.tsk_model_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                                  self.n_params))
+        return out
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(np.asarray(flat, dtype=np.float32))
+        _lib.check(self._lib.tsk_model_set_params(self._h, flat.ctypes.data_as(ctypes.c_void_p),
+                                                  flat.size))
+
+    def embed_series(self, values, offsets):
+        """Embeddings [n, embed] (CUDA float32) of the given series."""
+        torch = _torch()
+        v = _values(values, self.dim)
+        off = _offsets(offsets)
+        n = int(off.shape[0] - 1)
+        out = torch.empty((n, self.embed), dtype=torch.float32, device=v.device)
+        _lib.check(self._lib.tsk_model_embed(self._h, ctypes.c_void_p(v.data_ptr()),
+                                             off.ctypes.data_as(ctypes.c_void_p), n,
+                                             ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    @staticmethod
+    def _pairs(a, b, y):
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+        b = np.ascontiguousarray(np.asarray(b, dtype=np.int32))
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.float32))
+        if not (a.shape == b.shape == y.shape and a.ndim == 1):
+            raise ValueError("pair arrays must be 1-D of one length")
+        return a, b, y
+
+    def batch_grad(self, values, offsets, a, b, y):
+        """(loss, flat gradient [n_params]) of one batch of pairs."""
+        v = _values(values, self.dim)
+        off = _offsets(offsets)
+        a, b, y = self._pairs(a, b, y)
+        loss = ctypes.c_float()
+        grad = np.empty(self.n_params, np.float32)
+        _lib.check(self._lib.tsk_model_batch_grad(
+            self._h, ctypes.c_void_p(v.data_ptr()), off.ctypes.data_as(ctypes.c_void_p),
+            int(off.shape[0] - 1), a.ctypes.data_as(ctypes.c_void_p),
+            b.ctypes.data_as(ctypes.c_void_p), y.ctypes.data_as(ctypes.c_void_p), a.size,
+            ctypes.byref(loss), grad.ctypes.data_as(ctypes.c_void_p), _stream()))
+        return loss.value, grad
+
+    def train(self, values, offsets, a, b, y, epochs: int = 10, batch: int = 1024,
+              lr: float = 1e-3, seed: int = 0):
+        """Adam training on pairs (a[i], b[i]) with target distances y[i];
+        returns the mean batch loss of every epoch."""
+        v = _values(values, self.dim)
+        off = _offsets(offsets)
+        a, b, y = self._pairs(a, b, y)
+        o = _lib.TrainOpts(ctypes.sizeof(_lib.TrainOpts), int(epochs), int(batch), float(lr),
+                           0.0, 0.0, 0.0, int(seed))
+        losses = np.empty(int(epochs), np.float32)
+        _lib.check(self._lib.tsk_model_train(
+            self._h, ctypes.c_void_p(v.data_ptr()), off.ctypes.data_as(ctypes.c_void_p),
+            int(off.shape[0] - 1), a.ctypes.data_as(ctypes.c_void_p),
+            b.ctypes.data_as(ctypes.c_void_p), y.ctypes.data_as(ctypes.c_void_p), a.size,
+            ctypes.byref(o), losses.ctypes.data_as(ctypes.c_void_p), _stream()))
+        return losses

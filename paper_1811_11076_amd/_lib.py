@@ -16,7 +16,7 @@ TSK_ERR_CANCELLED = 6
 
 TSK_DTW, TSK_DK = 0, 1
 TSK_BAND_NONE, TSK_BAND_ABS, TSK_BAND_FRAC = 0, 1, 2
-TSK_ORDER_PLAIN, TSK_ORDER_GIVEN = 0, 1
+TSK_ORDER_PLAIN, TSK_ORDER_GIVEN, TSK_ORDER_LEARNED = 0, 1, 2
 
 _ERRNAMES = {1: "INVALID_ARG", 2: "OOM", 3: "DEVICE", 4: "UNSUPPORTED", 5: "IO", 6: "CANCELLED"}
 
@@ -36,7 +36,7 @@ class QueryOpts(ctypes.Structure):
                 ("order_dev", ctypes.c_void_p), ("use_graph", ctypes.c_int32),
                 ("dp_kernel", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("walk_pass", ctypes.c_int32), ("task_size", ctypes.c_int32),
-                ("tube_rows", ctypes.c_int32)]
+                ("tube_rows", ctypes.c_int32), ("model", ctypes.c_void_p)]
 
 
 class IndexOpts(ctypes.Structure):
@@ -53,10 +53,22 @@ class Stats(ctypes.Structure):
                 ("ms_seed", ctypes.c_float), ("ms_bound", ctypes.c_float),
                 ("ms_dp", ctypes.c_float), ("ms_final", ctypes.c_float),
                 ("ms_bound_kernel", ctypes.c_float), ("ms_dp_fast", ctypes.c_float),
-                ("ms_dp_general", ctypes.c_float), ("dp_valid_cells_general", ctypes.c_int64)]
+                ("ms_dp_general", ctypes.c_float), ("dp_valid_cells_general", ctypes.c_int64),
+                ("ms_order", ctypes.c_float)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class MlpShape(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int64), ("dim", ctypes.c_int32), ("points", ctypes.c_int32),
+                ("hidden", ctypes.c_int32), ("embed", ctypes.c_int32)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int64), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("seed", ctypes.c_uint64)]
 
 
 _vp = ctypes.c_void_p
@@ -74,6 +86,17 @@ SIGNATURES = {
     "tsk_index_profile": (ctypes.c_int, [_vp, _vp, _i32]),
     "tsk_pair_distances": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp]),
     "tsk_pair_bounds": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp, _vp, _vp]),
+    "tsk_model_create": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    "tsk_model_free": (ctypes.c_int, [_vp]),
+    "tsk_model_info": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_i64)]),
+    "tsk_model_get_params": (ctypes.c_int, [_vp, _vp, _i64]),
+    "tsk_model_set_params": (ctypes.c_int, [_vp, _vp, _i64]),
+    "tsk_model_embed": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    "tsk_model_batch_grad": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _vp,
+                                            _vp]),
+    "tsk_model_train": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "tsk_model_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "tsk_model_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
 }
 
 _lib = None

@@ -15,14 +15,17 @@
 #include <vector>
 
 #include "launch.hpp"
+#include "model.hpp"
+#include "runtime.hpp"
 #include "tsknn.h"
 
 using namespace tsk;
 
 // ------------------------------------------------------------------ errors
-static thread_local std::string g_err;
+namespace tsk {
+thread_local std::string g_err;
 
-static int set_err(int code, const char *fmt, ...)
+int set_err(int code, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -32,56 +35,7 @@ static int set_err(int code, const char *fmt, ...)
     g_err = buf;
     return code;
 }
-
-#define HIP_TRY(expr)                                                                              \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) {                                                                    \
-            (void)hipGetLastError();                                                               \
-            return set_err(e_ == hipErrorOutOfMemory ? TSK_ERR_OOM : TSK_ERR_DEVICE, "%s: %s",     \
-                           #expr, hipGetErrorString(e_));                                          \
-        }                                                                                          \
-    } while (0)
-
-#define TSK_TRY(expr)                                                                              \
-    do {                                                                                           \
-        int rc_ = (expr);                                                                          \
-        if (rc_ != TSK_OK)                                                                         \
-            return rc_;                                                                            \
-    } while (0)
-
-// ------------------------------------------------------------------ device buffers
-template <typename T> struct DevBuf {
-    T *p = nullptr;
-    size_t cap = 0; // elements
-    int ensure(size_t n)
-    {
-        if (n <= cap && p)
-            return TSK_OK;
-        if (p) {
-            (void)hipFree(p);
-            p = nullptr;
-            cap = 0;
-        }
-        size_t want = std::max<size_t>(n, 1);
-        hipError_t e = hipMalloc((void **)&p, want * sizeof(T));
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            return set_err(e == hipErrorOutOfMemory ? TSK_ERR_OOM : TSK_ERR_DEVICE,
-                           "hipMalloc of %zu bytes: %s", want * sizeof(T), hipGetErrorString(e));
-        }
-        cap = want;
-        return TSK_OK;
-    }
-    void release()
-    {
-        if (p)
-            (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-    }
-};
+} // namespace tsk
 
 struct Workspace {
     DevBuf<uint32_t> tau;
@@ -119,10 +73,11 @@ struct Workspace {
     }
 };
 
-// Stage marks recorded per chunk when timing: start, after seed, after the
-// bound kernel, after compaction (+ walks), after query staging, after the
-// fast DP, after the general DP, after the output kernel.
-constexpr int NEV = 8;
+// Stage marks recorded per chunk when timing: start, after the learned
+// order, after seed, after the bound kernel, after compaction (+ walks),
+// after query staging, after the fast DP, after the general DP, after the
+// output kernel.
+constexpr int NEV = 9;
 
 struct tsk_index {
     int device = 0;
@@ -148,6 +103,12 @@ struct tsk_index {
     int64_t *bt_off = nullptr;
     float *bsoa = nullptr;
     int64_t n_btiles = 0;
+    // candidate embeddings of the encoder (uid, version) last used for
+    // TSK_ORDER_LEARNED
+    DevBuf<float> emb;
+    uint64_t emb_uid = 0, emb_version = 0;
+    DevBuf<float> qemb;
+    DevBuf<int32_t> lorder;
     hipStream_t last_stream = nullptr;
     Workspace ws;
     std::mutex mu;
@@ -205,14 +166,15 @@ static int sum_events(tsk_index *ix, size_t from, size_t to, float t[NEV - 1])
 
 static void stats_times(tsk_stats *st, const float t[NEV - 1])
 {
-    st->ms_seed = t[0];
-    st->ms_bound_kernel = t[1];
-    st->ms_bound = t[1] + t[2];
-    st->ms_dp_fast = t[4];
-    st->ms_dp_general = t[5];
-    st->ms_dp = t[3] + t[4] + t[5];
-    st->ms_final = t[6];
-    st->ms_total = t[0] + t[1] + t[2] + t[3] + t[4] + t[5] + t[6];
+    st->ms_order = t[0];
+    st->ms_seed = t[1];
+    st->ms_bound_kernel = t[2];
+    st->ms_bound = t[2] + t[3];
+    st->ms_dp_fast = t[5];
+    st->ms_dp_general = t[6];
+    st->ms_dp = t[4] + t[5] + t[6];
+    st->ms_final = t[7];
+    st->ms_total = t[0] + t[1] + t[2] + t[3] + t[4] + t[5] + t[6] + t[7];
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -343,6 +305,9 @@ static void free_index_memory(tsk_index *ix)
     if (ix->bt_off) (void)hipFree(ix->bt_off);
     if (ix->bsoa) (void)hipFree(ix->bsoa);
     ix->ws.release();
+    ix->emb.release();
+    ix->qemb.release();
+    ix->lorder.release();
     ix->prof_ctr.release();
     for (auto &e : ix->ev_pool)
         for (auto &x : e)
@@ -789,10 +754,16 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             return set_err(TSK_ERR_INVALID_ARG, "opts->size mismatch");
         o = *opts;
     }
-    if (o.order != TSK_ORDER_PLAIN && o.order != TSK_ORDER_GIVEN)
+    if (o.order != TSK_ORDER_PLAIN && o.order != TSK_ORDER_GIVEN && o.order != TSK_ORDER_LEARNED)
         return set_err(TSK_ERR_INVALID_ARG, "opts->order %d unknown", o.order);
     if (o.order == TSK_ORDER_GIVEN && !o.order_dev)
         return set_err(TSK_ERR_INVALID_ARG, "TSK_ORDER_GIVEN needs order_dev");
+    if (o.order == TSK_ORDER_LEARNED) {
+        if (!o.model)
+            return set_err(TSK_ERR_INVALID_ARG, "TSK_ORDER_LEARNED needs opts->model");
+        if (o.model->dim != cix->dim || o.model->device != cix->device)
+            return set_err(TSK_ERR_INVALID_ARG, "the model's dim/device differ from the index's");
+    }
     if (o.seed_count < 0)
         return set_err(TSK_ERR_INVALID_ARG, "seed_count must be >= 0");
     if (o.walk_pass < -1 || o.walk_pass > 1)
@@ -829,6 +800,25 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         TSK_TRY(ix->prof_ctr.ensure(C_NUM));
     const size_t ev_first = ix->ev_used;
 
+    tsk_model *model = const_cast<tsk_model *>(o.model);
+    std::unique_lock<std::mutex> mlock;
+    if (o.order == TSK_ORDER_LEARNED) {
+        mlock = std::unique_lock<std::mutex>(model->mu);
+        TSK_TRY(ix->qemb.ensure((size_t)P.chunk * model->embed));
+        TSK_TRY(ix->lorder.ensure((size_t)P.chunk * ix->n));
+        if (ix->emb_uid != model->uid || ix->emb_version != model->version) {
+            // candidate embeddings for the model's current parameters
+            TSK_TRY(ix->emb.ensure((size_t)ix->n * model->embed));
+            TSK_TRY(model_embed_dev(model, ix->aos, ix->off, ix->n, ix->emb.p, s));
+            ix->emb_uid = model->uid;
+            ix->emb_version = model->version;
+        }
+    }
+#define TSK_MARK(i)                                                                                \
+    do {                                                                                           \
+        if (timed)                                                                                 \
+            HIP_TRY(hipEventRecord(ev[i], s));                                                     \
+    } while (0)
     fill_u64(W.ctr.p, 0ull, C_NUM, s);
     for (int64_t q0 = 0; q0 < n_queries; q0 += P.chunk) {
         const int nq = (int)std::min<int64_t>(P.chunk, n_queries - q0);
@@ -846,6 +836,15 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         fill_u64(W.resslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
         fill_u32((uint32_t *)W.max_cnt.p, 0u, 1, s);
         fill_u64(W.work.p, 0ull, 8, s); // every task / list counter of the call
+        if (o.order == TSK_ORDER_LEARNED) {
+            // embed the chunk's queries, score every candidate, bucket-sort;
+            // the bound pass overwrites lbv (the scores' scratch) later
+            TSK_TRY(model_embed_dev(model, qv, W.qoff.p, nq, ix->qemb.p, s));
+            launch_embed_score(ix->qemb.p, nq, ix->emb.p, ix->n, model->embed, W.lbv.p, s);
+            launch_bucket_order(W.lbv.p, nq, ix->n, ix->lorder.p, s);
+            order = ix->lorder.p;
+        }
+        TSK_MARK(1);
         int32_t qmin = INT32_MAX, qmax = 0;
         for (int i = 0; i < nq; ++i) {
             const int32_t L = (int32_t)(q_offsets_host[q0 + i + 1] - q_offsets_host[q0 + i]);
@@ -872,12 +871,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         } else {
             dispatch_d<SeedLaunch>(P.D, ix, qv, nq, P, order, s);
         }
-#define TSK_MARK(i)                                                                                \
-    do {                                                                                           \
-        if (timed)                                                                                 \
-            HIP_TRY(hipEventRecord(ev[i], s));                                                     \
-    } while (0)
-        TSK_MARK(1);
+        TSK_MARK(2);
         BoundArgs ba = bound_args(ix, qv, nq, P);
         const bool dk_split = dist == TSK_DK && lds_query;
         // uneven lengths: LB_Box per length bucket, lbv by sorted position
@@ -892,7 +886,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         } else {
             dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
         }
-        TSK_MARK(2);
+        TSK_MARK(3);
         hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, order,
                            lbu ? ix->perm : nullptr, lbu ? ix->inv : nullptr, W.tau.p,
                            W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
@@ -905,7 +899,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             wa.work = W.work.p + 4;
             launch_walk_dk(P.D, wa, qv, W.ubslots.p, ix->n_cu * 8, qmax, s);
         }
-        TSK_MARK(3);
+        TSK_MARK(4);
         int wsel = -1;
         const int fast = pick_fast(ix, dist, band, qmin, qmax, o.dp_kernel, &wsel);
         DpArgs da = dp_args(ix, qv, nq, P);
@@ -915,7 +909,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             const int qrows = qmax + 2 * QPAD;
             TSK_TRY(W.qpad.ensure((size_t)nq * qrows * DP));
             dispatch_d<QpadLaunch>(P.D, qv, W.qoff.p, nq, qrows, W.qpad.p, s);
-            TSK_MARK(4);
+            TSK_MARK(5);
             FastArgs fa = fast_args(ix, nq, P, qrows);
             fa.lb_inv = lbu ? ix->inv : nullptr;
             if (fast == FAST_TUBE32) {
@@ -926,22 +920,22 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             }
             else
                 launch_band(P.D, dist, wsel, fa, ix->n_cu * 8, s);
-            TSK_MARK(5);
+            TSK_MARK(6);
             da.work = W.work.p + 2;
             launch_dp_wave(P.D, dist, DPW_FALLBACK, da, dp_blocks(ix), s);
         } else {
-            TSK_MARK(4);
             TSK_MARK(5);
+            TSK_MARK(6);
             launch_dp_wave(P.D, dist, DPW_SURV, da, dp_blocks(ix), s);
         }
-        TSK_MARK(6);
+        TSK_MARK(7);
         if (dist == TSK_DK)
             hipLaunchKernelGGL(k_finalize<DIST_DK>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq, k,
                                out_ids_dev + q0 * k, out_dist_dev + q0 * k);
         else
             hipLaunchKernelGGL(k_finalize<DIST_DTW>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq, k,
                                out_ids_dev + q0 * k, out_dist_dev + q0 * k);
-        TSK_MARK(7);
+        TSK_MARK(8);
 #undef TSK_MARK
         HIP_TRY(hipGetLastError());
     }
