@@ -111,6 +111,65 @@ def kernel_rooflines(prof, dist, d, fast_kernel):
     return out
 
 
+def learned_order(w, args, db, dbo, dev_db, dev_q, qo, idx_dk, idx_dtw, plain_res):
+    """Trains the encoder on DK distances of the train stream (untimed), then
+    times the same step with each query's candidates in learned order and
+    checks the rows equal the plain scan's."""
+    import numpy as np
+    import torch
+    from paper_1811_11076_amd import Model, synth
+    from paper_1811_11076_amd.learned import dk_training_set
+    t0 = time.perf_counter()
+    gen = synth.ClassWarp(w["cfg_id"], w["classes"], w["L"], w["d"])
+    # 200k pairs: 500 anchors x (200 same-class + 200 random) of a 2000-series pool
+    tv, to, ta, tb, ty = dk_training_set(gen, 2000, 500, 200, w.get("lengths", w["L"]), seed=1)
+    model = Model(w["d"], seed=1)
+    losses = model.train(torch.from_numpy(tv).cuda(), to, ta, tb, ty, epochs=10, batch=1024,
+                         lr=1e-3, seed=1)
+    t_train = time.perf_counter() - t0
+    print(f"[bench] encoder trained on {ta.size} pairs in {t_train:.1f}s, loss "
+          f"{losses[0]:.3f} -> {losses[-1]:.3f}", file=sys.stderr, flush=True)
+    k = w["k"]
+
+    def step(profile):
+        a = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], profile=profile, order="learned",
+                       model=model)
+        b = idx_dtw.knn(dev_q, qo, k, "dtw", w["dtw_band"], profile=profile, order="learned",
+                        model=model)
+        return a, b
+
+    for _ in range(args.warmup):
+        res = step(False)
+    torch.cuda.synchronize()
+    idx_dk.profile(reset=True)
+    idx_dtw.profile(reset=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    pdk = idx_dk.profile(reset=True)
+    pdtw = idx_dtw.profile(reset=True)
+    same = all(torch.equal(x, y) for x, y in zip(res[0][:2] + res[1][:2],
+                                                 plain_res[0][:2] + plain_res[1][:2]))
+    pairs = w["Q"] * w["N"]
+    calls = max(1, pdk["calls"])
+    model.close()
+    return {"ms_per_step": elapsed * 1e3 / args.steps,
+            "pairs_per_s": pairs / (elapsed / args.steps),
+            "rows_equal_plain": bool(same),
+            "train": {"pairs": int(ta.size), "epochs": 10, "batch": 1024, "seconds": t_train,
+                      "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])},
+            "dk": {"device_ms": pdk["ms_total"] / calls, "order_ms": pdk["ms_order"] / calls,
+                   "dp_completed": pdk["dp_completed"] / calls,
+                   "dp_valid_cells": pdk["dp_valid_cells"] / calls},
+            "dtw": {"device_ms": pdtw["ms_total"] / max(1, pdtw["calls"]),
+                    "order_ms": pdtw["ms_order"] / max(1, pdtw["calls"]),
+                    "dp_completed": pdtw["dp_completed"] / max(1, pdtw["calls"])},
+            "dk_fraction_full_dps": pdk["dp_completed"] / calls / pairs}
+
+
 def cpu_baseline(db, dbo, qs, qo, w, nq_sample):
     import numpy as np
     import oracle as O
@@ -140,6 +199,7 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-queries", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
@@ -181,6 +241,10 @@ def main():
     prof_dk = idx_dk.profile(reset=True)
     prof_dtw = idx_dtw.profile(reset=True)
 
+    learned = None
+    if not args.no_learned and w["gen"] == "classwarp":
+        learned = learned_order(w, args, db, dbo, dev_db, dev_q, qo, idx_dk, idx_dtw, res)
+
     pairs = w["Q"] * w["N"]
     ms_step = elapsed * 1e3 / args.steps
     value = pairs / (ms_step * 1e-3)
@@ -219,6 +283,11 @@ def main():
                 "dp_valid_cells": prof_dtw["dp_valid_cells"] / max(1, prof_dtw["calls"])},
         "dk_vs_dtw_speedup": dtw_ms / dk_ms if dk_ms > 0 else None,
     }
+    if learned is not None:
+        learned["speedup_vs_plain"] = ms_step / learned["ms_per_step"]
+        learned["dk_speedup_vs_plain"] = dk_ms / learned["dk"]["device_ms"]
+        learned["dk_fraction_full_dps_plain"] = prof_dk["dp_completed"] / max(1, prof_dk["calls"]) / pairs
+        out["learned_order"] = learned
     if not args.no_cpu_baseline:
         cb, (sel, dk_ref, dtw_ref) = cpu_baseline(db, dbo, qs, qo, w, args.cpu_queries)
         out["cpu_baseline"] = cb

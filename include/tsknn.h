@@ -77,6 +77,8 @@ typedef struct {
  * how early the threshold falls (and so how much work is pruned). */
 enum { TSK_ORDER_PLAIN = 0, TSK_ORDER_GIVEN = 1, TSK_ORDER_LEARNED = 2 };
 
+enum { TSK_TUNE_OFF = 0, TSK_TUNE_CACHED = 1 };
+
 typedef struct tsk_index tsk_index;
 
 /* Encoder that predicts distances for TSK_ORDER_LEARNED (not part of the
@@ -120,7 +122,14 @@ typedef struct {
                                       the first seed_count entries form the
                                       seed set and survivors are processed in
                                       this order */
-    int32_t use_graph;             /* reserved (0) */
+    int32_t use_graph;             /* 1: the call (one chunk of queries:
+                                      up to 2^28 / n_series of them) runs as
+                                      one captured HIP graph, cached on the
+                                      index and replayed while the call
+                                      repeats (same pointers, offsets, k,
+                                      distance, band and options); excludes
+                                      profile and TSK_ORDER_LEARNED; with
+                                      stats_host only ms_total is timed */
     int32_t dp_kernel;             /* 0 auto, 1 force the general DP */
     int32_t profile;               /* 1: record per-stage HIP events on the
                                       stream and add this call's counters to
@@ -136,6 +145,14 @@ typedef struct {
                                       16);
                                       pairs whose live cells outgrow it finish
                                       in the general DP */
+    int32_t lb_qgroup;             /* queries per wave of the length-bucket
+                                      LB_Box kernel: 2, 4 or 8 (0 = 4) */
+    int32_t tune;                  /* TSK_TUNE_CACHED: take seed_count,
+                                      tube_rows, task_size, walk_pass and
+                                      lb_qgroup from the index's tuning cache
+                                      for this (distance, band, k), if
+                                      tsk_tune filled it; TSK_TUNE_OFF: as
+                                      given */
     const tsk_model *model;        /* TSK_ORDER_LEARNED: the encoder; each
                                       query's candidates are taken in
                                       ascending embedding distance.  The
@@ -217,6 +234,27 @@ int tsk_pair_bounds(const tsk_index *index, const float *q_values_dev,
                     const int64_t *q_offsets_host, int64_t n_queries, int32_t dist,
                     tsk_band band, float *out_lb_dev, float *out_ub_dev,
                     int32_t *out_steps_dev, void *hip_stream);
+
+typedef struct {
+    int64_t size;           /* sizeof(tsk_tune_opts) */
+    int32_t sample_queries; /* queries per trial (0 = min(n_queries, 64)) */
+    int32_t reps;           /* timed repetitions per trial, best kept (0 = 2) */
+} tsk_tune_opts;
+
+/* Autotuner (not in the paper: a scheduling aid whose choices never change
+ * results).  Times k-NN calls on the first sample_queries queries for a set
+ * of settings of the work-shaping options (seed size; DK sparse-DP window
+ * rows, survivors per wave task and the greedy pass; queries per wave of the
+ * length-bucket LB_Box kernel), one option at a time from the library
+ * defaults (coordinate descent), keeping the fastest.  *best_out receives
+ * base (nullable: defaults) with the tuned fields set, *best_ms_out
+ * (nullable) its time; the choice is cached on the index for (dist, band,
+ * k) and used by calls with opts->tune = TSK_TUNE_CACHED.  Synchronous.
+ * Errors: as tsk_knn_query. */
+int tsk_tune(tsk_index *index, const float *q_values_dev, const int64_t *q_offsets_host,
+             int64_t n_queries, int32_t k, int32_t dist, tsk_band band,
+             const tsk_query_opts *base, const tsk_tune_opts *tune_opts,
+             tsk_query_opts *best_out, float *best_ms_out, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Learned candidate ordering.  An MLP encoder maps a series, resampled to

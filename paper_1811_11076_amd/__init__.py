@@ -87,17 +87,28 @@ class Index:
 
     def knn(self, queries, q_offsets, k: int, distance: str = "dk", band=None, order=None,
             seed_count: int = 0, stats: bool = False, profile: bool = False,
-            walk_pass: int = -1, task_size: int = 0, tube_rows: int = 0, model=None):
+            walk_pass: int = -1, task_size: int = 0, tube_rows: int = 0, model=None,
+            lb_qgroup: int = 0, use_graph: bool = False, tune: bool = False, out=None):
         """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
         float32 [nq, k], stats dict or None); DK distances are unsquared.
         order: None (plain), a CUDA int32 [nq, n] permutation per query, or
-        "learned" with model= a Model (candidates by embedding distance)."""
+        "learned" with model= a Model (candidates by embedding distance).
+        use_graph: run as a cached, replayed HIP graph (pass the same `out`
+        tensors (ids, dist) to replay); tune: use the index's tuned options
+        (see tune())."""
         torch = _torch()
         qv = _values(queries, self.dim)
         qo = _offsets(q_offsets)
         nq = int(qo.shape[0] - 1)
-        ids = torch.empty((nq, k), dtype=torch.int64, device=qv.device)
-        dist = torch.empty((nq, k), dtype=torch.float32, device=qv.device)
+        if out is not None:
+            ids, dist = out
+            if (ids.dtype != torch.int64 or dist.dtype != torch.float32 or
+                    tuple(ids.shape) != (nq, k) or tuple(dist.shape) != (nq, k) or
+                    not ids.is_contiguous() or not dist.is_contiguous()):
+                raise ValueError("out must be contiguous (int64 [nq, k], float32 [nq, k])")
+        else:
+            ids = torch.empty((nq, k), dtype=torch.int64, device=qv.device)
+            dist = torch.empty((nq, k), dtype=torch.float32, device=qv.device)
         opts = _lib.QueryOpts()
         opts.size = ctypes.sizeof(_lib.QueryOpts)
         opts.seed_count = int(seed_count)
@@ -105,6 +116,9 @@ class Index:
         opts.walk_pass = int(walk_pass)
         opts.task_size = int(task_size)
         opts.tube_rows = int(tube_rows)
+        opts.lb_qgroup = int(lb_qgroup)
+        opts.use_graph = 1 if use_graph else 0
+        opts.tune = _lib.TSK_TUNE_CACHED if tune else _lib.TSK_TUNE_OFF
         if isinstance(order, str):
             if order != "learned" or model is None:
                 raise ValueError('order="learned" needs model=')
@@ -123,6 +137,24 @@ class Index:
             ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
             ctypes.byref(st) if st is not None else None, _stream()))
         return ids, dist, (st.as_dict() if st is not None else None)
+
+    def tune(self, queries, q_offsets, k: int, distance: str = "dk", band=None,
+             sample_queries: int = 0, reps: int = 0):
+        """Autotunes the work-shaping options on a query sample (C: tsk_tune);
+        returns (chosen options dict, milliseconds of the sample call).  Later
+        knn(..., tune=True) calls with this (distance, band, k) use them."""
+        qv = _values(queries, self.dim)
+        qo = _offsets(q_offsets)
+        nq = int(qo.shape[0] - 1)
+        to = _lib.TuneOpts(ctypes.sizeof(_lib.TuneOpts), int(sample_queries), int(reps))
+        best = _lib.QueryOpts()
+        ms = ctypes.c_float()
+        _lib.check(self._lib.tsk_tune(
+            self._h, ctypes.c_void_p(qv.data_ptr()), qo.ctypes.data_as(ctypes.c_void_p), nq,
+            int(k), _DIST[distance], _lib.band_struct(band), None, ctypes.byref(to),
+            ctypes.byref(best), ctypes.byref(ms), _stream()))
+        keys = ("seed_count", "tube_rows", "task_size", "walk_pass", "lb_qgroup")
+        return {key: getattr(best, key) for key in keys}, ms.value
 
     def profile(self, reset: bool = False) -> dict:
         """Counters and stage times accumulated by knn(..., profile=True)

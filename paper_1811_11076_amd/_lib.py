@@ -17,6 +17,7 @@ TSK_ERR_CANCELLED = 6
 TSK_DTW, TSK_DK = 0, 1
 TSK_BAND_NONE, TSK_BAND_ABS, TSK_BAND_FRAC = 0, 1, 2
 TSK_ORDER_PLAIN, TSK_ORDER_GIVEN, TSK_ORDER_LEARNED = 0, 1, 2
+TSK_TUNE_OFF, TSK_TUNE_CACHED = 0, 1
 
 _ERRNAMES = {1: "INVALID_ARG", 2: "OOM", 3: "DEVICE", 4: "UNSUPPORTED", 5: "IO", 6: "CANCELLED"}
 
@@ -36,7 +37,8 @@ class QueryOpts(ctypes.Structure):
                 ("order_dev", ctypes.c_void_p), ("use_graph", ctypes.c_int32),
                 ("dp_kernel", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("walk_pass", ctypes.c_int32), ("task_size", ctypes.c_int32),
-                ("tube_rows", ctypes.c_int32), ("model", ctypes.c_void_p)]
+                ("tube_rows", ctypes.c_int32), ("lb_qgroup", ctypes.c_int32),
+                ("tune", ctypes.c_int32), ("model", ctypes.c_void_p)]
 
 
 class IndexOpts(ctypes.Structure):
@@ -58,6 +60,11 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class TuneOpts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int64), ("sample_queries", ctypes.c_int32),
+                ("reps", ctypes.c_int32)]
 
 
 class MlpShape(ctypes.Structure):
@@ -86,6 +93,7 @@ SIGNATURES = {
     "tsk_index_profile": (ctypes.c_int, [_vp, _vp, _i32]),
     "tsk_pair_distances": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp]),
     "tsk_pair_bounds": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp, _vp, _vp]),
+    "tsk_tune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, Band, _vp, _vp, _vp, _vp, _vp]),
     "tsk_model_create": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "tsk_model_free": (ctypes.c_int, [_vp]),
     "tsk_model_info": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_i64)]),

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <array>
+#include <map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -109,6 +110,14 @@ struct tsk_index {
     uint64_t emb_uid = 0, emb_version = 0;
     DevBuf<float> qemb;
     DevBuf<int32_t> lorder;
+    // executable graph of the last use_graph call and what it was built for
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<int64_t> graph_key;
+    int64_t graph_builds = 0;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    hipStream_t cap_stream = nullptr; // capture-only stream of use_graph
+    // tsk_tune's choices per (dist, band mode, band r, band frac bits, k)
+    std::map<std::array<int64_t, 5>, tsk_query_opts> tune_cache;
     hipStream_t last_stream = nullptr;
     Workspace ws;
     std::mutex mu;
@@ -175,6 +184,13 @@ static void stats_times(tsk_stats *st, const float t[NEV - 1])
     st->ms_dp = t[4] + t[5] + t[6];
     st->ms_final = t[7];
     st->ms_total = t[0] + t[1] + t[2] + t[3] + t[4] + t[5] + t[6] + t[7];
+}
+
+static uint32_t f_bits_host(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, sizeof(u));
+    return u;
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -304,6 +320,13 @@ static void free_index_memory(tsk_index *ix)
         if (p) (void)hipFree(p);
     if (ix->bt_off) (void)hipFree(ix->bt_off);
     if (ix->bsoa) (void)hipFree(ix->bsoa);
+    if (ix->graph_exec)
+        (void)hipGraphExecDestroy(ix->graph_exec);
+    for (auto &e : ix->gev)
+        if (e)
+            (void)hipEventDestroy(e);
+    if (ix->cap_stream)
+        (void)hipStreamDestroy(ix->cap_stream);
     ix->ws.release();
     ix->emb.release();
     ix->qemb.release();
@@ -709,9 +732,11 @@ static int upload_qoff(tsk_index *ix, const int64_t *qoff, int64_t q0, int64_t n
     return TSK_OK;
 }
 
-// Sparse tables of a chunk's queries for the length-bucket bound pass.
-static int build_qtables(tsk_index *ix, const float *qv, const int64_t *qoff_host, int64_t q0,
-                         int nq, hipStream_t s)
+// Sparse-table offsets of a chunk's queries (length-bucket bound pass):
+// host arithmetic, allocation and upload; the tables themselves are built
+// by a kernel in the query sequence.
+static int prepare_qtables(tsk_index *ix, const int64_t *qoff_host, int64_t q0, int nq,
+                           hipStream_t s)
 {
     const int DP = ix->dim <= 4 ? 4 : 8;
     std::vector<int64_t> &h = ix->ws.h_qtab;
@@ -722,7 +747,6 @@ static int build_qtables(tsk_index *ix, const float *qv, const int64_t *qoff_hos
     TSK_TRY(ix->ws.qtab_off.ensure(nq + 1));
     HIP_TRY(hipMemcpyAsync(ix->ws.qtab_off.p, h.data(), (nq + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
-    launch_qtable(ix->dim, qv, ix->ws.qoff.p, nq, ix->ws.qtab_off.p, ix->ws.qtab.p, s);
     return TSK_OK;
 }
 
@@ -730,6 +754,21 @@ static int64_t chunk_queries(const tsk_index *ix, int64_t nq)
 {
     const int64_t budget = (int64_t)1 << 28; // (query, candidate) entries per chunk
     return std::max<int64_t>(1, std::min<int64_t>(nq, budget / std::max<int64_t>(1, ix->n)));
+}
+
+static std::array<int64_t, 5> tune_key(int32_t dist, tsk_band band, int32_t k)
+{
+    return {dist, band.mode, band.r, (int64_t)f_bits_host(band.frac), k};
+}
+
+// The fields tsk_tune chooses.
+static void apply_tuned(tsk_query_opts *o, const tsk_query_opts &t)
+{
+    o->seed_count = t.seed_count;
+    o->tube_rows = t.tube_rows;
+    o->task_size = t.task_size;
+    o->walk_pass = t.walk_pass;
+    o->lb_qgroup = t.lb_qgroup;
 }
 
 extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
@@ -772,9 +811,20 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "task_size out of range");
     if (o.tube_rows != 0 && o.tube_rows != 16 && o.tube_rows != 32)
         return set_err(TSK_ERR_INVALID_ARG, "tube_rows must be 0, 16 or 32");
+    if (o.lb_qgroup != 0 && o.lb_qgroup != 2 && o.lb_qgroup != 4 && o.lb_qgroup != 8)
+        return set_err(TSK_ERR_INVALID_ARG, "lb_qgroup must be 0, 2, 4 or 8");
+    if (o.use_graph && (o.profile || o.order == TSK_ORDER_LEARNED))
+        return set_err(TSK_ERR_UNSUPPORTED, "use_graph excludes profile and TSK_ORDER_LEARNED");
     tsk_index *ix = const_cast<tsk_index *>(cix);
     std::lock_guard<std::mutex> lock(ix->mu);
     hipStream_t s = (hipStream_t)hip_stream;
+    if (o.tune == TSK_TUNE_CACHED) {
+        auto it = ix->tune_cache.find(tune_key(dist, band, k));
+        if (it != ix->tune_cache.end())
+            apply_tuned(&o, it->second);
+    } else if (o.tune != TSK_TUNE_OFF) {
+        return set_err(TSK_ERR_INVALID_ARG, "opts->tune %d unknown", o.tune);
+    }
 
     QueryPlan P;
     P.D = ix->dim;
@@ -784,6 +834,9 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
     P.nq = n_queries;
     P.N = ix->n;
     P.chunk = chunk_queries(ix, n_queries);
+    if (o.use_graph && P.chunk < n_queries)
+        return set_err(TSK_ERR_UNSUPPORTED, "use_graph needs the queries to fit one chunk "
+                                            "(%lld here)", (long long)P.chunk);
     // seed sizes: the greedy DK seed is a latency-bound walk (a few hundred
     // candidates give a tight threshold); the diagonal DTW seed is a cheap
     // parallel sum, so it takes more candidates
@@ -814,22 +867,59 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             ix->emb_version = model->version;
         }
     }
+
+    // Host-side plan of one chunk of queries; prepare() does its uploads and
+    // allocations, enqueue() only launches kernels (so it can be captured).
+    struct Chunk {
+        int64_t q0;
+        int nq;
+        int32_t qmin, qmax;
+        const int32_t *order;
+        bool lds_query, dk_split, lbu, diag_seed;
+        int fast, wsel, qrows;
+    };
+    auto plan_chunk = [&](int64_t q0) {
+        Chunk c;
+        c.q0 = q0;
+        c.nq = (int)std::min<int64_t>(P.chunk, n_queries - q0);
+        c.order = o.order == TSK_ORDER_GIVEN ? o.order_dev + q0 * ix->n : nullptr;
+        if (o.order == TSK_ORDER_LEARNED)
+            c.order = ix->lorder.p;
+        c.qmin = INT32_MAX;
+        c.qmax = 0;
+        for (int i = 0; i < c.nq; ++i) {
+            const int32_t L = (int32_t)(q_offsets_host[q0 + i + 1] - q_offsets_host[q0 + i]);
+            c.qmin = std::min(c.qmin, L);
+            c.qmax = std::max(c.qmax, L);
+        }
+        c.lds_query = walk_lds_bytes(P.D, c.qmax) <= 64 * 1024 && o.dp_kernel != 1;
+        c.dk_split = dist == TSK_DK && c.lds_query;
+        // uneven lengths: LB_Box per length bucket, lbv by sorted position
+        c.lbu = dist == TSK_DTW && !P.env_ok && ix->bucketed && o.dp_kernel != 1;
+        c.diag_seed = P.seed > 0 && dist == TSK_DTW && c.qmin == c.qmax &&
+                      ix->min_len == ix->max_len && ix->min_len == c.qmin && o.dp_kernel != 1;
+        c.fast = pick_fast(ix, dist, band, c.qmin, c.qmax, o.dp_kernel, &c.wsel);
+        c.qrows = c.qmax + 2 * QPAD;
+        return c;
+    };
+    auto prepare_chunk = [&](const Chunk &c) -> int {
+        TSK_TRY(upload_qoff(ix, q_offsets_host, c.q0, c.nq, s));
+        if (c.lbu)
+            TSK_TRY(prepare_qtables(ix, q_offsets_host, c.q0, c.nq, s));
+        if (c.fast != FAST_NONE)
+            TSK_TRY(W.qpad.ensure((size_t)c.nq * c.qrows * (P.D <= 4 ? 4 : 8)));
+        return TSK_OK;
+    };
+    // s: the stream to enqueue on (the caller's, or the capture stream)
+    auto enqueue_chunk = [&](const Chunk &c, hipEvent_t *ev, hipStream_t s) -> int {
 #define TSK_MARK(i)                                                                                \
     do {                                                                                           \
-        if (timed)                                                                                 \
+        if (ev)                                                                                    \
             HIP_TRY(hipEventRecord(ev[i], s));                                                     \
     } while (0)
-    fill_u64(W.ctr.p, 0ull, C_NUM, s);
-    for (int64_t q0 = 0; q0 < n_queries; q0 += P.chunk) {
-        const int nq = (int)std::min<int64_t>(P.chunk, n_queries - q0);
-        const int32_t *order = o.order == TSK_ORDER_GIVEN ? o.order_dev + q0 * ix->n : nullptr;
-        TSK_TRY(upload_qoff(ix, q_offsets_host, q0, nq, s));
+        const int nq = c.nq;
         const float *qv = q_values_dev; // offsets are absolute into q_values_dev
-        hipEvent_t *ev = nullptr;
-        if (timed) {
-            TSK_TRY(take_events(ix, &ev));
-            HIP_TRY(hipEventRecord(ev[0], s));
-        }
+        TSK_MARK(0);
         fill_u32(W.tau.p, TSK_INF_BITS, nq, s);
         fill_u64(W.seedslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
         fill_u64(W.ubslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
@@ -842,84 +932,65 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             TSK_TRY(model_embed_dev(model, qv, W.qoff.p, nq, ix->qemb.p, s));
             launch_embed_score(ix->qemb.p, nq, ix->emb.p, ix->n, model->embed, W.lbv.p, s);
             launch_bucket_order(W.lbv.p, nq, ix->n, ix->lorder.p, s);
-            order = ix->lorder.p;
         }
         TSK_MARK(1);
-        int32_t qmin = INT32_MAX, qmax = 0;
-        for (int i = 0; i < nq; ++i) {
-            const int32_t L = (int32_t)(q_offsets_host[q0 + i + 1] - q_offsets_host[q0 + i]);
-            qmin = std::min(qmin, L);
-            qmax = std::max(qmax, L);
-        }
-        const size_t qrow_bytes = (size_t)(P.D <= 4 ? 4 : 8) * sizeof(float);
-        const size_t lds_cap = 64 * 1024;
         if (P.env_ok)
             dispatch_d<EnvLaunch>(P.D, ix, qv, nq, P.ba, s);
-        const bool lds_query = walk_lds_bytes(P.D, qmax) <= lds_cap && o.dp_kernel != 1;
-        (void)qrow_bytes;
-        SeedRingArgs seed_args{qv, W.qoff.p, nq, qmax, ix->aos, ix->off, ix->len, ix->n, order,
-                               0, P.seed, k, P.ba, W.seedslots.p, W.tau.p, W.ctr.p, nullptr,
-                               nullptr};
-        if (P.seed > 0 && dist == TSK_DTW && qmin == qmax && ix->min_len == ix->max_len &&
-            ix->min_len == qmin && o.dp_kernel != 1) {
+        SeedRingArgs seed_args{qv, W.qoff.p, nq, c.qmax, ix->aos, ix->off, ix->len, ix->n,
+                               c.order, 0, P.seed, k, P.ba, W.seedslots.p, W.tau.p, W.ctr.p,
+                               nullptr, nullptr};
+        if (c.diag_seed) {
             // equal lengths: diagonal-path sums seed the DTW threshold
             launch_seed_diag(P.D, seed_args, s);
-        } else if (P.seed > 0 && lds_query) {
+        } else if (P.seed > 0 && c.lds_query) {
             // the first 64 candidates walk to the end and set a threshold;
             // the rest of the seed set returns early against it
             launch_seed_ring(P.D, dist, seed_args, s);
         } else {
-            dispatch_d<SeedLaunch>(P.D, ix, qv, nq, P, order, s);
+            dispatch_d<SeedLaunch>(P.D, ix, qv, nq, P, c.order, s);
         }
         TSK_MARK(2);
         BoundArgs ba = bound_args(ix, qv, nq, P);
-        const bool dk_split = dist == TSK_DK && lds_query;
-        // uneven lengths: LB_Box per length bucket, lbv by sorted position
-        const bool lbu = dist == TSK_DTW && !P.env_ok && ix->bucketed && o.dp_kernel != 1;
-        if (dk_split) {
+        if (c.dk_split) {
             launch_corner(P.D, ba, s);
         } else if (dist == TSK_DTW && P.env_ok && o.dp_kernel != 1) {
             launch_bound_lb(P.D, ba, false, s);
-        } else if (lbu) {
-            TSK_TRY(build_qtables(ix, qv, q_offsets_host, q0, nq, s));
-            launch_bound_lbu(P.D, ba, bucket_args(ix), W.qtab.p, W.qtab_off.p, 4, false, s);
+        } else if (c.lbu) {
+            launch_qtable(P.D, qv, W.qoff.p, nq, W.qtab_off.p, W.qtab.p, s);
+            launch_bound_lbu(P.D, ba, bucket_args(ix), W.qtab.p, W.qtab_off.p,
+                             o.lb_qgroup > 0 ? o.lb_qgroup : 4, false, s);
         } else {
             dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
         }
         TSK_MARK(3);
-        hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, order,
-                           lbu ? ix->perm : nullptr, lbu ? ix->inv : nullptr, W.tau.p,
+        hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, c.order,
+                           c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr, W.tau.p,
                            W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
         // the greedy pass over the corner survivors costs more than the DP
         // work its tighter threshold saves on the class-warp workloads, so
         // it runs only on request
-        if (dk_split && o.walk_pass == 1) {
+        if (c.dk_split && o.walk_pass == 1) {
             // greedy bound (Alg. 1) of every survivor of the corner bound
             FastArgs wa = fast_args(ix, nq, P, 0);
             wa.work = W.work.p + 4;
-            launch_walk_dk(P.D, wa, qv, W.ubslots.p, ix->n_cu * 8, qmax, s);
+            launch_walk_dk(P.D, wa, qv, W.ubslots.p, ix->n_cu * 8, c.qmax, s);
         }
         TSK_MARK(4);
-        int wsel = -1;
-        const int fast = pick_fast(ix, dist, band, qmin, qmax, o.dp_kernel, &wsel);
         DpArgs da = dp_args(ix, qv, nq, P);
-        da.lb_inv = lbu ? ix->inv : nullptr;
-        if (fast != FAST_NONE) {
-            const int DP = P.D <= 4 ? 4 : 8;
-            const int qrows = qmax + 2 * QPAD;
-            TSK_TRY(W.qpad.ensure((size_t)nq * qrows * DP));
-            dispatch_d<QpadLaunch>(P.D, qv, W.qoff.p, nq, qrows, W.qpad.p, s);
+        da.lb_inv = c.lbu ? ix->inv : nullptr;
+        if (c.fast != FAST_NONE) {
+            dispatch_d<QpadLaunch>(P.D, qv, W.qoff.p, nq, c.qrows, W.qpad.p, s);
             TSK_MARK(5);
-            FastArgs fa = fast_args(ix, nq, P, qrows);
-            fa.lb_inv = lbu ? ix->inv : nullptr;
-            if (fast == FAST_TUBE32) {
+            FastArgs fa = fast_args(ix, nq, P, c.qrows);
+            fa.lb_inv = c.lbu ? ix->inv : nullptr;
+            if (c.fast == FAST_TUBE32) {
                 fa.task = o.task_size > 0 ? o.task_size : 64;
                 // 16-row windows: the live tube of near neighbours is a few
                 // rows wide; the rare wider ones finish in the general DP
-                launch_tube(P.D, fa, o.tube_rows == 32 ? 32 : 16, ix->n_cu * 8, qmax, s);
+                launch_tube(P.D, fa, o.tube_rows == 32 ? 32 : 16, ix->n_cu * 8, c.qmax, s);
+            } else {
+                launch_band(P.D, dist, c.wsel, fa, ix->n_cu * 8, s);
             }
-            else
-                launch_band(P.D, dist, wsel, fa, ix->n_cu * 8, s);
             TSK_MARK(6);
             da.work = W.work.p + 2;
             launch_dp_wave(P.D, dist, DPW_FALLBACK, da, dp_blocks(ix), s);
@@ -931,13 +1002,85 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         TSK_MARK(7);
         if (dist == TSK_DK)
             hipLaunchKernelGGL(k_finalize<DIST_DK>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq, k,
-                               out_ids_dev + q0 * k, out_dist_dev + q0 * k);
+                               out_ids_dev + c.q0 * k, out_dist_dev + c.q0 * k);
         else
-            hipLaunchKernelGGL(k_finalize<DIST_DTW>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq, k,
-                               out_ids_dev + q0 * k, out_dist_dev + q0 * k);
+            hipLaunchKernelGGL(k_finalize<DIST_DTW>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq,
+                               k, out_ids_dev + c.q0 * k, out_dist_dev + c.q0 * k);
         TSK_MARK(8);
 #undef TSK_MARK
         HIP_TRY(hipGetLastError());
+        return TSK_OK;
+    };
+
+    if (o.use_graph) {
+        // one chunk, replayed from a cached executable graph when the call
+        // repeats (same inputs, outputs, shape and options)
+        const Chunk c = plan_chunk(0);
+        TSK_TRY(prepare_chunk(c));
+        std::vector<int64_t> key = {(int64_t)(uintptr_t)q_values_dev, n_queries, k, dist,
+                                    band.mode, band.r, (int64_t)f_bits_host(band.frac),
+                                    (int64_t)(uintptr_t)out_ids_dev,
+                                    (int64_t)(uintptr_t)out_dist_dev, (int64_t)(uintptr_t)s,
+                                    o.order, (int64_t)(uintptr_t)o.order_dev, o.seed_count,
+                                    o.dp_kernel, o.walk_pass, o.task_size, o.tube_rows,
+                                    o.lb_qgroup};
+        // every workspace buffer the captured kernels address: a buffer
+        // reallocated by another call changes the key
+        for (const void *ptr :
+             {(const void *)W.tau.p, (const void *)W.seedslots.p, (const void *)W.ubslots.p,
+              (const void *)W.resslots.p, (const void *)W.lbv.p, (const void *)W.surv.p,
+              (const void *)W.surv_cnt.p, (const void *)W.max_cnt.p, (const void *)W.ctr.p,
+              (const void *)W.work.p, (const void *)W.qoff.p, (const void *)W.env.p,
+              (const void *)W.tbuf.p, (const void *)W.qpad.p, (const void *)W.fb.p,
+              (const void *)W.qtab.p, (const void *)W.qtab_off.p})
+            key.push_back((int64_t)(uintptr_t)ptr);
+        key.insert(key.end(), q_offsets_host, q_offsets_host + n_queries + 1);
+        if (stats_host) {
+            if (!ix->gev[0])
+                for (auto &e : ix->gev)
+                    HIP_TRY(hipEventCreate(&e));
+            HIP_TRY(hipEventRecord(ix->gev[0], s));
+        }
+        if (!ix->graph_exec || key != ix->graph_key) {
+            if (ix->graph_exec) {
+                (void)hipGraphExecDestroy(ix->graph_exec);
+                ix->graph_exec = nullptr;
+            }
+            // captured on a private stream (the caller's may be the null
+            // stream, which cannot be captured); launched on the caller's
+            if (!ix->cap_stream)
+                HIP_TRY(hipStreamCreateWithFlags(&ix->cap_stream, hipStreamNonBlocking));
+            hipStream_t cs = ix->cap_stream;
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            fill_u64(W.ctr.p, 0ull, C_NUM, cs);
+            const int rc = enqueue_chunk(c, nullptr, cs);
+            const hipError_t ec = hipStreamEndCapture(cs, &g);
+            if (rc != TSK_OK) {
+                if (g)
+                    (void)hipGraphDestroy(g);
+                return rc;
+            }
+            HIP_TRY(ec);
+            const hipError_t ei = hipGraphInstantiate(&ix->graph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_TRY(ei);
+            ix->graph_key = key;
+            ++ix->graph_builds;
+        }
+        HIP_TRY(hipGraphLaunch(ix->graph_exec, s));
+        if (stats_host)
+            HIP_TRY(hipEventRecord(ix->gev[1], s));
+    } else {
+        fill_u64(W.ctr.p, 0ull, C_NUM, s);
+        for (int64_t q0 = 0; q0 < n_queries; q0 += P.chunk) {
+            const Chunk c = plan_chunk(q0);
+            TSK_TRY(prepare_chunk(c));
+            hipEvent_t *ev = nullptr;
+            if (timed)
+                TSK_TRY(take_events(ix, &ev));
+            TSK_TRY(enqueue_chunk(c, ev, s));
+        }
     }
     HIP_TRY(hipGetLastError());
     if (profile) {
@@ -948,14 +1091,19 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         unsigned long long c[C_NUM];
         HIP_TRY(hipMemcpyAsync(c, W.ctr.p, sizeof(c), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        float t[NEV - 1];
-        TSK_TRY(sum_events(ix, ev_first, ix->ev_used, t));
-        if (!profile)
-            ix->ev_used = ev_first; // these events are not part of a profile
         memset(stats_host, 0, sizeof(*stats_host));
         stats_from(stats_host, c);
         stats_host->calls = 1;
-        stats_times(stats_host, t);
+        if (o.use_graph) {
+            // a replayed graph is timed as one interval (no stage marks)
+            HIP_TRY(hipEventElapsedTime(&stats_host->ms_total, ix->gev[0], ix->gev[1]));
+        } else {
+            float t[NEV - 1];
+            TSK_TRY(sum_events(ix, ev_first, ix->ev_used, t));
+            if (!profile)
+                ix->ev_used = ev_first; // these events are not part of a profile
+            stats_times(stats_host, t);
+        }
     }
     return TSK_OK;
 }
@@ -1056,7 +1204,8 @@ extern "C" int tsk_pair_bounds(const tsk_index *cix, const float *q_values_dev,
         if (dist == TSK_DTW && P.env_ok && ba.dbg_lb)
             launch_bound_lb(P.D, ba, true, s);
         if (dist == TSK_DTW && !P.env_ok && ix->bucketed && ba.dbg_lb) {
-            TSK_TRY(build_qtables(ix, q_values_dev, q_offsets_host, q0, nq, s));
+            TSK_TRY(prepare_qtables(ix, q_offsets_host, q0, nq, s));
+            launch_qtable(P.D, q_values_dev, ix->ws.qoff.p, nq, ix->ws.qtab_off.p, ix->ws.qtab.p, s);
             launch_bound_lbu(P.D, ba, bucket_args(ix), ix->ws.qtab.p, ix->ws.qtab_off.p, 4, true, s);
         }
         int32_t qmax = 0;
@@ -1072,4 +1221,115 @@ extern "C" int tsk_pair_bounds(const tsk_index *cix, const float *q_values_dev,
     }
     HIP_TRY(hipStreamSynchronize(s));
     return TSK_OK;
+}
+
+extern "C" int tsk_tune(tsk_index *ix, const float *q_values_dev, const int64_t *q_offsets_host,
+                        int64_t n_queries, int32_t k, int32_t dist, tsk_band band,
+                        const tsk_query_opts *base, const tsk_tune_opts *topts,
+                        tsk_query_opts *best_out, float *best_ms_out, void *hip_stream)
+{
+    g_err.clear();
+    TSK_TRY(check_queries(ix, q_values_dev, q_offsets_host, n_queries, dist, band));
+    if (k < 1 || k > TSK_MAX_K)
+        return set_err(k < 1 ? TSK_ERR_INVALID_ARG : TSK_ERR_UNSUPPORTED, "k %d out of range", k);
+    if (topts && topts->size != (int64_t)sizeof(tsk_tune_opts))
+        return set_err(TSK_ERR_INVALID_ARG, "tune_opts->size mismatch");
+    tsk_query_opts b;
+    memset(&b, 0, sizeof(b));
+    b.size = sizeof(b);
+    b.walk_pass = -1;
+    if (base) {
+        if (base->size != (int64_t)sizeof(tsk_query_opts))
+            return set_err(TSK_ERR_INVALID_ARG, "base->size mismatch");
+        b = *base;
+    }
+    b.profile = 0;
+    b.use_graph = 0;
+    b.tune = TSK_TUNE_OFF;
+    const int64_t S = std::min<int64_t>(n_queries, topts && topts->sample_queries > 0
+                                                      ? topts->sample_queries : 64);
+    const int reps = topts && topts->reps > 0 ? topts->reps : 2;
+    hipStream_t s = (hipStream_t)hip_stream;
+    DevBuf<int64_t> ids;
+    DevBuf<float> dd;
+    TSK_TRY(ids.ensure(S * k));
+    TSK_TRY(dd.ensure(S * k));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    std::vector<int64_t> first, got(S * k);
+    int trials = 0;
+    // best of `reps` timed calls after one untimed call; rows must not change
+    auto trial = [&](const tsk_query_opts &o, float *ms) -> int {
+        *ms = INFINITY;
+        for (int r = 0; r <= reps; ++r) {
+            HIP_TRY(hipEventRecord(e0, s));
+            TSK_TRY(tsk_knn_query(ix, q_values_dev, q_offsets_host, S, k, dist, band, &o, ids.p,
+                                  dd.p, nullptr, s));
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float t = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+            if (r > 0)
+                *ms = std::min(*ms, t);
+        }
+        HIP_TRY(hipMemcpy(got.data(), ids.p, got.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+        if (first.empty())
+            first = got;
+        else if (got != first)
+            return set_err(TSK_ERR_DEVICE, "tuning trial %d changed the k-NN rows", trials);
+        ++trials;
+        return TSK_OK;
+    };
+    auto run = [&]() -> int {
+        const bool dk_free = dist == TSK_DK && band.mode == TSK_BAND_NONE;
+        const bool lbu = dist == TSK_DTW && ix->bucketed;
+        struct Knob {
+            int32_t tsk_query_opts::*field;
+            std::vector<int32_t> values;
+        };
+        std::vector<Knob> knobs;
+        std::vector<int32_t> seeds;
+        for (int32_t v : {128, 256, 512, 1024, 2048, 4096})
+            if (v <= ix->n)
+                seeds.push_back(v);
+        knobs.push_back({&tsk_query_opts::seed_count, seeds});
+        if (dk_free) {
+            knobs.push_back({&tsk_query_opts::tube_rows, {16, 32}});
+            knobs.push_back({&tsk_query_opts::task_size, {32, 64, 128, 256}});
+            knobs.push_back({&tsk_query_opts::walk_pass, {0, 1}});
+        }
+        if (lbu)
+            knobs.push_back({&tsk_query_opts::lb_qgroup, {2, 4, 8}});
+        tsk_query_opts cur = b;
+        float cur_ms = 0.0f;
+        TSK_TRY(trial(cur, &cur_ms));
+        for (const Knob &kn : knobs) {
+            for (int32_t v : kn.values) {
+                if (cur.*(kn.field) == v)
+                    continue;
+                tsk_query_opts t = cur;
+                t.*(kn.field) = v;
+                float ms = 0.0f;
+                TSK_TRY(trial(t, &ms));
+                if (ms < 0.98f * cur_ms) { // a clear gain only
+                    cur = t;
+                    cur_ms = ms;
+                }
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lock(ix->mu);
+            ix->tune_cache[tune_key(dist, band, k)] = cur;
+        }
+        if (best_out)
+            *best_out = cur;
+        if (best_ms_out)
+            *best_ms_out = cur_ms;
+        return TSK_OK;
+    };
+    const int rc = run();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
