@@ -81,7 +81,7 @@ def make_data(w):
     return db, dbo, qs, qo
 
 
-def kernel_rooflines(prof, dist, d, fast_kernel):
+def kernel_rooflines(prof, dist, d, fast_kernel, uneven=False):
     """Per-kernel device time (HIP events around each kernel on its launch
     stream, averaged per call) and algorithmic work of one distance's
     profile.  Work units: DP = in-band in-matrix cells of live pairs, 2d+2
@@ -97,9 +97,13 @@ def kernel_rooflines(prof, dist, d, fast_kernel):
                           units=prof["dp_valid_cells_general"] / calls, unit_ops=cell_ops),
     }
     if dist == "dtw":
-        out["k_bound_lb"] = dict(ms=prof["ms_bound_kernel"] / calls,
-                                 units=prof["bound_steps"] / calls, unit_ops=4 * d + 1)
-        out["k_seed_diag"] = dict(ms=prof["ms_seed"] / calls, units=0, unit_ops=0)
+        out["k_bound_lbu" if uneven else "k_bound_lb"] = dict(
+            ms=prof["ms_bound_kernel"] / calls, units=prof["bound_steps"] / calls,
+            unit_ops=4 * d + 1)
+        if uneven:
+            out["k_seed_ring"] = dict(ms=prof["ms_seed"] / calls, units=0, unit_ops=0)
+        else:
+            out["k_seed_diag"] = dict(ms=prof["ms_seed"] / calls, units=0, unit_ops=0)
     else:
         out["k_corner"] = dict(ms=prof["ms_bound_kernel"] / calls, units=prof["pairs"] / calls,
                                unit_ops=4 * d + 1)
@@ -109,6 +113,71 @@ def kernel_rooflines(prof, dist, d, fast_kernel):
         v["ops"] = v["units"] * v["unit_ops"]
         v["tops"] = v["ops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0
     return out
+
+
+def tuned_graph(w, args, idx_dk, idx_dtw, dev_q, qs, qo, eager_res):
+    """Autotunes both distances on a query sample (untimed), then times the
+    step as one captured HIP graph per distance with the tuned options;
+    also times a sample of queries batched against one call per query."""
+    import numpy as np
+    import torch
+    k, nq = w["k"], w["Q"]
+    tuned = {}
+    t0 = time.perf_counter()
+    for name, idx, band in (("dk", idx_dk, w["dk_band"]), ("dtw", idx_dtw, w["dtw_band"])):
+        best, ms = idx.tune(dev_q, qo, k, name, band, sample_queries=min(nq, 64), reps=2)
+        tuned[name] = {"options": best, "sample_ms": ms}
+    t_tune = time.perf_counter() - t0
+    outs = {name: (torch.empty((nq, k), dtype=torch.int64, device="cuda"),
+                   torch.empty((nq, k), dtype=torch.float32, device="cuda")) for name in ("dk", "dtw")}
+
+    def step():
+        a = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], use_graph=True, tune=True, out=outs["dk"])
+        b = idx_dtw.knn(dev_q, qo, k, "dtw", w["dtw_band"], use_graph=True, tune=True,
+                        out=outs["dtw"])
+        return a, b
+
+    for _ in range(max(1, args.warmup)):
+        res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    same = all(torch.equal(x, y) for x, y in zip(res[0][:2] + res[1][:2],
+                                                 eager_res[0][:2] + eager_res[1][:2]))
+    print(f"[bench] tuned graph: {args.steps} steps in {el:.3f}s (tuning {t_tune:.1f}s)",
+          file=sys.stderr, flush=True)
+    # batched vs one call per query on a sample of queries
+    S = min(nq, args.per_query_sample)
+    sub_q = dev_q[:int(qo[S])]
+    sub_o = qo[:S + 1]
+    per = [(dev_q[int(qo[i]):int(qo[i + 1])], np.array([0, qo[i + 1] - qo[i]])) for i in range(S)]
+
+    def batched():
+        idx_dk.knn(sub_q, sub_o, k, "dk", w["dk_band"])
+        idx_dtw.knn(sub_q, sub_o, k, "dtw", w["dtw_band"])
+
+    def one_by_one():
+        for qv, qoff in per:
+            idx_dk.knn(qv, qoff, k, "dk", w["dk_band"])
+            idx_dtw.knn(qv, qoff, k, "dtw", w["dtw_band"])
+
+    times = {}
+    for name, fn in (("batched", batched), ("per_query", one_by_one)):
+        fn()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t2) / 3 * 1e3
+    return {"ms_per_step": el * 1e3 / args.steps, "rows_equal_eager": bool(same),
+            "tuned": tuned, "tuning_seconds": t_tune,
+            "sample_queries": S, "batched_ms": times["batched"],
+            "per_query_ms": times["per_query"],
+            "batched_vs_per_query_speedup": times["per_query"] / times["batched"]}
 
 
 def learned_order(w, args, db, dbo, dev_db, dev_q, qo, idx_dk, idx_dtw, plain_res):
@@ -200,6 +269,9 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="time the profiled eager step instead of the tuned graph step")
+    ap.add_argument("--per-query-sample", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
@@ -240,6 +312,13 @@ def main():
     print(f"[bench] {args.steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
     prof_dk = idx_dk.profile(reset=True)
     prof_dtw = idx_dtw.profile(reset=True)
+    eager = {"ms_per_step": elapsed * 1e3 / args.steps}
+
+    batching = None
+    if not args.eager:
+        batching = tuned_graph(w, args, idx_dk, idx_dtw, dev_q, qs, qo, res)
+        if batching["rows_equal_eager"]:
+            elapsed = batching["ms_per_step"] * args.steps * 1e-3
 
     learned = None
     if not args.no_learned and w["gen"] == "classwarp":
@@ -248,11 +327,15 @@ def main():
     pairs = w["Q"] * w["N"]
     ms_step = elapsed * 1e3 / args.steps
     value = pairs / (ms_step * 1e-3)
+    eager["pairs_per_s"] = pairs / (eager["ms_per_step"] * 1e-3)
     dk_ms = prof_dk["ms_total"] / max(1, prof_dk["calls"])
     dtw_ms = prof_dtw["ms_total"] / max(1, prof_dtw["calls"])
 
-    kern = {"dk": kernel_rooflines(prof_dk, "dk", w["d"], "k_dp_tube"),
-            "dtw": kernel_rooflines(prof_dtw, "dtw", w["d"], "k_dp_band")}
+    uneven = "lengths" in w
+    kern = {"dk": kernel_rooflines(prof_dk, "dk", w["d"], "k_dp_tube", uneven),
+            "dtw": kernel_rooflines(prof_dtw, "dtw", w["d"], "k_dp_band", uneven)}
+    if uneven:
+        kern["dtw"].pop("k_dp_band")  # uneven lengths: every DTW DP is a general one
     dist_dom, kname = max(((dd, kk) for dd in kern for kk in kern[dd]),
                           key=lambda x: kern[x[0]][x[1]]["ms"])
     dom = kern[dist_dom][kname]
@@ -282,7 +365,13 @@ def main():
                 "dp_started": prof_dtw["dp_started"] / max(1, prof_dtw["calls"]),
                 "dp_valid_cells": prof_dtw["dp_valid_cells"] / max(1, prof_dtw["calls"])},
         "dk_vs_dtw_speedup": dtw_ms / dk_ms if dk_ms > 0 else None,
+        "step": ("tuned options, captured HIP graph per distance (one launch each), replayed"
+                 if batching is not None and batching["rows_equal_eager"] else
+                 "eager calls with per-stage HIP events"),
+        "eager_profiled": eager,
     }
+    if batching is not None:
+        out["batching"] = batching
     if learned is not None:
         learned["speedup_vs_plain"] = ms_step / learned["ms_per_step"]
         learned["dk_speedup_vs_plain"] = dk_ms / learned["dk"]["device_ms"]
