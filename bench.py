@@ -272,6 +272,9 @@ def main():
     ap.add_argument("--eager", action="store_true",
                     help="time the profiled eager step instead of the tuned graph step")
     ap.add_argument("--per-query-sample", type=int, default=32)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (the reference "
+                         "dispatch that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
@@ -281,6 +284,15 @@ def main():
     import numpy as np
     import torch
     from paper_1811_11076_amd import Index
+
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     w = WORKLOADS[args.workload]
     t_gen = time.perf_counter()
