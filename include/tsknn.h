@@ -147,9 +147,16 @@ typedef struct {
                                       in the general DP */
     int32_t lb_qgroup;             /* queries per wave of the length-bucket
                                       LB_Box kernel: 2, 4 or 8 (0 = 4) */
+    int32_t dk_band_slots;         /* unbanded DK on equal lengths: 0 = the
+                                      sparse-DK tube kernel; 32, 56, 64, 104
+                                      or 128 = the lockstep banded kernel in
+                                      a virtual band of (slots-1)/2, pairs
+                                      whose live cells reach its edge finish
+                                      in the general DP (exact either way) */
     int32_t tune;                  /* TSK_TUNE_CACHED: take seed_count,
-                                      tube_rows, task_size, walk_pass and
-                                      lb_qgroup from the index's tuning cache
+                                      tube_rows, task_size, walk_pass,
+                                      lb_qgroup and dk_band_slots from the
+                                      index's tuning cache
                                       for this (distance, band, k), if
                                       tsk_tune filled it; TSK_TUNE_OFF: as
                                       given */

@@ -675,6 +675,8 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
     const int64_t total = ALLPAIRS ? (int64_t)a.nq * a.N
                           : MODE == DPW_FALLBACK ? (int64_t)(*a.fb_count)
                                                  : (int64_t)a.nq * (int64_t)(*a.max_cnt);
+    if (total == 0)
+        return; // nothing handed over: no contended counter traffic
     for (;;) {
         unsigned long long t = 0;
         if (lane == 0)

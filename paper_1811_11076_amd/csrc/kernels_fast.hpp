@@ -43,6 +43,9 @@ struct FastArgs {
     const float *qpad;        // [nq][qrows][DP]: query rows at QPAD.., +inf around
     int qrows;
     int task;                 // survivors per wave task (k_dp_tube)
+    int32_t *qcur;            // per-query survivor cursors (k_dp_band), zeroed per call
+    int dk_virtual;           // k_dp_band on unbanded DK: a band of (W-1)/2 whose edge
+                              // cells must stay above tau (else the general DP)
     unsigned long long *ctr;
 };
 
@@ -115,6 +118,65 @@ __device__ __forceinline__ bool next_chunk(const FastArgs &a, int64_t total, Chu
     }
 }
 
+// Dense variant for the lockstep banded kernel: a task names a query; the
+// wave then claims that query's survivors from its cursor until all 64 lanes
+// hold a pair still within the threshold (or the list ends), so survivors
+// that the tightening threshold has already pruned leave no idle lanes.
+// slot: 64 ints of the block's LDS (the block is one wave).
+__device__ __forceinline__ bool next_dense_chunk(const FastArgs &a, int64_t total, Chunk &ch,
+                                                 unsigned long long &late, int32_t *slot)
+{
+    const int lane = (int)threadIdx.x;
+    for (;;) {
+        unsigned long long t = 0;
+        if (lane == 0)
+            t = atomicAdd(a.work, 1ull);
+        t = uniform_u64(t);
+        // unsigned: a counter value can never pass as a negative index
+        if (t >= (unsigned long long)total)
+            return false;
+        const int q = uniform_i((int)(t % (unsigned long long)a.nq));
+        const int cnt = uniform_i(a.surv_cnt[q]);
+        if (uniform_i(__hip_atomic_load(a.qcur + q, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT)) >= cnt)
+            continue; // this query's list is used up
+        const float tau = bits_f(load_relaxed_u32(a.tau + q));
+        int filled = 0;
+        __syncthreads(); // the previous task's reads of slot are done
+        for (;;) {
+            const int need = 64 - filled;
+            int base = 0;
+            if (lane == 0)
+                base = atomicAdd(a.qcur + q, need);
+            base = uniform_i(base);
+            if (base >= cnt)
+                break;
+            bool keep = false;
+            int c = -1;
+            const int idx = base + lane;
+            if (lane < need && idx < cnt) {
+                c = a.surv[(int64_t)q * a.N + idx];
+                keep = !(a.lbv[(int64_t)q * a.N + (a.lb_inv ? a.lb_inv[c] : c)] > tau);
+                late += keep ? 0 : 1;
+            }
+            const unsigned long long mk = __ballot(keep);
+            if (keep)
+                slot[filled + __popcll(mk & ((1ull << lane) - 1ull))] = c;
+            filled += __popcll(mk);
+            if (filled == 64 || base + need >= cnt)
+                break;
+        }
+        if (filled == 0)
+            continue;
+        __syncthreads(); // slot entries written by other lanes are visible
+        ch.q = q;
+        ch.m = uniform_i((int)(a.qoff[q + 1] - a.qoff[q]));
+        ch.act = lane < filled;
+        ch.c = ch.act ? slot[lane] : -1;
+        return true;
+    }
+}
+
 __device__ __forceinline__ void push_fallback(const FastArgs &a, int q, int c)
 {
     const unsigned long long slot = atomicAdd(a.work + 1, 1ull);
@@ -155,12 +217,21 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
     unsigned long long started = 0, completed = 0, abandoned = 0, late = 0, fallback = 0;
     unsigned long long cells = 0, valid = 0;
     const int64_t total = (int64_t)a.nq * ((*a.max_cnt + 63) / 64);
+    __shared__ int32_t slot[64];
     Chunk ch;
-    while (next_chunk(a, total, ch, late)) {
+    while (next_dense_chunk(a, total, ch, late, slot)) {
         const int q = ch.q, m = ch.m;
         int w = band_w(a.ba.mode, a.ba.r, a.ba.frac, m, m);
         if (w < 0 || w > m - 1)
             w = m - 1;
+        // unbanded DK in a virtual band: every path with max <= tau runs
+        // through live cells only; one that left the band would cross an
+        // edge cell (|i - j| = w) reached in-band, whose in-band value is
+        // then <= tau.  So while both edge slots stay above tau (checked
+        // against a tau that only falls) the in-band DP is exact.
+        const bool vband = DIST == DIST_DK && a.dk_virtual && (W - 1) / 2 < m - 1;
+        if (DIST == DIST_DK && a.dk_virtual)
+            w = min((W - 1) / 2, m - 1);
         w = uniform_i(w);
         bool act = ch.act;
         if (act && (a.len[ch.c] != m || 2 * w + 1 > W || 2 * w + 1 < KMASK)) {
@@ -240,6 +311,16 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
             const int h = min(j + w, m - 1) - max(j - w, 0) + 1;
             valid += (unsigned long long)h * __popcll(__ballot(alive));
             cells += W;
+            if (vband) {
+                constexpr int TOP = 2 * ((W - 1) / 2);
+                if (alive && (Dv[0] <= tau || Dv[TOP] <= tau)) {
+                    push_fallback(a, q, ch.c);
+                    ++fallback;
+                    --started;
+                    alive = false;
+                    act = false;
+                }
+            }
             if ((j & 7) == 7) {
                 float cm = Dv[0];
 #pragma unroll

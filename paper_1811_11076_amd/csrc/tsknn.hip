@@ -42,7 +42,7 @@ struct Workspace {
     DevBuf<uint32_t> tau;
     DevBuf<unsigned long long> seedslots, ubslots, resslots;
     DevBuf<float> lbv;
-    DevBuf<int32_t> surv, surv_cnt, max_cnt;
+    DevBuf<int32_t> surv, surv_cnt, max_cnt, qcur;
     DevBuf<unsigned long long> ctr, work;
     DevBuf<int64_t> qoff;
     DevBuf<float> env;
@@ -62,6 +62,7 @@ struct Workspace {
         surv.release();
         surv_cnt.release();
         max_cnt.release();
+        qcur.release();
         ctr.release();
         work.release();
         qoff.release();
@@ -613,7 +614,7 @@ static int dp_blocks(const tsk_index *ix) { return ix->n_cu * 4; }
 
 // Which lane-per-pair kernel serves a call (0 = none: everything goes to the
 // general DP).
-enum { FAST_NONE = 0, FAST_BAND, FAST_TUBE32 };
+enum { FAST_NONE = 0, FAST_BAND, FAST_TUBE32, FAST_BAND_DKV };
 
 static FastArgs fast_args(tsk_index *ix, int nq, const QueryPlan &P, int qrows)
 {
@@ -638,6 +639,8 @@ static FastArgs fast_args(tsk_index *ix, int nq, const QueryPlan &P, int qrows)
     a.qpad = ix->ws.qpad.p;
     a.qrows = qrows;
     a.task = 64;
+    a.qcur = ix->ws.qcur.p;
+    a.dk_virtual = 0;
     a.ctr = ix->ws.ctr.p;
     return a;
 }
@@ -654,12 +657,20 @@ template <int D> struct QpadLaunch {
 // Picks the lane-per-pair kernel from the call's shape (per-pair exceptions
 // are handed to the general DP inside the kernels).
 static int pick_fast(const tsk_index *ix, int dist, const tsk_band &band, int32_t qmin, int32_t qmax,
-                     int dp_kernel, int *wsel)
+                     int dp_kernel, int dk_band_slots, int *wsel)
 {
     *wsel = -1;
     if (dp_kernel == 1)
         return FAST_NONE;
     const int DP = ix->dim <= 4 ? 4 : 8;
+    if (dist == TSK_DK && band.mode == TSK_BAND_NONE && dk_band_slots > 0 && qmin == qmax &&
+        ix->min_len == ix->max_len && ix->min_len == qmin) {
+        for (int i = 0; i < N_BAND_WS; ++i)
+            if (BAND_WS[i] == dk_band_slots) {
+                *wsel = i;
+                return FAST_BAND_DKV;
+            }
+    }
     if (dist == TSK_DK && band.mode == TSK_BAND_NONE) {
         if ((size_t)(qmax + 32) * DP * sizeof(float) <= 64 * 1024)
             return FAST_TUBE32;
@@ -713,6 +724,7 @@ static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env)
     TSK_TRY(w.surv.ensure(nq * N));
     TSK_TRY(w.surv_cnt.ensure(nq));
     TSK_TRY(w.max_cnt.ensure(1));
+    TSK_TRY(w.qcur.ensure(nq));
     TSK_TRY(w.ctr.ensure(C_NUM));
     TSK_TRY(w.work.ensure(8));
     TSK_TRY(w.qoff.ensure(nq + 1));
@@ -769,6 +781,7 @@ static void apply_tuned(tsk_query_opts *o, const tsk_query_opts &t)
     o->task_size = t.task_size;
     o->walk_pass = t.walk_pass;
     o->lb_qgroup = t.lb_qgroup;
+    o->dk_band_slots = t.dk_band_slots;
 }
 
 extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
@@ -811,6 +824,9 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "task_size out of range");
     if (o.tube_rows != 0 && o.tube_rows != 16 && o.tube_rows != 32)
         return set_err(TSK_ERR_INVALID_ARG, "tube_rows must be 0, 16 or 32");
+    if (o.dk_band_slots != 0 && o.dk_band_slots != 32 && o.dk_band_slots != 56 &&
+        o.dk_band_slots != 64 && o.dk_band_slots != 104 && o.dk_band_slots != 128)
+        return set_err(TSK_ERR_INVALID_ARG, "dk_band_slots must be 0, 32, 56, 64, 104 or 128");
     if (o.lb_qgroup != 0 && o.lb_qgroup != 2 && o.lb_qgroup != 4 && o.lb_qgroup != 8)
         return set_err(TSK_ERR_INVALID_ARG, "lb_qgroup must be 0, 2, 4 or 8");
     if (o.use_graph && (o.profile || o.order == TSK_ORDER_LEARNED))
@@ -898,7 +914,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         c.lbu = dist == TSK_DTW && !P.env_ok && ix->bucketed && o.dp_kernel != 1;
         c.diag_seed = P.seed > 0 && dist == TSK_DTW && c.qmin == c.qmax &&
                       ix->min_len == ix->max_len && ix->min_len == c.qmin && o.dp_kernel != 1;
-        c.fast = pick_fast(ix, dist, band, c.qmin, c.qmax, o.dp_kernel, &c.wsel);
+        c.fast = pick_fast(ix, dist, band, c.qmin, c.qmax, o.dp_kernel, o.dk_band_slots, &c.wsel);
         c.qrows = c.qmax + 2 * QPAD;
         return c;
     };
@@ -925,6 +941,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         fill_u64(W.ubslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
         fill_u64(W.resslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
         fill_u32((uint32_t *)W.max_cnt.p, 0u, 1, s);
+        fill_u32((uint32_t *)W.qcur.p, 0u, nq, s);
         fill_u64(W.work.p, 0ull, 8, s); // every task / list counter of the call
         if (o.order == TSK_ORDER_LEARNED) {
             // embed the chunk's queries, score every candidate, bucket-sort;
@@ -989,6 +1006,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
                 // rows wide; the rare wider ones finish in the general DP
                 launch_tube(P.D, fa, o.tube_rows == 32 ? 32 : 16, ix->n_cu * 8, c.qmax, s);
             } else {
+                fa.dk_virtual = c.fast == FAST_BAND_DKV ? 1 : 0;
                 launch_band(P.D, dist, c.wsel, fa, ix->n_cu * 8, s);
             }
             TSK_MARK(6);
@@ -1023,13 +1041,14 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
                                     (int64_t)(uintptr_t)out_dist_dev, (int64_t)(uintptr_t)s,
                                     o.order, (int64_t)(uintptr_t)o.order_dev, o.seed_count,
                                     o.dp_kernel, o.walk_pass, o.task_size, o.tube_rows,
-                                    o.lb_qgroup};
+                                    o.lb_qgroup, o.dk_band_slots};
         // every workspace buffer the captured kernels address: a buffer
         // reallocated by another call changes the key
         for (const void *ptr :
              {(const void *)W.tau.p, (const void *)W.seedslots.p, (const void *)W.ubslots.p,
               (const void *)W.resslots.p, (const void *)W.lbv.p, (const void *)W.surv.p,
               (const void *)W.surv_cnt.p, (const void *)W.max_cnt.p, (const void *)W.ctr.p,
+              (const void *)W.qcur.p,
               (const void *)W.work.p, (const void *)W.qoff.p, (const void *)W.env.p,
               (const void *)W.tbuf.p, (const void *)W.qpad.p, (const void *)W.fb.p,
               (const void *)W.qtab.p, (const void *)W.qtab_off.p})
@@ -1294,6 +1313,8 @@ extern "C" int tsk_tune(tsk_index *ix, const float *q_values_dev, const int64_t 
             if (v <= ix->n)
                 seeds.push_back(v);
         knobs.push_back({&tsk_query_opts::seed_count, seeds});
+        if (dk_free && ix->min_len == ix->max_len)
+            knobs.push_back({&tsk_query_opts::dk_band_slots, {32, 56, 104, 128}});
         if (dk_free) {
             knobs.push_back({&tsk_query_opts::tube_rows, {16, 32}});
             knobs.push_back({&tsk_query_opts::task_size, {32, 64, 128, 256}});

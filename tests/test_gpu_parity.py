@@ -236,6 +236,25 @@ def test_knn_dk_pipeline_options(walk, task, seed):
     idx.close()
 
 
+@pytest.mark.parametrize("slots", [32, 56, 104, 128])
+def test_knn_dk_virtual_band(slots):
+    """Unbanded DK through the lockstep banded kernel in a virtual band:
+    pairs whose live cells reach the band's edge go to the general DP; rows
+    equal the oracle's (class-warp pairs mostly fit, random walks often
+    overflow)."""
+    print(f"[case] knn dk virtual band slots={slots}", flush=True)
+    db, dbo, qs, qo = classwarp(2, 10, 256, 3, 1500, 5)
+    rdb, rdbo = ragged_walks(70 + slots, 300, (90, 90), 3)
+    rqs, rqo = ragged_walks(170 + slots, 3, (90, 90), 3)
+    for (d, do, q, qo_) in ((db, dbo, qs, qo), (rdb, rdbo, rqs, rqo)):
+        idx = _index(d, do)
+        ref_ids, ref_keys = O.knn_brute(d, do, q, qo_, 10, "dk", None)
+        ids, dst, st = idx.knn(to_dev(q), qo_, 10, "dk", None, stats=True, dk_band_slots=slots)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
+        print(f"  fallback {st['fallback_pairs']} of {st['dp_started']}", flush=True)
+        idx.close()
+
+
 def test_knn_general_dp_forced_equals_fast():
     """dp_kernel = 1 (general DP only) and the default give identical rows."""
     import ctypes
