@@ -120,8 +120,8 @@ typedef struct {
     const int32_t *order_dev;      /* TSK_ORDER_GIVEN: [n_queries][n_series]
                                       candidate ids, each row a permutation;
                                       the first seed_count entries form the
-                                      seed set and survivors are processed in
-                                      this order */
+                                      seed set, and with surv_order 2
+                                      survivors are processed in this order */
     int32_t use_graph;             /* 1: the call (one chunk of queries:
                                       up to 2^28 / n_series of them) runs as
                                       one captured HIP graph, cached on the
@@ -153,10 +153,15 @@ typedef struct {
                                       a virtual band of (slots-1)/2, pairs
                                       whose live cells reach its edge finish
                                       in the general DP (exact either way) */
+    int32_t surv_order;            /* survivors' DP order: 1 = ascending
+                                      bound (likely neighbours first), 2 =
+                                      the query's candidate order, 0 =
+                                      library default (DTW 1, DK 2) */
     int32_t tune;                  /* TSK_TUNE_CACHED: take seed_count,
                                       tube_rows, task_size, walk_pass,
-                                      lb_qgroup and dk_band_slots from the
-                                      index's tuning cache
+                                      lb_qgroup, dk_band_slots and
+                                      surv_order from the index's tuning
+                                      cache
                                       for this (distance, band, k), if
                                       tsk_tune filled it; TSK_TUNE_OFF: as
                                       given */

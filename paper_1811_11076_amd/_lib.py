@@ -38,7 +38,8 @@ class QueryOpts(ctypes.Structure):
                 ("dp_kernel", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("walk_pass", ctypes.c_int32), ("task_size", ctypes.c_int32),
                 ("tube_rows", ctypes.c_int32), ("lb_qgroup", ctypes.c_int32),
-                ("dk_band_slots", ctypes.c_int32), ("tune", ctypes.c_int32),
+                ("dk_band_slots", ctypes.c_int32), ("surv_order", ctypes.c_int32),
+                ("tune", ctypes.c_int32),
                 ("model", ctypes.c_void_p)]
 
 

@@ -506,6 +506,99 @@ static __global__ __launch_bounds__(256) void k_compact(const float *__restrict_
     }
 }
 
+// Survivors of one query ordered by ascending bound instead of candidate
+// order (a counting sort on bits 18.. of the non-negative fp32 bound, 8192
+// buckets of 2^-5 relative width; bucket-mates in arbitrary order): the
+// pairs most likely to be neighbours run first, so the threshold falls
+// early, and pairs of similar bound share a wave.  Same survivors as
+// k_compact (tau is fixed while it runs: no DP of this chunk has started).
+// One block of 1024 per query; SURV_BUCKETS counters in dynamic LDS.
+constexpr int SURV_BUCKETS = 8192;
+constexpr int SURV_SHIFT = 18;
+static __global__ __launch_bounds__(1024) void k_compact_sorted(
+    const float *__restrict__ lbv, int64_t N, const int32_t *__restrict__ order,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ inv,
+    const uint32_t *__restrict__ tau, int32_t *__restrict__ surv, int32_t *__restrict__ cnt,
+    int32_t *__restrict__ max_cnt, unsigned long long *ctr)
+{
+    extern __shared__ int32_t hist[];
+    __shared__ int32_t wsum[16];
+    const int q = blockIdx.x;
+    const int tid = threadIdx.x;
+    const float tq = bits_f(tau[q]);
+    for (int b = tid; b < SURV_BUCKETS; b += 1024)
+        hist[b] = 0;
+    __syncthreads();
+    unsigned long long late = 0;
+    auto cand = [&](int64_t p, int &c, float &lb) {
+        int64_t li;
+        if (order) {
+            c = order[(int64_t)q * N + p];
+            li = inv ? inv[c] : c;
+        } else {
+            c = perm ? perm[p] : (int)p;
+            li = p;
+        }
+        lb = lbv[(int64_t)q * N + li];
+    };
+    for (int64_t p = tid; p < N; p += 1024) {
+        int c;
+        float lb;
+        cand(p, c, lb);
+        if (lb <= tq)
+            atomicAdd(&hist[min(__float_as_uint(lb) >> SURV_SHIFT, (uint32_t)SURV_BUCKETS - 1)], 1);
+        else if (lb != tsk_inf())
+            ++late;
+    }
+    __syncthreads();
+    constexpr int PER = SURV_BUCKETS / 1024;
+    int loc[PER];
+    int tot = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        loc[i] = tot;
+        tot += hist[tid * PER + i];
+    }
+    const int lane = tid & 63, wv = tid >> 6;
+    int inc = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o)
+            inc += t;
+    }
+    if (lane == 63)
+        wsum[wv] = inc;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wv; ++w)
+        base += wsum[w];
+    const int excl = base + inc - tot;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        hist[tid * PER + i] = excl + loc[i];
+    __syncthreads();
+    for (int64_t p = tid; p < N; p += 1024) {
+        int c;
+        float lb;
+        cand(p, c, lb);
+        if (lb <= tq) {
+            const int pos =
+                atomicAdd(&hist[min(__float_as_uint(lb) >> SURV_SHIFT, (uint32_t)SURV_BUCKETS - 1)], 1);
+            surv[(int64_t)q * N + pos] = c;
+        }
+    }
+    wave_count(ctr + C_BOUND_PRUNED, late);
+    if (tid == 0) {
+        int all = 0;
+        for (int w = 0; w < 16; ++w)
+            all += wsum[w];
+        cnt[q] = all;
+        atomicMax(max_cnt, all);
+    }
+}
+
 // ------------------------------------------------------------------ general DP
 // One wave per pair: the quadratic DP of Sec. 2.1 (DTW: cost + min of the
 // three predecessors; DK: max(cost, min)), with D(-1,-1) = 0 and every other

@@ -782,6 +782,7 @@ static void apply_tuned(tsk_query_opts *o, const tsk_query_opts &t)
     o->walk_pass = t.walk_pass;
     o->lb_qgroup = t.lb_qgroup;
     o->dk_band_slots = t.dk_band_slots;
+    o->surv_order = t.surv_order;
 }
 
 extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
@@ -827,6 +828,8 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
     if (o.dk_band_slots != 0 && o.dk_band_slots != 32 && o.dk_band_slots != 56 &&
         o.dk_band_slots != 64 && o.dk_band_slots != 104 && o.dk_band_slots != 128)
         return set_err(TSK_ERR_INVALID_ARG, "dk_band_slots must be 0, 32, 56, 64, 104 or 128");
+    if (o.surv_order < 0 || o.surv_order > 2)
+        return set_err(TSK_ERR_INVALID_ARG, "surv_order must be 0, 1 or 2");
     if (o.lb_qgroup != 0 && o.lb_qgroup != 2 && o.lb_qgroup != 4 && o.lb_qgroup != 8)
         return set_err(TSK_ERR_INVALID_ARG, "lb_qgroup must be 0, 2, 4 or 8");
     if (o.use_graph && (o.profile || o.order == TSK_ORDER_LEARNED))
@@ -980,9 +983,18 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
         }
         TSK_MARK(3);
-        hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, c.order,
-                           c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr, W.tau.p,
-                           W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
+        // survivors by ascending bound by default for DTW (measured faster
+        // on every class-warp workload), candidate order for DK (mixed)
+        const int so = o.surv_order != 0 ? o.surv_order : (dist == TSK_DTW ? 1 : 2);
+        if (so == 1)
+            hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
+                               SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,
+                               c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr, W.tau.p,
+                               W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
+        else
+            hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, c.order,
+                               c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr, W.tau.p,
+                               W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
         // the greedy pass over the corner survivors costs more than the DP
         // work its tighter threshold saves on the class-warp workloads, so
         // it runs only on request
@@ -1041,7 +1053,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
                                     (int64_t)(uintptr_t)out_dist_dev, (int64_t)(uintptr_t)s,
                                     o.order, (int64_t)(uintptr_t)o.order_dev, o.seed_count,
                                     o.dp_kernel, o.walk_pass, o.task_size, o.tube_rows,
-                                    o.lb_qgroup, o.dk_band_slots};
+                                    o.lb_qgroup, o.dk_band_slots, o.surv_order};
         // every workspace buffer the captured kernels address: a buffer
         // reallocated by another call changes the key
         for (const void *ptr :
@@ -1322,6 +1334,7 @@ extern "C" int tsk_tune(tsk_index *ix, const float *q_values_dev, const int64_t 
         }
         if (lbu)
             knobs.push_back({&tsk_query_opts::lb_qgroup, {2, 4, 8}});
+        knobs.push_back({&tsk_query_opts::surv_order, {1, 2}});
         tsk_query_opts cur = b;
         float cur_ms = 0.0f;
         TSK_TRY(trial(cur, &cur_ms));

@@ -255,6 +255,27 @@ def test_knn_dk_virtual_band(slots):
         idx.close()
 
 
+@pytest.mark.parametrize("so", [1, 2])
+@pytest.mark.parametrize("kind", ["classwarp", "uneven", "ragged"])
+def test_knn_survivor_orders(kind, so):
+    """Survivors taken in ascending-bound order (surv_order = 1) or in
+    candidate order (2): same rows as the oracle for both distances."""
+    print(f"[case] knn survivor order {so} {kind}", flush=True)
+    if kind == "classwarp":
+        db, dbo, qs, qo = classwarp(2, 10, 256, 3, 2000, 6)
+    elif kind == "uneven":
+        db, dbo, qs, qo = classwarp(3, 50, (64, 512), 3, 800, 4, proto_len=512)
+    else:
+        db, dbo = ragged_walks(23, 300, (5, 60), 3)
+        qs, qo = ragged_walks(123, 5, (5, 60), 3)
+    idx = _index(db, dbo)
+    for dist, band in (("dk", None), ("dtw", 0.1)):
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, dist, band)
+        ids, dst, _ = idx.knn(to_dev(qs), qo, 10, dist, band, surv_order=so)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
+    idx.close()
+
+
 def test_knn_general_dp_forced_equals_fast():
     """dp_kernel = 1 (general DP only) and the default give identical rows."""
     import ctypes
