@@ -157,10 +157,13 @@ typedef struct {
                                       bound (likely neighbours first), 2 =
                                       the query's candidate order, 0 =
                                       library default (DTW 1, DK 2) */
+    int32_t dp_rows;               /* tile shape of the general DP: rows per
+                                      lane of its skewed strips (1 or 4;
+                                      0 = 4) */
     int32_t tune;                  /* TSK_TUNE_CACHED: take seed_count,
                                       tube_rows, task_size, walk_pass,
-                                      lb_qgroup, dk_band_slots and
-                                      surv_order from the index's tuning
+                                      lb_qgroup, dk_band_slots, surv_order
+                                      and dp_rows from the index's tuning
                                       cache
                                       for this (distance, band, k), if
                                       tsk_tune filled it; TSK_TUNE_OFF: as

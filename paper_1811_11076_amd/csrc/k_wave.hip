@@ -4,10 +4,10 @@
 namespace tsk {
 
 namespace {
-template <int D> void wave_d(int dist, int mode, const DpArgs &a, int blocks, hipStream_t s)
+template <int D, int R> void wave_r(int dist, int mode, const DpArgs &a, int blocks, hipStream_t s)
 {
     dim3 grid(blocks), block(256);
-#define TSK_DPW(DI, MO) hipLaunchKernelGGL((k_dp_wave<D, DI, MO>), grid, block, 0, s, a)
+#define TSK_DPW(DI, MO) hipLaunchKernelGGL((k_dp_wave<D, DI, MO, R>), grid, block, 0, s, a)
     if (dist == DIST_DK) {
         if (mode == DPW_ALLPAIRS) TSK_DPW(DIST_DK, DPW_ALLPAIRS);
         else if (mode == DPW_FALLBACK) TSK_DPW(DIST_DK, DPW_FALLBACK);
@@ -18,6 +18,14 @@ template <int D> void wave_d(int dist, int mode, const DpArgs &a, int blocks, hi
         else TSK_DPW(DIST_DTW, DPW_SURV);
     }
 #undef TSK_DPW
+}
+
+template <int D> void wave_d(int dist, int mode, const DpArgs &a, int blocks, hipStream_t s)
+{
+    if (a.rows_per_lane == 1)
+        wave_r<D, 1>(dist, mode, a, blocks, s);
+    else
+        wave_r<D, 4>(dist, mode, a, blocks, s);
 }
 } // namespace
 

@@ -603,18 +603,19 @@ static __global__ __launch_bounds__(1024) void k_compact_sorted(
 // One wave per pair: the quadratic DP of Sec. 2.1 (DTW: cost + min of the
 // three predecessors; DK: max(cost, min)), with D(-1,-1) = 0 and every other
 // outside cell +inf, restricted to the band.  Rows are processed in strips
-// of 256 (4 consecutive rows per lane); inside a strip lane l works on column
-// s - l at step s (a skewed wavefront), receiving the row below from lane
-// l-1 of the previous step; the strip's top row is handed to the next strip
-// through a per-wave buffer.
+// of 64 R (R consecutive rows per lane: 4 amortises the per-step work over
+// more cells, 1 wastes fewer out-of-band cells on narrow bands); inside a
+// strip lane l works on column s - l at step s (a skewed wavefront),
+// receiving the row below from lane l-1 of the previous step; the strip's
+// top row is handed to the next strip through a per-wave buffer.
 // Dead cells (value > tau) become +inf (the sparse-DK semantics of Alg. 3;
 // for DTW the same holds because values only grow along a path).  With
-// sigma(i, j) = j + floor(i / 4) a path moves sigma by 0, 1 or 2 per move,
+// sigma(i, j) = j + floor(i / R) a path moves sigma by 0, 1 or 2 per move,
 // so it cannot skip two consecutive steps of a strip: when two consecutive
 // steps are all dead and no live input from the strip below is still
 // pending, the rest of the strip is dead, and if it handed no live value up
 // the whole pair is > tau (abandoned).  Returns the value, or +inf if > tau.
-template <int D, int DIST>
+template <int D, int DIST, int R>
 __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *__restrict__ cp, int n,
                               const Band &band, const uint32_t *tau_ptr, float *__restrict__ tbuf,
                               unsigned long long &cells, unsigned long long &valid)
@@ -625,15 +626,16 @@ __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *
     int in_max = -1;  // largest column with a live value in the strip input
     int js_prev = 0;  // first column of the previous strip
     float *tb_in = tbuf, *tb_out = tbuf + n;
-    for (int base = 0; base < m; base += 256) {
+    constexpr int H = 64 * R; // strip height
+    for (int base = 0; base < m; base += H) {
         if (base > 0 && in_max < 0)
             break;
-        const bool last_strip = base + 256 >= m;
-        float qr[4][D];
-        int jlo[4], jhi[4];
+        const bool last_strip = base + H >= m;
+        float qr[R][D];
+        int jlo[R], jhi[R];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = base + 4 * lane + r;
+        for (int r = 0; r < R; ++r) {
+            const int i = base + R * lane + r;
             if (i < m) {
                 load_point<D>(qp + (int64_t)i * D, qr[r]);
                 band_cols(band, i, n, jlo[r], jhi[r]);
@@ -647,11 +649,14 @@ __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *
         }
         int js, je, tmp;
         band_cols(band, base, n, js, tmp);
-        band_cols(band, min(base + 255, m - 1), n, tmp, je);
+        band_cols(band, min(base + H - 1, m - 1), n, tmp, je);
         if (js > je)
             break;
         int out_max = -1;
-        float Dp[4] = {tsk_inf(), tsk_inf(), tsk_inf(), tsk_inf()};
+        float Dp[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            Dp[r] = tsk_inf();
         // lane 0's first cell (base, js) has the lower-left predecessor
         // (base-1, js-1), which a band can leave inside and finite; the
         // previous strip wrote it iff js-1 is within its columns
@@ -676,10 +681,10 @@ __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *
             }
             float down = recv, diag = recv_prev;
             bool any = false;
-            float Dc[4];
+            float Dc[R];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = base + 4 * lane + r;
+            for (int r = 0; r < R; ++r) {
+                const int i = base + R * lane + r;
                 const bool ok = jv && j >= jlo[r] && j <= jhi[r];
                 float pred = min3f(diag, down, Dp[r]);
                 if (i == 0 && j == 0)
@@ -694,21 +699,23 @@ __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *
                 any |= v != tsk_inf();
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < R; ++r)
                 Dp[r] = Dc[r];
             recv_prev = recv;
-            my_top = Dc[3];
+            my_top = Dc[R - 1];
             if (!last_strip && lane == 63 && jv) {
-                tb_out[j] = Dc[3];
-                if (Dc[3] != tsk_inf())
+                tb_out[j] = Dc[R - 1];
+                if (Dc[R - 1] != tsk_inf())
                     out_max = j;
             }
             if (last_strip && j == n - 1) {
-                const int rr = m - 1 - base - 4 * lane;
-                if (rr >= 0 && rr < 4)
-                    result = Dc[rr];
+                const int rr = m - 1 - base - R * lane;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (rr == r)
+                        result = Dc[r];
             }
-            cells += 4;
+            cells += R;
             const bool alive_now = __ballot(any) != 0ull;
             if (!alive_now && !alive_prev && js + s > in_max)
                 break;
@@ -750,6 +757,7 @@ struct DpArgs {
     float *out_all;     // ALLPAIRS: [nq][N]
     const int2 *fb;     // FALLBACK: (query, candidate) list
     const unsigned long long *fb_count;
+    int rows_per_lane;  // R of the strips: 1 or 4
 };
 
 enum { DPW_SURV = 0, DPW_ALLPAIRS = 1, DPW_FALLBACK = 2 };
@@ -757,7 +765,7 @@ enum { DPW_SURV = 0, DPW_ALLPAIRS = 1, DPW_FALLBACK = 2 };
 // MODE: DPW_SURV walks the compacted survivors (query-interleaved ranks),
 // DPW_ALLPAIRS every pair with no threshold (tsk_pair_distances),
 // DPW_FALLBACK the pairs the lane-per-pair kernels handed over.
-template <int D, int DIST, int MODE>
+template <int D, int DIST, int MODE, int R>
 __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
 {
     constexpr bool ALLPAIRS = MODE == DPW_ALLPAIRS;
@@ -803,7 +811,7 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
         const int m = (int)(a.qoff[q + 1] - a.qoff[q]);
         const int n = a.len[c];
         const Band b = pair_band(a.ba, m, n);
-        const float res = dp_wave_pair<D, DIST>(a.qv + a.qoff[q] * D, m, a.aos + a.off[c] * D, n, b,
+        const float res = dp_wave_pair<D, DIST, R>(a.qv + a.qoff[q] * D, m, a.aos + a.off[c] * D, n, b,
                                                 ALLPAIRS ? nullptr : a.tau + q, tb, cells, valid);
         if (ALLPAIRS) {
             if (lane == 0)

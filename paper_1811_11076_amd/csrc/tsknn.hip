@@ -607,6 +607,9 @@ static DpArgs dp_args(tsk_index *ix, const float *qv, int nq, const QueryPlan &P
     a.out_all = nullptr;
     a.fb = ix->ws.fb.p;
     a.fb_count = ix->ws.work.p + 1;
+    // one row per lane wastes fewer out-of-band cells on narrow bands but
+    // costs more per cell; four measured faster on the class-warp bands
+    a.rows_per_lane = 4;
     return a;
 }
 
@@ -783,6 +786,7 @@ static void apply_tuned(tsk_query_opts *o, const tsk_query_opts &t)
     o->lb_qgroup = t.lb_qgroup;
     o->dk_band_slots = t.dk_band_slots;
     o->surv_order = t.surv_order;
+    o->dp_rows = t.dp_rows;
 }
 
 extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
@@ -828,6 +832,8 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
     if (o.dk_band_slots != 0 && o.dk_band_slots != 32 && o.dk_band_slots != 56 &&
         o.dk_band_slots != 64 && o.dk_band_slots != 104 && o.dk_band_slots != 128)
         return set_err(TSK_ERR_INVALID_ARG, "dk_band_slots must be 0, 32, 56, 64, 104 or 128");
+    if (o.dp_rows != 0 && o.dp_rows != 1 && o.dp_rows != 4)
+        return set_err(TSK_ERR_INVALID_ARG, "dp_rows must be 0, 1 or 4");
     if (o.surv_order < 0 || o.surv_order > 2)
         return set_err(TSK_ERR_INVALID_ARG, "surv_order must be 0, 1 or 2");
     if (o.lb_qgroup != 0 && o.lb_qgroup != 2 && o.lb_qgroup != 4 && o.lb_qgroup != 8)
@@ -1007,6 +1013,8 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         TSK_MARK(4);
         DpArgs da = dp_args(ix, qv, nq, P);
         da.lb_inv = c.lbu ? ix->inv : nullptr;
+        if (o.dp_rows != 0)
+            da.rows_per_lane = o.dp_rows;
         if (c.fast != FAST_NONE) {
             dispatch_d<QpadLaunch>(P.D, qv, W.qoff.p, nq, c.qrows, W.qpad.p, s);
             TSK_MARK(5);
@@ -1053,7 +1061,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
                                     (int64_t)(uintptr_t)out_dist_dev, (int64_t)(uintptr_t)s,
                                     o.order, (int64_t)(uintptr_t)o.order_dev, o.seed_count,
                                     o.dp_kernel, o.walk_pass, o.task_size, o.tube_rows,
-                                    o.lb_qgroup, o.dk_band_slots, o.surv_order};
+                                    o.lb_qgroup, o.dk_band_slots, o.surv_order, o.dp_rows};
         // every workspace buffer the captured kernels address: a buffer
         // reallocated by another call changes the key
         for (const void *ptr :
@@ -1335,6 +1343,7 @@ extern "C" int tsk_tune(tsk_index *ix, const float *q_values_dev, const int64_t 
         if (lbu)
             knobs.push_back({&tsk_query_opts::lb_qgroup, {2, 4, 8}});
         knobs.push_back({&tsk_query_opts::surv_order, {1, 2}});
+        knobs.push_back({&tsk_query_opts::dp_rows, {1, 4}});
         tsk_query_opts cur = b;
         float cur_ms = 0.0f;
         TSK_TRY(trial(cur, &cur_ms));

@@ -276,6 +276,22 @@ def test_knn_survivor_orders(kind, so):
     idx.close()
 
 
+@pytest.mark.parametrize("rows", [1, 4])
+def test_knn_general_dp_tile_rows(rows):
+    """The general DP's strip shape (1 or 4 rows per lane) on uneven
+    lengths, where every DTW survivor and every DK tube overflow runs in it:
+    rows equal the oracle's."""
+    print(f"[case] knn general DP rows={rows}", flush=True)
+    db, dbo = ragged_walks(31 + rows, 200, (30, 400), 3)
+    qs, qo = ragged_walks(131 + rows, 4, (30, 400), 3)
+    idx = _index(db, dbo)
+    for dist, band in (("dk", None), ("dtw", 0.1), ("dtw", None), ("dk", 7)):
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 8, dist, band)
+        ids, dst, _ = idx.knn(to_dev(qs), qo, 8, dist, band, dp_rows=rows)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
+    idx.close()
+
+
 def test_knn_general_dp_forced_equals_fast():
     """dp_kernel = 1 (general DP only) and the default give identical rows."""
     import ctypes
