@@ -665,20 +665,35 @@ __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *
             recv_prev = tb_in[js - 1];
         bool alive_prev = true;
         const int nsteps = je - js + 64;
+        // software pipeline: the candidate point (and lane 0's strip input)
+        // of step s is loaded two steps ahead, so a step never waits on
+        // memory latency (single pairs run with few waves per SIMD)
+        auto cand = [&](int jj, float (&out)[D]) {
+            const int jc = min(max(jj, 0), n - 1);
+            load_point<D>(cp + (int64_t)jc * D, out);
+        };
+        auto strip_in = [&](int jj) -> float {
+            return (lane == 0 && base > 0 && jj >= 0 && jj <= in_max) ? tb_in[jj] : tsk_inf();
+        };
+        float c0[D], c1[D];
+        cand(js - lane, c0);
+        cand(js - lane + 1, c1);
+        float t0 = strip_in(js), t1 = strip_in(js + 1);
         for (int s = 0; s < nsteps; ++s) {
             const int j = js + s - lane;
             float recv = __shfl_up(my_top, 1, 64);
             if (lane == 0)
-                recv = (base > 0 && j <= in_max) ? tb_in[j] : tsk_inf();
+                recv = t0;
             const bool jv = j >= 0 && j < n;
             float cv[D];
-            if (jv)
-                load_point<D>(cp + (int64_t)j * D, cv);
-            else {
 #pragma unroll
-                for (int k = 0; k < D; ++k)
-                    cv[k] = 0.0f;
+            for (int k = 0; k < D; ++k) {
+                cv[k] = jv ? c0[k] : 0.0f;
+                c0[k] = c1[k];
             }
+            cand(j + 2, c1);
+            t0 = t1;
+            t1 = strip_in(js + s + 2);
             float down = recv, diag = recv_prev;
             bool any = false;
             float Dc[R];
