@@ -160,11 +160,14 @@ typedef struct {
     int32_t dp_rows;               /* tile shape of the general DP: rows per
                                       lane of its skewed strips (1 or 4;
                                       0 = 4) */
+    int32_t dp_waves_per_cu;       /* persistent waves per compute unit of
+                                      the lane-per-pair DP kernels: 8, 16
+                                      or 32 (0 = library default) */
     int32_t tune;                  /* TSK_TUNE_CACHED: take seed_count,
                                       tube_rows, task_size, walk_pass,
-                                      lb_qgroup, dk_band_slots, surv_order
-                                      and dp_rows from the index's tuning
-                                      cache
+                                      lb_qgroup, dk_band_slots, surv_order,
+                                      dp_rows and dp_waves_per_cu from the
+                                      index's tuning cache
                                       for this (distance, band, k), if
                                       tsk_tune filled it; TSK_TUNE_OFF: as
                                       given */

@@ -39,7 +39,7 @@ class QueryOpts(ctypes.Structure):
                 ("walk_pass", ctypes.c_int32), ("task_size", ctypes.c_int32),
                 ("tube_rows", ctypes.c_int32), ("lb_qgroup", ctypes.c_int32),
                 ("dk_band_slots", ctypes.c_int32), ("surv_order", ctypes.c_int32),
-                ("dp_rows", ctypes.c_int32),
+                ("dp_rows", ctypes.c_int32), ("dp_waves_per_cu", ctypes.c_int32),
                 ("tune", ctypes.c_int32),
                 ("model", ctypes.c_void_p)]
 

@@ -10,10 +10,11 @@ template <int D, int DIST> void band_d(int wsel, const FastArgs &a, int blocks, 
     switch (wsel) {
     case 0: hipLaunchKernelGGL((k_dp_band<D, DIST, 16, 1>), grid, block, 0, s, a, a.qpad); break;
     case 1: hipLaunchKernelGGL((k_dp_band<D, DIST, 32, 17>), grid, block, 0, s, a, a.qpad); break;
-    case 2: hipLaunchKernelGGL((k_dp_band<D, DIST, 56, 33>), grid, block, 0, s, a, a.qpad); break;
-    case 3: hipLaunchKernelGGL((k_dp_band<D, DIST, 64, 57>), grid, block, 0, s, a, a.qpad); break;
-    case 4: hipLaunchKernelGGL((k_dp_band<D, DIST, 104, 65>), grid, block, 0, s, a, a.qpad); break;
-    case 5: hipLaunchKernelGGL((k_dp_band<D, DIST, 128, 105>), grid, block, 0, s, a, a.qpad); break;
+    case 2: hipLaunchKernelGGL((k_dp_band<D, DIST, 52, 33>), grid, block, 0, s, a, a.qpad); break;
+    case 3: hipLaunchKernelGGL((k_dp_band<D, DIST, 56, 53>), grid, block, 0, s, a, a.qpad); break;
+    case 4: hipLaunchKernelGGL((k_dp_band<D, DIST, 64, 57>), grid, block, 0, s, a, a.qpad); break;
+    case 5: hipLaunchKernelGGL((k_dp_band<D, DIST, 104, 65>), grid, block, 0, s, a, a.qpad); break;
+    case 6: hipLaunchKernelGGL((k_dp_band<D, DIST, 128, 105>), grid, block, 0, s, a, a.qpad); break;
     default: break;
     }
 }

@@ -44,6 +44,7 @@ struct FastArgs {
     int qrows;
     int task;                 // survivors per wave task (k_dp_tube)
     int32_t *qcur;            // per-query survivor cursors (k_dp_band), zeroed per call
+    int qmajor;               // task order of the lane-per-pair kernels: query-major
     int dk_virtual;           // k_dp_band on unbanded DK: a band of (W-1)/2 whose edge
                               // cells must stay above tau (else the general DP)
     unsigned long long *ctr;
@@ -135,7 +136,10 @@ __device__ __forceinline__ bool next_dense_chunk(const FastArgs &a, int64_t tota
         // unsigned: a counter value can never pass as a negative index
         if (t >= (unsigned long long)total)
             return false;
-        const int q = uniform_i((int)(t % (unsigned long long)a.nq));
+        // query-major tasks (the waves in flight share few queries, whose
+        // rows stay in the scalar cache) or query-interleaved
+        const unsigned long long per_q = (unsigned long long)(total / a.nq);
+        const int q = uniform_i(a.qmajor ? (int)(t / per_q) : (int)(t % (unsigned long long)a.nq));
         const int cnt = uniform_i(a.surv_cnt[q]);
         if (uniform_i(__hip_atomic_load(a.qcur + q, __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT)) >= cnt)
@@ -212,8 +216,8 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
     // the pairs this instantiation serves (2w+1 >= KMASK), slots from KMASK
     // up are masked against 2w+1 at run time.
     constexpr int DP = PadDim<D>::value;
-    constexpr int G = 8;
-    static_assert(W % G == 0, "W must be a multiple of 8");
+    constexpr int G = W % 8 == 0 ? 8 : 4;
+    static_assert(W % G == 0, "W must be a multiple of 4");
     unsigned long long started = 0, completed = 0, abandoned = 0, late = 0, fallback = 0;
     unsigned long long cells = 0, valid = 0;
     const int64_t total = (int64_t)a.nq * ((*a.max_cnt + 63) / 64);
@@ -392,8 +396,9 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
         t = uniform_u64(t);
         if (t >= (unsigned long long)total)
             break;
-        const int q = uniform_i((int)(t % (unsigned long long)a.nq));
-        const int base = (int)(t / (unsigned long long)a.nq) * T;
+        const unsigned long long per_q = (unsigned long long)(total / a.nq);
+        const int q = uniform_i(a.qmajor ? (int)(t / per_q) : (int)(t % (unsigned long long)a.nq));
+        const int base = (int)(a.qmajor ? t % per_q : t / (unsigned long long)a.nq) * T;
         const int cnt = a.surv_cnt[q];
         if (base >= cnt)
             continue;

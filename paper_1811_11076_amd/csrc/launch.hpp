@@ -10,8 +10,8 @@ namespace tsk {
 // Window sizes of the banded kernel; a call uses the smallest W >= 2w+1.
 // Slots below the previous size are inside the band for every pair that
 // instantiation serves, so only the slots above it are masked.
-constexpr int BAND_WS[] = {16, 32, 56, 64, 104, 128};
-constexpr int N_BAND_WS = 6;
+constexpr int BAND_WS[] = {16, 32, 52, 56, 64, 104, 128};
+constexpr int N_BAND_WS = 7;
 
 struct SeedRingArgs {
     const float *qv;

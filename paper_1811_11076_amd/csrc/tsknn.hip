@@ -644,6 +644,10 @@ static FastArgs fast_args(tsk_index *ix, int nq, const QueryPlan &P, int qrows)
     a.task = 64;
     a.qcur = ix->ws.qcur.p;
     a.dk_virtual = 0;
+    // query-interleaved: each query's survivors spread over the kernel's
+    // lifetime, so later ones meet a tighter threshold (query-major
+    // measured 1.6x slower on the banded DP)
+    a.qmajor = 0;
     a.ctr = ix->ws.ctr.p;
     return a;
 }
@@ -787,6 +791,7 @@ static void apply_tuned(tsk_query_opts *o, const tsk_query_opts &t)
     o->dk_band_slots = t.dk_band_slots;
     o->surv_order = t.surv_order;
     o->dp_rows = t.dp_rows;
+    o->dp_waves_per_cu = t.dp_waves_per_cu;
 }
 
 extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
@@ -832,6 +837,9 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
     if (o.dk_band_slots != 0 && o.dk_band_slots != 32 && o.dk_band_slots != 56 &&
         o.dk_band_slots != 64 && o.dk_band_slots != 104 && o.dk_band_slots != 128)
         return set_err(TSK_ERR_INVALID_ARG, "dk_band_slots must be 0, 32, 56, 64, 104 or 128");
+    if (o.dp_waves_per_cu != 0 && o.dp_waves_per_cu != 8 && o.dp_waves_per_cu != 16 &&
+        o.dp_waves_per_cu != 32)
+        return set_err(TSK_ERR_INVALID_ARG, "dp_waves_per_cu must be 0, 8, 16 or 32");
     if (o.dp_rows != 0 && o.dp_rows != 1 && o.dp_rows != 4)
         return set_err(TSK_ERR_INVALID_ARG, "dp_rows must be 0, 1 or 4");
     if (o.surv_order < 0 || o.surv_order > 2)
@@ -935,6 +943,8 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             TSK_TRY(W.qpad.ensure((size_t)c.nq * c.qrows * (P.D <= 4 ? 4 : 8)));
         return TSK_OK;
     };
+    // 16 persistent waves per CU (4 per SIMD) hide the DP loops' load latency
+    const int fast_waves = o.dp_waves_per_cu > 0 ? o.dp_waves_per_cu : 16;
     // s: the stream to enqueue on (the caller's, or the capture stream)
     auto enqueue_chunk = [&](const Chunk &c, hipEvent_t *ev, hipStream_t s) -> int {
 #define TSK_MARK(i)                                                                                \
@@ -1024,10 +1034,11 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
                 fa.task = o.task_size > 0 ? o.task_size : 64;
                 // 16-row windows: the live tube of near neighbours is a few
                 // rows wide; the rare wider ones finish in the general DP
-                launch_tube(P.D, fa, o.tube_rows == 32 ? 32 : 16, ix->n_cu * 8, c.qmax, s);
+                launch_tube(P.D, fa, o.tube_rows == 32 ? 32 : 16, ix->n_cu * fast_waves, c.qmax,
+                            s);
             } else {
                 fa.dk_virtual = c.fast == FAST_BAND_DKV ? 1 : 0;
-                launch_band(P.D, dist, c.wsel, fa, ix->n_cu * 8, s);
+                launch_band(P.D, dist, c.wsel, fa, ix->n_cu * fast_waves, s);
             }
             TSK_MARK(6);
             da.work = W.work.p + 2;
@@ -1061,7 +1072,8 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
                                     (int64_t)(uintptr_t)out_dist_dev, (int64_t)(uintptr_t)s,
                                     o.order, (int64_t)(uintptr_t)o.order_dev, o.seed_count,
                                     o.dp_kernel, o.walk_pass, o.task_size, o.tube_rows,
-                                    o.lb_qgroup, o.dk_band_slots, o.surv_order, o.dp_rows};
+                                    o.lb_qgroup, o.dk_band_slots, o.surv_order, o.dp_rows,
+                                    o.dp_waves_per_cu};
         // every workspace buffer the captured kernels address: a buffer
         // reallocated by another call changes the key
         for (const void *ptr :
@@ -1344,6 +1356,7 @@ extern "C" int tsk_tune(tsk_index *ix, const float *q_values_dev, const int64_t 
             knobs.push_back({&tsk_query_opts::lb_qgroup, {2, 4, 8}});
         knobs.push_back({&tsk_query_opts::surv_order, {1, 2}});
         knobs.push_back({&tsk_query_opts::dp_rows, {1, 4}});
+        knobs.push_back({&tsk_query_opts::dp_waves_per_cu, {8, 16, 32}});
         tsk_query_opts cur = b;
         float cur_ms = 0.0f;
         TSK_TRY(trial(cur, &cur_ms));
