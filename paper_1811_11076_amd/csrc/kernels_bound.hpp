@@ -198,16 +198,15 @@ __global__ __launch_bounds__(256) void k_bound_lb(BoundArgs a, const float *__re
             const int gg = g < nqg ? g : 0;
             cfloat *e = E + ((int64_t)gg * n + j) * 2 * D;
             float t = 0.0f;
-            bool empty = false;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const float lo = e[k], hi = e[D + k];
-                empty |= lo > hi;
-                // distance to [lo, hi]: lo - x below, x - hi above, 0 inside
+                // distance to [lo, hi]: lo - x below, x - hi above, 0 inside;
+                // an empty window ([+inf, -inf]) gives +inf by itself
                 const float d = fmaxf(fmaxf(lo - x[k], x[k] - hi), 0.0f);
                 t = (k == 0) ? d * d : __builtin_fmaf(d, d, t);
             }
-            acc[g] = (empty ? tsk_inf() : t) + acc[g];
+            acc[g] = t + acc[g];
         }
     }
     unsigned long long pruned = 0, pairs = 0;
