@@ -131,10 +131,19 @@ def tuned_graph(w, args, idx_dk, idx_dtw, dev_q, qs, qo, eager_res):
     outs = {name: (torch.empty((nq, k), dtype=torch.int64, device="cuda"),
                    torch.empty((nq, k), dtype=torch.float32, device="cuda")) for name in ("dk", "dtw")}
 
+    # the two distances' graphs run on two streams (default priority) at
+    # once: each call's latency-bound stages overlap the other's
+    # throughput-bound ones
+    streams = (torch.cuda.Stream(), torch.cuda.Stream())
+    torch.cuda.synchronize()
+
     def step():
-        a = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], use_graph=True, tune=True, out=outs["dk"])
-        b = idx_dtw.knn(dev_q, qo, k, "dtw", w["dtw_band"], use_graph=True, tune=True,
-                        out=outs["dtw"])
+        with torch.cuda.stream(streams[0]):
+            a = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], use_graph=True, tune=True,
+                           out=outs["dk"])
+        with torch.cuda.stream(streams[1]):
+            b = idx_dtw.knn(dev_q, qo, k, "dtw", w["dtw_band"], use_graph=True, tune=True,
+                            out=outs["dtw"])
         return a, b
 
     for _ in range(max(1, args.warmup)):
@@ -334,7 +343,8 @@ def main():
         # timed over the same number of steps with identical rows
         if batching["rows_equal_eager"] and batching["ms_per_step"] < eager["ms_per_step"]:
             elapsed = batching["ms_per_step"] * args.steps * 1e-3
-            mode = "tuned options, captured HIP graph per distance (one launch each), replayed"
+            mode = ("tuned options; one captured HIP graph per distance, replayed, the two "
+                    "on concurrent streams")
 
     learned = None
     if not args.no_learned and w["gen"] == "classwarp":

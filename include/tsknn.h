@@ -163,11 +163,14 @@ typedef struct {
     int32_t dp_waves_per_cu;       /* persistent waves per compute unit of
                                       the lane-per-pair DP kernels: 8, 16
                                       or 32 (0 = library default) */
+    int32_t dk_seed;               /* DK threshold seed: 0 = greedy walks
+                                      (Alg. 1), 1 = the diagonal path's
+                                      largest cost (equal lengths only) */
     int32_t tune;                  /* TSK_TUNE_CACHED: take seed_count,
                                       tube_rows, task_size, walk_pass,
                                       lb_qgroup, dk_band_slots, surv_order,
-                                      dp_rows and dp_waves_per_cu from the
-                                      index's tuning cache
+                                      dp_rows, dp_waves_per_cu and dk_seed
+                                      from the index's tuning cache
                                       for this (distance, band, k), if
                                       tsk_tune filled it; TSK_TUNE_OFF: as
                                       given */

@@ -90,7 +90,7 @@ class Index:
             walk_pass: int = -1, task_size: int = 0, tube_rows: int = 0, model=None,
             lb_qgroup: int = 0, use_graph: bool = False, tune: bool = False, out=None,
             dk_band_slots: int = 0, surv_order: int = 0, dp_rows: int = 0,
-            dp_waves_per_cu: int = 0):
+            dp_waves_per_cu: int = 0, dk_seed: int = 0):
         """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
         float32 [nq, k], stats dict or None); DK distances are unsquared.
         order: None (plain), a CUDA int32 [nq, n] permutation per query, or
@@ -123,6 +123,7 @@ class Index:
         opts.surv_order = int(surv_order)
         opts.dp_rows = int(dp_rows)
         opts.dp_waves_per_cu = int(dp_waves_per_cu)
+        opts.dk_seed = int(dk_seed)
         opts.use_graph = 1 if use_graph else 0
         opts.tune = _lib.TSK_TUNE_CACHED if tune else _lib.TSK_TUNE_OFF
         if isinstance(order, str):
@@ -160,7 +161,7 @@ class Index:
             int(k), _DIST[distance], _lib.band_struct(band), None, ctypes.byref(to),
             ctypes.byref(best), ctypes.byref(ms), _stream()))
         keys = ("seed_count", "tube_rows", "task_size", "walk_pass", "lb_qgroup", "dk_band_slots",
-                "surv_order", "dp_rows", "dp_waves_per_cu")
+                "surv_order", "dp_rows", "dp_waves_per_cu", "dk_seed")
         return {key: getattr(best, key) for key in keys}, ms.value
 
     def profile(self, reset: bool = False) -> dict:

@@ -40,6 +40,7 @@ class QueryOpts(ctypes.Structure):
                 ("tube_rows", ctypes.c_int32), ("lb_qgroup", ctypes.c_int32),
                 ("dk_band_slots", ctypes.c_int32), ("surv_order", ctypes.c_int32),
                 ("dp_rows", ctypes.c_int32), ("dp_waves_per_cu", ctypes.c_int32),
+                ("dk_seed", ctypes.c_int32),
                 ("tune", ctypes.c_int32),
                 ("model", ctypes.c_void_p)]
 

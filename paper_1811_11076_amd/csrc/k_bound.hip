@@ -28,11 +28,15 @@ void seed_ring_d(int dist, const SeedRingArgs &r, hipStream_t s)
                            r.aos, r.off, r.len, r.N, r.order, r.P0, r.S, r.maxm, r.k, r.ba, r.seedslots,
                            r.tau, r.ctr, r.dbg_ub, r.dbg_steps);
 }
-template <int D> void seed_diag_d(const SeedRingArgs &r, hipStream_t s)
+template <int D> void seed_diag_d(int dist, const SeedRingArgs &r, hipStream_t s)
 {
     dim3 grid((r.S + 63) / 64, r.nq);
-    hipLaunchKernelGGL((k_seed_diag<D>), grid, dim3(64), 0, s, r.qv, r.qoff, r.nq, r.aos, r.off,
-                       r.len, r.N, r.order, r.S, r.k, r.seedslots, r.tau, r.ctr);
+    if (dist == DIST_DK)
+        hipLaunchKernelGGL((k_seed_diag<D, DIST_DK>), grid, dim3(64), 0, s, r.qv, r.qoff, r.nq,
+                           r.aos, r.off, r.len, r.N, r.order, r.S, r.k, r.seedslots, r.tau, r.ctr);
+    else
+        hipLaunchKernelGGL((k_seed_diag<D, DIST_DTW>), grid, dim3(64), 0, s, r.qv, r.qoff, r.nq,
+                           r.aos, r.off, r.len, r.N, r.order, r.S, r.k, r.seedslots, r.tau, r.ctr);
 }
 
 template <int D> void corner_d(const BoundArgs &a, hipStream_t s)
@@ -71,9 +75,9 @@ void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s)
 #undef CALL
 }
 
-void launch_seed_diag(int D, const SeedRingArgs &r, hipStream_t s)
+void launch_seed_diag(int D, int dist, const SeedRingArgs &r, hipStream_t s)
 {
-#define CALL(d) seed_diag_d<d>(r, s)
+#define CALL(d) seed_diag_d<d>(dist, r, s)
     TSK_SWITCH_D(D, CALL)
 #undef CALL
 }

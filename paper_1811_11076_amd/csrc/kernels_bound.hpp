@@ -331,7 +331,7 @@ __global__ __launch_bounds__(64) void k_walk_dk(FastArgs a, const float *__restr
 // No sequential walk: one lane per candidate, query rows wave-uniform
 // (scalar loads), candidate rows per lane.  Candidates whose length differs
 // from the query's are skipped.
-template <int D>
+template <int D, int DIST>
 __global__ __launch_bounds__(64) void k_seed_diag(const float *__restrict__ qv,
                                                   const int64_t *__restrict__ qoff, int nq,
                                                   const float *__restrict__ aos,
@@ -360,7 +360,10 @@ __global__ __launch_bounds__(64) void k_seed_diag(const float *__restrict__ qv,
         for (int e = 0; e < D; ++e)
             qq[e] = Q[(int64_t)i * D + e];
         load_point<D>(cp + (int64_t)(ok ? i : 0) * D, cc);
-        ub = point_cost<D>(qq, cc) + ub;
+        const float cst = point_cost<D>(qq, cc);
+        // the diagonal is a warping path: its cost sum bounds DTW, its
+        // largest cost bounds the squared DK
+        ub = DIST == DIST_DK ? fmaxf(cst, ub) : cst + ub;
     }
     wave_topk_insert(seedslots + (int64_t)q * k, k, ok, make_key(ub, (uint32_t)c), tau + q);
     wave_count(ctr + C_SEED_PAIRS, ok ? 1ull : 0ull);

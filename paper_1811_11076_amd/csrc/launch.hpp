@@ -43,7 +43,7 @@ inline size_t walk_lds_bytes(int D, int maxm)
 void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s);
 void launch_seed_ring(int D, int dist, const SeedRingArgs &r, hipStream_t s);
 void launch_corner(int D, const BoundArgs &a, hipStream_t s);
-void launch_seed_diag(int D, const SeedRingArgs &r, hipStream_t s);
+void launch_seed_diag(int D, int dist, const SeedRingArgs &r, hipStream_t s);
 void launch_walk_dk(int D, const FastArgs &a, const float *qv, unsigned long long *ubslots,
                     int blocks, int maxm, hipStream_t s);
 void launch_band(int D, int dist, int wsel, const FastArgs &a, int blocks, hipStream_t s);

@@ -792,6 +792,7 @@ static void apply_tuned(tsk_query_opts *o, const tsk_query_opts &t)
     o->surv_order = t.surv_order;
     o->dp_rows = t.dp_rows;
     o->dp_waves_per_cu = t.dp_waves_per_cu;
+    o->dk_seed = t.dk_seed;
 }
 
 extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
@@ -840,6 +841,8 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
     if (o.dp_waves_per_cu != 0 && o.dp_waves_per_cu != 8 && o.dp_waves_per_cu != 16 &&
         o.dp_waves_per_cu != 32)
         return set_err(TSK_ERR_INVALID_ARG, "dp_waves_per_cu must be 0, 8, 16 or 32");
+    if (o.dk_seed != 0 && o.dk_seed != 1)
+        return set_err(TSK_ERR_INVALID_ARG, "dk_seed must be 0 or 1");
     if (o.dp_rows != 0 && o.dp_rows != 1 && o.dp_rows != 4)
         return set_err(TSK_ERR_INVALID_ARG, "dp_rows must be 0, 1 or 4");
     if (o.surv_order < 0 || o.surv_order > 2)
@@ -929,7 +932,8 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         c.dk_split = dist == TSK_DK && c.lds_query;
         // uneven lengths: LB_Box per length bucket, lbv by sorted position
         c.lbu = dist == TSK_DTW && !P.env_ok && ix->bucketed && o.dp_kernel != 1;
-        c.diag_seed = P.seed > 0 && dist == TSK_DTW && c.qmin == c.qmax &&
+        // equal lengths: the diagonal path seeds DTW, and DK on request
+        c.diag_seed = P.seed > 0 && (dist == TSK_DTW || o.dk_seed == 1) && c.qmin == c.qmax &&
                       ix->min_len == ix->max_len && ix->min_len == c.qmin && o.dp_kernel != 1;
         c.fast = pick_fast(ix, dist, band, c.qmin, c.qmax, o.dp_kernel, o.dk_band_slots, &c.wsel);
         c.qrows = c.qmax + 2 * QPAD;
@@ -977,7 +981,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
                                nullptr, nullptr};
         if (c.diag_seed) {
             // equal lengths: diagonal-path sums seed the DTW threshold
-            launch_seed_diag(P.D, seed_args, s);
+            launch_seed_diag(P.D, dist, seed_args, s);
         } else if (P.seed > 0 && c.lds_query) {
             // the first 64 candidates walk to the end and set a threshold;
             // the rest of the seed set returns early against it
@@ -1073,7 +1077,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
                                     o.order, (int64_t)(uintptr_t)o.order_dev, o.seed_count,
                                     o.dp_kernel, o.walk_pass, o.task_size, o.tube_rows,
                                     o.lb_qgroup, o.dk_band_slots, o.surv_order, o.dp_rows,
-                                    o.dp_waves_per_cu};
+                                    o.dp_waves_per_cu, o.dk_seed};
         // every workspace buffer the captured kernels address: a buffer
         // reallocated by another call changes the key
         for (const void *ptr :
@@ -1345,8 +1349,10 @@ extern "C" int tsk_tune(tsk_index *ix, const float *q_values_dev, const int64_t 
             if (v <= ix->n)
                 seeds.push_back(v);
         knobs.push_back({&tsk_query_opts::seed_count, seeds});
-        if (dk_free && ix->min_len == ix->max_len)
+        if (dk_free && ix->min_len == ix->max_len) {
+            knobs.push_back({&tsk_query_opts::dk_seed, {1}});
             knobs.push_back({&tsk_query_opts::dk_band_slots, {32, 56, 104, 128}});
+        }
         if (dk_free) {
             knobs.push_back({&tsk_query_opts::tube_rows, {16, 32}});
             knobs.push_back({&tsk_query_opts::task_size, {32, 64, 128, 256}});

@@ -182,10 +182,11 @@ def test_knn_classwarp_uneven_reduced():
     idx.close()
 
 
-@pytest.mark.parametrize("w", [3, 12, 20, 30, 45, 60])
+@pytest.mark.parametrize("w", [3, 12, 20, 25, 27, 30, 45, 60])
 def test_knn_band_kernel_widths(w):
-    """Equal lengths, one band width per lane-per-pair window size (2w+1 of
-    7, 25, 41, 61, 91, 121 slots), both distances, against the oracle."""
+    """Equal lengths, band widths covering every lane-per-pair window size
+    (2w+1 of 7, 25, 41, 51, 55, 61, 91, 121 in windows of 16, 32, 52, 52,
+    56, 64, 104, 128 slots), both distances, against the oracle."""
     print(f"[case] knn band widths w={w}", flush=True)
     db, dbo = ragged_walks(40 + w, 150, (128, 128), 3)
     qs, qo = ragged_walks(140 + w, 3, (128, 128), 3)
@@ -290,6 +291,21 @@ def test_knn_general_dp_tile_rows(rows):
         ids, dst, _ = idx.knn(to_dev(qs), qo, 8, dist, band, dp_rows=rows)
         assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
     idx.close()
+
+
+@pytest.mark.parametrize("seed", [64, 1024])
+def test_knn_dk_diagonal_seed(seed):
+    """DK seeded by the diagonal path's largest cost (equal lengths; ragged
+    data falls back to the greedy walks): rows equal the oracle's."""
+    print(f"[case] knn dk diagonal seed S={seed}", flush=True)
+    cases = [classwarp(2, 10, 256, 3, 2000, 5),
+             ragged_walks(51, 300, (20, 60), 3) + ragged_walks(151, 4, (20, 60), 3)]
+    for db, dbo, qs, qo in cases:
+        idx = _index(db, dbo)
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, "dk", None)
+        ids, dst, _ = idx.knn(to_dev(qs), qo, 10, "dk", None, dk_seed=1, seed_count=seed)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
+        idx.close()
 
 
 def test_knn_general_dp_forced_equals_fast():
