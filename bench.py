@@ -397,8 +397,10 @@ def main():
     if batching is not None:
         out["batching"] = batching
     if learned is not None:
-        learned["speedup_vs_plain"] = ms_step / learned["ms_per_step"]
+        # both legs eager and sequential: the learned order's effect alone
+        learned["step_speedup_vs_plain"] = eager["ms_per_step"] / learned["ms_per_step"]
         learned["dk_speedup_vs_plain"] = dk_ms / learned["dk"]["device_ms"]
+        learned["dtw_speedup_vs_plain"] = dtw_ms / learned["dtw"]["device_ms"]
         learned["dk_fraction_full_dps_plain"] = prof_dk["dp_completed"] / max(1, prof_dk["calls"]) / pairs
         out["learned_order"] = learned
     if not args.no_cpu_baseline:
