@@ -608,8 +608,10 @@ static __global__ __launch_bounds__(1024) void k_compact_sorted(
 // strip lane l works on column s - l at step s (a skewed wavefront),
 // receiving the row below from lane l-1 of the previous step; the strip's
 // top row is handed to the next strip through a per-wave buffer.
-// Dead cells (value > tau) become +inf (the sparse-DK semantics of Alg. 3;
-// for DTW the same holds because values only grow along a path).  With
+// Cells above tau are dead (the sparse-DK semantics of Alg. 3; for DTW the
+// same holds because values only grow along a path): they keep their value,
+// which can only feed values above tau, and liveness tests compare with tau.
+// A strip hands up only columns up to its last live one.  With
 // sigma(i, j) = j + floor(i / R) a path moves sigma by 0, 1 or 2 per move,
 // so it cannot skip two consecutive steps of a strip: when two consecutive
 // steps are all dead and no live input from the strip below is still
@@ -632,20 +634,25 @@ __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *
             break;
         const bool last_strip = base + H >= m;
         float qr[R][D];
-        int jlo[R], jhi[R];
+        // row r's band columns: j is inside iff (unsigned)(j - jlo) <= span;
+        // rows past the query or with an empty band never are
+        int jlo[R];
+        unsigned span[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = base + R * lane + r;
+            int lo = 1 << 30, hi = -1;
             if (i < m) {
                 load_point<D>(qp + (int64_t)i * D, qr[r]);
-                band_cols(band, i, n, jlo[r], jhi[r]);
+                band_cols(band, i, n, lo, hi);
             } else {
 #pragma unroll
                 for (int k = 0; k < D; ++k)
                     qr[r][k] = 0.0f;
-                jlo[r] = n;
-                jhi[r] = -1;
             }
+            const bool empty = lo > hi;
+            jlo[r] = empty ? (1 << 30) : lo;
+            span[r] = empty ? 0u : (unsigned)(hi - lo);
         }
         int js, je, tmp;
         band_cols(band, base, n, js, tmp);
@@ -663,6 +670,9 @@ __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *
         float recv_prev = tsk_inf(), my_top = tsk_inf();
         if (lane == 0 && base > 0 && js - 1 >= js_prev && js - 1 <= in_max)
             recv_prev = tb_in[js - 1];
+        // cell (0,0): its lower-left predecessor is the virtual D(-1,-1) = 0
+        if (lane == 0 && base == 0)
+            recv_prev = 0.0f;
         bool alive_prev = true;
         const int nsteps = je - js + 64;
         // software pipeline: the candidate point (and lane 0's strip input)
@@ -688,31 +698,32 @@ __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *
             float cv[D];
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                cv[k] = jv ? c0[k] : 0.0f;
+                cv[k] = c0[k]; // a clamped point where j is outside: masked below
                 c0[k] = c1[k];
             }
             cand(j + 2, c1);
             t0 = t1;
             t1 = strip_in(js + s + 2);
             float down = recv, diag = recv_prev;
-            bool any = false;
+            float vmin = tsk_inf();
             float Dc[R];
+            // Out-of-band cells get an infinite cost.  Cells above tau keep
+            // their (exact) value: every extension of them stays above tau,
+            // so liveness is tested against tau instead of killing them.
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int i = base + R * lane + r;
-                const bool ok = jv && j >= jlo[r] && j <= jhi[r];
-                float pred = min3f(diag, down, Dp[r]);
-                if (i == 0 && j == 0)
-                    pred = 0.0f;
-                const float cst = point_cost<D>(qr[r], cv);
-                float v = DIST == DIST_DK ? fmaxf(cst, pred) : cst + pred;
-                v = (ok && v <= tau) ? v : tsk_inf();
+                const bool ok = (unsigned)(j - jlo[r]) <= span[r];
+                const float pred = min3f(diag, down, Dp[r]);
+                float cst = point_cost<D>(qr[r], cv);
+                cst = ok ? cst : tsk_inf();
+                const float v = DIST == DIST_DK ? fmaxf(cst, pred) : cst + pred;
                 valid += __popcll(__ballot(ok));
                 diag = Dp[r];
                 down = v;
                 Dc[r] = v;
-                any |= v != tsk_inf();
+                vmin = fminf(vmin, v);
             }
+            const bool any = vmin <= tau;
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 Dp[r] = Dc[r];
@@ -720,7 +731,7 @@ __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *
             my_top = Dc[R - 1];
             if (!last_strip && lane == 63 && jv) {
                 tb_out[j] = Dc[R - 1];
-                if (Dc[R - 1] != tsk_inf())
+                if (Dc[R - 1] <= tau)
                     out_max = j;
             }
             if (last_strip && j == n - 1) {
@@ -745,7 +756,8 @@ __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *
         if (last_strip)
             break;
     }
-    return wave_min(result);
+    result = wave_min(result);
+    return result <= tau ? result : tsk_inf();
 }
 
 struct DpArgs {
