@@ -105,3 +105,44 @@ def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "lib_path", lambda: str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         L.load()
+
+
+@needs_lib
+def test_query_and_tune_reject_null_index():
+    lib = _lib.load()
+    off = np.array([0, 4], np.int64)
+    offp = off.ctypes.data_as(ctypes.c_void_p)
+    fake = ctypes.c_void_p(0x1000)
+    band = _lib.band_struct(None)
+    rc = lib.tsk_knn_query(None, fake, offp, 1, 3, _lib.TSK_DK, band, None, fake, fake, None, None)
+    assert rc == _lib.TSK_ERR_INVALID_ARG and b"index is NULL" in lib.tsk_last_error()
+    rc = lib.tsk_tune(None, fake, offp, 1, 3, _lib.TSK_DTW, band, None, None, None, None, None)
+    assert rc == _lib.TSK_ERR_INVALID_ARG
+    rc = lib.tsk_pair_distances(None, fake, offp, 1, _lib.TSK_DK, band, fake, None)
+    assert rc == _lib.TSK_ERR_INVALID_ARG
+
+
+@needs_lib
+def test_model_shape_and_file_errors_before_device_work(tmp_path):
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    size = ctypes.sizeof(_lib.MlpShape)
+    for dim, points, hidden, embed, code in ((0, 32, 256, 64, _lib.TSK_ERR_UNSUPPORTED),
+                                             (9, 32, 256, 64, _lib.TSK_ERR_UNSUPPORTED),
+                                             (3, 1, 256, 64, _lib.TSK_ERR_UNSUPPORTED),
+                                             (3, 32, 100, 64, _lib.TSK_ERR_UNSUPPORTED),
+                                             (3, 32, 256, 300, _lib.TSK_ERR_UNSUPPORTED)):
+        sh = _lib.MlpShape(size, dim, points, hidden, embed)
+        assert lib.tsk_model_create(ctypes.byref(sh), 0, ctypes.byref(h)) == code
+        assert h.value is None
+    bad = _lib.MlpShape(size + 8, 3, 32, 256, 64)
+    assert lib.tsk_model_create(ctypes.byref(bad), 0, ctypes.byref(h)) == _lib.TSK_ERR_INVALID_ARG
+    assert lib.tsk_model_create(None, 0, ctypes.byref(h)) == _lib.TSK_ERR_INVALID_ARG
+    # unreadable and malformed encoder files
+    missing = str(tmp_path / "missing.bin").encode()
+    assert lib.tsk_model_load(missing, ctypes.byref(h)) == _lib.TSK_ERR_IO
+    junk = tmp_path / "junk.bin"
+    junk.write_bytes(b"not an encoder file at all")
+    assert lib.tsk_model_load(str(junk).encode(), ctypes.byref(h)) == _lib.TSK_ERR_IO
+    assert lib.tsk_model_save(None, missing) == _lib.TSK_ERR_INVALID_ARG
+    assert lib.tsk_model_free(None) == _lib.TSK_OK
