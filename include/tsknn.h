@@ -226,6 +226,29 @@ int tsk_knn_query(const tsk_index *index, const float *q_values_dev, const int64
                   const tsk_query_opts *opts, int64_t *out_ids_dev, float *out_dist_dev,
                   tsk_stats *stats_host, void *hip_stream);
 
+/* Range query (Sec. 1: all database series within a distance of the
+ * query, the paper's second query type beside k-NN), through the same
+ * bound and DP kernels with the threshold fixed at the radius (no seeding,
+ * no tightening).  Hits of query q are written in ascending id order to
+ * out_ids_dev / out_dist_dev[out_offsets_host[q] .. out_offsets_host[q+1])
+ * (distances as for tsk_knn_query: DTW sums; DK the correctly rounded sqrt
+ * of the squared DK; a hit is a series whose reported distance is
+ * <= radius).  out_offsets_host: [n_queries + 1] host int64, always filled.
+ * band: by pointer (NULL = no band).  radius: a hit's fp32 distance is
+ * <= radius (taken as the largest fp32 value not above it).
+ * capacity: entries of the output buffers; if the hits exceed it, nothing
+ * but the offsets is written and INVALID_ARG is returned (call again with
+ * capacity >= out_offsets_host[n_queries]).  Synchronous.  opts as for
+ * tsk_knn_query (use_graph excluded; walk_pass and seed_count ignored).
+ * Errors: INVALID_ARG (radius < 0 or NaN, NULL outputs, capacity), as
+ * tsk_knn_query otherwise. */
+int tsk_range_query(const tsk_index *index, const float *q_values_dev,
+                    const int64_t *q_offsets_host, int64_t n_queries, double radius,
+                    int32_t dist, const tsk_band *band, const tsk_query_opts *opts,
+                    int64_t capacity,
+                    int64_t *out_ids_dev, float *out_dist_dev, int64_t *out_offsets_host,
+                    tsk_stats *stats_host, void *hip_stream);
+
 /* Reads (and with reset != 0 clears) the profile accumulated by calls made
  * with opts->profile = 1 on this index: counters summed over those calls and
  * per-stage device milliseconds measured by HIP events recorded on each

@@ -268,3 +268,17 @@ def pair_keys(db, db_off, qs, q_off, dist="dk", band=None):
 def dk_distance(keys: np.ndarray) -> np.ndarray:
     """Distance from squared DK keys: correctly rounded fp32 square root."""
     return np.sqrt(np.asarray(keys, dtype=np.float32))
+
+
+def range_brute(db, db_off, qs, q_off, radius, dist="dk", band=None):
+    """Plain range query (Sec. 1): for each query, the ids (ascending) of
+    every series whose distance is <= radius, and those distances; the
+    distance of a pair is its full-DP key (DTW), or the correctly rounded
+    fp32 sqrt of the squared key (DK).  Returns a list of (ids, dists)."""
+    keys = pair_keys(db, db_off, qs, q_off, dist, band)
+    d = dk_distance(keys) if dist == "dk" else keys.astype(np.float32)
+    out = []
+    for q in range(d.shape[0]):
+        ids = np.nonzero(d[q] <= np.float32(radius))[0].astype(np.int64)
+        out.append((ids, d[q][ids]))
+    return out

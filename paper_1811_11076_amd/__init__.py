@@ -145,6 +145,37 @@ class Index:
             ctypes.byref(st) if st is not None else None, _stream()))
         return ids, dist, (st.as_dict() if st is not None else None)
 
+    def range(self, queries, q_offsets, radius: float, distance: str = "dk", band=None,
+              capacity: int = 0, stats: bool = False):
+        """Range query (C: tsk_range_query): every series within `radius` of
+        each query.  Returns (offsets int64 [nq+1] numpy, ids int64 CUDA [total],
+        dist float32 CUDA [total], stats dict or None); query q's hits are
+        ids[offsets[q]:offsets[q+1]] in ascending id order."""
+        torch = _torch()
+        qv = _values(queries, self.dim)
+        qo = _offsets(q_offsets)
+        nq = int(qo.shape[0] - 1)
+        offs = np.zeros(nq + 1, np.int64)
+        cap = int(capacity) if capacity > 0 else 64 * nq
+        for attempt in range(2):
+            ids = torch.empty(max(cap, 1), dtype=torch.int64, device=qv.device)
+            dist = torch.empty(max(cap, 1), dtype=torch.float32, device=qv.device)
+            st = _lib.Stats() if stats else None
+            rc = self._lib.tsk_range_query(
+                self._h, ctypes.c_void_p(qv.data_ptr()), qo.ctypes.data_as(ctypes.c_void_p), nq,
+                ctypes.c_double(radius), _DIST[distance], ctypes.byref(_lib.band_struct(band)),
+                None, cap,
+                ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
+                offs.ctypes.data_as(ctypes.c_void_p),
+                ctypes.byref(st) if st is not None else None, _stream())
+            if rc == _lib.TSK_ERR_INVALID_ARG and offs[nq] > cap and attempt == 0:
+                cap = int(offs[nq])  # the first call measured the total
+                continue
+            _lib.check(rc)
+            break
+        total = int(offs[nq])
+        return offs, ids[:total], dist[:total], (st.as_dict() if st is not None else None)
+
     def tune(self, queries, q_offsets, k: int, distance: str = "dk", band=None,
              sample_queries: int = 0, reps: int = 0):
         """Autotunes the work-shaping options on a query sample (C: tsk_tune);

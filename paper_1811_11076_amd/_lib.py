@@ -98,6 +98,10 @@ SIGNATURES = {
     "tsk_pair_distances": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp]),
     "tsk_pair_bounds": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp, _vp, _vp]),
     "tsk_tune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, Band, _vp, _vp, _vp, _vp, _vp]),
+    # band by pointer: libffi misplaces a float scalar next to a by-value
+    # struct with a float member, so this entry point takes neither
+    "tsk_range_query": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_double, _i32, _vp, _vp,
+                                       _i64, _vp, _vp, _vp, _vp, _vp]),
     "tsk_model_create": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "tsk_model_free": (ctypes.c_int, [_vp]),
     "tsk_model_info": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_i64)]),

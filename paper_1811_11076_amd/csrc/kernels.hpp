@@ -369,7 +369,9 @@ __global__ __launch_bounds__(256) void k_bounds(BoundArgs a)
                         a.dbg_ub[(int64_t)q * a.N + c] = g;
                     if (a.dbg_steps)
                         a.dbg_steps[(int64_t)q * a.N + c] = steps;
-                } else if (done && g != tsk_inf() && g <= bits_f(load_relaxed_u32(a.tau + q))) {
+                } else if (a.ubslots && done && g != tsk_inf() &&
+                           g <= bits_f(load_relaxed_u32(a.tau + q))) {
+                    // (no ubslots: a range query, whose threshold is fixed)
                     topk_insert(a.ubslots + (int64_t)q * a.k, a.k, make_key(g, (uint32_t)c));
                     tau_from_slots(a.ubslots + (int64_t)q * a.k, a.k, a.tau + q);
                 }
@@ -599,6 +601,63 @@ static __global__ __launch_bounds__(1024) void k_compact_sorted(
     }
 }
 
+// ------------------------------------------------------------------ range query output
+// Hits of one query in ascending id order: cnt pass (one block per query),
+// then fill at the query's offset; DK keys leave as correctly rounded sqrt.
+static __global__ __launch_bounds__(256) void k_range_count(const float *__restrict__ hits,
+                                                            int64_t N, int64_t *__restrict__ cnt)
+{
+    const int q = blockIdx.x;
+    __shared__ int64_t part[4];
+    int64_t c = 0;
+    for (int64_t p = threadIdx.x; p < N; p += 256)
+        c += hits[(int64_t)q * N + p] != tsk_inf() ? 1 : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        cnt[q] = part[0] + part[1] + part[2] + part[3];
+}
+
+template <int DIST>
+__global__ __launch_bounds__(256) void k_range_fill(const float *__restrict__ hits, int64_t N,
+                                                    const int64_t *__restrict__ qoffs,
+                                                    int64_t *__restrict__ ids,
+                                                    float *__restrict__ dist)
+{
+    const int q = blockIdx.x;
+    __shared__ int wave_tot[4];
+    __shared__ int64_t base_s;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0)
+        base_s = qoffs[q];
+    __syncthreads();
+    for (int64_t p0 = 0; p0 < N; p0 += 256) {
+        const int64_t p = p0 + threadIdx.x;
+        const float v = p < N ? hits[(int64_t)q * N + p] : tsk_inf();
+        const bool hit = v != tsk_inf();
+        const unsigned long long bal = __ballot(hit);
+        const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0)
+            wave_tot[wv] = __popcll(bal);
+        __syncthreads();
+        int64_t off = base_s;
+        for (int w = 0; w < wv; ++w)
+            off += wave_tot[w];
+        if (hit) {
+            ids[off + rank] = p;
+            dist[off + rank] = DIST == DIST_DK ? sqrt_rn_f32(v) : v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            base_s += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ general DP
 // One wave per pair: the quadratic DP of Sec. 2.1 (DTW: cost + min of the
 // three predecessors; DK: max(cost, min)), with D(-1,-1) = 0 and every other
@@ -785,6 +844,7 @@ struct DpArgs {
     const int2 *fb;     // FALLBACK: (query, candidate) list
     const unsigned long long *fb_count;
     int rows_per_lane;  // R of the strips: 1 or 4
+    float *range_out;   // range query: [nq][N] keys of hits, else null (top-k)
 };
 
 enum { DPW_SURV = 0, DPW_ALLPAIRS = 1, DPW_FALLBACK = 2 };
@@ -848,8 +908,13 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
             if (res != tsk_inf()) {
                 ++completed;
                 if (lane == 0 && res <= bits_f(load_relaxed_u32(a.tau + q))) {
-                    topk_insert(a.resslots + (int64_t)q * a.k, a.k, make_key(res, (uint32_t)c));
-                    tau_from_slots(a.resslots + (int64_t)q * a.k, a.k, a.tau + q);
+                    if (a.range_out) {
+                        a.range_out[(int64_t)q * a.N + c] = res;
+                    } else {
+                        topk_insert(a.resslots + (int64_t)q * a.k, a.k,
+                                    make_key(res, (uint32_t)c));
+                        tau_from_slots(a.resslots + (int64_t)q * a.k, a.k, a.tau + q);
+                    }
                 }
             } else {
                 ++abandoned;

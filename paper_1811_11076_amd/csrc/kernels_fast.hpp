@@ -44,6 +44,7 @@ struct FastArgs {
     int qrows;
     int task;                 // survivors per wave task (k_dp_tube)
     int32_t *qcur;            // per-query survivor cursors (k_dp_band), zeroed per call
+    float *range_out;         // range query: [nq][N] keys of hits, else null (top-k)
     int qmajor;               // task order of the lane-per-pair kernels: query-major
     int dk_virtual;           // k_dp_band on unbanded DK: a band of (W-1)/2 whose edge
                               // cells must stay above tau (else the general DP)
@@ -190,6 +191,14 @@ __device__ __forceinline__ void push_fallback(const FastArgs &a, int q, int c)
 __device__ __forceinline__ void finish_lane(const FastArgs &a, int q, int c, float res,
                                             unsigned long long &completed)
 {
+    if (a.range_out) {
+        // range query: the threshold is the fixed radius; record the hit
+        if (res != tsk_inf() && res <= bits_f(load_relaxed_u32(a.tau + q))) {
+            ++completed;
+            a.range_out[(int64_t)q * a.N + c] = res;
+        }
+        return;
+    }
     if (res != tsk_inf() && res <= bits_f(load_relaxed_u32(a.tau + q))) {
         ++completed;
         topk_insert(a.resslots + (int64_t)q * a.k, a.k, make_key(res, (uint32_t)c));

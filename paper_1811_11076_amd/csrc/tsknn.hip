@@ -43,6 +43,8 @@ struct Workspace {
     DevBuf<unsigned long long> seedslots, ubslots, resslots;
     DevBuf<float> lbv;
     DevBuf<int32_t> surv, surv_cnt, max_cnt, qcur;
+    DevBuf<float> rng;            // range query hit map [q][N]
+    DevBuf<int64_t> rcnt, rqoff;  // its per-query counts and output offsets
     DevBuf<unsigned long long> ctr, work;
     DevBuf<int64_t> qoff;
     DevBuf<float> env;
@@ -63,6 +65,9 @@ struct Workspace {
         surv_cnt.release();
         max_cnt.release();
         qcur.release();
+        rng.release();
+        rcnt.release();
+        rqoff.release();
         ctr.release();
         work.release();
         qoff.release();
@@ -610,6 +615,7 @@ static DpArgs dp_args(tsk_index *ix, const float *qv, int nq, const QueryPlan &P
     // one row per lane wastes fewer out-of-band cells on narrow bands but
     // costs more per cell; four measured faster on the class-warp bands
     a.rows_per_lane = 4;
+    a.range_out = nullptr;
     return a;
 }
 
@@ -643,6 +649,7 @@ static FastArgs fast_args(tsk_index *ix, int nq, const QueryPlan &P, int qrows)
     a.qrows = qrows;
     a.task = 64;
     a.qcur = ix->ws.qcur.p;
+    a.range_out = nullptr;
     a.dk_virtual = 0;
     // query-interleaved: each query's survivors spread over the kernel's
     // lifetime, so later ones meet a tighter threshold (query-major
@@ -732,6 +739,7 @@ static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env)
     TSK_TRY(w.surv_cnt.ensure(nq));
     TSK_TRY(w.max_cnt.ensure(1));
     TSK_TRY(w.qcur.ensure(nq));
+    TSK_TRY(w.rcnt.ensure(nq));
     TSK_TRY(w.ctr.ensure(C_NUM));
     TSK_TRY(w.work.ensure(8));
     TSK_TRY(w.qoff.ensure(nq + 1));
@@ -795,11 +803,21 @@ static void apply_tuned(tsk_query_opts *o, const tsk_query_opts &t)
     o->dk_seed = t.dk_seed;
 }
 
-extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
-                             const int64_t *q_offsets_host, int64_t n_queries, int32_t k,
-                             int32_t dist, tsk_band band, const tsk_query_opts *opts,
-                             int64_t *out_ids_dev, float *out_dist_dev, tsk_stats *stats_host,
-                             void *hip_stream)
+// A range query (fixed threshold, every hit reported) riding on the k-NN
+// pipeline: the threshold never tightens, results go to a per-pair hit map.
+struct RangeReq {
+    float tau_key;    // largest key whose distance is within the radius
+    int64_t capacity; // entries of ids / dist
+    int64_t *ids;
+    float *dist;
+    int64_t *offsets_host; // [n_queries + 1]
+};
+
+static int scan_impl(const tsk_index *cix, const float *q_values_dev,
+                     const int64_t *q_offsets_host, int64_t n_queries, int32_t k, int32_t dist,
+                     tsk_band band, const tsk_query_opts *opts, int64_t *out_ids_dev,
+                     float *out_dist_dev, tsk_stats *stats_host, void *hip_stream,
+                     const RangeReq *rr)
 {
     g_err.clear();
     TSK_TRY(check_queries(cix, q_values_dev, q_offsets_host, n_queries, dist, band));
@@ -807,7 +825,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "k must be >= 1");
     if (k > TSK_MAX_K)
         return set_err(TSK_ERR_UNSUPPORTED, "k %d > %d", k, TSK_MAX_K);
-    if (!out_ids_dev || !out_dist_dev)
+    if (!rr && (!out_ids_dev || !out_dist_dev))
         return set_err(TSK_ERR_INVALID_ARG, "output pointers are NULL");
     tsk_query_opts o;
     memset(&o, 0, sizeof(o));
@@ -851,6 +869,11 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "lb_qgroup must be 0, 2, 4 or 8");
     if (o.use_graph && (o.profile || o.order == TSK_ORDER_LEARNED))
         return set_err(TSK_ERR_UNSUPPORTED, "use_graph excludes profile and TSK_ORDER_LEARNED");
+    if (rr) {
+        if (o.use_graph)
+            return set_err(TSK_ERR_UNSUPPORTED, "a range query cannot run as a graph");
+        o.walk_pass = 0; // its threshold is the radius: no pass may lower it
+    }
     tsk_index *ix = const_cast<tsk_index *>(cix);
     std::lock_guard<std::mutex> lock(ix->mu);
     hipStream_t s = (hipStream_t)hip_stream;
@@ -878,10 +901,14 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
     // parallel sum, so it takes more candidates
     const int default_seed = dist == TSK_DK ? 512 : 1024;
     P.seed = (int)std::min<int64_t>(ix->n, o.seed_count > 0 ? o.seed_count : default_seed);
+    if (rr)
+        P.seed = 0; // no threshold seeding: the radius is the threshold
     P.env_ok = (dist == TSK_DTW) && ix->min_len == ix->max_len;
 
     TSK_TRY(ensure_ws(ix, P.chunk, k, P.env_ok));
     Workspace &W = ix->ws;
+    if (rr)
+        TSK_TRY(W.rng.ensure((size_t)P.chunk * ix->n));
 
     const bool profile = o.profile != 0;
     const bool timed = stats_host != nullptr || profile;
@@ -959,7 +986,9 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         const int nq = c.nq;
         const float *qv = q_values_dev; // offsets are absolute into q_values_dev
         TSK_MARK(0);
-        fill_u32(W.tau.p, TSK_INF_BITS, nq, s);
+        fill_u32(W.tau.p, rr ? f_bits_host(rr->tau_key) : TSK_INF_BITS, nq, s);
+        if (rr)
+            fill_u32((uint32_t *)W.rng.p, TSK_INF_BITS, (int64_t)nq * ix->n, s);
         fill_u64(W.seedslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
         fill_u64(W.ubslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
         fill_u64(W.resslots.p, TSK_KEY_EMPTY, (int64_t)nq * k, s);
@@ -991,6 +1020,8 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         }
         TSK_MARK(2);
         BoundArgs ba = bound_args(ix, qv, nq, P);
+        if (rr)
+            ba.ubslots = nullptr;
         if (c.dk_split) {
             launch_corner(P.D, ba, s);
         } else if (dist == TSK_DTW && P.env_ok && o.dp_kernel != 1) {
@@ -1027,6 +1058,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
         TSK_MARK(4);
         DpArgs da = dp_args(ix, qv, nq, P);
         da.lb_inv = c.lbu ? ix->inv : nullptr;
+        da.range_out = rr ? W.rng.p : nullptr;
         if (o.dp_rows != 0)
             da.rows_per_lane = o.dp_rows;
         if (c.fast != FAST_NONE) {
@@ -1034,6 +1066,7 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             TSK_MARK(5);
             FastArgs fa = fast_args(ix, nq, P, c.qrows);
             fa.lb_inv = c.lbu ? ix->inv : nullptr;
+            fa.range_out = rr ? W.rng.p : nullptr;
             if (c.fast == FAST_TUBE32) {
                 fa.task = o.task_size > 0 ? o.task_size : 64;
                 // 16-row windows: the live tube of near neighbours is a few
@@ -1053,7 +1086,10 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             launch_dp_wave(P.D, dist, DPW_SURV, da, dp_blocks(ix), s);
         }
         TSK_MARK(7);
-        if (dist == TSK_DK)
+        if (rr)
+            hipLaunchKernelGGL(k_range_count, dim3(nq), dim3(256), 0, s, W.rng.p, ix->n,
+                               W.rcnt.p);
+        else if (dist == TSK_DK)
             hipLaunchKernelGGL(k_finalize<DIST_DK>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq, k,
                                out_ids_dev + c.q0 * k, out_dist_dev + c.q0 * k);
         else
@@ -1135,6 +1171,33 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             if (timed)
                 TSK_TRY(take_events(ix, &ev));
             TSK_TRY(enqueue_chunk(c, ev, s));
+            if (rr) {
+                // counts to the host, then this chunk's hits in id order
+                std::vector<int64_t> cnt(c.nq);
+                HIP_TRY(hipMemcpyAsync(cnt.data(), W.rcnt.p, c.nq * sizeof(int64_t),
+                                       hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                std::vector<int64_t> qo(c.nq + 1);
+                qo[0] = rr->offsets_host[c.q0];
+                for (int i = 0; i < c.nq; ++i)
+                    qo[i + 1] = qo[i] + cnt[i];
+                for (int i = 0; i < c.nq; ++i)
+                    rr->offsets_host[c.q0 + i + 1] = qo[i + 1];
+                if (qo[c.nq] <= rr->capacity && qo[c.nq] > qo[0]) {
+                    TSK_TRY(W.rqoff.ensure(c.nq + 1));
+                    HIP_TRY(hipMemcpyAsync(W.rqoff.p, qo.data(), (c.nq + 1) * sizeof(int64_t),
+                                           hipMemcpyHostToDevice, s));
+                    if (dist == TSK_DK)
+                        hipLaunchKernelGGL(k_range_fill<DIST_DK>, dim3(c.nq), dim3(256), 0, s,
+                                           W.rng.p, ix->n, W.rqoff.p, rr->ids, rr->dist);
+                    else
+                        hipLaunchKernelGGL(k_range_fill<DIST_DTW>, dim3(c.nq), dim3(256), 0, s,
+                                           W.rng.p, ix->n, W.rqoff.p, rr->ids, rr->dist);
+                    HIP_TRY(hipGetLastError());
+                    // the offsets upload reads qo: finish before it goes away
+                    HIP_TRY(hipStreamSynchronize(s));
+                }
+            }
         }
     }
     HIP_TRY(hipGetLastError());
@@ -1160,6 +1223,85 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
             stats_times(stats_host, t);
         }
     }
+    return TSK_OK;
+}
+
+extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
+                             const int64_t *q_offsets_host, int64_t n_queries, int32_t k,
+                             int32_t dist, tsk_band band, const tsk_query_opts *opts,
+                             int64_t *out_ids_dev, float *out_dist_dev, tsk_stats *stats_host,
+                             void *hip_stream)
+{
+    return scan_impl(cix, q_values_dev, q_offsets_host, n_queries, k, dist, band, opts,
+                     out_ids_dev, out_dist_dev, stats_host, hip_stream, nullptr);
+}
+
+// Largest fp32 key whose reported distance is within the radius: DTW keys
+// are distances; a DK key's distance is its correctly rounded sqrt, which
+// is monotone, so the set of keys within the radius is a prefix.  The fp32
+// sqrt is taken through double (exact square root rounded twice, which is
+// the correctly rounded fp32 value) and neighbours by stepping bit patterns.
+static bool sqrt_within(float key, float radius)
+{
+    return (float)std::sqrt((double)key) <= radius;
+}
+
+static float step_bits(float x, int d)
+{
+    uint32_t u;
+    memcpy(&u, &x, sizeof(u));
+    u = (uint32_t)((int64_t)u + d);
+    memcpy(&x, &u, sizeof(u));
+    return x;
+}
+
+static float range_key(int32_t dist, float radius)
+{
+    if (dist == TSK_DTW)
+        return radius;
+    if (std::isinf(radius))
+        return radius;
+    float t = (float)((double)radius * (double)radius);
+    while (!std::isinf(step_bits(t, 1)) && sqrt_within(step_bits(t, 1), radius))
+        t = step_bits(t, 1);
+    while (t > 0.0f && !sqrt_within(t, radius))
+        t = step_bits(t, -1);
+    return t;
+}
+
+extern "C" int tsk_range_query(const tsk_index *cix, const float *q_values_dev,
+                               const int64_t *q_offsets_host, int64_t n_queries, double radius_d,
+                               int32_t dist, const tsk_band *band_p, const tsk_query_opts *opts,
+                               int64_t capacity, int64_t *out_ids_dev, float *out_dist_dev,
+                               int64_t *out_offsets_host, tsk_stats *stats_host,
+                               void *hip_stream)
+{
+    g_err.clear();
+    if (!(radius_d >= 0.0)) // also rejects NaN
+        return set_err(TSK_ERR_INVALID_ARG, "radius must be >= 0");
+    // distances are fp32: a hit is a series whose fp32 distance is <= the
+    // radius rounded down to fp32
+    float radius = (float)radius_d;
+    if ((double)radius > radius_d)
+        radius = step_bits(radius, -1);
+    tsk_band band;
+    memset(&band, 0, sizeof(band));
+    band.mode = TSK_BAND_NONE;
+    if (band_p)
+        band = *band_p;
+    if (!out_offsets_host)
+        return set_err(TSK_ERR_INVALID_ARG, "out_offsets_host is NULL");
+    if (capacity < 0 || (capacity > 0 && (!out_ids_dev || !out_dist_dev)))
+        return set_err(TSK_ERR_INVALID_ARG, "capacity < 0, or output pointers NULL");
+    if (n_queries >= 1)
+        out_offsets_host[0] = 0;
+    RangeReq rr{range_key(dist, radius), capacity, out_ids_dev, out_dist_dev, out_offsets_host};
+    TSK_TRY(scan_impl(cix, q_values_dev, q_offsets_host, n_queries, 1, dist, band, opts, nullptr,
+                      nullptr, stats_host, hip_stream, &rr));
+    if (out_offsets_host[n_queries] > capacity)
+        return set_err(TSK_ERR_INVALID_ARG,
+                       "%lld hits do not fit the capacity of %lld (offsets are filled)",
+                       (long long)out_offsets_host[n_queries], (long long)capacity);
     return TSK_OK;
 }
 

@@ -403,3 +403,30 @@ def test_fp32_dtw_close_to_fp64():
             a, b = O.dtw_f32(S, T, w), O.dtw_f64(S, T, w)
             worst = max(worst, abs(a - b) / b)
     assert worst < 1e-5
+
+
+def test_range_brute_against_knn_definitions():
+    """The range query's definition checked against the k-NN one: radius +inf
+    returns every series; radius = the k-th nearest distance returns the k
+    nearest (and only series at or below it); just below the nearest
+    distance returns nothing."""
+    r = np.random.default_rng(41)
+    N, d = 40, 3
+    L = r.integers(5, 14, size=N)
+    dbo = np.concatenate([[0], np.cumsum(L)]).astype(np.int64)
+    db = np.cumsum(r.normal(size=(int(dbo[-1]), d)), axis=0).astype(np.float32)
+    qs = np.cumsum(r.normal(size=(20, d)), axis=0).astype(np.float32)
+    qo = np.array([0, 9, 20], np.int64)
+    for dist, band in (("dk", None), ("dtw", 2), ("dtw", None)):
+        k = 6
+        ids, keys = O.knn_brute(db, dbo, qs, qo, k, dist, band)
+        dk_ = O.dk_distance(keys) if dist == "dk" else keys
+        allr = O.range_brute(db, dbo, qs, qo, np.inf, dist, band)
+        for q in range(2):
+            finite = np.isfinite(O.pair_keys(db, dbo, qs, qo, dist, band)[q])
+            assert np.array_equal(allr[q][0], np.nonzero(finite)[0])
+            rk = O.range_brute(db, dbo, qs, qo, dk_[q, k - 1], dist, band)[q]
+            assert set(ids[q].tolist()) <= set(rk[0].tolist())
+            assert np.all(rk[1] <= dk_[q, k - 1]) and np.all(np.diff(rk[0]) > 0)
+            below = np.nextafter(np.float32(dk_[q, 0]), np.float32(-1))
+            assert O.range_brute(db, dbo, qs, qo, below, dist, band)[q][0].size == 0
