@@ -66,6 +66,18 @@ def _load():
                                 _i64p]),
         "orc_pair_keys": (None, [_f32p, _i64p, _i64, _f32p, _i64p, _i64, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, _i64, ctypes.c_float, _f32p]),
+        "orc_subseq_dk_sq_f32": (ctypes.c_float, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64p]),
+        "orc_subseq_start": (_i64, [_f32p, _i64, _f32p, _i64, ctypes.c_int, ctypes.c_float]),
+        "orc_subseq_brute_f32": (ctypes.c_float, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64p,
+                                                  _i64p]),
+        "orc_sub_gdk_sq_f32": (ctypes.c_float, [_f32p, _i64, _f32p, _i64, ctypes.c_int,
+                                                ctypes.c_float, _i64p]),
+        "orc_sparse_dk_sub_sq_f32": (ctypes.c_float, [_f32p, _i64, _f32p, _i64, ctypes.c_int,
+                                                      ctypes.c_float, _i64p, _i64p]),
+        "orc_subseq_knn": (None, [_f32p, _i64p, _i64, _f32p, _i64p, _i64, ctypes.c_int, _i64,
+                                  _i64p, _f32p, _i64p, _i64p]),
+        "orc_subseq_scan": (None, [_f32p, _i64p, _i64, _f32p, _i64p, _i64, ctypes.c_int, _i64,
+                                   _i64p, _f32p, _i64p, _i64p, _i64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -282,3 +294,90 @@ def range_brute(db, db_off, qs, q_off, radius, dist="dk", band=None):
         ids = np.nonzero(d[q] <= np.float32(radius))[0].astype(np.int64)
         out.append((ids, d[q][ids]))
     return out
+
+
+# ---------------------------------------------------------------- subsequence search
+
+def _sub_call(name, S, T, *extra):
+    S = _series(S)
+    T = _series(T)
+    assert S.shape[1] == T.shape[1]
+    _, sp = _f32(S)
+    _, tp = _f32(T)
+    return getattr(_load(), name)(sp, S.shape[0], tp, T.shape[0], S.shape[1], *extra)
+
+
+def subseq_dk(S, T):
+    """(squared key, end, start) of the best match of S anywhere in T: the
+    plain SUB DP (Alg. 3 with SUB, every cell), the start by definition."""
+    e = ctypes.c_int64(-1)
+    v = float(_sub_call("orc_subseq_dk_sq_f32", S, T, ctypes.byref(e)))
+    if e.value < 0:
+        return v, -1, -1
+    return v, int(e.value), subseq_start(S, T, int(e.value), v)
+
+
+def subseq_start(S, T, end, key):
+    """Latest a <= end with DK(S, T[a..end]) == key (-1 if none)."""
+    S = _series(S)
+    T = _series(T)
+    _, sp = _f32(S)
+    _, tp = _f32(T)
+    return int(_load().orc_subseq_start(sp, S.shape[0], tp, end, S.shape[1], ctypes.c_float(key)))
+
+
+def subseq_brute(S, T):
+    """(key, end, start) from the definition: DK(S, T[a..b]) for all a <= b."""
+    e, a = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    v = float(_sub_call("orc_subseq_brute_f32", S, T, ctypes.byref(e), ctypes.byref(a)))
+    return v, int(e.value), int(a.value)
+
+
+def sub_gdk_sq_f32(S, T, eps=float("inf")):
+    """(value, steps) of the greedy bound for subsequence search, Alg. 2."""
+    st = ctypes.c_int64(0)
+    v = _sub_call("orc_sub_gdk_sq_f32", S, T, ctypes.c_float(eps), ctypes.byref(st))
+    return float(v), int(st.value)
+
+
+def sparse_dk_sub_sq_f32(S, T, eps=float("inf")):
+    """(value, end, visited cells) of Alg. 3 with SUB = true."""
+    e, cells = ctypes.c_int64(-1), ctypes.c_int64(0)
+    v = _sub_call("orc_sparse_dk_sub_sq_f32", S, T, ctypes.c_float(eps), ctypes.byref(e),
+                  ctypes.byref(cells))
+    return float(v), int(e.value), int(cells.value)
+
+
+def _subseq_common(fn, ser, s_off, qs, q_off, k, stats):
+    ser, sp = _f32(_series(ser))
+    s_off, sop = _i64a(s_off)
+    qs, qp = _f32(_series(qs))
+    q_off, qop = _i64a(q_off)
+    d = ser.shape[1]
+    assert qs.shape[1] == d
+    N = s_off.shape[0] - 1
+    nq = q_off.shape[0] - 1
+    ids = np.zeros((nq, k), np.int64)
+    keys = np.zeros((nq, k), np.float32)
+    end = np.zeros((nq, k), np.int64)
+    start = np.zeros((nq, k), np.int64)
+    args = [sp, sop, N, qp, qop, nq, d, k, ids.ctypes.data_as(_i64p),
+            keys.ctypes.data_as(_f32p), end.ctypes.data_as(_i64p), start.ctypes.data_as(_i64p)]
+    st = None
+    if stats:
+        st = np.zeros(nq, np.int64)
+        args.append(st.ctypes.data_as(_i64p))
+    fn(*args)
+    return ids, keys, end, start, st
+
+
+def subseq_knn(ser, s_off, qs, q_off, k):
+    """Plain subsequence k-NN: (ids, squared keys, end, start), each [nq, k];
+    series ranked by (key, id); (-1, +inf, -1, -1) padding."""
+    return _subseq_common(_load().orc_subseq_knn, ser, s_off, qs, q_off, k, False)[:4]
+
+
+def subseq_scan(ser, s_off, qs, q_off, k):
+    """The paper's pruned subsequence scan (Alg. 2 threshold + Alg. 3 SUB):
+    same outputs as subseq_knn plus visited cells per query."""
+    return _subseq_common(_load().orc_subseq_scan, ser, s_off, qs, q_off, k, True)

@@ -803,3 +803,266 @@ void orc_knn_scan(const float *db, const int64_t *db_off, int64_t N,
         free(top);
     }
 }
+
+/* ================================================================ subsequence search
+ * Sec. 4.2-4.3: a match may start and end anywhere in the long series T
+ * (the query S is matched against a contiguous part T[a..b]).  The
+ * subsequence DK of (S, T) is min over 0 <= a <= b < n of DK(S, T[a..b]);
+ * its end is the first column b at which that minimum is reached, its start
+ * the latest a <= b with DK(S, T[a..b]) equal to it (the shortest match
+ * ending at b).  Squared domain as everywhere else.
+ *
+ * Readings (listed in the design notes too):
+ *   R-sub0   in SUB mode row 0 has a virtual predecessor of -inf in every
+ *            column (a match may start in any column), so D(0,k) = c(0,k);
+ *            the printed vectors start at +inf and would never start.
+ *   R-subd   the running minimum d of Alg. 3 is set to +inf once, before the
+ *            column loop (the listing resets it inside the loop, which would
+ *            keep only the last column's value).
+ *   R-sgdk   Alg. 2's walk starts at the first j minimising c(s_0, t_j) and
+ *            stops once the last row is reached; a move past the last column
+ *            counts as +inf; ties as in Alg. 1. */
+
+/* Plain SUB DP (Alg. 3 with SUB, every cell visited): columns of T in
+ * order, D(i,k) = max(c(i,k), min(D(i-1,k), D(i,k-1), D(i-1,k-1))) with
+ * D(0,k) = c(0,k).  Returns min_k D(m-1,k); *end = first such k. */
+ORC_CLONES
+float orc_subseq_dk_sq_f32(const float *S, int64_t m, const float *T, int64_t n, int d,
+                           int64_t *end)
+{
+    if (end) *end = -1;
+    if (m <= 0 || n <= 0)
+        return ORC_INF;
+    float *E = malloc(sizeof(float) * m), *D = malloc(sizeof(float) * m);
+    for (int64_t i = 0; i < m; ++i) E[i] = ORC_INF;
+    float best = ORC_INF;
+    for (int64_t k = 0; k < n; ++k) {
+        for (int64_t i = 0; i < m; ++i) {
+            float c = orc_cost_f32(S + i * d, T + k * d, d);
+            if (i == 0) {
+                D[0] = c; /* R-sub0 */
+            } else {
+                float pred = fmin3f(D[i - 1], E[i], E[i - 1]);
+                D[i] = c > pred ? c : pred;
+            }
+        }
+        if (D[m - 1] < best) {
+            best = D[m - 1];
+            if (end) *end = k;
+        }
+        float *t = E; E = D; D = t;
+    }
+    free(E); free(D);
+    return best;
+}
+
+/* The latest start a <= e with DK(S, T[a..e]) == key (whole-match DK of the
+ * sub-series, Sec. 2.1), or -1 if there is none. */
+int64_t orc_subseq_start(const float *S, int64_t m, const float *T, int64_t e, int d, float key)
+{
+    for (int64_t a = e; a >= 0; --a)
+        if (orc_dk_sq_f32(S, m, T + a * d, e - a + 1, d, -1) == key)
+            return a;
+    return -1;
+}
+
+/* Definition by brute force: DK(S, T[a..b]) for every a <= b (tiny inputs
+ * only).  Returns the minimum; *end = first b reaching it, *start = latest
+ * a for that b. */
+float orc_subseq_brute_f32(const float *S, int64_t m, const float *T, int64_t n, int d,
+                           int64_t *end, int64_t *start)
+{
+    float best = ORC_INF;
+    int64_t be = -1, bs = -1;
+    for (int64_t b = 0; b < n; ++b)
+        for (int64_t a = b; a >= 0; --a) {
+            float v = orc_dk_sq_f32(S, m, T + a * d, b - a + 1, d, -1);
+            if (v < best) { best = v; be = b; bs = a; }
+        }
+    if (end) *end = be;
+    if (start) *start = bs;
+    return best;
+}
+
+/* Alg. 2 (greedy DK for subsequence search), reading R-sgdk; early return
+ * once the running max exceeds eps.  *steps = moves made. */
+ORC_CLONES
+float orc_sub_gdk_sq_f32(const float *S, int64_t m, const float *T, int64_t n, int d, float eps,
+                         int64_t *steps)
+{
+    int64_t st = 0;
+    if (steps) *steps = 0;
+    if (m <= 0 || n <= 0)
+        return ORC_INF;
+    int64_t j = 0;
+    float g = orc_cost_f32(S, T, d);
+    for (int64_t jj = 1; jj < n; ++jj) {
+        float c = orc_cost_f32(S, T + jj * d, d);
+        if (c < g) { g = c; j = jj; }
+    }
+    int64_t i = 0;
+    if (g > eps) return g;
+    while (i != m - 1) {
+        float c_dn = orc_cost_f32(S + (i + 1) * d, T + j * d, d);
+        float c_dg = j + 1 < n ? orc_cost_f32(S + (i + 1) * d, T + (j + 1) * d, d) : ORC_INF;
+        float c_rt = j + 1 < n ? orc_cost_f32(S + i * d, T + (j + 1) * d, d) : ORC_INF;
+        float c;
+        if (c_dn <= c_dg && c_dn <= c_rt) { c = c_dn; i += 1; }
+        else if (c_dg <= c_rt) { c = c_dg; i += 1; j += 1; }
+        else { c = c_rt; j += 1; }
+        ++st;
+        if (c > g) g = c;
+        if (g > eps) break;
+    }
+    if (steps) *steps = st;
+    return g;
+}
+
+/* Alg. 3 with SUB = true: the sparse column sweep that only visits a cell
+ * whose own cost is <= eps, its visits of the next column coming from the
+ * live cells of this one, plus row 0 in every column (any column may start
+ * a match).  Returns the subsequence DK if it is <= eps, else +inf; *end =
+ * first column reaching it; *cells = visited cells. */
+ORC_CLONES
+float orc_sparse_dk_sub_sq_f32(const float *S, int64_t m, const float *T, int64_t n, int d,
+                               float eps, int64_t *end, int64_t *cells)
+{
+    if (end) *end = -1;
+    if (cells) *cells = 0;
+    if (m <= 0 || n <= 0)
+        return ORC_INF;
+    float *D = malloc(sizeof(float) * m), *E = malloc(sizeof(float) * m);
+    char *inI = calloc(m + 1, 1), *inJ = calloc(m + 1, 1);
+    for (int64_t i = 0; i < m; ++i) D[i] = E[i] = ORC_INF;
+    float dmin = ORC_INF; /* R-subd */
+    int64_t visited = 0;
+    inI[0] = 1;
+    for (int64_t k = 0; k < n; ++k) {
+        /* rows in ascending order; visiting a live row adds the next row of
+         * this column (I = I + {i+1}) and rows i, i+1 of the next (J) */
+        for (int64_t i = 0; i < m; ++i) {
+            if (!inI[i])
+                continue;
+            ++visited;
+            float c = orc_cost_f32(S + i * d, T + k * d, d);
+            if (c <= eps) {
+                float pred = i == 0 ? -ORC_INF /* R-sub0 */
+                                    : fmin3f(D[i - 1], E[i], E[i - 1]);
+                D[i] = c > pred ? c : pred;
+                inI[i + 1] = 1;
+                inJ[i] = 1;
+                inJ[i + 1] = 1;
+            }
+        }
+        if (D[m - 1] < dmin) {
+            dmin = D[m - 1];
+            if (end) *end = k;
+        }
+        /* E = D; D = +inf; I = J + {0}; J = {} */
+        for (int64_t i = 0; i < m; ++i) { E[i] = D[i]; D[i] = ORC_INF; }
+        for (int64_t i = 0; i <= m; ++i) { inI[i] = inJ[i]; inJ[i] = 0; }
+        inI[0] = 1;
+    }
+    free(D); free(E); free(inI); free(inJ);
+    if (cells) *cells = visited;
+    if (dmin > eps) {
+        if (end) *end = -1;
+        return ORC_INF;
+    }
+    return dmin;
+}
+
+/* Plain definition of the subsequence k-NN query: for every (query, series)
+ * the subsequence DK by the plain SUB DP, then a (key, id) sort.  Outputs
+ * [nq][k]: ids, keys (squared), end and start columns of each match (-1,
+ * +inf, -1, -1 padding).  Queries in parallel under OpenMP. */
+void orc_subseq_knn(const float *ser, const int64_t *s_off, int64_t N, const float *qs,
+                    const int64_t *q_off, int64_t nq, int d, int64_t k, int64_t *out_ids,
+                    float *out_keys, int64_t *out_end, int64_t *out_start)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nq; ++q) {
+        const float *S = qs + q_off[q] * d;
+        int64_t m = q_off[q + 1] - q_off[q];
+        orc_kv *all = malloc(sizeof(orc_kv) * (N > 0 ? N : 1));
+        int64_t *ends = malloc(sizeof(int64_t) * (N > 0 ? N : 1));
+        for (int64_t c = 0; c < N; ++c) {
+            all[c].key = orc_subseq_dk_sq_f32(S, m, ser + s_off[c] * d, s_off[c + 1] - s_off[c], d,
+                                              &ends[c]);
+            all[c].id = c;
+        }
+        qsort(all, N, sizeof(orc_kv), orc_kv_cmp);
+        for (int64_t r = 0; r < k; ++r) {
+            int64_t o = q * k + r;
+            if (r < N && all[r].key != ORC_INF) {
+                int64_t c = all[r].id, e = ends[c];
+                out_ids[o] = c;
+                out_keys[o] = all[r].key;
+                out_end[o] = e;
+                out_start[o] = orc_subseq_start(S, m, ser + s_off[c] * d, e, d, all[r].key);
+            } else {
+                out_ids[o] = -1; out_keys[o] = ORC_INF; out_end[o] = -1; out_start[o] = -1;
+            }
+        }
+        free(all); free(ends);
+    }
+}
+
+/* The paper's pruned subsequence scan (Sec. 4.4 with the SUB variants):
+ * threshold = k-th smallest Alg. 2 bound over the series, then Alg. 3 with
+ * SUB per series in id order, the threshold falling to the k-th best value
+ * found.  Same outputs as orc_subseq_knn; stats[q] = visited cells. */
+void orc_subseq_scan(const float *ser, const int64_t *s_off, int64_t N, const float *qs,
+                     const int64_t *q_off, int64_t nq, int d, int64_t k, int64_t *out_ids,
+                     float *out_keys, int64_t *out_end, int64_t *out_start, int64_t *stats)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nq; ++q) {
+        const float *S = qs + q_off[q] * d;
+        int64_t m = q_off[q + 1] - q_off[q];
+        orc_kv *ub = malloc(sizeof(orc_kv) * k), *top = malloc(sizeof(orc_kv) * k);
+        int64_t *tend = malloc(sizeof(int64_t) * k);
+        int64_t nub = 0, cnt = 0, cells = 0;
+        for (int64_t c = 0; c < N; ++c) {
+            float eps = (nub == k) ? ub[k - 1].key : ORC_INF;
+            float g = orc_sub_gdk_sq_f32(S, m, ser + s_off[c] * d, s_off[c + 1] - s_off[c], d, eps,
+                                         NULL);
+            if (g <= eps && g != ORC_INF) {
+                orc_kv x = {g, c};
+                orc_topk_insert(ub, &nub, k, x);
+            }
+        }
+        float tau = (nub == k) ? ub[k - 1].key : ORC_INF;
+        for (int64_t c = 0; c < N; ++c) {
+            int64_t e = -1, vis = 0;
+            float v = orc_sparse_dk_sub_sq_f32(S, m, ser + s_off[c] * d, s_off[c + 1] - s_off[c],
+                                               d, tau, &e, &vis);
+            cells += vis;
+            if (v != ORC_INF) {
+                orc_kv x = {v, c};
+                /* keep each kept entry's end column beside it */
+                if (orc_topk_insert(top, &cnt, k, x)) {
+                    int64_t p = 0;
+                    while (top[p].id != c) ++p;
+                    for (int64_t r = cnt - 1; r > p; --r) tend[r] = tend[r - 1];
+                    tend[p] = e;
+                }
+                if (cnt == k && top[k - 1].key < tau) tau = top[k - 1].key;
+            }
+        }
+        for (int64_t r = 0; r < k; ++r) {
+            int64_t o = q * k + r;
+            if (r < cnt) {
+                int64_t c = top[r].id;
+                out_ids[o] = c;
+                out_keys[o] = top[r].key;
+                out_end[o] = tend[r];
+                out_start[o] = orc_subseq_start(S, m, ser + s_off[c] * d, tend[r], d, top[r].key);
+            } else {
+                out_ids[o] = -1; out_keys[o] = ORC_INF; out_end[o] = -1; out_start[o] = -1;
+            }
+        }
+        if (stats) stats[q] = cells;
+        free(ub); free(top); free(tend);
+    }
+}
