@@ -249,6 +249,50 @@ int tsk_range_query(const tsk_index *index, const float *q_values_dev,
                     int64_t *out_ids_dev, float *out_dist_dev, int64_t *out_offsets_host,
                     tsk_stats *stats_host, void *hip_stream);
 
+/* ---------------------------------------------------------------- subsequence search */
+
+/* Longest query of tsk_subseq_query (16 rows per lane of one wave). */
+#define TSK_SUB_MAX_QLEN 1024
+
+typedef struct {
+    int64_t size;         /* sizeof(tsk_subseq_opts) */
+    int32_t chunk_cols;   /* start columns per work item (0 = library default:
+                             about four items per resident wave) */
+    int32_t seed;         /* 1: greedy bounds (Alg. 2) seed the threshold
+                             (default); 0: no seeding (the threshold only falls
+                             as matches are found; much slower, for checks) */
+    int32_t waves_per_cu; /* waves per compute unit of the DP kernel
+                             (0 = 16, at most 32) */
+    int32_t reserved;
+} tsk_subseq_opts;
+
+/* Subsequence k-NN (Sec. 4.2-4.3; Alg. 2 and Alg. 3 with SUB): a match of a
+ * query may start and end anywhere in a series.  The subsequence DK of
+ * (query S, series T) is min over a <= b of DK(S, T[a..b]) (squared point
+ * costs, as for tsk_knn_query, reported as the correctly rounded sqrt).  For
+ * every query the k series with the smallest (subsequence DK, id) are written
+ * to out_ids_dev / out_dist_dev[q*k .. q*k+k-1], with the match's end column
+ * (the first column b reaching the minimum) in out_end_dev and its start (the
+ * latest a with DK(S, T[a..b]) equal to it) in out_start_dev; empty ranks get
+ * (-1, +inf, -1, -1).
+ * series_dev: caller-owned device fp32 AoS [s_offsets_host[n_series]][dim]
+ * (no index: the series are read in place, lengths 1 .. 2^31-1);
+ * q_values_dev / q_offsets_host: the queries, lengths 1 .. TSK_SUB_MAX_QLEN.
+ * All output buffers are device [n_queries * k]; out_start_dev may be NULL
+ * (no start pass).  opts may be NULL.  stats_host (nullable): pairs, seed_pairs
+ * (greedy walks that reached the last row), bound_pruned (work items skipped
+ * by their row-0 minimum), dp_started / dp_completed / dp_abandoned (work
+ * items swept / with a value <= threshold / without), dp_cells, dp_valid_cells,
+ * bound_steps (greedy moves + row-0 costs scanned), ms_total / ms_seed /
+ * ms_dp / ms_final.  The call allocates its working memory and is
+ * synchronous.  Errors: INVALID_ARG, UNSUPPORTED (dim, k > TSK_MAX_K, query
+ * longer than TSK_SUB_MAX_QLEN), OOM, DEVICE. */
+int tsk_subseq_query(const float *series_dev, const int64_t *s_offsets_host, int64_t n_series,
+                     int32_t dim, const float *q_values_dev, const int64_t *q_offsets_host,
+                     int64_t n_queries, int32_t k, const tsk_subseq_opts *opts,
+                     int64_t *out_ids_dev, float *out_dist_dev, int64_t *out_end_dev,
+                     int64_t *out_start_dev, tsk_stats *stats_host, void *hip_stream);
+
 /* Reads (and with reset != 0 clears) the profile accumulated by calls made
  * with opts->profile = 1 on this index: counters summed over those calls and
  * per-stage device milliseconds measured by HIP events recorded on each

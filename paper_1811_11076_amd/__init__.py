@@ -17,7 +17,7 @@ import numpy as np
 
 from . import _lib
 
-__all__ = ["Index", "Model", "TskError", "version"]
+__all__ = ["Index", "Model", "TskError", "subseq_query", "version"]
 
 TskError = _lib.TskError
 
@@ -229,6 +229,41 @@ class Index:
             _DIST[distance], _lib.band_struct(band), ctypes.c_void_p(lb.data_ptr()),
             ctypes.c_void_p(ub.data_ptr()), ctypes.c_void_p(steps.data_ptr()), _stream()))
         return lb, ub, steps
+
+
+def subseq_query(series, s_offsets, queries, q_offsets, k: int = 1, chunk_cols: int = 0,
+                 seed: bool = True, waves_per_cu: int = 0, start: bool = True,
+                 stats: bool = False):
+    """Subsequence k-NN (C: tsk_subseq_query): for each query the k series
+    holding the best matches of the query anywhere inside them, by
+    subsequence DK.  series: CUDA float32 [sum_len, d] with offsets
+    [n+1] (long series; no index); queries likewise (lengths <= 1024).
+    Returns (ids int64, dist float32, end int64, start int64 or None), each
+    CUDA [nq, k], and the stats dict (or None); a match covers columns
+    start..end of its series.  Synchronous."""
+    torch = _torch()
+    lib = _lib.load()
+    sv = _values(series)
+    so = _offsets(s_offsets)
+    qv = _values(queries, sv.shape[1])
+    qo = _offsets(q_offsets)
+    n, nq = int(so.shape[0] - 1), int(qo.shape[0] - 1)
+    dev = sv.device
+    ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    end = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    st_ = torch.empty((nq, k), dtype=torch.int64, device=dev) if start else None
+    o = _lib.SubseqOpts(ctypes.sizeof(_lib.SubseqOpts), int(chunk_cols), 1 if seed else 0,
+                        int(waves_per_cu), 0)
+    st = _lib.Stats() if stats else None
+    _lib.check(lib.tsk_subseq_query(
+        ctypes.c_void_p(sv.data_ptr()), so.ctypes.data_as(ctypes.c_void_p), n, int(sv.shape[1]),
+        ctypes.c_void_p(qv.data_ptr()), qo.ctypes.data_as(ctypes.c_void_p), nq, int(k),
+        ctypes.byref(o), ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
+        ctypes.c_void_p(end.data_ptr()),
+        ctypes.c_void_p(st_.data_ptr()) if st_ is not None else None,
+        ctypes.byref(st) if st is not None else None, _stream()))
+    return ids, dist, end, st_, (st.as_dict() if st is not None else None)
 
 
 class Model:

@@ -71,6 +71,11 @@ class TuneOpts(ctypes.Structure):
                 ("reps", ctypes.c_int32)]
 
 
+class SubseqOpts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int64), ("chunk_cols", ctypes.c_int32), ("seed", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class MlpShape(ctypes.Structure):
     _fields_ = [("size", ctypes.c_int64), ("dim", ctypes.c_int32), ("points", ctypes.c_int32),
                 ("hidden", ctypes.c_int32), ("embed", ctypes.c_int32)]
@@ -102,6 +107,8 @@ SIGNATURES = {
     # struct with a float member, so this entry point takes neither
     "tsk_range_query": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_double, _i32, _vp, _vp,
                                        _i64, _vp, _vp, _vp, _vp, _vp]),
+    "tsk_subseq_query": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp, _i64, _i32, _vp, _vp, _vp,
+                                        _vp, _vp, _vp, _vp]),
     "tsk_model_create": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "tsk_model_free": (ctypes.c_int, [_vp]),
     "tsk_model_info": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_i64)]),

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtsknn.so")
 ARCH = os.environ.get("TSK_ARCH", "gfx950")
 
-SOURCES = ["tsknn.hip", "k_band.hip", "k_tube.hip", "k_wave.hip", "k_bound.hip", "k_lbu.hip", "mlp.hip"]
+SOURCES = ["tsknn.hip", "k_band.hip", "k_tube.hip", "k_wave.hip", "k_bound.hip", "k_lbu.hip", "mlp.hip", "subseq.hip"]
 
 
 def lib_path() -> str:

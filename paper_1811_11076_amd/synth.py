@@ -152,3 +152,53 @@ def flat_equal(arr: np.ndarray):
     n, length, d = arr.shape
     return (np.ascontiguousarray(arr.reshape(n * length, d)),
             np.arange(n + 1, dtype=np.int64) * length)
+
+
+# ---------------------------------------------------------------- long series and planted queries
+# Subsequence search (Sec. 4.2-4.3 and the long-series experiment of Sec. 5)
+# queries short series against long ones; these stand in for the long ECG
+# recording.
+
+WALK_PIECE = 1 << 20
+
+
+def long_walk(length: int, d: int, cfg_id: int, stream: str = "db", index: int = 0) -> np.ndarray:
+    """One Gaussian random walk of `length` points, float32 [length, d];
+    piece p of 2^20 steps is drawn from its own seed (index * 4096 + p)."""
+    out = np.empty((length, d), dtype=np.float32)
+    level = np.zeros(d)
+    for p in range(0, (length + WALK_PIECE - 1) // WALK_PIECE):
+        lo, hi = p * WALK_PIECE, min(length, (p + 1) * WALK_PIECE)
+        steps = _rng(cfg_id, stream, int(index) * 4096 + p).standard_normal((hi - lo, d))
+        w = np.cumsum(steps, axis=0) + level
+        out[lo:hi] = w
+        level = w[-1]
+    return out
+
+
+def planted_queries(values: np.ndarray, offsets: np.ndarray, n: int, m: int, cfg_id: int,
+                    stream: str = "query"):
+    """n queries of m points cut from the given series: query q takes series
+    s ~ U{0..N-1}, a window of round(m * U[0.8, 1.2]) points (clipped to the
+    series) at a uniform position, resamples it onto m points under a random
+    piecewise-linear warp (as the class-warp members) and adds N(0, 0.1^2)
+    noise.  Returns (values float32 [n*m, d], offsets int64 [n+1],
+    origin int64 [n, 3] = (series, window start, window length))."""
+    N = offsets.shape[0] - 1
+    d = values.shape[1]
+    out = np.empty((n * m, d), dtype=np.float32)
+    origin = np.zeros((n, 3), dtype=np.int64)
+    for q in range(n):
+        rng = _rng(cfg_id, stream, q)
+        s = int(rng.integers(0, N))
+        L = int(offsets[s + 1] - offsets[s])
+        w = int(min(L, max(1, round(m * rng.uniform(SLOPE_LO, SLOPE_HI)))))
+        a = int(rng.integers(0, L - w + 1))
+        win = values[offsets[s] + a: offsets[s] + a + w].astype(np.float64)
+        slopes = rng.uniform(SLOPE_LO, SLOPE_HI, size=(1, N_SEGMENTS))
+        pos = _warp_positions(slopes, m, w)
+        vals = _interp(win[None], np.zeros(1, np.int64), pos)[0]
+        vals += rng.standard_normal((m, d)) * NOISE_SIGMA
+        out[q * m:(q + 1) * m] = vals
+        origin[q] = (s, a, w)
+    return out, np.arange(n + 1, dtype=np.int64) * m, origin

@@ -146,3 +146,43 @@ def test_model_shape_and_file_errors_before_device_work(tmp_path):
     assert lib.tsk_model_load(str(junk).encode(), ctypes.byref(h)) == _lib.TSK_ERR_IO
     assert lib.tsk_model_save(None, missing) == _lib.TSK_ERR_INVALID_ARG
     assert lib.tsk_model_free(None) == _lib.TSK_OK
+
+
+@needs_lib
+def test_subseq_rejects_bad_arguments_before_device_work():
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    soff = np.array([0, 5000], np.int64)  # long series are fine here
+    qoff = np.array([0, 8], np.int64)
+    sp, qp = soff.ctypes.data_as(ctypes.c_void_p), qoff.ctypes.data_as(ctypes.c_void_p)
+
+    def call(ser=fake, so=sp, n=1, dim=3, qv=fake, qo=qp, nq=1, k=1, opts=None, ids=fake,
+             dist=fake, end=fake):
+        return lib.tsk_subseq_query(ser, so, n, dim, qv, qo, nq, k, opts, ids, dist, end, None,
+                                    None, None)
+
+    assert call(ser=None) == _lib.TSK_ERR_INVALID_ARG
+    assert call(qv=None) == _lib.TSK_ERR_INVALID_ARG
+    assert call(dim=0) == _lib.TSK_ERR_UNSUPPORTED
+    assert call(dim=9) == _lib.TSK_ERR_UNSUPPORTED
+    assert call(k=0) == _lib.TSK_ERR_INVALID_ARG
+    assert call(k=65) == _lib.TSK_ERR_UNSUPPORTED
+    assert call(ids=None) == _lib.TSK_ERR_INVALID_ARG
+    assert call(end=None) == _lib.TSK_ERR_INVALID_ARG
+    assert call(so=None) == _lib.TSK_ERR_INVALID_ARG
+    assert call(n=0) == _lib.TSK_ERR_INVALID_ARG
+    empty = np.array([0, 0], np.int64)
+    assert call(so=empty.ctypes.data_as(ctypes.c_void_p)) == _lib.TSK_ERR_INVALID_ARG
+    long_q = np.array([0, 1025], np.int64)
+    assert call(qo=long_q.ctypes.data_as(ctypes.c_void_p)) == _lib.TSK_ERR_UNSUPPORTED
+    assert b"1025 > 1024" in lib.tsk_last_error()
+    bad = _lib.SubseqOpts(ctypes.sizeof(_lib.SubseqOpts) + 8, 0, 1, 0, 0)
+    assert call(opts=ctypes.byref(bad)) == _lib.TSK_ERR_INVALID_ARG
+    bad = _lib.SubseqOpts(ctypes.sizeof(_lib.SubseqOpts), -1, 1, 0, 0)
+    assert call(opts=ctypes.byref(bad)) == _lib.TSK_ERR_INVALID_ARG
+    bad = _lib.SubseqOpts(ctypes.sizeof(_lib.SubseqOpts), 0, 2, 0, 0)
+    assert call(opts=ctypes.byref(bad)) == _lib.TSK_ERR_INVALID_ARG
+    import torch
+    if not torch.cuda.is_available():
+        # valid arguments reach the device query, which fails without a GPU
+        assert call() == _lib.TSK_ERR_DEVICE
