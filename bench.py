@@ -277,6 +277,66 @@ def cpu_baseline(db, dbo, qs, qo, w, nq_sample, n_series=0):
                 seconds=t2 - t0), (sel, dk, dtw)
 
 
+# subsequence search (Alg. 2 + Alg. 3 with SUB): one long 3-D random walk,
+# queries cut from it, warped and noised (the long-recording experiment)
+SUBSEQ = dict(cfg_id=6, n=1 << 22, d=3, Q=64, m=256, k=1)
+
+
+def subsequence(args):
+    """Times tsk_subseq_query on the long-series workload (device time of
+    the call from its own HIP events; the call is synchronous and allocates
+    its working memory, which the wall-clock figure includes) and times the
+    oracle's pruned scan on a query sample, checking the GPU rows for it."""
+    import numpy as np
+    import torch
+    from paper_1811_11076_amd import subseq_query, synth
+    w = SUBSEQ
+    ser = synth.long_walk(w["n"], w["d"], w["cfg_id"])
+    soff = np.array([0, w["n"]], np.int64)
+    qs, qo, _ = synth.planted_queries(ser, soff, w["Q"], w["m"], w["cfg_id"])
+    dser, dq = torch.from_numpy(ser).cuda(), torch.from_numpy(qs).cuda()
+    for _ in range(2):
+        subseq_query(dser, soff, dq, qo, w["k"])
+    dev_ms, wall, st = [], [], None
+    for _ in range(5):
+        t0 = time.perf_counter()
+        ids, dist, end, start, st = subseq_query(dser, soff, dq, qo, w["k"], stats=True)
+        wall.append(time.perf_counter() - t0)
+        dev_ms.append(st["ms_total"])
+    ms = float(np.median(dev_ms))
+    positions = w["Q"] * w["n"]
+    out = {
+        "workload": f"walk-n{w['n']}-d{w['d']}-q{w['Q']}-m{w['m']}-k{w['k']}",
+        "unit": "query-positions/s",
+        "positions_per_s": positions / (ms * 1e-3),
+        "ms_per_call": ms,
+        "wall_ms_per_call": float(np.median(wall)) * 1e3,
+        "stages_ms": {"seed": st["ms_seed"], "dp": st["ms_dp"], "final_and_start": st["ms_final"]},
+        "work_items": st["dp_started"] + st["bound_pruned"],
+        "items_skipped_by_row0_bound": st["bound_pruned"],
+        "dp_lane_cells": st["dp_cells"],
+        "seed_moves_and_scans": st["bound_steps"],
+        "dense_cells": positions * w["m"],
+    }
+    if not args.no_cpu_baseline:
+        import oracle as O
+        sel = 8
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        rids, rkeys, rend, rstart, _ = O.subseq_scan(ser, soff, qs[:qo[sel]], qo[:sel + 1], w["k"])
+        sec = time.perf_counter() - t0
+        out["cpu_oracle"] = {"positions_per_s": sel * w["n"] / sec, "queries": sel, "cores": threads,
+                             "seconds": sec, "kind": "oracle",
+                             "sample": f"first {sel} of {w['Q']} queries, oracle.subseq_scan (Alg. 2 "
+                                       "threshold + Alg. 3 with SUB), OpenMP over queries"}
+        ok = (np.array_equal(ids[:sel].cpu().numpy(), rids)
+              and np.array_equal(dist[:sel].cpu().numpy(), np.sqrt(rkeys.astype(np.float32)))
+              and np.array_equal(end[:sel].cpu().numpy(), rend)
+              and np.array_equal(start[:sel].cpu().numpy(), rstart))
+        out["verified"] = {"queries": sel, "rows_equal_oracle": bool(ok)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,6 +348,10 @@ def main():
                     help="limit the CPU baseline sample to the first S series (0 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-subseq", action="store_true",
+                    help="skip the subsequence-search measurement")
+    ap.add_argument("--subseq-only", action="store_true",
+                    help="run only the subsequence-search measurement (one JSON line)")
     ap.add_argument("--eager", action="store_true",
                     help="time the profiled eager step instead of the tuned graph step")
     ap.add_argument("--per-query-sample", type=int, default=32)
@@ -299,6 +363,9 @@ def main():
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
                                    "(the multi-GPU sharding is described, not built)"}))
         sys.exit(2)
+    if args.subseq_only:
+        print(json.dumps({"subsequence": subsequence(args)}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -421,6 +488,10 @@ def main():
                                 "beforehand, untimed), DTW plain"})
         learned["dk_fraction_full_dps_plain"] = prof_dk["dp_completed"] / max(1, prof_dk["calls"]) / pairs
         out["learned_order"] = learned
+    if not args.no_subseq:
+        out["subsequence"] = subsequence(args)
+        print(f"[bench] subsequence search: {out['subsequence']['ms_per_call']:.3f} ms per call",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         cb, (sel, dk_ref, dtw_ref) = cpu_baseline(db, dbo, qs, qo, w, args.cpu_queries,
                                                   args.cpu_series)

@@ -257,7 +257,7 @@ int tsk_range_query(const tsk_index *index, const float *q_values_dev,
 typedef struct {
     int64_t size;         /* sizeof(tsk_subseq_opts) */
     int32_t chunk_cols;   /* start columns per work item (0 = library default:
-                             about four items per resident wave) */
+                             64 to 4096, about 2^18 items per group of queries) */
     int32_t seed;         /* 1: greedy bounds (Alg. 2) seed the threshold
                              (default); 0: no seeding (the threshold only falls
                              as matches are found; much slower, for checks) */

@@ -34,6 +34,11 @@ struct SubArgs {
     unsigned long long *pbest;// [nq][N] (key bits << 32) | end column
     uint32_t *pcnt;           // [nq][N] chunks of the pair finished
     float *clb;               // [nq * chunks] row-0 minimum of each chunk
+    int32_t *cj;              // [nq * chunks] its first column, relative to the chunk
+    uint32_t *pclb;           // [nq][N] smallest row-0 cost of the pair (fp32 bits)
+    int64_t *live;            // items left for the DP after the row-0 test
+    unsigned long long *nlive;// their count
+    uint32_t *plive;          // [nq][N] live items per pair
     unsigned long long *seedslots, *resslots; // [nq][k]
     uint32_t *tau;            // [nq] running threshold (fp32 bits)
     unsigned long long *work; // item counter of the DP kernel
@@ -71,30 +76,40 @@ __device__ __forceinline__ SubItem sub_item(const SubArgs &a, int64_t t)
     return it;
 }
 
-// Greedy bound per item (Alg. 2, one thread per item): the walk starts at
-// the first column of the chunk minimising c(s_0, t_j) and moves to the
-// cheapest of (i+1,j), (i+1,j+1), (i,j+1) (first of them on ties; past the
-// last column +inf) until it reaches the last row; the path's maximum cost
-// is an upper bound of the pair's subsequence DK.  The walk stops early
-// once it exceeds the pair's best bound so far or after a move budget; only
-// walks that reach the last row lower the pair's bound.  The chunk's row-0
-// minimum is kept: every match starting in the chunk costs at least that.
+// Row-0 minimum of each item: the first column of the chunk minimising
+// c(s_0, t_j), and the pair's minimum over its chunks.  Every match
+// starting in the chunk costs at least the chunk's minimum.  One thread per
+// item; consecutive items are the queries of one chunk, so a wave's lanes
+// read the same column, four columns per iteration (loads issued together).
 template <int D>
-__global__ __launch_bounds__(256) void k_sub_seed(SubArgs a)
+__global__ __launch_bounds__(256) void k_sub_rowmin(SubArgs a)
 {
     const int64_t total = (int64_t)a.nq * a.chunks;
-    unsigned long long moves = 0, done = 0;
+    unsigned long long scans = 0;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const SubItem it = sub_item(a, t);
-        const int64_t m = a.qoff[it.q + 1] - a.qoff[it.q];
-        const float *S = a.qv + a.qoff[it.q] * D;
         const float *T = a.ser + a.soff[it.c] * D;
-        float s0[D], p[D];
-        load_point<D>(S, s0);
+        float s0[D];
+        load_point<D>(a.qv + a.qoff[it.q] * D, s0);
         float g = tsk_inf();
-        int64_t j = it.a0;
-        for (int64_t jj = it.a0; jj < it.a1; ++jj) {
+        int64_t j = it.a0, jj = it.a0;
+        for (; jj + 4 <= it.a1; jj += 4) {
+            float p[4][D];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                load_point<D>(T + (jj + u) * D, p[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float c = point_cost<D>(s0, p[u]);
+                if (c < g) {
+                    g = c;
+                    j = jj + u;
+                }
+            }
+        }
+        for (; jj < it.a1; ++jj) {
+            float p[D];
             load_point<D>(T + jj * D, p);
             const float c = point_cost<D>(s0, p);
             if (c < g) {
@@ -102,13 +117,46 @@ __global__ __launch_bounds__(256) void k_sub_seed(SubArgs a)
                 j = jj;
             }
         }
-        moves += (unsigned long long)(it.a1 - it.a0);
+        scans += (unsigned long long)(it.a1 - it.a0);
         a.clb[t] = g;
-        uint32_t *ps = a.pseed + (int64_t)it.q * a.N + it.c;
-        float eps = bits_f(load_relaxed_u32(ps));
-        if (g > eps)
+        a.cj[t] = (int32_t)(j - it.a0);
+        atomicMin(a.pclb + (int64_t)it.q * a.N + it.c, f_bits(g));
+    }
+    if (scans)
+        atomicAdd(a.ctr + C_BOUND_STEPS, scans);
+}
+
+// Greedy bound (Alg. 2), one thread per item, walking from the item's
+// row-0 minimum: moves to the cheapest of (i+1,j), (i+1,j+1), (i,j+1) (the
+// first of them on ties; past the last column +inf) until the last row;
+// the path's maximum cost bounds the pair's subsequence DK from above.
+// Pass 0 walks only from the items holding the pair's smallest row-0 cost,
+// which contain Alg. 2's own start (the first column minimising c(s_0, t_j)
+// over the whole series); pass 1 from every other item whose row-0 minimum
+// is still below the pair's bound (no other walk can lower it).  A walk
+// stops once above the pair's bound or after a move budget; only walks that
+// reach the last row lower the bound.
+template <int D>
+__global__ __launch_bounds__(256) void k_sub_walk(SubArgs a, int pass)
+{
+    const int64_t total = (int64_t)a.nq * a.chunks;
+    unsigned long long moves = 0, done = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const SubItem it = sub_item(a, t);
+        const int64_t pair = (int64_t)it.q * a.N + it.c;
+        const float g0 = a.clb[t];
+        const bool first = f_bits(g0) == a.pclb[pair];
+        uint32_t *ps = a.pseed + pair;
+        float eps = bits_f(*ps); // a stale (larger) value only costs a walk
+        if (pass == 0 ? !first : (first || !(g0 < eps)))
             continue;
-        int64_t i = 0, st = 0;
+        eps = bits_f(load_relaxed_u32(ps));
+        const int64_t m = a.qoff[it.q + 1] - a.qoff[it.q];
+        const float *S = a.qv + a.qoff[it.q] * D;
+        const float *T = a.ser + a.soff[it.c] * D;
+        int64_t i = 0, j = it.a0 + a.cj[t], st = 0;
+        float g = g0;
         const int64_t cap = SUB_WALK_CAP_MUL * (m + a.C);
         float si[D], sn[D], tj[D], tn[D];
         load_point<D>(S, si);
@@ -327,67 +375,97 @@ __device__ __forceinline__ void sub_load_rows(const float *S, int m, bool rev, f
     }
 }
 
-// The DP over the items: persistent waves take items from a counter.  The
-// threshold of an item is min(query threshold, the pair's greedy bound, the
-// pair's best value so far); an item whose row-0 minimum exceeds it is
-// skipped.  A chunk's best (value, column) lowers the pair's entry; the
-// pair's last finishing chunk inserts the pair into the query's result
-// slots (each series once, with its final value) and lowers the threshold.
+// Threshold of a pair: min(query threshold, the pair's greedy bound, the
+// pair's best value so far).
+__device__ __forceinline__ float sub_thr(const SubArgs &a, int q, int64_t pair)
+{
+    const float tq = bits_f(load_relaxed_u32(a.tau + q));
+    const float ts = bits_f(load_relaxed_u32(a.pseed + pair));
+    const float tb = bits_f((uint32_t)(load_relaxed_u64(a.pbest + pair) >> 32));
+    return fminf(tq, fminf(ts, tb)); // an empty pbest reads as NaN: ignored
+}
+
+// Items whose row-0 minimum is within their pair's threshold (after the
+// seed) go to the live list, counted per pair; the rest cannot hold a match
+// within the threshold and are dropped.  One thread per item.
+static __global__ __launch_bounds__(256) void k_sub_compact(SubArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t total = (int64_t)a.nq * a.chunks;
+    unsigned long long dropped = 0;
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < total;
+         t0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = t0 + threadIdx.x;
+        bool live = false;
+        int64_t pair = 0;
+        if (t < total) {
+            const SubItem it = sub_item(a, t);
+            pair = (int64_t)it.q * a.N + it.c;
+            // no sweep has run yet: the threshold is the seed's
+            live = a.clb[t] <= fminf(bits_f(a.tau[it.q]), bits_f(a.pseed[pair]));
+            dropped += live ? 0 : 1;
+        }
+        const unsigned long long bal = __ballot(live);
+        unsigned long long base = 0;
+        if (lane == 0 && bal)
+            base = atomicAdd(a.nlive, (unsigned long long)__popcll(bal));
+        base = uniform_u64(base);
+        if (live) {
+            a.live[base + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+            atomicAdd(a.plive + pair, 1u);
+        }
+    }
+    if (dropped)
+        atomicAdd(a.ctr + C_BOUND_PRUNED, dropped);
+}
+
+// The DP over the live items: persistent waves take items from a counter
+// and sweep them (the sweep re-tests row-0 costs against the current
+// threshold).  A sweep's best (value, column) lowers the pair's entry; the
+// pair's last live item inserts the pair into the query's result slots
+// (each series once, with its final value, if within the threshold) and
+// lowers the threshold.  The fences order an item's result before its count
+// and the last item's reads after it.
 template <int D, int R>
 __global__ __launch_bounds__(256) void k_sub_dp(SubArgs a)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t total = (int64_t)a.nq * a.chunks;
-    unsigned long long cells = 0, valid = 0, scanned = 0, started = 0, skipped = 0, hits = 0,
-                       none = 0;
+    const unsigned long long total = *a.nlive;
+    unsigned long long cells = 0, valid = 0, scanned = 0, started = 0, hits = 0, none = 0;
     for (;;) {
-        unsigned long long t = 0;
+        unsigned long long w = 0;
         if (lane == 0)
-            t = atomicAdd(a.work, 1ull);
-        t = uniform_u64(t);
-        if (t >= (unsigned long long)total)
+            w = atomicAdd(a.work, 1ull);
+        w = uniform_u64(w);
+        if (w >= total)
             break;
-        const SubItem it = sub_item(a, (int64_t)t);
+        const int64_t t = a.live[w];
+        const SubItem it = sub_item(a, t);
         const int64_t pair = (int64_t)it.q * a.N + it.c;
         const int m = (int)(a.qoff[it.q + 1] - a.qoff[it.q]);
         auto thr = [&]() -> float {
-            float v = 0.0f;
-            if (lane == 0) {
-                const float tq = bits_f(load_relaxed_u32(a.tau + it.q));
-                const float ts = bits_f(load_relaxed_u32(a.pseed + pair));
-                const float tb = bits_f((uint32_t)(load_relaxed_u64(a.pbest + pair) >> 32));
-                v = fminf(tq, fminf(ts, tb));
-            }
+            const float v = lane == 0 ? sub_thr(a, it.q, pair) : 0.0f;
             return bits_f(__builtin_amdgcn_readfirstlane(f_bits(v)));
         };
-        if (a.clb[t] > thr()) {
-            ++skipped;
-        } else {
-            ++started;
-            const float *S = a.qv + a.qoff[it.q] * D;
-            float qr[R][D], q0[D];
-            sub_load_rows<D, R>(S, m, false, qr);
-            load_point<D>(S, q0);
-            float best;
-            int64_t bcol;
-            sub_sweep<D, R>(qr, q0, m, a.ser + a.soff[it.c] * D, D, it.n, it.a0, it.a1, thr, best,
-                            bcol, cells, valid, scanned);
-            if (best != tsk_inf()) {
-                ++hits;
-                if (lane == 0)
-                    atomicMin(a.pbest + pair,
-                              ((unsigned long long)f_bits(best) << 32) | (uint32_t)bcol);
-            } else {
-                ++none;
-            }
-        }
+        ++started;
+        const float *S = a.qv + a.qoff[it.q] * D;
+        float qr[R][D], q0[D];
+        sub_load_rows<D, R>(S, m, false, qr);
+        load_point<D>(S, q0);
+        float best;
+        int64_t bcol;
+        sub_sweep<D, R>(qr, q0, m, a.ser + a.soff[it.c] * D, D, it.n, it.a0, it.a1, thr, best,
+                        bcol, cells, valid, scanned);
+        if (best != tsk_inf())
+            ++hits;
+        else
+            ++none;
         if (lane == 0) {
-            // release this chunk's result before counting it; the last chunk
-            // of the pair sees every other chunk's result
+            if (best != tsk_inf())
+                atomicMin(a.pbest + pair, ((unsigned long long)f_bits(best) << 32) | (uint32_t)bcol);
             __threadfence();
-            const uint32_t nch = (uint32_t)(a.coff[it.c + 1] - a.coff[it.c]);
             const uint32_t prev = atomicAdd(a.pcnt + pair, 1u);
-            if (prev + 1 == nch) {
+            if (prev + 1 == a.plive[pair]) {
                 __threadfence();
                 const unsigned long long pb = load_relaxed_u64(a.pbest + pair);
                 if (pb != TSK_KEY_EMPTY) {
@@ -410,8 +488,6 @@ __global__ __launch_bounds__(256) void k_sub_dp(SubArgs a)
             atomicAdd(a.ctr + C_BOUND_STEPS, scanned);
         if (started)
             atomicAdd(a.ctr + C_DP_STARTED, started);
-        if (skipped)
-            atomicAdd(a.ctr + C_BOUND_PRUNED, skipped);
         if (hits)
             atomicAdd(a.ctr + C_DP_COMPLETED, hits);
         if (none)

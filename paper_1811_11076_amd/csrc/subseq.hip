@@ -63,7 +63,11 @@ void launch_sub_seed(int D, const SubArgs &a, int blocks, hipStream_t s)
 {
     switch (D) {
 #define TSK_SEED(DD)                                                                               \
-    case DD: hipLaunchKernelGGL(k_sub_seed<DD>, dim3(blocks), dim3(256), 0, s, a); break;
+    case DD:                                                                                       \
+        hipLaunchKernelGGL(k_sub_rowmin<DD>, dim3(blocks), dim3(256), 0, s, a);                    \
+        hipLaunchKernelGGL(k_sub_walk<DD>, dim3(blocks), dim3(256), 0, s, a, 0);                   \
+        hipLaunchKernelGGL(k_sub_walk<DD>, dim3(blocks), dim3(256), 0, s, a, 1);                   \
+        break;
         TSK_SEED(1)
         TSK_SEED(2)
         TSK_SEED(3)
@@ -97,8 +101,10 @@ void fill64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t 
 struct SubBufs {
     hipStream_t s = nullptr;
     DevBuf<int64_t> qoff, soff, coff;
-    DevBuf<uint32_t> pseed, pcnt, tau;
-    DevBuf<unsigned long long> pbest, seedslots, resslots, work, ctr;
+    DevBuf<uint32_t> pseed, pcnt, tau, pclb, plive;
+    DevBuf<int64_t> live;
+    DevBuf<int32_t> cj;
+    DevBuf<unsigned long long> pbest, seedslots, resslots, work, ctr, nlive;
     DevBuf<float> clb;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     ~SubBufs()
@@ -114,8 +120,13 @@ struct SubBufs {
         seedslots.release();
         resslots.release();
         work.release();
+        nlive.release();
         ctr.release();
         clb.release();
+        pclb.release();
+        plive.release();
+        live.release();
+        cj.release();
         for (auto &e : ev)
             if (e)
                 (void)hipEventDestroy(e);
@@ -200,10 +211,10 @@ extern "C" int tsk_subseq_query(const float *series_dev, const int64_t *s_offset
         total_cols += s_offsets_host[c + 1] - s_offsets_host[c];
     int64_t C = o.chunk_cols;
     if (C == 0) {
-        // about 4 items per resident wave of the DP kernel
-        const int64_t target = (int64_t)n_cu * 16 * 4;
-        C = (total_cols * G + target - 1) / target;
-        C = std::min<int64_t>(std::max<int64_t>(((C + 63) / 64) * 64, 256), (int64_t)1 << 16);
+        // about 2^18 items per group (one thread each in the row-minimum,
+        // walk and compaction passes), 64 to 4096 columns each
+        C = (total_cols * G + ((int64_t)1 << 18) - 1) >> 18;
+        C = std::min<int64_t>(std::max<int64_t>(((C + 63) / 64) * 64, 64), 4096);
     }
     C = std::min<int64_t>(C, INT32_MAX);
     std::vector<int64_t> coff(N + 1, 0);
@@ -225,6 +236,11 @@ extern "C" int tsk_subseq_query(const float *series_dev, const int64_t *s_offset
     TSK_TRY(b.work.ensure(1));
     TSK_TRY(b.ctr.ensure(C_NUM));
     TSK_TRY(b.clb.ensure(G * chunks));
+    TSK_TRY(b.cj.ensure(G * chunks));
+    TSK_TRY(b.pclb.ensure(G * N));
+    TSK_TRY(b.plive.ensure(G * N));
+    TSK_TRY(b.live.ensure(G * chunks));
+    TSK_TRY(b.nlive.ensure(1));
     for (auto &e : b.ev)
         HIP_TRY(hipEventCreate(&e));
     HIP_TRY(hipMemcpyAsync(b.soff.p, s_offsets_host, (N + 1) * sizeof(int64_t),
@@ -259,6 +275,11 @@ extern "C" int tsk_subseq_query(const float *series_dev, const int64_t *s_offset
         a.pbest = b.pbest.p;
         a.pcnt = b.pcnt.p;
         a.clb = b.clb.p;
+        a.cj = b.cj.p;
+        a.pclb = b.pclb.p;
+        a.plive = b.plive.p;
+        a.live = b.live.p;
+        a.nlive = b.nlive.p;
         a.seedslots = b.seedslots.p;
         a.resslots = b.resslots.p;
         a.tau = b.tau.p;
@@ -270,6 +291,9 @@ extern "C" int tsk_subseq_query(const float *series_dev, const int64_t *s_offset
         a.out_start = out_start_dev ? out_start_dev + q0 * k : nullptr;
         HIP_TRY(hipEventRecord(b.ev[0], s));
         fill32(b.pseed.p, TSK_INF_BITS, g * N, s);
+        fill32(b.pclb.p, TSK_INF_BITS, g * N, s);
+        fill32(b.plive.p, 0u, g * N, s);
+        fill64(b.nlive.p, 0ull, 1, s);
         fill32(b.pcnt.p, 0u, g * N, s);
         fill64(b.pbest.p, TSK_KEY_EMPTY, g * N, s);
         fill32(b.tau.p, TSK_INF_BITS, g, s);
@@ -284,6 +308,8 @@ extern "C" int tsk_subseq_query(const float *series_dev, const int64_t *s_offset
             fill32((uint32_t *)b.clb.p, 0u, g * chunks, s); // row-0 minima unknown: skip nothing
         }
         HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_sub_compact, dim3(grid_of(g * chunks, 256, 1 << 16)), dim3(256), 0,
+                           s, a);
         HIP_TRY(hipEventRecord(b.ev[1], s));
         launch_sub(D, R, false, a, dp_blocks, s);
         HIP_TRY(hipGetLastError());
