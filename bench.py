@@ -337,6 +337,57 @@ def subsequence(args):
     return out
 
 
+# tightness and pruning power of LB_Box over dimension x length (Thm. 3.3;
+# Sec. 5, tightness and pruning-power heat maps), on three generators:
+# class-warp, independent random walks, and i.i.d. Gaussian points (the
+# theorem's own assumption)
+SWEEP = dict(cfg_id=7, classes=10, Q=16, N=2000, k=10, band=0.1,
+             gens=("classwarp", "randomwalk", "iid"),
+             dims=(1, 2, 3, 4, 5, 6, 7, 8), lengths=(32, 64, 128, 256, 512))
+
+
+def tightness_sweep():
+    """Per (generator, d, L): mean LB_Box / DTW over all (query, series)
+    pairs, the pruning power (share of pairs whose LB_Box exceeds the
+    query's k-th nearest DTW, i.e. prunable whatever the scan order) and the
+    share the scan itself pruned (tsk_knn_query counters).  LB_Box and DTW
+    come from tsk_pair_bounds / tsk_pair_distances (the scan's own kernels)."""
+    import numpy as np
+    import torch
+    from paper_1811_11076_amd import Index, synth
+    w = SWEEP
+    rows = []
+    for gen in w["gens"]:
+        for d in w["dims"]:
+            for L in w["lengths"]:
+                cfg = w["cfg_id"] * 100 + d
+                if gen == "classwarp":
+                    g = synth.ClassWarp(cfg, w["classes"], L, d)
+                    db, dbo, _ = g.members(w["N"], "db", length=L)
+                    qs, qo, _ = g.members(w["Q"], "query", length=L, class_mode="uniform")
+                else:
+                    f = synth.random_walks if gen == "randomwalk" else synth.gaussian_iid
+                    db, dbo = synth.flat_equal(f(w["N"], L, d, cfg, "db"))
+                    qs, qo = synth.flat_equal(f(w["Q"], L, d, cfg, "query"))
+                idx = Index(torch.from_numpy(db).cuda(), dbo)
+                dq = torch.from_numpy(qs).cuda()
+                lb, _, _ = idx.pair_bounds(dq, qo, "dtw", w["band"])
+                dtw = idx.pair_distances(dq, qo, "dtw", w["band"])
+                _, _, st = idx.knn(dq, qo, w["k"], "dtw", w["band"], stats=True)
+                lb = lb.double().cpu().numpy()
+                dtw = dtw.double().cpu().numpy()
+                tau = np.sort(dtw, axis=1)[:, w["k"] - 1:w["k"]]
+                pos = dtw > 0
+                rows.append({"gen": gen, "d": d, "L": L,
+                             "tightness": float((lb[pos] / dtw[pos]).mean()),
+                             "pruning_power": float((lb > tau).mean()),
+                             "scan_pruned": st["bound_pruned"] / max(1, st["pairs"])})
+                idx.close()
+                print(f"[sweep] {gen} d={d} L={L} tightness {rows[-1]['tightness']:.4f} "
+                      f"pruning {rows[-1]['pruning_power']:.4f}", file=sys.stderr, flush=True)
+    return {"queries": w["Q"], "series": w["N"], "k": w["k"], "band": w["band"], "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +401,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-subseq", action="store_true",
                     help="skip the subsequence-search measurement")
+    ap.add_argument("--tightness-sweep", action="store_true",
+                    help="run only the LB_Box tightness / pruning-power sweep (one JSON line)")
     ap.add_argument("--subseq-only", action="store_true",
                     help="run only the subsequence-search measurement (one JSON line)")
     ap.add_argument("--eager", action="store_true",
@@ -363,6 +416,9 @@ def main():
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
                                    "(the multi-GPU sharding is described, not built)"}))
         sys.exit(2)
+    if args.tightness_sweep:
+        print(json.dumps({"tightness_sweep": tightness_sweep()}), flush=True)
+        return
     if args.subseq_only:
         print(json.dumps({"subsequence": subsequence(args)}), flush=True)
         return

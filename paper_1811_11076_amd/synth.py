@@ -202,3 +202,18 @@ def planted_queries(values: np.ndarray, offsets: np.ndarray, n: int, m: int, cfg
         out[q * m:(q + 1) * m] = vals
         origin[q] = (s, a, w)
     return out, np.arange(n + 1, dtype=np.int64) * m, origin
+
+
+def gaussian_iid(n: int, length: int, d: int, cfg_id: int, stream: str, start: int = 0) -> np.ndarray:
+    """Series whose points are independent N(0, I_d) draws (the setting of
+    the curse-of-dimensionality theorem for LB_Box), float32 [n, length, d];
+    chunked and seeded like random_walks."""
+    out = np.empty((n, length, d), dtype=np.float32)
+    first_chunk = start // CHUNK
+    last_chunk = (start + n - 1) // CHUNK if n > 0 else first_chunk - 1
+    for ch in range(first_chunk, last_chunk + 1):
+        pts = _rng(cfg_id, stream, ch).standard_normal((CHUNK, length, d))
+        lo = max(start, ch * CHUNK)
+        hi = min(start + n, (ch + 1) * CHUNK)
+        out[lo - start:hi - start] = pts[lo - ch * CHUNK:hi - ch * CHUNK]
+    return out
