@@ -4,6 +4,14 @@
 namespace tsk {
 
 namespace {
+template <int D> void bound_lb_pp_d(const BoundArgs &a, hipStream_t s)
+{
+    const int64_t runs = (a.N + LBP_CANDS - 1) / LBP_CANDS;
+    const int64_t blocks = (int64_t)a.nq * ((runs + 3) / 4);
+    hipLaunchKernelGGL((k_bound_lb_pp<D>), dim3((unsigned)blocks), dim3(256),
+                       lb_pp_lds_bytes(D, a.env_n), s, a);
+}
+
 template <int D> void bound_lb_d(const BoundArgs &a, bool debug, hipStream_t s)
 {
     constexpr int QG = 8;
@@ -71,6 +79,13 @@ void walk_d(const FastArgs &a, const float *qv, unsigned long long *ubslots, int
 void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s)
 {
 #define CALL(d) bound_lb_d<d>(a, debug, s)
+    TSK_SWITCH_D(D, CALL)
+#undef CALL
+}
+
+void launch_bound_lb_pp(int D, const BoundArgs &a, hipStream_t s)
+{
+#define CALL(d) bound_lb_pp_d<d>(a, s)
     TSK_SWITCH_D(D, CALL)
 #undef CALL
 }

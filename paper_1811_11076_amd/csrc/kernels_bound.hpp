@@ -235,6 +235,157 @@ __global__ __launch_bounds__(256) void k_bound_lb(BoundArgs a, const float *__re
     wave_count(a.ctr + C_BOUND_STEPS, valid ? (unsigned long long)n * nqg : 0ull);
 }
 
+// Sum over the 16 lanes of a row through DPP adds: swap neighbours, swap
+// pairs within quads, mirror within half-rows, mirror within the row.  At
+// every stage the two lanes that meet add the same two values, so all 16
+// lanes end with the same sum.
+template <int CTRL> __device__ __forceinline__ float dpp_f32(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 8 lanes of a half-row through DPP adds: swap neighbours,
+// swap pairs within quads, mirror within the half-row.  At every stage the
+// two lanes that meet add the same two values, so all 8 lanes end with the
+// same sum.
+__device__ __forceinline__ float row8_sum(float v)
+{
+    v += dpp_f32<0xB1>(v);  // quad_perm [1,0,3,2]
+    v += dpp_f32<0x4E>(v);  // quad_perm [2,3,0,1]
+    v += dpp_f32<0x141>(v); // row_half_mirror
+    return v;
+}
+
+// LB_Box with early abandoning per pair (equal lengths).  A block takes one
+// query (its envelope staged in LDS) and four runs of LBP_CANDS candidates,
+// one per wave; blocks are ordered candidate-major.  Each group of 8 lanes holds one (query, candidate) pair;
+// per step lane l of the group adds the box terms of positions
+// pos + LBP_P l .. pos + LBP_P l + LBP_P - 1 (contiguous AoS points and
+// envelope entries), and the group sums its 8 lanes: 8 LBP_P positions per
+// step.  A group stops as soon as its partial sum exceeds the threshold
+// (every term is >= 0, so the full sum would too) and takes the next
+// candidate of its wave's run.
+// The terms are those of k_bound_lb, but the summation order differs from
+// the sequential one for which LB_fp32 <= DTW_fp32 holds exactly; any order
+// of n <= 4096 non-negative fp32 terms is within (n-1) 2^-24 (relative) of
+// the exact sum, so the sum scaled by (1 - 2^-9) (rounding included) is <=
+// the sequential sum and thus <= the fp32 DTW.  That scaled value is the
+// pair's bound: compared with the threshold and stored in lbv.
+constexpr int LBP_CANDS = 256;
+constexpr int LBP_P = 8;
+
+template <int D>
+__global__ __launch_bounds__(256) void k_bound_lb_pp(BoundArgs a)
+{
+    extern __shared__ float senv[]; // [n][2][D] of this block's query
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 3, gl = lane & 7;
+    const int64_t runs = (a.N + LBP_CANDS - 1) / LBP_CANDS;
+    // consecutive blocks take the same candidates for different queries, so
+    // the candidates are read from L2 by all but the first
+    const int q = (int)(blockIdx.x % a.nq);
+    const int64_t run = (int64_t)(blockIdx.x / a.nq) * 4 + (threadIdx.x >> 6);
+    const int n = a.env_n;
+    const float *E = a.env + (int64_t)q * n * 2 * D;
+    for (int i = threadIdx.x; i < n * 2 * D; i += blockDim.x)
+        senv[i] = E[i];
+    __syncthreads();
+    if (run >= runs)
+        return;
+    const int c_end = (int)min((run + 1) * LBP_CANDS, a.N);
+    constexpr float SCALE = 1.0f - 1.0f / 512.0f;
+    constexpr int STEP = 8 * LBP_P; // positions per group step
+    float tau = bits_f(load_relaxed_u32(a.tau + q));
+    int c = (int)(run * LBP_CANDS) + grp; // groups start on consecutive candidates
+    if (c >= c_end)
+        c = -1;
+    int next = (int)(run * LBP_CANDS) + 8;
+    // this lane's first point of the current step (equal lengths: the
+    // candidate's offset is c n)
+    const float *xp = c >= 0 ? a.aos + ((int64_t)c * n + LBP_P * gl) * D : a.aos;
+    int pos = 0;
+    float part = 0.0f;
+    unsigned long long pruned = 0, pairs = 0, terms = 0;
+    for (int it = 0; __ballot(c >= 0) != 0ull; ++it) {
+        const int p0 = pos + LBP_P * gl;
+        float t = 0.0f;
+        if (c >= 0 && p0 < n) {
+            const float *e = senv + p0 * 2 * D;
+            auto term = [&](const float *x, const float *ep) -> float {
+                float tu = 0.0f;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const float d = fmaxf(fmaxf(ep[k] - x[k], x[k] - ep[D + k]), 0.0f);
+                    tu = (k == 0) ? d * d : __builtin_fmaf(d, d, tu);
+                }
+                return tu;
+            };
+            if (p0 + LBP_P <= n) {
+                // whole positions: the envelope entries are 16-byte aligned
+                // (p0 is a multiple of 4) and read as vectors
+                float xv[LBP_P * D], ev[2 * LBP_P * D];
+#pragma unroll
+                for (int i = 0; i < LBP_P * D; ++i)
+                    xv[i] = xp[i];
+                const float4 *e4 = reinterpret_cast<const float4 *>(e);
+#pragma unroll
+                for (int i = 0; i < LBP_P * D / 2; ++i) {
+                    const float4 v = e4[i];
+                    ev[4 * i] = v.x;
+                    ev[4 * i + 1] = v.y;
+                    ev[4 * i + 2] = v.z;
+                    ev[4 * i + 3] = v.w;
+                }
+#pragma unroll
+                for (int u = 0; u < LBP_P; ++u)
+                    t += term(xv + u * D, ev + u * 2 * D);
+                terms += LBP_P;
+            } else {
+                for (int u = 0; u < n - p0; ++u)
+                    t += term(xp + u * D, e + u * 2 * D);
+                terms += n - p0;
+            }
+        }
+        part += row8_sum(t);
+        pos += STEP;
+        xp += STEP * D;
+        if ((it & 3) == 3)
+            tau = bits_f(load_relaxed_u32(a.tau + q));
+        bool fin = false;
+        if (c >= 0) {
+            const float lb = part * SCALE;
+            if (lb > tau || pos >= n) {
+                fin = true;
+                if (gl == 0) {
+                    const bool keep = lb <= tau;
+                    a.lbv[(int64_t)q * a.N + c] = keep ? lb : tsk_inf();
+                    pruned += keep ? 0 : 1;
+                    ++pairs;
+                }
+            }
+        }
+        // finished groups take the next candidates of the run, in group order
+        const unsigned long long need = __ballot(fin && gl == 0);
+        if (need) {
+            if (fin) {
+                const int nc = next + __popcll(need & ((1ull << (grp * 8)) - 1ull));
+                c = nc < c_end ? nc : -1;
+                pos = 0;
+                part = 0.0f;
+                xp = c >= 0 ? a.aos + ((int64_t)c * n + LBP_P * gl) * D : a.aos;
+            }
+            next += __popcll(need);
+        }
+    }
+    wave_count(a.ctr + C_BOUND_PRUNED, pruned);
+    wave_count(a.ctr + C_PAIRS, pairs);
+    wave_count(a.ctr + C_BOUND_STEPS, terms);
+}
+
+// LDS of k_bound_lb_pp, and the largest the launcher uses it with.
+inline size_t lb_pp_lds_bytes(int D, int n) { return (size_t)n * 2 * D * sizeof(float); }
+constexpr size_t LB_PP_MAX_LDS = 64 * 1024;
+
 // DK corner pass: every warping path starts at (0,0) and ends at (m-1,n-1),
 // so max(c(0,0), c(m-1,n-1)) <= squared DK.  One lane per candidate, a
 // group of QG queries per block (their end points via scalar loads); lbv gets

@@ -41,6 +41,7 @@ inline size_t walk_lds_bytes(int D, int maxm)
 }
 
 void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s);
+void launch_bound_lb_pp(int D, const BoundArgs &a, hipStream_t s);
 void launch_seed_ring(int D, int dist, const SeedRingArgs &r, hipStream_t s);
 void launch_corner(int D, const BoundArgs &a, hipStream_t s);
 void launch_seed_diag(int D, int dist, const SeedRingArgs &r, hipStream_t s);

@@ -865,8 +865,9 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "dp_rows must be 0, 1 or 4");
     if (o.surv_order < 0 || o.surv_order > 2)
         return set_err(TSK_ERR_INVALID_ARG, "surv_order must be 0, 1 or 2");
-    if (o.lb_qgroup != 0 && o.lb_qgroup != 2 && o.lb_qgroup != 4 && o.lb_qgroup != 8)
-        return set_err(TSK_ERR_INVALID_ARG, "lb_qgroup must be 0, 2, 4 or 8");
+    if (o.lb_qgroup != 0 && o.lb_qgroup != 1 && o.lb_qgroup != 2 && o.lb_qgroup != 4 &&
+        o.lb_qgroup != 8)
+        return set_err(TSK_ERR_INVALID_ARG, "lb_qgroup must be 0, 1, 2, 4 or 8");
     if (o.use_graph && (o.profile || o.order == TSK_ORDER_LEARNED))
         return set_err(TSK_ERR_UNSUPPORTED, "use_graph excludes profile and TSK_ORDER_LEARNED");
     if (rr) {
@@ -1025,11 +1026,14 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         if (c.dk_split) {
             launch_corner(P.D, ba, s);
         } else if (dist == TSK_DTW && P.env_ok && o.dp_kernel != 1) {
-            launch_bound_lb(P.D, ba, false, s);
+            if (o.lb_qgroup == 1 && lb_pp_lds_bytes(P.D, ba.env_n) <= LB_PP_MAX_LDS)
+                launch_bound_lb_pp(P.D, ba, s); // per pair, early abandoning
+            else
+                launch_bound_lb(P.D, ba, false, s);
         } else if (c.lbu) {
             launch_qtable(P.D, qv, W.qoff.p, nq, W.qtab_off.p, W.qtab.p, s);
             launch_bound_lbu(P.D, ba, bucket_args(ix), W.qtab.p, W.qtab_off.p,
-                             o.lb_qgroup > 0 ? o.lb_qgroup : 4, false, s);
+                             o.lb_qgroup > 1 ? o.lb_qgroup : 4, false, s);
         } else {
             dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
         }
@@ -1502,6 +1506,8 @@ extern "C" int tsk_tune(tsk_index *ix, const float *q_values_dev, const int64_t 
         }
         if (lbu)
             knobs.push_back({&tsk_query_opts::lb_qgroup, {2, 4, 8}});
+        else if (dist == TSK_DTW)
+            knobs.push_back({&tsk_query_opts::lb_qgroup, {1}}); // the per-pair abandoning LB kernel
         knobs.push_back({&tsk_query_opts::surv_order, {1, 2}});
         knobs.push_back({&tsk_query_opts::dp_rows, {1, 4}});
         knobs.push_back({&tsk_query_opts::dp_waves_per_cu, {8, 16, 32}});
