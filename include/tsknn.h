@@ -141,8 +141,8 @@ typedef struct {
     int32_t task_size;             /* survivors per wave task of the sparse-DK
                                       kernel (0 = library default) */
     int32_t tube_rows;             /* rows per lane window of the sparse-DK
-                                      kernel: 16 or 32 (0 = library default,
-                                      16);
+                                      kernel: 8, 16 or 32 (0 = library
+                                      default, 16);
                                       pairs whose live cells outgrow it finish
                                       in the general DP */
     int32_t lb_qgroup;             /* queries per wave of the length-bucket

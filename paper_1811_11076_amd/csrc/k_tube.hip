@@ -8,7 +8,9 @@ template <int D> void tube_d(const FastArgs &a, int rows, int blocks, int maxm, 
 {
     constexpr int DP = PadDim<D>::value;
     const size_t lds = (size_t)(maxm + 32) * DP * sizeof(float);
-    if (rows == 16)
+    if (rows == 8)
+        hipLaunchKernelGGL((k_dp_tube<D, 8>), dim3(blocks), dim3(64), lds, s, a);
+    else if (rows == 16)
         hipLaunchKernelGGL((k_dp_tube<D, 16>), dim3(blocks), dim3(64), lds, s, a);
     else
         hipLaunchKernelGGL((k_dp_tube<D, 32>), dim3(blocks), dim3(64), lds, s, a);

@@ -851,8 +851,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "walk_pass must be -1, 0 or 1");
     if (o.task_size < 0 || o.task_size > (1 << 20))
         return set_err(TSK_ERR_INVALID_ARG, "task_size out of range");
-    if (o.tube_rows != 0 && o.tube_rows != 16 && o.tube_rows != 32)
-        return set_err(TSK_ERR_INVALID_ARG, "tube_rows must be 0, 16 or 32");
+    if (o.tube_rows != 0 && o.tube_rows != 8 && o.tube_rows != 16 && o.tube_rows != 32)
+        return set_err(TSK_ERR_INVALID_ARG, "tube_rows must be 0, 8, 16 or 32");
     if (o.dk_band_slots != 0 && o.dk_band_slots != 32 && o.dk_band_slots != 56 &&
         o.dk_band_slots != 64 && o.dk_band_slots != 104 && o.dk_band_slots != 128)
         return set_err(TSK_ERR_INVALID_ARG, "dk_band_slots must be 0, 32, 56, 64, 104 or 128");
@@ -1075,7 +1075,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                 fa.task = o.task_size > 0 ? o.task_size : 64;
                 // 16-row windows: the live tube of near neighbours is a few
                 // rows wide; the rare wider ones finish in the general DP
-                launch_tube(P.D, fa, o.tube_rows == 32 ? 32 : 16, ix->n_cu * fast_waves, c.qmax,
+                launch_tube(P.D, fa, o.tube_rows == 0 ? 16 : o.tube_rows, ix->n_cu * fast_waves, c.qmax,
                             s);
             } else {
                 fa.dk_virtual = c.fast == FAST_BAND_DKV ? 1 : 0;
@@ -1500,7 +1500,7 @@ extern "C" int tsk_tune(tsk_index *ix, const float *q_values_dev, const int64_t 
             knobs.push_back({&tsk_query_opts::dk_band_slots, {32, 56, 104, 128}});
         }
         if (dk_free) {
-            knobs.push_back({&tsk_query_opts::tube_rows, {16, 32}});
+            knobs.push_back({&tsk_query_opts::tube_rows, {8, 16, 32}});
             knobs.push_back({&tsk_query_opts::task_size, {32, 64, 128, 256}});
             knobs.push_back({&tsk_query_opts::walk_pass, {0, 1}});
         }

@@ -199,7 +199,7 @@ def test_knn_band_kernel_widths(w):
     idx.close()
 
 
-@pytest.mark.parametrize("rows", [16, 32])
+@pytest.mark.parametrize("rows", [8, 16, 32])
 def test_knn_tube_overflow_goes_to_general_dp(rows):
     """k = N keeps every DK cell alive, so every tube outgrows its window and
     the pair is finished by the general DP; results stay exact."""
@@ -367,3 +367,17 @@ def test_knn_dtw_lb_per_pair_abandoning(d, L, w):
 def torch_equal(a, b):
     import torch
     return bool(torch.equal(a, b))
+
+
+@pytest.mark.parametrize("rows", [8, 16, 32])
+def test_knn_dk_tube_rows_classwarp(rows):
+    """Class-warp DK (the live region follows the warped diagonal) with every
+    tube window: rows equal the oracle's."""
+    print(f"[case] knn dk tube rows={rows} classwarp", flush=True)
+    db, dbo, qs, qo = classwarp(2, 10, 256, 3, 3000, 6)
+    idx = _index(db, dbo)
+    ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, "dk", None)
+    ids, dst, st = idx.knn(to_dev(qs), qo, 10, "dk", None, stats=True, tube_rows=rows)
+    assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
+    print(f"  fallback {st['fallback_pairs']} cells {st['dp_valid_cells']}", flush=True)
+    idx.close()
