@@ -269,12 +269,32 @@ def cpu_baseline(db, dbo, qs, qo, w, nq_sample, n_series=0):
     dtw = O.knn_scan(db, dbo, qsub, qosub, w["k"], "dtw", w["dtw_band"])
     t2 = time.perf_counter()
     pairs = sel * N
-    return dict(value=pairs / (t2 - t0), unit="pairs/s", cores=threads, kind="oracle",
-                sample=f"first {sel} of {w['Q']} queries x first {N} of {w['N']} series, DK then DTW, "
-                       f"oracle.knn_scan (the paper's pruned scan: Alg. 1 seed + Alg. 3; "
-                       f"LB_Box + early-abandoning DTW), OpenMP over queries",
-                dk_pairs_per_s=pairs / (t1 - t0), dtw_pairs_per_s=pairs / (t2 - t1),
-                seconds=t2 - t0), (sel, dk, dtw)
+    out = dict(value=pairs / (t2 - t0), unit="pairs/s", cores=threads, kind="oracle",
+               sample=f"first {sel} of {w['Q']} queries x first {N} of {w['N']} series, DK then DTW, "
+                      f"oracle.knn_scan (the paper's pruned scan: Alg. 1 seed + Alg. 3; "
+                      f"LB_Box + early-abandoning DTW), OpenMP over queries",
+               dk_pairs_per_s=pairs / (t1 - t0), dtw_pairs_per_s=pairs / (t2 - t1),
+               seconds=t2 - t0)
+    # the same scan on one core (the paper's own setting), and the plain
+    # definition (full DP of every pair) on all cores, each on a small sample
+    prev = O.set_threads(1)
+    n1 = min(2, sel)
+    t0 = time.perf_counter()
+    O.knn_scan(db, dbo, qs[:qo[n1]], qo[:n1 + 1], w["k"], "dk", w["dk_band"])
+    O.knn_scan(db, dbo, qs[:qo[n1]], qo[:n1 + 1], w["k"], "dtw", w["dtw_band"])
+    t1 = time.perf_counter()
+    O.set_threads(prev)
+    nb = min(threads, sel)
+    O.knn_brute(db, dbo, qs[:qo[nb]], qo[:nb + 1], w["k"], "dk", w["dk_band"])
+    O.knn_brute(db, dbo, qs[:qo[nb]], qo[:nb + 1], w["k"], "dtw", w["dtw_band"])
+    t2 = time.perf_counter()
+    out["pruned_scan_1_core"] = {"pairs_per_s": n1 * N / (t1 - t0), "queries": n1,
+                                 "seconds": t1 - t0}
+    out["brute_force_all_cores"] = {"pairs_per_s": nb * N / (t2 - t1), "queries": nb,
+                                    "cores": threads, "seconds": t2 - t1,
+                                    "what": "oracle.knn_brute: full DP of every pair, then "
+                                            "a (key, id) sort"}
+    return out, (sel, dk, dtw)
 
 
 # subsequence search (Alg. 2 + Alg. 3 with SUB): one long 3-D random walk,

@@ -66,6 +66,7 @@ def _load():
                                 _i64p]),
         "orc_pair_keys": (None, [_f32p, _i64p, _i64, _f32p, _i64p, _i64, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, _i64, ctypes.c_float, _f32p]),
+        "orc_set_threads": (ctypes.c_int, [ctypes.c_int]),
         "orc_subseq_dk_sq_f32": (ctypes.c_float, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64p]),
         "orc_subseq_start": (_i64, [_f32p, _i64, _f32p, _i64, ctypes.c_int, ctypes.c_float]),
         "orc_subseq_brute_f32": (ctypes.c_float, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64p,
@@ -120,6 +121,12 @@ def _band_args(band):
     if isinstance(band, float):
         return BAND_FRAC, -1, band
     return BAND_ABS, int(band), 0.0
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's loops over queries; returns the
+    previous setting (n <= 0 only queries it)."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def cost_f32(s, t) -> float:

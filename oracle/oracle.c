@@ -46,6 +46,24 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the OpenMP loops over queries (for timing the oracle on one
+ * core or on all); returns the previous setting. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    int old = omp_get_max_threads();
+    if (n > 0)
+        omp_set_num_threads(n);
+    return old;
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 #define ORC_INF INFINITY
 
