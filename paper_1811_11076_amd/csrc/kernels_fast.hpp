@@ -271,7 +271,120 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
         int j = 0;
         float cv[D];
         load_point<D>(cp, cv);
-        for (; j < m; ++j) {
+        bool stop = false;
+        {
+            // Two columns per iteration.  Slot k of column j and slot k-1 of
+            // column j+1 read the same query row (j - w + k), so each row is
+            // loaded once per two cells, and the two columns' dependency
+            // chains interleave: cell (k, j+1) needs slots k-1 and k of
+            // column j, computed just before.  Column j+1's top slot reads one
+            // more row (j - w + W, inside the +inf padding).
+            constexpr int TOP = 2 * ((W - 1) / 2);
+            float c1[D];
+            load_point<D>(cp + (int64_t)min(1, nl - 1) * D, c1);
+            auto combine = [](float cst, float pred) -> float {
+                return DIST == DIST_DK ? fmaxf(cst, pred) : cst + pred;
+            };
+            for (; j + 1 < m; j += 2) {
+                float n0[D], n1[D];
+                load_point<D>(cp + (int64_t)min(j + 2, nl - 1) * D, n0);
+                load_point<D>(cp + (int64_t)min(j + 3, nl - 1) * D, n1);
+                cfloat *qrow = qbase + (int64_t)j * DP;
+                int wl = wact;
+                asm volatile("" : "+s"(wl));
+                float down0 = tsk_inf(), down1 = tsk_inf(), pa = tsk_inf();
+                float e0 = tsk_inf(), eT = tsk_inf();
+                float qc[G][D], qn[G][D];
+#pragma unroll
+                for (int u = 0; u < G; ++u)
+#pragma unroll
+                    for (int e = 0; e < D; ++e)
+                        qc[u][e] = qrow[u * DP + e];
+#pragma unroll
+                for (int g = 0; g < W / G; ++g) {
+                    if (g + 1 < W / G) {
+#pragma unroll
+                        for (int u = 0; u < G; ++u)
+#pragma unroll
+                            for (int e = 0; e < D; ++e)
+                                qn[u][e] = qrow[((g + 1) * G + u) * DP + e];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int u = 0; u < G; ++u) {
+                        const int k = g * G + u;
+                        float ca = point_cost<D>(qc[u], cv);
+                        if (k >= KMASK)
+                            ca = k < wl ? ca : tsk_inf();
+                        const float left = (k + 1 < W) ? Dv[k + 1] : tsk_inf();
+                        const float va = combine(ca, min3f(down0, Dv[k], left));
+                        if (k >= 1) {
+                            float cb = point_cost<D>(qc[u], c1);
+                            if (k - 1 >= KMASK)
+                                cb = k - 1 < wl ? cb : tsk_inf();
+                            const float vb = combine(cb, min3f(down1, pa, va));
+                            Dv[k - 1] = vb;
+                            down1 = vb;
+                        }
+                        if (k == 0)
+                            e0 = va;
+                        if (k == TOP)
+                            eT = va;
+                        down0 = va;
+                        pa = va;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int u = 0; u < G; ++u)
+#pragma unroll
+                        for (int e = 0; e < D; ++e)
+                            qc[u][e] = qn[u][e];
+                }
+                {
+                    // top slot of column j+1
+                    float qt[D];
+#pragma unroll
+                    for (int e = 0; e < D; ++e)
+                        qt[e] = qrow[W * DP + e];
+                    float cb = point_cost<D>(qt, c1);
+                    if (W - 1 >= KMASK)
+                        cb = W - 1 < wl ? cb : tsk_inf();
+                    Dv[W - 1] = combine(cb, min3f(down1, pa, tsk_inf()));
+                }
+#pragma unroll
+                for (int e = 0; e < D; ++e) {
+                    cv[e] = n0[e];
+                    c1[e] = n1[e];
+                }
+                const int h0 = min(j + w, m - 1) - max(j - w, 0) + 1;
+                const int h1 = min(j + 1 + w, m - 1) - max(j + 1 - w, 0) + 1;
+                valid += (unsigned long long)(h0 + h1) * __popcll(__ballot(alive));
+                cells += 2 * W;
+                if (vband) {
+                    if (alive && (e0 <= tau || eT <= tau || Dv[0] <= tau || Dv[TOP] <= tau)) {
+                        push_fallback(a, q, ch.c);
+                        ++fallback;
+                        --started;
+                        alive = false;
+                        act = false;
+                    }
+                }
+                if (((j + 1) & 7) == 7) {
+                    float cm = Dv[0];
+#pragma unroll
+                    for (int k = 1; k < W; ++k)
+                        cm = fminf(cm, Dv[k]);
+                    tau = bits_f(load_relaxed_u32(a.tau + q));
+                    alive = alive && cm <= tau;
+                    if (__ballot(alive) == 0ull) {
+                        j += 2;
+                        stop = true;
+                        break;
+                    }
+                }
+            }
+        }
+        for (; !stop && j < m; ++j) {
             float cn[D];
             load_point<D>(cp + (int64_t)min(j + 1, nl - 1) * D, cn);
             cfloat *qrow = qbase + (int64_t)j * DP;
