@@ -141,15 +141,33 @@ def tuned_graph(w, args, idx_dk, idx_dtw, dev_q, qs, qo, eager_res):
     streams = (torch.cuda.Stream(), torch.cuda.Stream())
     torch.cuda.synchronize()
 
-    def step():
-        with torch.cuda.stream(streams[0]):
-            a = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], use_graph=True, tune=True,
-                           out=outs["dk"])
-        with torch.cuda.stream(streams[1]):
-            b = idx_dtw.knn(dev_q, qo, k, "dtw", w["dtw_band"], use_graph=True, tune=True,
-                            out=outs["dtw"])
-        return a, b
+    def make_step(use_tuned):
+        def step():
+            with torch.cuda.stream(streams[0]):
+                a = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], use_graph=True, tune=use_tuned,
+                               out=outs["dk"])
+            with torch.cuda.stream(streams[1]):
+                b = idx_dtw.knn(dev_q, qo, k, "dtw", w["dtw_band"], use_graph=True,
+                                tune=use_tuned, out=outs["dtw"])
+            return a, b
+        return step
 
+    # the options were tuned per distance alone; the step runs both at once,
+    # so a short untimed trial of the concurrent step decides between the
+    # tuned and the default options before the timed steps
+    trial_ms = {}
+    for use_tuned in (True, False):
+        st = make_step(use_tuned)
+        for _ in range(3):
+            st()
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        for _ in range(10):
+            st()
+        torch.cuda.synchronize()
+        trial_ms["tuned" if use_tuned else "default"] = (time.perf_counter() - tt) * 100.0
+    chosen = min(trial_ms, key=trial_ms.get)
+    step = make_step(chosen == "tuned")
     for _ in range(max(1, args.warmup)):
         res = step()
     torch.cuda.synchronize()
@@ -187,7 +205,8 @@ def tuned_graph(w, args, idx_dk, idx_dtw, dev_q, qs, qo, eager_res):
         torch.cuda.synchronize()
         times[name] = (time.perf_counter() - t2) / 3 * 1e3
     return {"ms_per_step": el * 1e3 / args.steps, "rows_equal_eager": bool(same),
-            "tuned": tuned, "tuning_seconds": t_tune,
+            "tuned": tuned, "tuning_seconds": t_tune, "step_options": chosen,
+            "trial_ms_per_step": trial_ms,
             "sample_queries": S, "batched_ms": times["batched"],
             "per_query_ms": times["per_query"],
             "batched_vs_per_query_speedup": times["per_query"] / times["batched"]}

@@ -218,6 +218,8 @@ __device__ __forceinline__ void finish_lane(const FastArgs &a, int q, int c, flo
 // whole wave (scalar loads); the candidate point is per lane.  Every path
 // visits every column, so a column whose values all exceed tau ends the
 // lane's pair (checked every 8 columns).
+constexpr int BAND_NC = 2; // columns per iteration of k_dp_band
+
 template <int D, int DIST, int W, int KMASK>
 __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restrict__ qpad)
 {
@@ -273,27 +275,42 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
         load_point<D>(cp, cv);
         bool stop = false;
         {
-            // Two columns per iteration.  Slot k of column j and slot k-1 of
-            // column j+1 read the same query row (j - w + k), so each row is
-            // loaded once per two cells, and the two columns' dependency
-            // chains interleave: cell (k, j+1) needs slots k-1 and k of
-            // column j, computed just before.  Column j+1's top slot reads one
-            // more row (j - w + W, inside the +inf padding).
+            // NC columns per iteration.  At step k, slot k - r of column j + r
+            // (r = 0 .. NC-1) reads query row j - w + k, so each row is loaded
+            // once for NC cells and the NC dependency chains interleave.  Cell
+            // (slot s, column j+r) takes its lower-left predecessor from slot s
+            // of column j+r-1 (the previous step's value) and its left one from
+            // slot s+1 of that column (this step's value); column j's come from
+            // the registers of column j-1.  Only column j+NC-1 is written back
+            // (slot s once no later step reads it).  The last NC-1 steps finish
+            // the top slots of columns j+1.. with rows past j - w + W - 1
+            // (inside the +inf padding).
+            constexpr int NC = BAND_NC;
             constexpr int TOP = 2 * ((W - 1) / 2);
-            float c1[D];
-            load_point<D>(cp + (int64_t)min(1, nl - 1) * D, c1);
+            constexpr int KS = W + NC - 1;               // steps
+            constexpr int KSG = (KS + G - 1) / G * G;    // rounded to whole groups
+            float cc[NC][D];
+#pragma unroll
+            for (int r = 0; r < NC; ++r)
+                load_point<D>(cp + (int64_t)min(r, nl - 1) * D, cc[r]);
             auto combine = [](float cst, float pred) -> float {
                 return DIST == DIST_DK ? fmaxf(cst, pred) : cst + pred;
             };
-            for (; j + 1 < m; j += 2) {
-                float n0[D], n1[D];
-                load_point<D>(cp + (int64_t)min(j + 2, nl - 1) * D, n0);
-                load_point<D>(cp + (int64_t)min(j + 3, nl - 1) * D, n1);
+            for (; j + NC - 1 < m; j += NC) {
+                float nx[NC][D];
+#pragma unroll
+                for (int r = 0; r < NC; ++r)
+                    load_point<D>(cp + (int64_t)min(j + NC + r, nl - 1) * D, nx[r]);
                 cfloat *qrow = qbase + (int64_t)j * DP;
                 int wl = wact;
                 asm volatile("" : "+s"(wl));
-                float down0 = tsk_inf(), down1 = tsk_inf(), pa = tsk_inf();
-                float e0 = tsk_inf(), eT = tsk_inf();
+                float prv[NC], cur[NC], e0[NC], eT[NC];
+#pragma unroll
+                for (int r = 0; r < NC; ++r) {
+                    prv[r] = tsk_inf();
+                    e0[r] = tsk_inf();
+                    eT[r] = tsk_inf();
+                }
                 float qc[G][D], qn[G][D];
 #pragma unroll
                 for (int u = 0; u < G; ++u)
@@ -301,8 +318,8 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                     for (int e = 0; e < D; ++e)
                         qc[u][e] = qrow[u * DP + e];
 #pragma unroll
-                for (int g = 0; g < W / G; ++g) {
-                    if (g + 1 < W / G) {
+                for (int g = 0; g < KSG / G; ++g) {
+                    if (g + 1 < KSG / G) {
 #pragma unroll
                         for (int u = 0; u < G; ++u)
 #pragma unroll
@@ -313,25 +330,38 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
 #pragma unroll
                     for (int u = 0; u < G; ++u) {
                         const int k = g * G + u;
-                        float ca = point_cost<D>(qc[u], cv);
-                        if (k >= KMASK)
-                            ca = k < wl ? ca : tsk_inf();
-                        const float left = (k + 1 < W) ? Dv[k + 1] : tsk_inf();
-                        const float va = combine(ca, min3f(down0, Dv[k], left));
-                        if (k >= 1) {
-                            float cb = point_cost<D>(qc[u], c1);
-                            if (k - 1 >= KMASK)
-                                cb = k - 1 < wl ? cb : tsk_inf();
-                            const float vb = combine(cb, min3f(down1, pa, va));
-                            Dv[k - 1] = vb;
-                            down1 = vb;
+                        if (k < KS) {
+#pragma unroll
+                            for (int r = 0; r < NC; ++r) {
+                                const int sl = k - r;
+                                if (sl >= 0 && sl < W) {
+                                    float cst = point_cost<D>(qc[u], cc[r]);
+                                    if (sl >= KMASK)
+                                        cst = sl < wl ? cst : tsk_inf();
+                                    float diag, left;
+                                    if (r == 0) {
+                                        diag = Dv[sl];
+                                        left = (sl + 1 < W) ? Dv[sl + 1] : tsk_inf();
+                                    } else {
+                                        diag = prv[r - 1];
+                                        left = cur[r - 1];
+                                    }
+                                    const float v = combine(cst, min3f(prv[r], diag, left));
+                                    cur[r] = v;
+                                    if (sl == 0)
+                                        e0[r] = v;
+                                    if (sl == TOP)
+                                        eT[r] = v;
+                                    if (r == NC - 1)
+                                        Dv[sl] = v;
+                                } else {
+                                    cur[r] = tsk_inf();
+                                }
+                            }
+#pragma unroll
+                            for (int r = 0; r < NC; ++r)
+                                prv[r] = cur[r];
                         }
-                        if (k == 0)
-                            e0 = va;
-                        if (k == TOP)
-                            eT = va;
-                        down0 = va;
-                        pa = va;
                     }
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -340,28 +370,23 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                         for (int e = 0; e < D; ++e)
                             qc[u][e] = qn[u][e];
                 }
-                {
-                    // top slot of column j+1
-                    float qt[D];
+#pragma unroll
+                for (int r = 0; r < NC; ++r)
 #pragma unroll
                     for (int e = 0; e < D; ++e)
-                        qt[e] = qrow[W * DP + e];
-                    float cb = point_cost<D>(qt, c1);
-                    if (W - 1 >= KMASK)
-                        cb = W - 1 < wl ? cb : tsk_inf();
-                    Dv[W - 1] = combine(cb, min3f(down1, pa, tsk_inf()));
-                }
+                        cc[r][e] = nx[r][e];
+                int hs = 0;
 #pragma unroll
-                for (int e = 0; e < D; ++e) {
-                    cv[e] = n0[e];
-                    c1[e] = n1[e];
-                }
-                const int h0 = min(j + w, m - 1) - max(j - w, 0) + 1;
-                const int h1 = min(j + 1 + w, m - 1) - max(j + 1 - w, 0) + 1;
-                valid += (unsigned long long)(h0 + h1) * __popcll(__ballot(alive));
-                cells += 2 * W;
+                for (int r = 0; r < NC; ++r)
+                    hs += min(j + r + w, m - 1) - max(j + r - w, 0) + 1;
+                valid += (unsigned long long)hs * __popcll(__ballot(alive));
+                cells += NC * W;
                 if (vband) {
-                    if (alive && (e0 <= tau || eT <= tau || Dv[0] <= tau || Dv[TOP] <= tau)) {
+                    bool edge = false;
+#pragma unroll
+                    for (int r = 0; r < NC; ++r)
+                        edge = edge || e0[r] <= tau || eT[r] <= tau;
+                    if (alive && edge) {
                         push_fallback(a, q, ch.c);
                         ++fallback;
                         --started;
@@ -369,7 +394,7 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                         act = false;
                     }
                 }
-                if (((j + 1) & 7) == 7) {
+                if ((j + NC) / 8 != j / 8) { // about every 8 columns
                     float cm = Dv[0];
 #pragma unroll
                     for (int k = 1; k < W; ++k)
@@ -377,12 +402,15 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                     tau = bits_f(load_relaxed_u32(a.tau + q));
                     alive = alive && cm <= tau;
                     if (__ballot(alive) == 0ull) {
-                        j += 2;
+                        j += NC;
                         stop = true;
                         break;
                     }
                 }
             }
+#pragma unroll
+            for (int e = 0; e < D; ++e)
+                cv[e] = cc[0][e]; // the next column's point, for the single-column tail
         }
         for (; !stop && j < m; ++j) {
             float cn[D];
