@@ -515,7 +515,11 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
 
 // ------------------------------------------------------------------ sparse DK tube
 // Unbanded DK with the sparse-DK semantics of Alg. 3 (Sec. 4.2): a cell above
-// tau is dead (+inf), and a pair with no live cell left in a column is > tau.
+// tau is dead, and a pair with no live cell left in a column is > tau.  Dead
+// cells keep their (exact) values: max(cost, min(preds)) of cells whose
+// predecessors are all above tau is above tau too, so they never lower a
+// live cell, and liveness is tested against tau (which only falls) instead
+// of killing them.
 // Each lane keeps a window of W consecutive rows [lo, lo+W) of its current
 // column.  Cells below lo are dead (nothing below a dead prefix can come
 // back: every predecessor is lower or to the left), so after each column lo
@@ -611,7 +615,7 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
             load_point<D>(cp + (int64_t)min(j, n - 1) * D, cv);
             float down = tsk_inf();
             float diag = (j == 0) ? 0.0f : tsk_inf(); // D(-1,-1) = 0 feeds (0,0)
-            bool any = false;
+            float vmin = tsk_inf();
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 const float *qr = qs + (lo + k) * DP;
@@ -621,12 +625,11 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
                     qq[e] = qr[e];
                 const float cst = point_cost<D>(qq, cv);
                 const float old = Dv[k];
-                float v = fmaxf(cst, min3f(down, old, diag));
-                v = v <= tau ? v : tsk_inf();
+                const float v = fmaxf(cst, min3f(down, old, diag));
                 diag = old;
                 Dv[k] = v;
                 down = v;
-                any |= v != tsk_inf();
+                vmin = fminf(vmin, v);
             }
             cells += W;
             valid += __popcll(__ballot(running)) * (unsigned long long)W;
@@ -637,21 +640,22 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
 #pragma unroll
                     for (int k = 0; k < W; ++k)
                         res = (k == slot) ? Dv[k] : res;
+                    res = res <= tau ? res : tsk_inf();
                     if (res == tsk_inf())
                         ++abandoned;
                     finish_lane(a, q, c, res, completed);
                     running = false;
-                } else if (!any) {
+                } else if (!(vmin <= tau)) {
                     ++abandoned;
                     running = false;
-                } else if (Dv[W - 1] != tsk_inf()) {
+                } else if (Dv[W - 1] <= tau) {
                     push_fallback(a, q, c);
                     ++fallback;
                     running = false;
                 }
             }
             // drop up to two leading dead slots (idle lanes keep lo)
-            int sh = Dv[0] != tsk_inf() ? 0 : (Dv[1] != tsk_inf() ? 1 : 2);
+            int sh = Dv[0] <= tau ? 0 : (Dv[1] <= tau ? 1 : 2);
             sh = running ? sh : 0;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
