@@ -294,23 +294,27 @@ def cpu_baseline(db, dbo, qs, qo, w, nq_sample, n_series=0):
                       f"LB_Box + early-abandoning DTW), OpenMP over queries",
                dk_pairs_per_s=pairs / (t1 - t0), dtw_pairs_per_s=pairs / (t2 - t1),
                seconds=t2 - t0)
+    print(f"[bench] cpu baseline: pruned scan on {threads} cores done", file=sys.stderr, flush=True)
     # the same scan on one core (the paper's own setting), and the plain
     # definition (full DP of every pair) on all cores, each on a small sample
+    # (one query x the first 5000 series; up to 16 queries x the first 2000)
+    n1, s1 = 1, min(N, 5000)
+    nb, sb = min(threads, sel, 16), min(N, 2000)
     prev = O.set_threads(1)
-    n1 = min(2, sel)
     t0 = time.perf_counter()
-    O.knn_scan(db, dbo, qs[:qo[n1]], qo[:n1 + 1], w["k"], "dk", w["dk_band"])
-    O.knn_scan(db, dbo, qs[:qo[n1]], qo[:n1 + 1], w["k"], "dtw", w["dtw_band"])
+    O.knn_scan(db[:dbo[s1]], dbo[:s1 + 1], qs[:qo[n1]], qo[:n1 + 1], w["k"], "dk", w["dk_band"])
+    O.knn_scan(db[:dbo[s1]], dbo[:s1 + 1], qs[:qo[n1]], qo[:n1 + 1], w["k"], "dtw", w["dtw_band"])
     t1 = time.perf_counter()
     O.set_threads(prev)
-    nb = min(threads, sel)
-    O.knn_brute(db, dbo, qs[:qo[nb]], qo[:nb + 1], w["k"], "dk", w["dk_band"])
-    O.knn_brute(db, dbo, qs[:qo[nb]], qo[:nb + 1], w["k"], "dtw", w["dtw_band"])
+    print("[bench] cpu baseline: pruned scan on one core done", file=sys.stderr, flush=True)
+    O.knn_brute(db[:dbo[sb]], dbo[:sb + 1], qs[:qo[nb]], qo[:nb + 1], w["k"], "dk", w["dk_band"])
+    O.knn_brute(db[:dbo[sb]], dbo[:sb + 1], qs[:qo[nb]], qo[:nb + 1], w["k"], "dtw", w["dtw_band"])
     t2 = time.perf_counter()
-    out["pruned_scan_1_core"] = {"pairs_per_s": n1 * N / (t1 - t0), "queries": n1,
+    print("[bench] cpu baseline: brute force done", file=sys.stderr, flush=True)
+    out["pruned_scan_1_core"] = {"pairs_per_s": n1 * s1 / (t1 - t0), "queries": n1, "series": s1,
                                  "seconds": t1 - t0}
-    out["brute_force_all_cores"] = {"pairs_per_s": nb * N / (t2 - t1), "queries": nb,
-                                    "cores": threads, "seconds": t2 - t1,
+    out["brute_force_all_cores"] = {"pairs_per_s": nb * sb / (t2 - t1), "queries": nb,
+                                    "series": sb, "cores": threads, "seconds": t2 - t1,
                                     "what": "oracle.knn_brute: full DP of every pair, then "
                                             "a (key, id) sort"}
     return out, (sel, dk, dtw)
