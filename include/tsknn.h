@@ -146,12 +146,15 @@ typedef struct {
                                       pairs whose live cells outgrow it finish
                                       in the general DP */
     int32_t lb_qgroup;             /* queries per wave of the length-bucket
-                                      LB_Box kernel: 2, 4 or 8 (0 or 1 = 4);
+                                      LB_Box kernel: 2, 4 or 8 (0 or 1 = 4,
+                                      16 = 8);
                                       equal lengths: 1 = one pair per 8
                                       lanes, each sum abandoned once above
                                       the threshold (query envelopes up to
-                                      64 KiB, else as 0); any other value =
-                                      8 queries sharing each candidate load */
+                                      64 KiB, else as 0); 16 = 16 queries
+                                      sharing each candidate load; 0 = 16 for
+                                      databases above 256 MiB, else 8; other
+                                      values = 8 */
     int32_t dk_band_slots;         /* unbanded DK on equal lengths: 0 = the
                                       sparse-DK tube kernel; 32, 56, 64, 104
                                       or 128 = the lockstep banded kernel in

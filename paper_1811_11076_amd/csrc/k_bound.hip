@@ -14,6 +14,15 @@ template <int D> void bound_lb_pp_d(const BoundArgs &a, hipStream_t s)
 
 template <int D> void bound_lb_d(const BoundArgs &a, bool debug, hipStream_t s)
 {
+    // 8 queries share each candidate load (VALU-bound while the database
+    // sits in the MALL); 16 when asked for (a.qgroup), for databases that
+    // stream from HBM
+    if (!debug && a.qgroup == 16) {
+        constexpr int QG = 16;
+        dim3 grid((unsigned)((a.N + 255) / 256), (unsigned)((a.nq + QG - 1) / QG));
+        hipLaunchKernelGGL((k_bound_lb<D, QG, false>), grid, dim3(256), 0, s, a, a.env);
+        return;
+    }
     constexpr int QG = 8;
     dim3 grid((unsigned)((a.N + 255) / 256), (unsigned)((a.nq + QG - 1) / QG));
     if (debug)

@@ -866,8 +866,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
     if (o.surv_order < 0 || o.surv_order > 2)
         return set_err(TSK_ERR_INVALID_ARG, "surv_order must be 0, 1 or 2");
     if (o.lb_qgroup != 0 && o.lb_qgroup != 1 && o.lb_qgroup != 2 && o.lb_qgroup != 4 &&
-        o.lb_qgroup != 8)
-        return set_err(TSK_ERR_INVALID_ARG, "lb_qgroup must be 0, 1, 2, 4 or 8");
+        o.lb_qgroup != 8 && o.lb_qgroup != 16)
+        return set_err(TSK_ERR_INVALID_ARG, "lb_qgroup must be 0, 1, 2, 4, 8 or 16");
     if (o.use_graph && (o.profile || o.order == TSK_ORDER_LEARNED))
         return set_err(TSK_ERR_UNSUPPORTED, "use_graph excludes profile and TSK_ORDER_LEARNED");
     if (rr) {
@@ -1026,14 +1026,19 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         if (c.dk_split) {
             launch_corner(P.D, ba, s);
         } else if (dist == TSK_DTW && P.env_ok && o.dp_kernel != 1) {
-            if (o.lb_qgroup == 1 && lb_pp_lds_bytes(P.D, ba.env_n) <= LB_PP_MAX_LDS)
+            if (o.lb_qgroup == 1 && lb_pp_lds_bytes(P.D, ba.env_n) <= LB_PP_MAX_LDS) {
                 launch_bound_lb_pp(P.D, ba, s); // per pair, early abandoning
-            else
+            } else {
+                // 16 queries per candidate load when asked for, or by default
+                // once the database outgrows the 256 MB MALL
+                const bool big = (int64_t)ix->total * ix->dim * 4 > ((int64_t)256 << 20);
+                ba.qgroup = (o.lb_qgroup == 16 || (o.lb_qgroup == 0 && big)) ? 16 : 8;
                 launch_bound_lb(P.D, ba, false, s);
+            }
         } else if (c.lbu) {
             launch_qtable(P.D, qv, W.qoff.p, nq, W.qtab_off.p, W.qtab.p, s);
             launch_bound_lbu(P.D, ba, bucket_args(ix), W.qtab.p, W.qtab_off.p,
-                             o.lb_qgroup > 1 ? o.lb_qgroup : 4, false, s);
+                             o.lb_qgroup > 1 ? std::min(o.lb_qgroup, 8) : 4, false, s);
         } else {
             dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
         }
@@ -1507,7 +1512,7 @@ extern "C" int tsk_tune(tsk_index *ix, const float *q_values_dev, const int64_t 
         if (lbu)
             knobs.push_back({&tsk_query_opts::lb_qgroup, {2, 4, 8}});
         else if (dist == TSK_DTW)
-            knobs.push_back({&tsk_query_opts::lb_qgroup, {1}}); // the per-pair abandoning LB kernel
+            knobs.push_back({&tsk_query_opts::lb_qgroup, {1, 8, 16}}); // LB kernel and query group
         knobs.push_back({&tsk_query_opts::surv_order, {1, 2}});
         knobs.push_back({&tsk_query_opts::dp_rows, {1, 4}});
         knobs.push_back({&tsk_query_opts::dp_waves_per_cu, {8, 16, 32}});

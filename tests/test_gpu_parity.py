@@ -336,20 +336,23 @@ def test_knn_general_dp_forced_equals_fast():
     idx.close()
 
 
+@pytest.mark.parametrize("lbq", [1, 16])
 @pytest.mark.parametrize("w", [0, 3, 25, 60, None])
 @pytest.mark.parametrize("d,L", [(1, 33), (3, 128), (6, 300), (8, 17)])
-def test_knn_dtw_lb_per_pair_abandoning(d, L, w):
-    """DTW with the per-pair early-abandoning LB_Box kernel (lb_qgroup = 1):
-    rows equal the oracle's for lengths that are and are not multiples of a
-    step (ragged last step), unbanded and banded, and equal the default
-    kernel's rows; the class-warp data has ties at the threshold's scale."""
-    print(f"[case] dtw lb per pair d={d} L={L} w={w}", flush=True)
+def test_knn_dtw_lb_per_pair_abandoning(d, L, w, lbq):
+    """DTW with the per-pair early-abandoning LB_Box kernel (lb_qgroup = 1)
+    and with 16 queries per candidate load (lb_qgroup = 16): rows equal the
+    oracle's for lengths that are and are not multiples of a step (ragged
+    last step), unbanded and banded, 5 queries (a partial group), and equal
+    the default kernel's rows; the class-warp data has ties at the
+    threshold's scale."""
+    print(f"[case] dtw lb kernel {lbq} d={d} L={L} w={w}", flush=True)
     db, dbo = ragged_walks(700 + d + L, 600, (L, L), d)
     qs, qo = ragged_walks(800 + d + L, 5, (L, L), d)
     db[dbo[17]:dbo[18]] = qs[qo[1]:qo[2]]  # an exact copy: DTW 0, LB 0
     idx = _index(db, dbo)
     ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 7, "dtw", w)
-    ids, dst, st = idx.knn(to_dev(qs), qo, 7, "dtw", w, stats=True, lb_qgroup=1)
+    ids, dst, st = idx.knn(to_dev(qs), qo, 7, "dtw", w, stats=True, lb_qgroup=lbq)
     assert_same_knn(ids, dst, ref_ids, ref_keys, "dtw")
     ids0, dst0, st0 = idx.knn(to_dev(qs), qo, 7, "dtw", w, stats=True)
     assert torch_equal(ids, ids0) and torch_equal(dst, dst0)
@@ -359,7 +362,7 @@ def test_knn_dtw_lb_per_pair_abandoning(d, L, w):
     db, dbo, qs, qo = classwarp(2, 10, 256, 3, 3000, 6)
     idx = _index(db, dbo)
     ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, "dtw", 0.1)
-    ids, dst, _ = idx.knn(to_dev(qs), qo, 10, "dtw", 0.1, lb_qgroup=1)
+    ids, dst, _ = idx.knn(to_dev(qs), qo, 10, "dtw", 0.1, lb_qgroup=lbq)
     assert_same_knn(ids, dst, ref_ids, ref_keys, "dtw")
     idx.close()
 
