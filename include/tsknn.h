@@ -187,6 +187,13 @@ typedef struct {
                                       ascending embedding distance.  The
                                       index caches the candidates' embeddings
                                       for the model's current parameters */
+    const volatile int32_t *cancel_flag_host; /* nullable host flag, read before
+                                      each chunk of queries (and before any
+                                      device work): non-zero stops the call
+                                      with TSK_ERR_CANCELLED.  Work already
+                                      enqueued still runs on the stream;
+                                      rows of queries not reached are not
+                                      written */
 } tsk_query_opts;
 
 typedef struct {

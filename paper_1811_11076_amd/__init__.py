@@ -90,14 +90,16 @@ class Index:
             walk_pass: int = -1, task_size: int = 0, tube_rows: int = 0, model=None,
             lb_qgroup: int = 0, use_graph: bool = False, tune: bool = False, out=None,
             dk_band_slots: int = 0, surv_order: int = 0, dp_rows: int = 0,
-            dp_waves_per_cu: int = 0, dk_seed: int = 0):
+            dp_waves_per_cu: int = 0, dk_seed: int = 0, cancel=None):
         """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
         float32 [nq, k], stats dict or None); DK distances are unsquared.
         order: None (plain), a CUDA int32 [nq, n] permutation per query, or
         "learned" with model= a Model (candidates by embedding distance).
         use_graph: run as a cached, replayed HIP graph (pass the same `out`
         tensors (ids, dist) to replay); tune: use the index's tuned options
-        (see tune())."""
+        (see tune()); cancel: a host numpy int32 array whose first entry,
+        set non-zero (e.g. by another thread), stops the call before its next
+        chunk of queries (TskError with code TSK_ERR_CANCELLED)."""
         torch = _torch()
         qv = _values(queries, self.dim)
         qo = _offsets(q_offsets)
@@ -126,6 +128,10 @@ class Index:
         opts.dk_seed = int(dk_seed)
         opts.use_graph = 1 if use_graph else 0
         opts.tune = _lib.TSK_TUNE_CACHED if tune else _lib.TSK_TUNE_OFF
+        if cancel is not None:
+            if not (isinstance(cancel, np.ndarray) and cancel.dtype == np.int32 and cancel.size >= 1):
+                raise TypeError("cancel must be a host numpy int32 array")
+            opts.cancel_flag_host = cancel.ctypes.data
         if isinstance(order, str):
             if order != "learned" or model is None:
                 raise ValueError('order="learned" needs model=')

@@ -42,7 +42,8 @@ class QueryOpts(ctypes.Structure):
                 ("dp_rows", ctypes.c_int32), ("dp_waves_per_cu", ctypes.c_int32),
                 ("dk_seed", ctypes.c_int32),
                 ("tune", ctypes.c_int32),
-                ("model", ctypes.c_void_p)]
+                ("model", ctypes.c_void_p),
+                ("cancel_flag_host", ctypes.c_void_p)]
 
 
 class IndexOpts(ctypes.Structure):

@@ -1110,6 +1110,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return TSK_OK;
     };
 
+    if (o.cancel_flag_host && *o.cancel_flag_host != 0)
+        return set_err(TSK_ERR_CANCELLED, "cancelled before any device work");
     if (o.use_graph) {
         // one chunk, replayed from a cached executable graph when the call
         // repeats (same inputs, outputs, shape and options)
@@ -1174,6 +1176,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
     } else {
         fill_u64(W.ctr.p, 0ull, C_NUM, s);
         for (int64_t q0 = 0; q0 < n_queries; q0 += P.chunk) {
+            if (o.cancel_flag_host && *o.cancel_flag_host != 0)
+                return set_err(TSK_ERR_CANCELLED, "cancelled before query %lld", (long long)q0);
             const Chunk c = plan_chunk(q0);
             TSK_TRY(prepare_chunk(c));
             hipEvent_t *ev = nullptr;

@@ -384,3 +384,30 @@ def test_knn_dk_tube_rows_classwarp(rows):
     assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
     print(f"  fallback {st['fallback_pairs']} cells {st['dp_valid_cells']}", flush=True)
     idx.close()
+
+
+def test_knn_cancel_flag():
+    """A set host flag stops a k-NN call (eager or graph) before any device
+    work (TSK_ERR_CANCELLED, outputs untouched); a clear flag changes
+    nothing."""
+    import numpy as np
+    import torch
+    from paper_1811_11076_amd import TskError, _lib
+    print("[case] cancel flag", flush=True)
+    db, dbo = ragged_walks(61, 200, (40, 40), 3)
+    qs, qo = ragged_walks(62, 4, (40, 40), 3)
+    idx = _index(db, dbo)
+    flag = np.zeros(1, np.int32)
+    ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 5, "dtw", 4)
+    ids, dst, _ = idx.knn(to_dev(qs), qo, 5, "dtw", 4, cancel=flag)
+    assert_same_knn(ids, dst, ref_ids, ref_keys, "dtw")
+    flag[0] = 1
+    out = (torch.full((4, 5), -7, dtype=torch.int64, device="cuda"),
+           torch.full((4, 5), -7.0, dtype=torch.float32, device="cuda"))
+    for kw in ({}, {"use_graph": True}):
+        with pytest.raises(TskError) as ei:
+            idx.knn(to_dev(qs), qo, 5, "dk", None, out=out, cancel=flag, **kw)
+        assert ei.value.code == _lib.TSK_ERR_CANCELLED
+        torch.cuda.synchronize()
+        assert bool((out[0] == -7).all()) and bool((out[1] == -7.0).all())
+    idx.close()
