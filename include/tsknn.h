@@ -198,7 +198,13 @@ typedef struct {
 
 typedef struct {
     int64_t size;                  /* sizeof(tsk_index_opts) */
-    int64_t reserved;
+    int64_t workspace_limit_bytes; /* bound on the workspace of a query call
+                                      (0 = library default: chunks of up to
+                                      2^28 (query, series) pairs); calls
+                                      split their queries into chunks whose
+                                      workspace fits (at least one query per
+                                      chunk).  use_graph calls need one
+                                      chunk for all their queries */
 } tsk_index_opts;
 
 /* Library version. */

@@ -63,16 +63,19 @@ _DIST = {"dtw": _lib.TSK_DTW, "dk": _lib.TSK_DK}
 class Index:
     """Read-only device index over database series (C: tsk_index_build)."""
 
-    def __init__(self, values, offsets):
+    def __init__(self, values, offsets, workspace_limit_bytes: int = 0):
+        """workspace_limit_bytes: bound on a query call's workspace (0 = the
+        library default); queries are processed in chunks that fit."""
         self._lib = _lib.load()
         v = _values(values)
         off = _offsets(offsets)
         self.n = int(off.shape[0] - 1)
         self.dim = int(v.shape[1])
         self._h = ctypes.c_void_p()
+        io = _lib.IndexOpts(ctypes.sizeof(_lib.IndexOpts), int(workspace_limit_bytes))
         _lib.check(self._lib.tsk_index_build(
             ctypes.c_void_p(v.data_ptr()), off.ctypes.data_as(ctypes.c_void_p), self.n, self.dim,
-            None, _stream(), ctypes.byref(self._h)))
+            ctypes.byref(io), _stream(), ctypes.byref(self._h)))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -47,7 +47,7 @@ class QueryOpts(ctypes.Structure):
 
 
 class IndexOpts(ctypes.Structure):
-    _fields_ = [("size", ctypes.c_int64), ("reserved", ctypes.c_int64)]
+    _fields_ = [("size", ctypes.c_int64), ("workspace_limit_bytes", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):

@@ -88,6 +88,7 @@ constexpr int NEV = 9;
 
 struct tsk_index {
     int device = 0;
+    int64_t ws_limit = 0; // workspace bound of a query call (0 = none)
     int dim = 0;
     int64_t n = 0;
     int64_t total = 0;
@@ -467,6 +468,8 @@ extern "C" int tsk_index_build(const float *values_dev, const int64_t *offsets_h
         return set_err(TSK_ERR_UNSUPPORTED, "dim %d outside [1, %d]", dim, TSK_MAX_DIM);
     if (opts && opts->size != (int64_t)sizeof(tsk_index_opts))
         return set_err(TSK_ERR_INVALID_ARG, "opts->size mismatch");
+    if (opts && opts->workspace_limit_bytes < 0)
+        return set_err(TSK_ERR_INVALID_ARG, "workspace_limit_bytes must be >= 0");
     int32_t mn = 0, mx = 0;
     TSK_TRY(check_series(offsets_host, n_series, "series", &mn, &mx));
     int dev = 0, ndev = 0;
@@ -479,6 +482,7 @@ extern "C" int tsk_index_build(const float *values_dev, const int64_t *offsets_h
     if (!ix)
         return set_err(TSK_ERR_OOM, "host allocation failed");
     ix->device = dev;
+    ix->ws_limit = opts ? opts->workspace_limit_bytes : 0;
     ix->dim = dim;
     ix->n = n_series;
     ix->total = offsets_host[n_series];
@@ -780,7 +784,14 @@ static int prepare_qtables(tsk_index *ix, const int64_t *qoff_host, int64_t q0, 
 static int64_t chunk_queries(const tsk_index *ix, int64_t nq)
 {
     const int64_t budget = (int64_t)1 << 28; // (query, candidate) entries per chunk
-    return std::max<int64_t>(1, std::min<int64_t>(nq, budget / std::max<int64_t>(1, ix->n)));
+    int64_t q = budget / std::max<int64_t>(1, ix->n);
+    if (ix->ws_limit > 0) {
+        // per query: bounds, survivors, fallback pairs and range hits per
+        // series (20 bytes), the envelope and staged rows per point
+        const int64_t per_q = ix->n * 20 + (int64_t)ix->max_len * (8 * ix->dim + 32) + 1024;
+        q = std::min<int64_t>(q, ix->ws_limit / per_q);
+    }
+    return std::max<int64_t>(1, std::min<int64_t>(nq, q));
 }
 
 static std::array<int64_t, 5> tune_key(int32_t dist, tsk_band band, int32_t k)

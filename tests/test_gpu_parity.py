@@ -411,3 +411,25 @@ def test_knn_cancel_flag():
         torch.cuda.synchronize()
         assert bool((out[0] == -7).all()) and bool((out[1] == -7.0).all())
     idx.close()
+
+
+@pytest.mark.parametrize("limit", [1, 300_000, 2_000_000])
+def test_knn_workspace_limit_chunks(limit):
+    """An index with a small workspace bound splits calls into chunks (down
+    to one query each); rows equal the oracle's for both distances and the
+    range query."""
+    from paper_1811_11076_amd import Index
+    print(f"[case] workspace limit {limit}", flush=True)
+    db, dbo = ragged_walks(71, 500, (30, 90), 3)
+    qs, qo = ragged_walks(72, 9, (30, 90), 3)
+    idx = Index(to_dev(db), dbo, workspace_limit_bytes=limit)
+    for dist, band in (("dk", None), ("dtw", 0.1)):
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 6, dist, band)
+        ids, dst, st = idx.knn(to_dev(qs), qo, 6, dist, band, stats=True)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
+        assert st["pairs"] == 9 * 500
+    offs, rids, _, _ = idx.range(to_dev(qs), qo, 4.0, "dk", None)
+    ref = O.range_brute(db, dbo, qs, qo, 4.0, "dk", None)
+    for q in range(9):
+        assert np.array_equal(rids[offs[q]:offs[q + 1]].cpu().numpy(), ref[q][0])
+    idx.close()
