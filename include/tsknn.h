@@ -225,6 +225,14 @@ const char *tsk_last_error(void);
 int tsk_index_build(const float *values_dev, const int64_t *offsets_host, int64_t n_series,
                     int32_t dim, const tsk_index_opts *opts, void *hip_stream, tsk_index **out);
 
+/* Opt-in input check (series values must be finite; the scan does not test
+ * them): *first_bad_host (nullable) receives the index of the first
+ * non-finite float of values_dev[0 .. count), or -1.  Returns TSK_OK when
+ * all are finite, TSK_ERR_INVALID_ARG otherwise (or for NULL values with
+ * count > 0, count < 0).  Synchronous on hip_stream. */
+int tsk_validate_values(const float *values_dev, int64_t count, int64_t *first_bad_host,
+                        void *hip_stream);
+
 /* Frees an index and its device memory after synchronising its stream.
  * NULL is accepted. */
 int tsk_index_free(tsk_index *index);

@@ -17,7 +17,7 @@ import numpy as np
 
 from . import _lib
 
-__all__ = ["Index", "Model", "TskError", "subseq_query", "version"]
+__all__ = ["Index", "Model", "TskError", "subseq_query", "validate_values", "version"]
 
 TskError = _lib.TskError
 
@@ -27,6 +27,21 @@ def version():
     a, b = ctypes.c_int(), ctypes.c_int()
     _lib.check(lib.tsk_version(ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
+
+
+def validate_values(values) -> int:
+    """Index of the first non-finite value of a CUDA float32 tensor, or -1
+    (C: tsk_validate_values)."""
+    lib = _lib.load()
+    v = values.contiguous()
+    if not v.is_cuda or v.dtype != _torch().float32:
+        raise TypeError("values must be a CUDA float32 tensor")
+    bad = ctypes.c_int64(-1)
+    rc = lib.tsk_validate_values(ctypes.c_void_p(v.data_ptr()), int(v.numel()), ctypes.byref(bad),
+                                 _stream())
+    if rc != _lib.TSK_ERR_INVALID_ARG or bad.value < 0:
+        _lib.check(rc)
+    return int(bad.value)
 
 
 def _torch():

@@ -97,6 +97,7 @@ SIGNATURES = {
     "tsk_last_error": (ctypes.c_char_p, []),
     "tsk_index_build": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp, ctypes.POINTER(_vp)]),
     "tsk_index_free": (ctypes.c_int, [_vp]),
+    "tsk_validate_values": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(_i64), _vp]),
     "tsk_index_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
     "tsk_knn_query": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, Band, _vp, _vp, _vp, _vp,
                                      _vp]),

@@ -345,6 +345,50 @@ static void free_index_memory(tsk_index *ix)
     ix->ev_pool.clear();
 }
 
+// first non-finite element: grid-stride, atomic minimum of the index
+static __global__ void k_first_nonfinite(const float *__restrict__ v, int64_t n,
+                                         unsigned long long *first)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (!__builtin_isfinite(v[i]))
+            atomicMin(first, (unsigned long long)i);
+}
+
+extern "C" int tsk_validate_values(const float *values_dev, int64_t count, int64_t *first_bad_host,
+                                   void *hip_stream)
+{
+    g_err.clear();
+    if (first_bad_host)
+        *first_bad_host = -1;
+    if (count < 0)
+        return set_err(TSK_ERR_INVALID_ARG, "count must be >= 0");
+    if (count == 0)
+        return TSK_OK;
+    if (!values_dev)
+        return set_err(TSK_ERR_INVALID_ARG, "values_dev is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    DevBuf<unsigned long long> first;
+    TSK_TRY(first.ensure(1));
+    fill_u64(first.p, ~0ull, 1, s);
+    hipLaunchKernelGGL(k_first_nonfinite, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s,
+                       values_dev, count, first.p);
+    unsigned long long h = ~0ull;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&h, first.p, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    first.release();
+    if (e != hipSuccess)
+        return set_err(TSK_ERR_DEVICE, "validate: %s", hipGetErrorString(e));
+    if (h == ~0ull)
+        return TSK_OK;
+    if (first_bad_host)
+        *first_bad_host = (int64_t)h;
+    return set_err(TSK_ERR_INVALID_ARG, "value %lld is not finite", (long long)h);
+}
+
 extern "C" int tsk_index_free(tsk_index *ix)
 {
     if (!ix)

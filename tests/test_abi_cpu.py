@@ -186,3 +186,13 @@ def test_subseq_rejects_bad_arguments_before_device_work():
     if not torch.cuda.is_available():
         # valid arguments reach the device query, which fails without a GPU
         assert call() == _lib.TSK_ERR_DEVICE
+
+
+@needs_lib
+def test_validate_values_arguments():
+    lib = _lib.load()
+    bad = ctypes.c_int64(5)
+    assert lib.tsk_validate_values(None, 0, ctypes.byref(bad), None) == _lib.TSK_OK
+    assert bad.value == -1
+    assert lib.tsk_validate_values(None, 3, ctypes.byref(bad), None) == _lib.TSK_ERR_INVALID_ARG
+    assert lib.tsk_validate_values(ctypes.c_void_p(0x1000), -1, None, None) == _lib.TSK_ERR_INVALID_ARG

@@ -433,3 +433,15 @@ def test_knn_workspace_limit_chunks(limit):
     for q in range(9):
         assert np.array_equal(rids[offs[q]:offs[q + 1]].cpu().numpy(), ref[q][0])
     idx.close()
+
+
+def test_validate_values_finds_first_nonfinite():
+    import torch
+    from paper_1811_11076_amd import validate_values
+    v = torch.randn(1_000_003, device="cuda")
+    assert validate_values(v) == -1
+    v[777_777] = float("inf")
+    v[900_001] = float("nan")
+    assert validate_values(v) == 777_777
+    v[5] = float("-inf")
+    assert validate_values(v) == 5
