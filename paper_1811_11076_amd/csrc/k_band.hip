@@ -15,6 +15,9 @@ template <int D, int DIST> void band_d(int wsel, const FastArgs &a, int blocks, 
     case 4: hipLaunchKernelGGL((k_dp_band<D, DIST, 64, 57>), grid, block, 0, s, a, a.qpad); break;
     case 5: hipLaunchKernelGGL((k_dp_band<D, DIST, 104, 65>), grid, block, 0, s, a, a.qpad); break;
     case 6: hipLaunchKernelGGL((k_dp_band<D, DIST, 128, 105>), grid, block, 0, s, a, a.qpad); break;
+    case BAND_W52_TIGHT:
+        hipLaunchKernelGGL((k_dp_band<D, DIST, 52, 49>), grid, block, 0, s, a, a.qpad);
+        break;
     default: break;
     }
 }

@@ -12,6 +12,9 @@ namespace tsk {
 // instantiation serves, so only the slots above it are masked.
 constexpr int BAND_WS[] = {16, 32, 52, 56, 64, 104, 128};
 constexpr int N_BAND_WS = 7;
+// the 52-slot kernel for bands of 49..52 slots (w = 24, 25): only slots 49
+// and up are masked at run time
+constexpr int BAND_W52_TIGHT = 7;
 
 struct SeedRingArgs {
     const float *qv;

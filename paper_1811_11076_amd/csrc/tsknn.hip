@@ -752,7 +752,7 @@ static int pick_fast(const tsk_index *ix, int dist, const tsk_band &band, int32_
     w = std::min(w, m - 1);
     for (int i = 0; i < N_BAND_WS; ++i)
         if (2 * w + 1 <= BAND_WS[i]) {
-            *wsel = i;
+            *wsel = (BAND_WS[i] == 52 && 2 * w + 1 >= 49) ? BAND_W52_TIGHT : i;
             return FAST_BAND;
         }
     return FAST_NONE;

@@ -182,11 +182,12 @@ def test_knn_classwarp_uneven_reduced():
     idx.close()
 
 
-@pytest.mark.parametrize("w", [3, 12, 20, 25, 27, 30, 45, 60])
+@pytest.mark.parametrize("w", [3, 12, 20, 23, 24, 25, 27, 30, 45, 60])
 def test_knn_band_kernel_widths(w):
     """Equal lengths, band widths covering every lane-per-pair window size
-    (2w+1 of 7, 25, 41, 51, 55, 61, 91, 121 in windows of 16, 32, 52, 52,
-    56, 64, 104, 128 slots), both distances, against the oracle."""
+    (2w+1 of 7, 25, 41, 47, 49, 51, 55, 61, 91, 121 in windows of 16, 32, 52,
+    52, 52 (tight mask), 52 (tight mask), 56, 64, 104, 128 slots), both
+    distances, against the oracle."""
     print(f"[case] knn band widths w={w}", flush=True)
     db, dbo = ragged_walks(40 + w, 150, (128, 128), 3)
     qs, qo = ragged_walks(140 + w, 3, (128, 128), 3)
