@@ -257,6 +257,9 @@ def learned_order(w, args, db, dbo, dev_db, dev_q, qo, idx_dk, idx_dtw, plain_re
                                                  plain_res[0][:2] + plain_res[1][:2]))
     pairs = w["Q"] * w["N"]
     calls = max(1, pdk["calls"])
+    controls = None
+    if pairs <= 10_000_000:
+        controls = order_controls(w, idx_dk, dev_q, qo, model, plain_res[0], pdk)
     model.close()
     return {"ms_per_step": elapsed * 1e3 / args.steps,
             "pairs_per_s": pairs / (elapsed / args.steps),
@@ -267,7 +270,53 @@ def learned_order(w, args, db, dbo, dev_db, dev_q, qo, idx_dk, idx_dtw, plain_re
                    "dp_completed": pdk["dp_completed"] / calls,
                    "dp_valid_cells": pdk["dp_valid_cells"] / calls},
             "dtw": {"device_ms": pdtw["ms_total"] / max(1, pdtw["calls"]), "order": "plain"},
-            "dk_fraction_full_dps": pdk["dp_completed"] / calls / pairs}
+            "dk_fraction_full_dps": pdk["dp_completed"] / calls / pairs,
+            "dk_controls": controls}
+
+
+def order_controls(w, idx_dk, dev_q, qo, model, plain_dk, learned_prof, reps=3):
+    """DK work under the order and seeding controls: the plain order with
+    Alg. 1 over every candidate (the paper's own first pass), the learned
+    order with that full seed, the learned order with the library's top-M
+    seed (its first 512 candidates), the plain order with the top-M seed,
+    and an untrained (random-init) encoder with the top-M seed.  Each row
+    gives the fraction of (query, series) pairs whose DP ran to
+    completion, DPs started, DP cells and device time per call; every
+    control's rows must equal the plain scan's."""
+    import torch
+    from paper_1811_11076_amd import Model
+    pairs = w["Q"] * w["N"]
+    k = w["k"]
+    untrained = Model(w["d"], seed=2)
+    full = {"seed_count": w["N"]}
+    runs = [("plain_full_seed", full),
+            ("learned_full_seed", dict(order="learned", model=model, **full)),
+            ("plain_top_m_seed", {}),
+            ("untrained_top_m_seed", dict(order="learned", model=untrained))]
+    out = {}
+    for name, kw in runs:
+        ids, dist, _ = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], **kw)
+        torch.cuda.synchronize()
+        same = torch.equal(ids, plain_dk[0]) and torch.equal(dist, plain_dk[1])
+        idx_dk.profile(reset=True)
+        for _ in range(reps):
+            idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], profile=True, **kw)
+        p = idx_dk.profile(reset=True)
+        out[name] = _control_row(p, pairs, same)
+        print(f"[bench] order control {name}: {out[name]['fraction_full_dps']:.5f} full DPs, "
+              f"{out[name]['device_ms']:.3f} ms", file=sys.stderr, flush=True)
+    untrained.close()
+    out["learned_top_m_seed"] = _control_row(learned_prof, pairs, True)
+    return out
+
+
+def _control_row(p, pairs, same):
+    c = max(1, p["calls"])
+    return {"fraction_full_dps": p["dp_completed"] / c / pairs,
+            "dp_started": p["dp_started"] / c, "dp_completed": p["dp_completed"] / c,
+            "dp_valid_cells": p["dp_valid_cells"] / c, "seed_pairs": p["seed_pairs"] / c,
+            "device_ms": p["ms_total"] / c, "seed_ms": p["ms_seed"] / c,
+            "order_ms": p["ms_order"] / c, "rows_equal_plain": bool(same)}
 
 
 def cpu_baseline(db, dbo, qs, qo, w, nq_sample, n_series=0):

@@ -117,7 +117,9 @@ def test_learned_order_exact_and_gain():
     """The class-warp workload at reduced size (10 classes, L = 256, d = 3):
     an encoder trained on DK distances from the train stream orders each
     query's candidates; the k-NN rows equal the oracle's and the plain
-    scan's, and fewer DPs run to completion than with the plain order.  An
+    scan's, and fewer DPs run to completion than with the plain order.  The
+    threshold seeded by Alg. 1 over every candidate (the paper's first
+    pass) gives the same rows in either order.  An
     untrained (random-weight) encoder is reported beside it: random ReLU
     features already preserve much of the resampled series' geometry on
     this data, so no margin over it is asserted."""
@@ -137,8 +139,11 @@ def test_learned_order_exact_and_gain():
     idx = Index(to_dev(db), dbo)
     ref_ids, ref_keys, _ = O.knn_scan(db, dbo, qs, qo, 10, "dk", None)
     res = {}
+    full = dict(seed_count=len(dbo) - 1)   # Alg. 1 over every candidate
     for name, kw in (("plain", {}), ("untrained", dict(order="learned", model=untrained)),
-                     ("trained", dict(order="learned", model=trained))):
+                     ("trained", dict(order="learned", model=trained)),
+                     ("plain_full_seed", full),
+                     ("trained_full_seed", dict(order="learned", model=trained, **full))):
         ids, dst, st = idx.knn(to_dev(qs), qo, 10, "dk", None, stats=True, **kw)
         assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
         res[name] = st
