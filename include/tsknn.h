@@ -166,7 +166,7 @@ typedef struct {
                                       the query's candidate order, 0 =
                                       library default (DTW 1, DK 2) */
     int32_t dp_rows;               /* tile shape of the general DP: rows per
-                                      lane of its skewed strips (1 or 4;
+                                      lane of its skewed strips (1, 2 or 4;
                                       0 = 4) */
     int32_t dp_waves_per_cu;       /* persistent waves per compute unit of
                                       the lane-per-pair DP kernels: 8, 16

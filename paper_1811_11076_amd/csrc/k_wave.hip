@@ -24,6 +24,8 @@ template <int D> void wave_d(int dist, int mode, const DpArgs &a, int blocks, hi
 {
     if (a.rows_per_lane == 1)
         wave_r<D, 1>(dist, mode, a, blocks, s);
+    else if (a.rows_per_lane == 2)
+        wave_r<D, 2>(dist, mode, a, blocks, s);
     else
         wave_r<D, 4>(dist, mode, a, blocks, s);
 }

@@ -663,7 +663,7 @@ __global__ __launch_bounds__(256) void k_range_fill(const float *__restrict__ hi
 // three predecessors; DK: max(cost, min)), with D(-1,-1) = 0 and every other
 // outside cell +inf, restricted to the band.  Rows are processed in strips
 // of 64 R (R consecutive rows per lane: 4 amortises the per-step work over
-// more cells, 1 wastes fewer out-of-band cells on narrow bands); inside a
+// more cells, 1 and 2 waste fewer out-of-band cells on narrow bands); inside a
 // strip lane l works on column s - l at step s (a skewed wavefront),
 // receiving the row below from lane l-1 of the previous step; the strip's
 // top row is handed to the next strip through a per-wave buffer.
@@ -843,7 +843,7 @@ struct DpArgs {
     float *out_all;     // ALLPAIRS: [nq][N]
     const int2 *fb;     // FALLBACK: (query, candidate) list
     const unsigned long long *fb_count;
-    int rows_per_lane;  // R of the strips: 1 or 4
+    int rows_per_lane;  // R of the strips: 1, 2 or 4
     float *range_out;   // range query: [nq][N] keys of hits, else null (top-k)
 };
 

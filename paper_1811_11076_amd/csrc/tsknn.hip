@@ -916,8 +916,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "dp_waves_per_cu must be 0, 8, 16 or 32");
     if (o.dk_seed != 0 && o.dk_seed != 1)
         return set_err(TSK_ERR_INVALID_ARG, "dk_seed must be 0 or 1");
-    if (o.dp_rows != 0 && o.dp_rows != 1 && o.dp_rows != 4)
-        return set_err(TSK_ERR_INVALID_ARG, "dp_rows must be 0, 1 or 4");
+    if (o.dp_rows != 0 && o.dp_rows != 1 && o.dp_rows != 2 && o.dp_rows != 4)
+        return set_err(TSK_ERR_INVALID_ARG, "dp_rows must be 0, 1, 2 or 4");
     if (o.surv_order < 0 || o.surv_order > 2)
         return set_err(TSK_ERR_INVALID_ARG, "surv_order must be 0, 1 or 2");
     if (o.lb_qgroup != 0 && o.lb_qgroup != 1 && o.lb_qgroup != 2 && o.lb_qgroup != 4 &&
@@ -1573,7 +1573,7 @@ extern "C" int tsk_tune(tsk_index *ix, const float *q_values_dev, const int64_t 
         else if (dist == TSK_DTW)
             knobs.push_back({&tsk_query_opts::lb_qgroup, {1, 8, 16}}); // LB kernel and query group
         knobs.push_back({&tsk_query_opts::surv_order, {1, 2}});
-        knobs.push_back({&tsk_query_opts::dp_rows, {1, 4}});
+        knobs.push_back({&tsk_query_opts::dp_rows, {1, 2, 4}});
         knobs.push_back({&tsk_query_opts::dp_waves_per_cu, {8, 16, 32}});
         tsk_query_opts cur = b;
         float cur_ms = 0.0f;

@@ -278,9 +278,9 @@ def test_knn_survivor_orders(kind, so):
     idx.close()
 
 
-@pytest.mark.parametrize("rows", [1, 4])
+@pytest.mark.parametrize("rows", [1, 2, 4])
 def test_knn_general_dp_tile_rows(rows):
-    """The general DP's strip shape (1 or 4 rows per lane) on uneven
+    """The general DP's strip shape (1, 2 or 4 rows per lane) on uneven
     lengths, where every DTW survivor and every DK tube overflow runs in it:
     rows equal the oracle's."""
     print(f"[case] knn general DP rows={rows}", flush=True)
