@@ -274,6 +274,27 @@ def test_envelope_bruteforce(rng):
                 assert np.array_equal(lo[i], T[cols].min(0)) and np.array_equal(hi[i], T[cols].max(0))
 
 
+def test_wider_window_lowers_lb_box(rng):
+    """A superset window can only widen each box, so LB_Box over a wider
+    band is never larger (the bound stays valid when a kernel uses a
+    superset of the exact window), and every band's LB_Box stays below its
+    own DTW."""
+    for _ in range(40):
+        m = int(rng.integers(1, 30))
+        n = int(rng.integers(1, 30))
+        d = int(rng.integers(1, 4))
+        S = rng.normal(size=(m, d)).astype(np.float32)
+        T = rng.normal(size=(n, d)).astype(np.float32)
+        prev = None
+        for w in (0, 1, 3, 7, 30, -1):
+            lb = O.lb_box_f64(S, T, w)
+            if prev is not None:
+                assert lb <= prev * (1 + 1e-12) + 1e-12
+            dtw = O.dtw_f64(S, T, w)
+            assert lb <= dtw * (1 + 1e-12) + 1e-12
+            prev = lb
+
+
 # ------------------------------------------------------------------ greedy bounds
 def test_greedy_upper_bounds(rng):
     """Alg. 1 returns an upper bound of DK (Sec. 4.1) in at most m+n-2 moves;
@@ -389,6 +410,42 @@ def test_knn_permutation_invariance(rng):
         assert np.array_equal(keys, keys2)
         # ids agree wherever the key is unique among the candidates
         assert np.array_equal(perm[ids2], ids)
+
+
+def _merge_shards(parts, k):
+    """Per-query top-k of the shards' top-k lists, ordered by (key, id)."""
+    ids = np.concatenate([p[0] for p in parts], axis=1)
+    keys = np.concatenate([p[1] for p in parts], axis=1)
+    out_i = np.full((ids.shape[0], k), -1, np.int64)
+    out_k = np.full((ids.shape[0], k), INF, np.float32)
+    for q in range(ids.shape[0]):
+        cand = sorted((float(keys[q, t]), int(ids[q, t])) for t in range(ids.shape[1])
+                      if ids[q, t] >= 0)[:k]
+        for r, (kk, ii) in enumerate(cand):
+            out_i[q, r], out_k[q, r] = ii, kk
+    return out_i, out_k
+
+
+@pytest.mark.parametrize("shards", [2, 3, 5])
+def test_knn_shard_and_merge(rng, shards):
+    """The k-NN definition splits over database shards: each shard's top-k
+    (ids offset by the shard's first series), merged by (key, id), equals
+    the top-k of the whole database, padding included when k exceeds a
+    shard."""
+    db, dbo = _db(rng, 61, (5, 30), 3)
+    qs, qo = _db(rng, 4, (5, 30), 3)
+    cuts = np.linspace(0, 61, shards + 1).astype(int)
+    for dist, band in (("dk", None), ("dtw", 0.2), ("dtw", None)):
+        for k in (1, 6, 15):
+            full = O.knn_brute(db, dbo, qs, qo, k, dist, band)
+            parts = []
+            for a, b in zip(cuts[:-1], cuts[1:]):
+                sdb = db[dbo[a]:dbo[b]]
+                sdo = (dbo[a:b + 1] - dbo[a]).astype(np.int64)
+                ids, keys = O.knn_brute(sdb, sdo, qs, qo, k, dist, band)
+                parts.append((np.where(ids >= 0, ids + a, -1), keys))
+            mi, mk = _merge_shards(parts, k)
+            assert np.array_equal(mi, full[0]) and np.array_equal(mk, full[1])
 
 
 def test_fp32_dtw_close_to_fp64():
