@@ -6,43 +6,62 @@
 
 namespace tsk {
 
+// floats of LDS per lane for the greedy walk's candidate ring, and the
+// distance between two lanes' rings: odd, so that the 64 lanes' rings start
+// in different LDS banks (a stride of 128 floats puts every lane's slot s in
+// one bank and serialises each ring access 64 ways)
+constexpr int WALK_RING_FLOATS = 128;
+constexpr int WALK_RING_STRIDE = WALK_RING_FLOATS + 1;
+
 // Greedy walk of Alg. 1 (Sec. 4.1), same moves, tie order and value as
 // greedy_walk().  Latency layout for gfx950: the query comes from LDS (row
 // stride DP floats); the candidate goes through a lane-private LDS ring of
-// 16 points (slot = point mod 16) that always holds points [jb, jb+16) with
-// jb = 8 * floor(j / 8).  Each time j enters a new block of 8, the 8 points
-// loaded into registers one block earlier are written to the ring and the
-// next 8 are requested, so global loads are waited on once per 8 advances
-// and long after they were issued.  The points at j, j+1, j+2 (and i, i+1,
-// i+2) sit in registers, the third one read from LDS one move before use.
-// The running threshold is re-read every 8 moves and used 8 moves later.
+// RN = 4B points (slot = point mod RN; B = 8 points per block for DP = 4, 4
+// for DP = 8, so a ring is 128 floats either way).  Every B moves, on the
+// same moves for every lane still walking (lanes advance j at their own
+// pace, and a refill taken by some lanes only would wait on loads that
+// others had just issued into the same registers), each lane writes the B
+// points it loaded at the previous refill, [jb' + 3B, jb' + 4B) for its
+// block jb' then, and requests [jb + 3B, jb + 4B) for its current block
+// jb = B floor(j / B); a lane that has not changed block rewrites the same
+// points.  After a refill the ring holds the 4B points from jb' on, and a
+// walk of B moves from j < jb' + 2B reads points below jb' + 3B: every
+// point read is staged, and the slots written hold points behind the walk.
+// Global loads are thus waited on B moves after they were issued.  The
+// points at j, j+1, j+2 (and i, i+1, i+2) sit in registers, the third one
+// read from LDS one move before use.  The running threshold is re-read at
+// each refill and used at the next.
 template <int D, int DIST, bool BANDED>
 __device__ float greedy_walk_ring(const float *qs, int m, const float *__restrict__ c, int n,
                                   float *ring, const Band &band, float eps, const uint32_t *tau,
                                   int &steps_out, bool &completed)
 {
     constexpr int DP = PadDim<D>::value;
-    constexpr int RB = 8; // block of points
+    constexpr int B = WALK_RING_FLOATS / (4 * DP); // points per block
+    constexpr int RN = 4 * B;                       // ring points
+    static_assert((B & (B - 1)) == 0 && B >= 2, "block of points: a power of two >= 2");
     float q0[D], q1[D], q2[D];
     float r0[D], r1[D], r2[D];
-    float pf[RB][D];
+    float pf[B][D];
 #pragma unroll
     for (int e = 0; e < D; ++e) {
         q0[e] = qs[e];
         q1[e] = qs[min(1, m - 1) * DP + e];
         q2[e] = qs[min(2, m - 1) * DP + e];
     }
-    // ring <- points 0..15, registers <- points 16..23 (indices clamped)
+    // ring <- points 0 .. RN-1, registers <- points 3B .. 4B-1 (the pending
+    // refill of block 0; indices clamped)
 #pragma unroll
-    for (int t = 0; t < 2 * RB; ++t)
+    for (int t = 0; t < RN; ++t)
 #pragma unroll
         for (int e = 0; e < D; ++e)
             ring[t * DP + e] = c[(int64_t)min(t, n - 1) * D + e];
+    int pjb = 0; // block whose points 3B .. 4B-1 are pending in pf
 #pragma unroll
-    for (int t = 0; t < RB; ++t)
+    for (int t = 0; t < B; ++t)
 #pragma unroll
         for (int e = 0; e < D; ++e)
-            pf[t][e] = c[(int64_t)min(2 * RB + t, n - 1) * D + e];
+            pf[t][e] = c[(int64_t)min(3 * B + t, n - 1) * D + e];
 #pragma unroll
     for (int e = 0; e < D; ++e) {
         r0[e] = ring[0 * DP + e];
@@ -50,14 +69,25 @@ __device__ float greedy_walk_ring(const float *qs, int m, const float *__restric
         r2[e] = ring[2 * DP + e];
     }
     float g = point_cost<D>(q0, r0);
-    int i = 0, j = 0, jb = 0, steps = 0;
+    int i = 0, j = 0, steps = 0;
     completed = false;
     if (g > eps) {
         steps_out = 0;
         return g;
     }
     uint32_t tau_next = tau ? load_relaxed_u32(tau) : TSK_INF_BITS;
-    while (i < m - 1 || j < n - 1) {
+    // The lanes move in lockstep: a lane whose walk has ended (corner
+    // reached: status 1, an infinite move: 2, value above eps: 3) keeps
+    // executing the moves without changing its state, and the loop ends
+    // when no lane walks.  mv counts the wave's moves (the refill cadence);
+    // steps counts the lane's own.
+    int status = 0;
+    for (int mv = 1;; ++mv) {
+        if (status == 0 && !(i < m - 1 || j < n - 1))
+            status = 1;
+        if (__ballot(status == 0) == 0ull)
+            break;
+        const bool walk = status == 0;
         const bool di = i + 1 < m, dj = j + 1 < n;
         bool ok_dn = di, ok_dg = di && dj, ok_rt = dj;
         if (BANDED) {
@@ -72,32 +102,39 @@ __device__ float greedy_walk_ring(const float *qs, int m, const float *__restric
         const bool pick_dn = c_dn <= c_dg && c_dn <= c_rt;
         const bool pick_dg = !pick_dn && c_dg <= c_rt;
         const float cst = pick_dn ? c_dn : (pick_dg ? c_dg : c_rt);
-        ++steps;
-        if (cst == tsk_inf()) {
-            steps_out = steps;
-            return tsk_inf();
-        }
-        g = DIST == DIST_DK ? fmaxf(g, cst) : cst + g;
-        const bool adv_i = pick_dn || pick_dg;
-        const bool adv_j = !pick_dn;
+        steps += walk ? 1 : 0;
+        if (walk && cst == tsk_inf())
+            status = 2;
+        const bool mov = status == 0;
+        if (mov)
+            g = DIST == DIST_DK ? fmaxf(g, cst) : cst + g;
+        const bool adv_i = mov && (pick_dn || pick_dg);
+        const bool adv_j = mov && !pick_dn;
         i += adv_i ? 1 : 0;
         j += adv_j ? 1 : 0;
-        if (j >= jb + RB) {
-            // points jb+16 .. jb+23 replace jb .. jb+7 in the ring
-            jb += RB;
+        if ((mv & (B - 1)) == 0) {
+            // Every B moves of the wave: take in the threshold read at the
+            // previous refill, write the points loaded then, then issue the
+            // next loads (points, threshold), so each wait here covers loads
+            // a block of moves old.  A lane's j grows by at most one a move.
+            if (tau)
+                eps = fminf(eps, bits_f(tau_next));
 #pragma unroll
-            for (int t = 0; t < RB; ++t)
+            for (int t = 0; t < B; ++t)
 #pragma unroll
                 for (int e = 0; e < D; ++e)
-                    ring[((jb + RB + t) & (2 * RB - 1)) * DP + e] = pf[t][e];
+                    ring[((pjb + 3 * B + t) & (RN - 1)) * DP + e] = pf[t][e];
+            pjb = j & ~(B - 1);
 #pragma unroll
-            for (int t = 0; t < RB; ++t)
+            for (int t = 0; t < B; ++t)
 #pragma unroll
                 for (int e = 0; e < D; ++e)
-                    pf[t][e] = c[(int64_t)min(jb + 2 * RB + t, n - 1) * D + e];
+                    pf[t][e] = c[(int64_t)min(pjb + 3 * B + t, n - 1) * D + e];
+            if (tau)
+                tau_next = load_relaxed_u32(tau);
         }
         const int ni = min(i + 2, m - 1);
-        const int nj = min(j + 2, n - 1) & (2 * RB - 1);
+        const int nj = min(j + 2, n - 1) & (RN - 1);
 #pragma unroll
         for (int e = 0; e < D; ++e) {
             const float qn = qs[ni * DP + e];
@@ -109,18 +146,12 @@ __device__ float greedy_walk_ring(const float *qs, int m, const float *__restric
             r1[e] = adv_j ? r2[e] : r1[e];
             r2[e] = adv_j ? rn : r2[e];
         }
-        if (tau && (steps & 7) == 0) {
-            eps = fminf(eps, bits_f(tau_next));
-            tau_next = load_relaxed_u32(tau);
-        }
-        if (g > eps) {
-            steps_out = steps;
-            return g;
-        }
+        if (mov && g > eps)
+            status = 3;
     }
     steps_out = steps;
-    completed = true;
-    return g;
+    completed = status == 1;
+    return status == 2 ? tsk_inf() : g;
 }
 
 // The walk with the band test only where a band exists.
@@ -438,8 +469,8 @@ __global__ __launch_bounds__(64) void k_walk_dk(FastArgs a, const float *__restr
 {
     constexpr int DP = PadDim<D>::value;
     extern __shared__ float qs[];
-    // LDS: the query (maxm rows), then one 16-point candidate ring per lane
-    float *ring = qs + maxm * DP + threadIdx.x * 16 * DP;
+    // LDS: the query (maxm rows), then one candidate ring per lane
+    float *ring = qs + maxm * DP + threadIdx.x * WALK_RING_STRIDE;
     unsigned long long steps_cnt = 0, late = 0;
     const int64_t total = (int64_t)a.nq * ((*a.max_cnt + 63) / 64);
     int staged = -1;
@@ -540,8 +571,8 @@ __global__ __launch_bounds__(64) void k_seed_ring(const float *__restrict__ qv,
     extern __shared__ float qs[];
     const int q = blockIdx.y;
     const int m = (int)(qoff[q + 1] - qoff[q]);
-    // LDS: the query (maxm rows), then one 16-point candidate ring per lane
-    float *ring = qs + maxm * DP + threadIdx.x * 16 * DP;
+    // LDS: the query (maxm rows), then one candidate ring per lane
+    float *ring = qs + maxm * DP + threadIdx.x * WALK_RING_STRIDE;
     const float *src = qv + qoff[q] * D;
     for (int t = threadIdx.x; t < m * DP; t += blockDim.x) {
         const int row = t / DP, e = t % DP;

@@ -35,12 +35,12 @@ struct SeedRingArgs {
     int32_t *dbg_steps; // debug: per-pair move count
 };
 
-// LDS of the 64-lane greedy-walk kernels: the query, then a 16-point ring
-// per lane.
+// LDS of the 64-lane greedy-walk kernels: the query, then a candidate ring
+// per lane, WALK_RING_STRIDE floats apart.
 inline size_t walk_lds_bytes(int D, int maxm)
 {
     const int DP = D <= 4 ? 4 : 8;
-    return (size_t)(maxm + 64 * 16) * DP * sizeof(float);
+    return ((size_t)maxm * DP + 64 * WALK_RING_STRIDE) * sizeof(float);
 }
 
 void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s);
