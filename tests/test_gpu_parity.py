@@ -89,6 +89,29 @@ def test_pair_bounds(case, band):
     idx.close()
 
 
+@pytest.mark.parametrize("d,lens", [(5, (40, 300)), (6, (10, 80)), (8, (100, 400))])
+@pytest.mark.parametrize("band", BANDS, ids=lambda b: f"band{b}")
+def test_pair_bounds_high_dim(d, lens, band):
+    """The greedy walks for d >= 5 (points padded to 8 floats: the walk's
+    candidate ring refills every 4 moves instead of 8): values and move
+    counts bit-exact against Alg. 1 in the oracle, for both distances, over
+    walks long enough for many refills."""
+    print(f"[case] pair_bounds d={d} lens={lens} band={band}", flush=True)
+    db, dbo = ragged_walks(40 + d, 24, lens, d)
+    qs, qo = ragged_walks(140 + d, 2, lens, d)
+    idx = _index(db, dbo)
+    for dist in ("dk", "dtw"):
+        _, ub, steps = (t.cpu().numpy() for t in idx.pair_bounds(to_dev(qs), qo, dist, band))
+        for q in range(len(qo) - 1):
+            S = qs[qo[q]:qo[q + 1]]
+            for c in range(len(dbo) - 1):
+                T = db[dbo[c]:dbo[c + 1]]
+                w = O.band_w(band, S.shape[0], T.shape[0])
+                v, st = O.gdk_sq_f32(S, T, w) if dist == "dk" else O.greedy_sum_f32(S, T, w)
+                assert ub[q, c] == np.float32(v) and steps[q, c] == st, (dist, q, c, ub[q, c], v)
+    idx.close()
+
+
 KNN_CASES = [
     # (name, seed, Q, N, lens, d, k)
     ("tiny_k_gt_n", 10, 2, 5, (3, 12), 2, 8),
