@@ -194,6 +194,15 @@ typedef struct {
                                       enqueued still runs on the stream;
                                       rows of queries not reached are not
                                       written */
+    int32_t lb_both;               /* DTW on an index of equal-length series:
+                                      1 = after the query-envelope LB_Box,
+                                      also the candidate-envelope one (eq. (1)
+                                      in the paper's own orientation) for the
+                                      survivors of queries of that length,
+                                      keeping the larger bound.  Needs
+                                      N x length x 2 x dim floats of
+                                      workspace; 0 = off (default).  k-NN
+                                      only (ignored by range queries) */
 } tsk_query_opts;
 
 typedef struct {

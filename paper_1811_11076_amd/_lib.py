@@ -43,7 +43,8 @@ class QueryOpts(ctypes.Structure):
                 ("dk_seed", ctypes.c_int32),
                 ("tune", ctypes.c_int32),
                 ("model", ctypes.c_void_p),
-                ("cancel_flag_host", ctypes.c_void_p)]
+                ("cancel_flag_host", ctypes.c_void_p),
+                ("lb_both", ctypes.c_int32)]
 
 
 class IndexOpts(ctypes.Structure):

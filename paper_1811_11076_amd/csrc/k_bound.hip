@@ -92,6 +92,29 @@ void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s)
 #undef CALL
 }
 
+namespace {
+template <int D>
+void bound_lb_rev_d(const float *aos, const int64_t *off, int64_t N, int n, BandArgs ba,
+                    float *cenv, const float *qv, const int64_t *qoff, int nq,
+                    const int32_t *surv, const int32_t *surv_cnt, float *lbv, hipStream_t s)
+{
+    const int64_t cells = N * n;
+    hipLaunchKernelGGL(k_cenv<D>, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, aos, off,
+                       N, n, ba, cenv);
+    hipLaunchKernelGGL(k_bound_lb_rev<D>, dim3((unsigned)((N + 255) / 256), nq), dim3(256), 0, s,
+                       qv, qoff, n, cenv, surv, surv_cnt, N, lbv);
+}
+} // namespace
+
+void launch_bound_lb_rev(int D, const float *aos, const int64_t *off, int64_t N, int n,
+                         BandArgs ba, float *cenv, const float *qv, const int64_t *qoff, int nq,
+                         const int32_t *surv, const int32_t *surv_cnt, float *lbv, hipStream_t s)
+{
+#define CALL(d) bound_lb_rev_d<d>(aos, off, N, n, ba, cenv, qv, qoff, nq, surv, surv_cnt, lbv, s)
+    TSK_SWITCH_D(D, CALL)
+#undef CALL
+}
+
 void launch_bound_lb_pp(int D, const BoundArgs &a, hipStream_t s)
 {
 #define CALL(d) bound_lb_pp_d<d>(a, s)

@@ -611,4 +611,84 @@ __global__ __launch_bounds__(64) void k_seed_ring(const float *__restrict__ qv,
     wave_count(ctr + C_SEED_PAIRS, pairs);
 }
 
+// ------------------------------------------------------------------ LB_Box, both orientations
+// Boxes around the candidate (eq. (1) in the paper's own orientation: the
+// candidate enveloped, summed over the query's points), for an index of
+// equal-length series and queries of that length: cenv[c][i] is the
+// per-dimension [min, max] of the candidate points the band lets align with
+// query row i (brute-force window; an empty one gives [+inf, -inf]).
+// cenv: [N][n][2][D].
+template <int D>
+__global__ __launch_bounds__(256) void k_cenv(const float *__restrict__ aos,
+                                              const int64_t *__restrict__ off, int64_t N, int n,
+                                              BandArgs ba, float *__restrict__ cenv)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * n)
+        return;
+    const int64_t c = t / n;
+    const int i = (int)(t % n);
+    const Band b = pair_band(ba, n, n);
+    int lo, hi;
+    band_cols(b, i, n, lo, hi);
+    const float *C = aos + off[c] * D;
+    float mn[D], mx[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        mn[k] = tsk_inf();
+        mx[k] = -tsk_inf();
+    }
+    for (int j = lo; j <= hi; ++j) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float v = C[j * D + k];
+            mn[k] = fminf(mn[k], v);
+            mx[k] = fmaxf(mx[k], v);
+        }
+    }
+    float *e = cenv + (c * n + i) * 2 * D;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        e[k] = mn[k];
+        e[D + k] = mx[k];
+    }
+}
+
+// The candidate-envelope LB_Box of every survivor of the query-envelope
+// bound (queries of another length than the series are left as they are),
+// summed in query-row order in fp32 with the point cost's operation order,
+// so it stays <= the fp32 DTW like the other orientation.  The survivor's
+// bound becomes the larger of the two; the DP stage drops the pair if that
+// exceeds the threshold.  One lane per survivor; grid (.., queries).
+template <int D>
+__global__ __launch_bounds__(256) void k_bound_lb_rev(const float *__restrict__ qv,
+                                                      const int64_t *__restrict__ qoff, int n,
+                                                      const float *__restrict__ cenv,
+                                                      const int32_t *__restrict__ surv,
+                                                      const int32_t *__restrict__ surv_cnt,
+                                                      int64_t N, float *__restrict__ lbv)
+{
+    const int q = blockIdx.y;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = (int)(qoff[q + 1] - qoff[q]);
+    if (m != n || idx >= surv_cnt[q])
+        return;
+    const int c = surv[(int64_t)q * N + idx];
+    const float *Q = qv + qoff[q] * D;
+    const float *E = cenv + (int64_t)c * n * 2 * D;
+    float acc = 0.0f;
+    for (int i = 0; i < m; ++i) {
+        float t = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float x = Q[i * D + k];
+            const float d = fmaxf(fmaxf(E[i * 2 * D + k] - x, x - E[i * 2 * D + D + k]), 0.0f);
+            t = (k == 0) ? d * d : __builtin_fmaf(d, d, t);
+        }
+        acc = t + acc;
+    }
+    float *p = lbv + (int64_t)q * N + c;
+    *p = fmaxf(*p, acc);
+}
+
 } // namespace tsk

@@ -44,6 +44,11 @@ inline size_t walk_lds_bytes(int D, int maxm)
 }
 
 void launch_bound_lb(int D, const BoundArgs &a, bool debug, hipStream_t s);
+// candidate envelopes (k_cenv) then the candidate-envelope LB_Box of the
+// survivors (k_bound_lb_rev); equal-length index of length n
+void launch_bound_lb_rev(int D, const float *aos, const int64_t *off, int64_t N, int n,
+                         BandArgs ba, float *cenv, const float *qv, const int64_t *qoff, int nq,
+                         const int32_t *surv, const int32_t *surv_cnt, float *lbv, hipStream_t s);
 void launch_bound_lb_pp(int D, const BoundArgs &a, hipStream_t s);
 void launch_seed_ring(int D, int dist, const SeedRingArgs &r, hipStream_t s);
 void launch_corner(int D, const BoundArgs &a, hipStream_t s);

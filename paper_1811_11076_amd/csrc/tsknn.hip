@@ -48,6 +48,7 @@ struct Workspace {
     DevBuf<unsigned long long> ctr, work;
     DevBuf<int64_t> qoff;
     DevBuf<float> env;
+    DevBuf<float> cenv;       // candidate envelopes [N][n][2][D] (option lb_both)
     DevBuf<float> tbuf;
     DevBuf<float> qpad;
     DevBuf<int2> fb;
@@ -72,6 +73,7 @@ struct Workspace {
         work.release();
         qoff.release();
         env.release();
+        cenv.release();
         tbuf.release();
         qpad.release();
         fb.release();
@@ -774,7 +776,7 @@ static int check_queries(const tsk_index *ix, const float *qv, const int64_t *qo
 }
 
 // Workspace for a chunk of nq queries; sizes follow the index.
-static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env)
+static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env, bool need_cenv = false)
 {
     Workspace &w = ix->ws;
     const int64_t N = ix->n;
@@ -793,6 +795,8 @@ static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env)
     TSK_TRY(w.qoff.ensure(nq + 1));
     if (need_env)
         TSK_TRY(w.env.ensure(nq * (int64_t)ix->max_len * 2 * ix->dim));
+    if (need_cenv)
+        TSK_TRY(w.cenv.ensure((size_t)N * ix->max_len * 2 * ix->dim));
     TSK_TRY(w.tbuf.ensure((size_t)dp_blocks(ix) * 4 * 2 * ix->max_len));
     TSK_TRY(w.fb.ensure(nq * N));
     return TSK_OK;
@@ -923,6 +927,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
     if (o.lb_qgroup != 0 && o.lb_qgroup != 1 && o.lb_qgroup != 2 && o.lb_qgroup != 4 &&
         o.lb_qgroup != 8 && o.lb_qgroup != 16)
         return set_err(TSK_ERR_INVALID_ARG, "lb_qgroup must be 0, 1, 2, 4, 8 or 16");
+    if (o.lb_both != 0 && o.lb_both != 1)
+        return set_err(TSK_ERR_INVALID_ARG, "lb_both must be 0 or 1");
     if (o.use_graph && (o.profile || o.order == TSK_ORDER_LEARNED))
         return set_err(TSK_ERR_UNSUPPORTED, "use_graph excludes profile and TSK_ORDER_LEARNED");
     if (rr) {
@@ -961,7 +967,9 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         P.seed = 0; // no threshold seeding: the radius is the threshold
     P.env_ok = (dist == TSK_DTW) && ix->min_len == ix->max_len;
 
-    TSK_TRY(ensure_ws(ix, P.chunk, k, P.env_ok));
+    // the candidate-envelope bound: DTW on an equal-length index
+    const bool lb_rev = o.lb_both && dist == TSK_DTW && P.env_ok && o.dp_kernel != 1 && !rr;
+    TSK_TRY(ensure_ws(ix, P.chunk, k, P.env_ok, lb_rev));
     Workspace &W = ix->ws;
     if (rr)
         TSK_TRY(W.rng.ensure((size_t)P.chunk * ix->n));
@@ -1110,6 +1118,12 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, c.order,
                                c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr, W.tau.p,
                                W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
+        if (lb_rev) {
+            // LB_Box in both orientations: the survivors' bounds become the
+            // larger one (queries of another length keep theirs)
+            launch_bound_lb_rev(P.D, ix->aos, ix->off, ix->n, ix->max_len, P.ba, W.cenv.p, qv,
+                                W.qoff.p, nq, W.surv.p, W.surv_cnt.p, W.lbv.p, s);
+        }
         // the greedy pass over the corner survivors costs more than the DP
         // work its tighter threshold saves on the class-warp workloads, so
         // it runs only on request
@@ -1179,7 +1193,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                                     o.order, (int64_t)(uintptr_t)o.order_dev, o.seed_count,
                                     o.dp_kernel, o.walk_pass, o.task_size, o.tube_rows,
                                     o.lb_qgroup, o.dk_band_slots, o.surv_order, o.dp_rows,
-                                    o.dp_waves_per_cu, o.dk_seed};
+                                    o.dp_waves_per_cu, o.dk_seed, o.lb_both};
         // every workspace buffer the captured kernels address: a buffer
         // reallocated by another call changes the key
         for (const void *ptr :
@@ -1189,7 +1203,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
               (const void *)W.qcur.p,
               (const void *)W.work.p, (const void *)W.qoff.p, (const void *)W.env.p,
               (const void *)W.tbuf.p, (const void *)W.qpad.p, (const void *)W.fb.p,
-              (const void *)W.qtab.p, (const void *)W.qtab_off.p})
+              (const void *)W.qtab.p, (const void *)W.qtab_off.p, (const void *)W.cenv.p})
             key.push_back((int64_t)(uintptr_t)ptr);
         key.insert(key.end(), q_offsets_host, q_offsets_host + n_queries + 1);
         if (stats_host) {

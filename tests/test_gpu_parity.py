@@ -112,6 +112,41 @@ def test_pair_bounds_high_dim(d, lens, band):
     idx.close()
 
 
+@pytest.mark.parametrize("band", [0.1, 3, None], ids=lambda b: f"band{b}")
+def test_knn_dtw_lb_both_orientations(band):
+    """DTW with LB_Box in both orientations (option lb_both: the survivors of
+    the query-envelope bound also get the candidate-envelope bound, eq. (1)
+    in the paper's own orientation, and keep the larger): rows equal the
+    oracle's on random walks and class-warp data; queries of another length
+    than the (equal-length) series keep their one bound; a graph replay
+    gives the same rows."""
+    print(f"[case] knn dtw lb_both band={band}", flush=True)
+    from paper_1811_11076_amd import synth
+    rw_db, rw_dbo = synth.flat_equal(synth.random_walks(600, 64, 3, 61, "db"))
+    rw_qs, rw_qo = synth.flat_equal(synth.random_walks(6, 64, 3, 61, "query"))
+    cases = [(rw_db, rw_dbo, rw_qs, rw_qo), classwarp(2, 10, 128, 3, 1200, 5)]
+    # equal-length index, queries of mixed lengths (64 and others)
+    mq, mqo = ragged_walks(62, 4, (40, 90), 3)
+    qs_mix = np.concatenate([rw_qs, mq])
+    qo_mix = np.concatenate([rw_qo, rw_qo[-1] + mqo[1:]])
+    cases.append((rw_db, rw_dbo, qs_mix, qo_mix))
+    for db, dbo, qs, qo in cases:
+        idx = _index(db, dbo)
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, "dtw", band)
+        ids, dst, st = idx.knn(to_dev(qs), qo, 10, "dtw", band, stats=True, lb_both=True)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, "dtw")
+        _, _, st0 = idx.knn(to_dev(qs), qo, 10, "dtw", band, stats=True)
+        print(f"  pruned {st['bound_pruned']} vs {st0['bound_pruned']}, DPs started "
+              f"{st['dp_started']} vs {st0['dp_started']}", flush=True)
+        import torch
+        out = (torch.empty_like(ids), torch.empty_like(dst))
+        for _ in range(2):
+            idx.knn(to_dev(qs), qo, 10, "dtw", band, use_graph=True, out=out, lb_both=True)
+            torch.cuda.synchronize()
+            assert_same_knn(out[0], out[1], ref_ids, ref_keys, "dtw")
+        idx.close()
+
+
 KNN_CASES = [
     # (name, seed, Q, N, lens, d, k)
     ("tiny_k_gt_n", 10, 2, 5, (3, 12), 2, 8),
