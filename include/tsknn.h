@@ -123,7 +123,8 @@ typedef struct {
                                       seed set, and with surv_order 2
                                       survivors are processed in this order */
     int32_t use_graph;             /* 1: the call (one chunk of queries:
-                                      up to 2^28 / n_series of them) runs as
+                                      up to min(2^28 / n_series, 65535)
+                                      of them) runs as
                                       one captured HIP graph, cached on the
                                       index and replayed while the call
                                       repeats (same pointers, offsets, k,
@@ -209,7 +210,8 @@ typedef struct {
     int64_t size;                  /* sizeof(tsk_index_opts) */
     int64_t workspace_limit_bytes; /* bound on the workspace of a query call
                                       (0 = library default: chunks of up to
-                                      2^28 (query, series) pairs); calls
+                                      2^28 (query, series) pairs and 65535
+                                      queries); calls
                                       split their queries into chunks whose
                                       workspace fits (at least one query per
                                       chunk).  use_graph calls need one

@@ -832,7 +832,9 @@ static int prepare_qtables(tsk_index *ix, const int64_t *qoff_host, int64_t q0, 
 static int64_t chunk_queries(const tsk_index *ix, int64_t nq)
 {
     const int64_t budget = (int64_t)1 << 28; // (query, candidate) entries per chunk
-    int64_t q = budget / std::max<int64_t>(1, ix->n);
+    // at most 65535 queries: several kernels put the chunk's queries on the
+    // grid's y dimension
+    int64_t q = std::min<int64_t>(budget / std::max<int64_t>(1, ix->n), 65535);
     if (ix->ws_limit > 0) {
         // per query: bounds, survivors, fallback pairs and range hits per
         // series (20 bytes), the envelope and staged rows per point
