@@ -505,8 +505,8 @@ def main():
                          "dispatch that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
-                                   "(the multi-GPU sharding is described, not built)"}))
+        print(json.dumps({"error": "the scan runs on exactly one GPU; --gpus must be 1 "
+                                   "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     if args.tightness_sweep:
         print(json.dumps({"tightness_sweep": tightness_sweep()}), flush=True)
