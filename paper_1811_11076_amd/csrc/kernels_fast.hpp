@@ -620,9 +620,18 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
             for (int k = 0; k < W; ++k) {
                 const float *qr = qs + (lo + k) * DP;
                 float qq[D];
+                if (DP == 4) {
+                    // one 16-byte LDS read per row (rows are 16-byte aligned)
+                    const float4 r4 = *reinterpret_cast<const float4 *>(qr);
+                    const float rv[4] = {r4.x, r4.y, r4.z, r4.w};
 #pragma unroll
-                for (int e = 0; e < D; ++e)
-                    qq[e] = qr[e];
+                    for (int e = 0; e < D; ++e)
+                        qq[e] = rv[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < D; ++e)
+                        qq[e] = qr[e];
+                }
                 const float cst = point_cost<D>(qq, cv);
                 const float old = Dv[k];
                 const float v = fmaxf(cst, min3f(down, old, diag));
