@@ -620,17 +620,23 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
             for (int k = 0; k < W; ++k) {
                 const float *qr = qs + (lo + k) * DP;
                 float qq[D];
-                if (DP == 4) {
-                    // one 16-byte LDS read per row (rows are 16-byte aligned)
-                    const float4 r4 = *reinterpret_cast<const float4 *>(qr);
-                    const float rv[4] = {r4.x, r4.y, r4.z, r4.w};
+                {
+                    // whole rows with 16-byte LDS reads (rows are DP floats,
+                    // 16-byte aligned); scattered rows conflict less that way
+                    // than dword pairs that straddle rows
+                    const float4 *r4 = reinterpret_cast<const float4 *>(qr);
+                    float rv[DP];
+#pragma unroll
+                    for (int h = 0; h < DP / 4; ++h) {
+                        const float4 v = r4[h];
+                        rv[4 * h] = v.x;
+                        rv[4 * h + 1] = v.y;
+                        rv[4 * h + 2] = v.z;
+                        rv[4 * h + 3] = v.w;
+                    }
 #pragma unroll
                     for (int e = 0; e < D; ++e)
                         qq[e] = rv[e];
-                } else {
-#pragma unroll
-                    for (int e = 0; e < D; ++e)
-                        qq[e] = qr[e];
                 }
                 const float cst = point_cost<D>(qq, cv);
                 const float old = Dv[k];
