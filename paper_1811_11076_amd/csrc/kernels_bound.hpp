@@ -250,11 +250,16 @@ __global__ __launch_bounds__(256) void k_bound_lb(BoundArgs a, const float *__re
         return;
     }
     if (valid) {
+        // the group's thresholds first: independent loads, one latency
+        float tq[QG];
+#pragma unroll
+        for (int g = 0; g < QG; ++g)
+            tq[g] = g < nqg ? bits_f(load_relaxed_u32(a.tau + q0 + g)) : 0.0f;
 #pragma unroll
         for (int g = 0; g < QG; ++g) {
             if (g < nqg) {
                 const int q = q0 + g;
-                const bool keep = acc[g] <= bits_f(load_relaxed_u32(a.tau + q));
+                const bool keep = acc[g] <= tq[g];
                 a.lbv[(int64_t)q * a.N + c] = keep ? acc[g] : tsk_inf();
                 pruned += keep ? 0 : 1;
                 ++pairs;
@@ -440,7 +445,15 @@ __global__ __launch_bounds__(256) void k_corner(BoundArgs a)
         cl[k] = tb[((int64_t)(n - 1) * D + k) * 64];
     }
     unsigned long long pruned = 0;
-    for (int g = 0; g < nqg; ++g) {
+    // the group's thresholds first: independent loads, one latency
+    float tq[QG];
+#pragma unroll
+    for (int g = 0; g < QG; ++g)
+        tq[g] = g < nqg ? bits_f(load_relaxed_u32(a.tau + q0 + g)) : 0.0f;
+#pragma unroll
+    for (int g = 0; g < QG; ++g) {
+        if (g >= nqg)
+            break;
         const int q = q0 + g;
         const int64_t o0 = a.qoff[q], o1 = a.qoff[q + 1];
         cfloat *Q = (cfloat *)a.qv;
@@ -451,7 +464,7 @@ __global__ __launch_bounds__(256) void k_corner(BoundArgs a)
             qz[e] = Q[(o1 - 1) * D + e];
         }
         const float lb = fmaxf(point_cost<D>(qa, c0), point_cost<D>(qz, cl));
-        const bool keep = lb <= bits_f(load_relaxed_u32(a.tau + q));
+        const bool keep = lb <= tq[g];
         a.lbv[(int64_t)q * a.N + c] = keep ? lb : tsk_inf();
         pruned += keep ? 0 : 1;
     }

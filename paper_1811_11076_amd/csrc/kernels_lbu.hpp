@@ -179,11 +179,16 @@ __global__ __launch_bounds__(64) void k_bound_lbu(BoundArgs a, BucketArgs bk,
     }
     unsigned long long pruned = 0, pairs = 0;
     if (valid) {
+        // the group's thresholds first: independent loads, one latency
+        float tq[QG];
+#pragma unroll
+        for (int g = 0; g < QG; ++g)
+            tq[g] = g < nqg ? bits_f(load_relaxed_u32(a.tau + q0 + g)) : 0.0f;
 #pragma unroll
         for (int g = 0; g < QG; ++g) {
             if (g < nqg) {
                 const int q = q0 + g;
-                const bool keep = acc[g] <= bits_f(load_relaxed_u32(a.tau + q));
+                const bool keep = acc[g] <= tq[g];
                 a.lbv[(int64_t)q * a.N + pos] = keep ? acc[g] : tsk_inf();
                 pruned += keep ? 0 : 1;
                 ++pairs;
