@@ -35,13 +35,24 @@ __device__ __forceinline__ Band pair_band(const BandArgs &ba, int m, int n)
 }
 
 // Wave-wide sum of a per-lane counter, added once per wave.
-__device__ __forceinline__ void wave_count(unsigned long long *ctr, unsigned long long v)
+// Statistics counters (ctr[C_...]): a null base turns counting off (calls
+// that ask for neither stats nor a profile), sparing every wave its atomics
+// on the few shared counter words.
+__device__ __forceinline__ void wave_count(unsigned long long *ctr, int idx, unsigned long long v)
 {
+    if (ctr == nullptr)
+        return;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
         v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0 && v)
-        atomicAdd(ctr, v);
+        atomicAdd(ctr + idx, v);
+}
+
+__device__ __forceinline__ void ctr_add(unsigned long long *ctr, int idx, unsigned long long v)
+{
+    if (ctr != nullptr)
+        atomicAdd(ctr + idx, v);
 }
 
 __device__ __forceinline__ float wave_min(float v)
@@ -282,8 +293,8 @@ __global__ void k_seed(const float *__restrict__ qv, const int64_t *__restrict__
         steps_cnt = steps;
         pairs = 1;
     }
-    wave_count(ctr + C_BOUND_STEPS, steps_cnt);
-    wave_count(ctr + C_SEED_PAIRS, pairs);
+    wave_count(ctr, C_BOUND_STEPS, steps_cnt);
+    wave_count(ctr, C_SEED_PAIRS, pairs);
 }
 
 // ------------------------------------------------------------------ bound pass
@@ -438,10 +449,10 @@ __global__ __launch_bounds__(256) void k_bounds(BoundArgs a)
         }
     }
     if (!DEBUG) {
-        wave_count(a.ctr + C_BOUND_PRUNED, pruned);
-        wave_count(a.ctr + C_PAIRS, pairs);
+        wave_count(a.ctr, C_BOUND_PRUNED, pruned);
+        wave_count(a.ctr, C_PAIRS, pairs);
     }
-    wave_count(a.ctr + C_BOUND_STEPS, steps_cnt);
+    wave_count(a.ctr, C_BOUND_STEPS, steps_cnt);
 }
 
 // ------------------------------------------------------------------ compaction
@@ -501,7 +512,7 @@ static __global__ __launch_bounds__(256) void k_compact(const float *__restrict_
             base_s += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
         __syncthreads();
     }
-    wave_count(ctr + C_BOUND_PRUNED, late);
+    wave_count(ctr, C_BOUND_PRUNED, late);
     if (threadIdx.x == 0) {
         cnt[q] = base_s;
         atomicMax(max_cnt, base_s);
@@ -591,7 +602,7 @@ static __global__ __launch_bounds__(1024) void k_compact_sorted(
             surv[(int64_t)q * N + pos] = c;
         }
     }
-    wave_count(ctr + C_BOUND_PRUNED, late);
+    wave_count(ctr, C_BOUND_PRUNED, late);
     if (tid == 0) {
         int all = 0;
         for (int w = 0; w < 16; ++w)
@@ -923,20 +934,20 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
     }
     if (lane == 0) {
         if (cells)
-            atomicAdd(a.ctr + C_DP_CELLS, cells * 64ull);
+            ctr_add(a.ctr, C_DP_CELLS, cells * 64ull);
         if (valid) {
-            atomicAdd(a.ctr + C_VALID_CELLS, valid);
-            atomicAdd(a.ctr + C_VALID_GEN, valid);
+            ctr_add(a.ctr, C_VALID_CELLS, valid);
+            ctr_add(a.ctr, C_VALID_GEN, valid);
         }
         if (!ALLPAIRS) {
             if (started)
-                atomicAdd(a.ctr + C_DP_STARTED, started);
+                ctr_add(a.ctr, C_DP_STARTED, started);
             if (completed)
-                atomicAdd(a.ctr + C_DP_COMPLETED, completed);
+                ctr_add(a.ctr, C_DP_COMPLETED, completed);
             if (abandoned)
-                atomicAdd(a.ctr + C_DP_ABANDONED, abandoned);
+                ctr_add(a.ctr, C_DP_ABANDONED, abandoned);
             if (late)
-                atomicAdd(a.ctr + C_BOUND_PRUNED, late);
+                ctr_add(a.ctr, C_BOUND_PRUNED, late);
         }
     }
 }

@@ -266,9 +266,9 @@ __global__ __launch_bounds__(256) void k_bound_lb(BoundArgs a, const float *__re
             }
         }
     }
-    wave_count(a.ctr + C_BOUND_PRUNED, pruned);
-    wave_count(a.ctr + C_PAIRS, pairs);
-    wave_count(a.ctr + C_BOUND_STEPS, valid ? (unsigned long long)n * nqg : 0ull);
+    wave_count(a.ctr, C_BOUND_PRUNED, pruned);
+    wave_count(a.ctr, C_PAIRS, pairs);
+    wave_count(a.ctr, C_BOUND_STEPS, valid ? (unsigned long long)n * nqg : 0ull);
 }
 
 // Sum over the 16 lanes of a row through DPP adds: swap neighbours, swap
@@ -413,9 +413,9 @@ __global__ __launch_bounds__(256) void k_bound_lb_pp(BoundArgs a)
             next += __popcll(need);
         }
     }
-    wave_count(a.ctr + C_BOUND_PRUNED, pruned);
-    wave_count(a.ctr + C_PAIRS, pairs);
-    wave_count(a.ctr + C_BOUND_STEPS, terms);
+    wave_count(a.ctr, C_BOUND_PRUNED, pruned);
+    wave_count(a.ctr, C_PAIRS, pairs);
+    wave_count(a.ctr, C_BOUND_STEPS, terms);
 }
 
 // LDS of k_bound_lb_pp, and the largest the launcher uses it with.
@@ -468,8 +468,8 @@ __global__ __launch_bounds__(256) void k_corner(BoundArgs a)
         a.lbv[(int64_t)q * a.N + c] = keep ? lb : tsk_inf();
         pruned += keep ? 0 : 1;
     }
-    wave_count(a.ctr + C_BOUND_PRUNED, pruned);
-    wave_count(a.ctr + C_PAIRS, (unsigned long long)nqg);
+    wave_count(a.ctr, C_BOUND_PRUNED, pruned);
+    wave_count(a.ctr, C_PAIRS, (unsigned long long)nqg);
 }
 
 // DK greedy pass over the compacted survivors (Sec. 4.4, first loop): a wave
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(64) void k_walk_dk(FastArgs a, const float *__restr
         wave_topk_insert(ubslots + (int64_t)q * a.k, a.k, want,
                          make_key(g, (uint32_t)(ch.act ? ch.c : 0)), a.tau + q);
     }
-    wave_count(a.ctr + C_BOUND_STEPS, steps_cnt);
+    wave_count(a.ctr, C_BOUND_STEPS, steps_cnt);
 }
 
 // DTW threshold seed for equal lengths: the diagonal path (i, i) is a
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(64) void k_seed_diag(const float *__restrict__ qv,
         ub = DIST == DIST_DK ? fmaxf(cst, ub) : cst + ub;
     }
     wave_topk_insert(seedslots + (int64_t)q * k, k, ok, make_key(ub, (uint32_t)c), tau + q);
-    wave_count(ctr + C_SEED_PAIRS, ok ? 1ull : 0ull);
+    wave_count(ctr, C_SEED_PAIRS, ok ? 1ull : 0ull);
 }
 
 // Threshold seed with the LDS query and the prefetching walk (see k_seed).
@@ -620,8 +620,8 @@ __global__ __launch_bounds__(64) void k_seed_ring(const float *__restrict__ qv,
     if (dbg_ub)
         return;
     wave_topk_insert(seedslots + (int64_t)q * k, k, want, make_key(g, (uint32_t)c), tau + q);
-    wave_count(ctr + C_BOUND_STEPS, steps_cnt);
-    wave_count(ctr + C_SEED_PAIRS, pairs);
+    wave_count(ctr, C_BOUND_STEPS, steps_cnt);
+    wave_count(ctr, C_SEED_PAIRS, pairs);
 }
 
 // ------------------------------------------------------------------ LB_Box, both orientations

@@ -502,14 +502,14 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
             finish_lane(a, q, ch.c, res, completed);
         }
     }
-    wave_count(a.ctr + C_DP_STARTED, started);
-    wave_count(a.ctr + C_DP_COMPLETED, completed);
-    wave_count(a.ctr + C_DP_ABANDONED, abandoned);
-    wave_count(a.ctr + C_BOUND_PRUNED, late);
-    wave_count(a.ctr + C_FALLBACK, fallback);
+    wave_count(a.ctr, C_DP_STARTED, started);
+    wave_count(a.ctr, C_DP_COMPLETED, completed);
+    wave_count(a.ctr, C_DP_ABANDONED, abandoned);
+    wave_count(a.ctr, C_BOUND_PRUNED, late);
+    wave_count(a.ctr, C_FALLBACK, fallback);
     if (threadIdx.x == 0) {
-        atomicAdd(a.ctr + C_DP_CELLS, cells * 64ull);
-        atomicAdd(a.ctr + C_VALID_CELLS, valid);
+        ctr_add(a.ctr, C_DP_CELLS, cells * 64ull);
+        ctr_add(a.ctr, C_VALID_CELLS, valid);
     }
 }
 
@@ -682,14 +682,14 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
             j += running ? 1 : 0;
         }
     }
-    wave_count(a.ctr + C_DP_STARTED, started);
-    wave_count(a.ctr + C_DP_COMPLETED, completed);
-    wave_count(a.ctr + C_DP_ABANDONED, abandoned);
-    wave_count(a.ctr + C_BOUND_PRUNED, late);
-    wave_count(a.ctr + C_FALLBACK, fallback);
+    wave_count(a.ctr, C_DP_STARTED, started);
+    wave_count(a.ctr, C_DP_COMPLETED, completed);
+    wave_count(a.ctr, C_DP_ABANDONED, abandoned);
+    wave_count(a.ctr, C_BOUND_PRUNED, late);
+    wave_count(a.ctr, C_FALLBACK, fallback);
     if (threadIdx.x == 0) {
-        atomicAdd(a.ctr + C_DP_CELLS, cells * 64ull);
-        atomicAdd(a.ctr + C_VALID_CELLS, valid);
+        ctr_add(a.ctr, C_DP_CELLS, cells * 64ull);
+        ctr_add(a.ctr, C_VALID_CELLS, valid);
     }
 }
 

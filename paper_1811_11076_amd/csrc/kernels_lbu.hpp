@@ -195,9 +195,9 @@ __global__ __launch_bounds__(64) void k_bound_lbu(BoundArgs a, BucketArgs bk,
             }
         }
     }
-    wave_count(a.ctr + C_BOUND_PRUNED, pruned);
-    wave_count(a.ctr + C_PAIRS, pairs);
-    wave_count(a.ctr + C_BOUND_STEPS, valid ? (unsigned long long)n * nqg : 0ull);
+    wave_count(a.ctr, C_BOUND_PRUNED, pruned);
+    wave_count(a.ctr, C_PAIRS, pairs);
+    wave_count(a.ctr, C_BOUND_STEPS, valid ? (unsigned long long)n * nqg : 0ull);
 }
 
 // SoA packing of the length buckets: block t fills tile t.

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_sub_rowmin(SubArgs a)
         atomicMin(a.pclb + (int64_t)it.q * a.N + it.c, f_bits(g));
     }
     if (scans)
-        atomicAdd(a.ctr + C_BOUND_STEPS, scans);
+        ctr_add(a.ctr, C_BOUND_STEPS, scans);
 }
 
 // Greedy bound (Alg. 2), one thread per item, walking from the item's
@@ -206,9 +206,9 @@ __global__ __launch_bounds__(256) void k_sub_walk(SubArgs a, int pass)
         }
     }
     if (moves)
-        atomicAdd(a.ctr + C_BOUND_STEPS, moves);
+        ctr_add(a.ctr, C_BOUND_STEPS, moves);
     if (done)
-        atomicAdd(a.ctr + C_SEED_PAIRS, done);
+        ctr_add(a.ctr, C_SEED_PAIRS, done);
 }
 
 // Pair bounds -> the query's seed slots (k smallest, distinct series) and
@@ -416,7 +416,7 @@ static __global__ __launch_bounds__(256) void k_sub_compact(SubArgs a)
         }
     }
     if (dropped)
-        atomicAdd(a.ctr + C_BOUND_PRUNED, dropped);
+        ctr_add(a.ctr, C_BOUND_PRUNED, dropped);
 }
 
 // The DP over the live items: persistent waves take items from a counter
@@ -481,17 +481,17 @@ __global__ __launch_bounds__(256) void k_sub_dp(SubArgs a)
     }
     if (lane == 0) {
         if (cells)
-            atomicAdd(a.ctr + C_DP_CELLS, cells * 64ull);
+            ctr_add(a.ctr, C_DP_CELLS, cells * 64ull);
         if (valid)
-            atomicAdd(a.ctr + C_VALID_CELLS, valid);
+            ctr_add(a.ctr, C_VALID_CELLS, valid);
         if (scanned)
-            atomicAdd(a.ctr + C_BOUND_STEPS, scanned);
+            ctr_add(a.ctr, C_BOUND_STEPS, scanned);
         if (started)
-            atomicAdd(a.ctr + C_DP_STARTED, started);
+            ctr_add(a.ctr, C_DP_STARTED, started);
         if (hits)
-            atomicAdd(a.ctr + C_DP_COMPLETED, hits);
+            ctr_add(a.ctr, C_DP_COMPLETED, hits);
         if (none)
-            atomicAdd(a.ctr + C_DP_ABANDONED, none);
+            ctr_add(a.ctr, C_DP_ABANDONED, none);
     }
 }
 
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void k_sub_start(SubArgs a)
             a.out_start[t] = (bcol >= 0 && best == kv) ? e - bcol : -1;
     }
     if ((threadIdx.x & 63) == 0 && cells)
-        atomicAdd(a.ctr + C_DP_CELLS, cells * 64ull);
+        ctr_add(a.ctr, C_DP_CELLS, cells * 64ull);
 }
 
 } // namespace tsk

@@ -978,6 +978,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
 
     const bool profile = o.profile != 0;
     const bool timed = stats_host != nullptr || profile;
+    // statistics counters only when a call reports them
+    unsigned long long *const ctr = timed ? W.ctr.p : nullptr;
     if (profile)
         TSK_TRY(ix->prof_ctr.ensure(C_NUM));
     const size_t ev_first = ix->ev_used;
@@ -1072,7 +1074,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         if (P.env_ok)
             dispatch_d<EnvLaunch>(P.D, ix, qv, nq, P.ba, s);
         SeedRingArgs seed_args{qv, W.qoff.p, nq, c.qmax, ix->aos, ix->off, ix->len, ix->n,
-                               c.order, 0, P.seed, k, P.ba, W.seedslots.p, W.tau.p, W.ctr.p,
+                               c.order, 0, P.seed, k, P.ba, W.seedslots.p, W.tau.p, ctr,
                                nullptr, nullptr};
         if (c.diag_seed) {
             // equal lengths: diagonal-path sums seed the DTW threshold
@@ -1086,6 +1088,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         }
         TSK_MARK(2);
         BoundArgs ba = bound_args(ix, qv, nq, P);
+        ba.ctr = ctr;
         if (rr)
             ba.ubslots = nullptr;
         if (c.dk_split) {
@@ -1115,11 +1118,11 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
                                SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,
                                c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr, W.tau.p,
-                               W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
+                               W.surv.p, W.surv_cnt.p, W.max_cnt.p, ctr);
         else
             hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, c.order,
                                c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr, W.tau.p,
-                               W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.ctr.p);
+                               W.surv.p, W.surv_cnt.p, W.max_cnt.p, ctr);
         if (lb_rev) {
             // LB_Box in both orientations: the survivors' bounds become the
             // larger one (queries of another length keep theirs)
@@ -1132,11 +1135,13 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         if (c.dk_split && o.walk_pass == 1) {
             // greedy bound (Alg. 1) of every survivor of the corner bound
             FastArgs wa = fast_args(ix, nq, P, 0);
+            wa.ctr = ctr;
             wa.work = W.work.p + 4;
             launch_walk_dk(P.D, wa, qv, W.ubslots.p, ix->n_cu * 8, c.qmax, s);
         }
         TSK_MARK(4);
         DpArgs da = dp_args(ix, qv, nq, P);
+        da.ctr = ctr;
         da.lb_inv = c.lbu ? ix->inv : nullptr;
         da.range_out = rr ? W.rng.p : nullptr;
         if (o.dp_rows != 0)
@@ -1145,6 +1150,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             dispatch_d<QpadLaunch>(P.D, qv, W.qoff.p, nq, c.qrows, W.qpad.p, s);
             TSK_MARK(5);
             FastArgs fa = fast_args(ix, nq, P, c.qrows);
+            fa.ctr = ctr;
             fa.lb_inv = c.lbu ? ix->inv : nullptr;
             fa.range_out = rr ? W.rng.p : nullptr;
             if (c.fast == FAST_TUBE32) {
@@ -1195,7 +1201,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                                     o.order, (int64_t)(uintptr_t)o.order_dev, o.seed_count,
                                     o.dp_kernel, o.walk_pass, o.task_size, o.tube_rows,
                                     o.lb_qgroup, o.dk_band_slots, o.surv_order, o.dp_rows,
-                                    o.dp_waves_per_cu, o.dk_seed, o.lb_both};
+                                    o.dp_waves_per_cu, o.dk_seed, o.lb_both,
+                                    (int64_t)timed};
         // every workspace buffer the captured kernels address: a buffer
         // reallocated by another call changes the key
         for (const void *ptr :
