@@ -64,6 +64,13 @@ def _load():
         "orc_knn_scan": (None, [_f32p, _i64p, _i64, _f32p, _i64p, _i64, ctypes.c_int, _i64,
                                 ctypes.c_int, ctypes.c_int, _i64, ctypes.c_float, _i64p, _f32p,
                                 _i64p]),
+        "orc_knn_verify": (None, [_f32p, _i64p, _i64, _f32p, _i64p, _i64, ctypes.c_int, _i64,
+                                  ctypes.c_int, ctypes.c_int, _i64, ctypes.c_float, _i64p, _f32p,
+                                  _i64p]),
+        "orc_pair_list_keys": (None, [_f32p, _i64p, _f32p, _i64p, ctypes.c_int, _i64, _i64p,
+                                      _i64p, ctypes.c_int, ctypes.c_int, _i64, ctypes.c_float,
+                                      _f32p]),
+        "orc_qenv": (None, [_f32p, _i64, _i64, ctypes.c_int, _i64, _f32p, _f32p]),
         "orc_pair_keys": (None, [_f32p, _i64p, _i64, _f32p, _i64p, _i64, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, _i64, ctypes.c_float, _f32p]),
         "orc_set_threads": (ctypes.c_int, [ctypes.c_int]),
@@ -263,10 +270,48 @@ def knn_brute(db, db_off, qs, q_off, k, dist="dk", band=None):
 
 
 def knn_scan(db, db_off, qs, q_off, k, dist="dk", band=None):
-    """The paper's pruned scan (Sec. 4.4 for DK, LB_Box + DTW otherwise).
+    """The paper's pruned scan (Sec. 4.3 for DK, LB_Box + DTW otherwise).
 
     Returns (ids, keys, stats[nq, 4] = pruned, DP started, DP finite, cells)."""
     return _knn_common(_load().orc_knn_scan, db, db_off, qs, q_off, k, dist, band, True)
+
+
+def knn_verify(db, db_off, qs, q_off, k, dist="dk", band=None):
+    """The pruned scan of knn_scan with each query's envelope kept per
+    candidate length (same values, far less work at full size).
+
+    Returns (ids, keys, stats) as knn_scan."""
+    return _knn_common(_load().orc_knn_verify, db, db_off, qs, q_off, k, dist, band, True)
+
+
+def pair_list_keys(db, db_off, qs, q_off, qi, ci, dist="dk", band=None):
+    """Full-DP keys of the pairs (qi[p], ci[p]) -> float32 [len(qi)]."""
+    db, dbp = _f32(db)
+    db_off, dop = _i64a(db_off)
+    qs, qp = _f32(qs)
+    q_off, qop = _i64a(q_off)
+    qi, qip = _i64a(qi)
+    ci, cip = _i64a(ci)
+    assert qi.shape == ci.shape
+    out = np.zeros(qi.shape[0], np.float32)
+    mode, r, frac = _band_args(band)
+    _load().orc_pair_list_keys(dbp, dop, qp, qop, db.shape[1], qi.shape[0], qip, cip,
+                               DK if dist == "dk" else DTW, mode, r, ctypes.c_float(frac),
+                               out.ctypes.data_as(_f32p))
+    return out
+
+
+def qenv(S, n: int, w=-1):
+    """Envelope of the query S for the columns of a candidate of length n:
+    (lo, hi), each float32 [n, d]."""
+    S = _series(S)
+    m, d = S.shape
+    lo = np.zeros((n, d), np.float32)
+    hi = np.zeros((n, d), np.float32)
+    _, sp = _f32(S)
+    _load().orc_qenv(sp, m, n, d, band_w(w, m, n) if isinstance(w, float) else w,
+                     lo.ctypes.data_as(_f32p), hi.ctypes.data_as(_f32p))
+    return lo, hi
 
 
 def pair_keys(db, db_off, qs, q_off, dist="dk", band=None):

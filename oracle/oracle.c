@@ -40,7 +40,7 @@
  *           reads D after it was reset).
  *   R-lb    LB terms are summed sequentially, in series order, in fp32.
  *   R-knn   k-NN order is (key, id) ascending; the k-NN threshold for DK is
- *           the k-th smallest greedy bound (Sec. 4.4 states the 1-NN case).
+ *           the k-th smallest greedy bound (Sec. 4.3 states the 1-NN case).
  */
 #include <math.h>
 #include <stdint.h>
@@ -66,6 +66,8 @@ int orc_set_threads(int n)
 }
 
 #define ORC_INF INFINITY
+/* longest series the envelope cache of orc_knn_verify keys by length */
+#define ORC_MAX_LEN 4096
 
 #if defined(__x86_64__)
 #define ORC_CLONES __attribute__((target_clones("fma", "default")))
@@ -714,15 +716,12 @@ static float orc_dtw_abandon_f32(const float *S, int64_t m, const float *T, int6
     return r;
 }
 
-/* LB_Box with the envelope of the query S around each point of the
- * candidate T: sum over the candidate's points t_j of the squared distance to
- * the box of S over the rows i that the band lets column j align with.  This
- * is LB_Box(T, S) of eq. (1) with the roles of the series exchanged; fp32 in
- * candidate order (R-lb). */
-float orc_lb_box_qenv_f32(const float *S, int64_t m, const float *T, int64_t n, int d, int64_t w)
+/* Envelope of the query S (m rows) for the columns of a candidate of length
+ * n: for column j, the per-dimension [min, max] of the rows i that the band
+ * lets j align with (the transposed band test of Sec. 2.3's windows).
+ * lo, hi: [n][d]; an empty window gives lo = +inf, hi = -inf. */
+void orc_qenv(const float *S, int64_t m, int64_t n, int d, int64_t w, float *lo, float *hi)
 {
-    /* the envelope of S for the rows of T uses the transposed band test */
-    float *lo = malloc(sizeof(float) * n * d), *hi = malloc(sizeof(float) * n * d);
     for (int64_t j = 0; j < n; ++j) {
         for (int k = 0; k < d; ++k) { lo[j * d + k] = ORC_INF; hi[j * d + k] = -ORC_INF; }
         for (int64_t i = 0; i < m; ++i) {
@@ -734,15 +733,36 @@ float orc_lb_box_qenv_f32(const float *S, int64_t m, const float *T, int64_t n, 
             }
         }
     }
+}
+
+/* Sum over the candidate's points t_j of the squared distance to the query
+ * envelope's box of column j (lo, hi from orc_qenv), fp32 in candidate order
+ * (R-lb). */
+static float orc_lb_box_qenv_sum_f32(const float *T, int64_t n, int d, const float *lo,
+                                     const float *hi)
+{
     float acc = 0.0f;
     for (int64_t j = 0; j < n; ++j)
         acc = orc_box_term_f32(T + j * d, lo + j * d, hi + j * d, d) + acc;
+    return acc;
+}
+
+/* LB_Box with the envelope of the query S around each point of the
+ * candidate T: sum over the candidate's points t_j of the squared distance to
+ * the box of S over the rows i that the band lets column j align with.  This
+ * is LB_Box(T, S) of eq. (1) with the roles of the series exchanged; fp32 in
+ * candidate order (R-lb). */
+float orc_lb_box_qenv_f32(const float *S, int64_t m, const float *T, int64_t n, int d, int64_t w)
+{
+    float *lo = malloc(sizeof(float) * n * d), *hi = malloc(sizeof(float) * n * d);
+    orc_qenv(S, m, n, d, w, lo, hi);
+    float acc = orc_lb_box_qenv_sum_f32(T, n, d, lo, hi);
     free(lo); free(hi);
     return acc;
 }
 
 /* Paper-faithful pruned scan, one query at a time in candidate-id order.
- *   DK  (Sec. 4.4): a first pass computes the greedy bound (Alg. 1) of every
+ *   DK  (Sec. 4.3): a first pass computes the greedy bound (Alg. 1) of every
  *       candidate with early return against the running k-th smallest bound;
  *       its k-th smallest value is the threshold; a second pass runs the
  *       sparse DK (Alg. 3) of every candidate against the current threshold,
@@ -752,15 +772,19 @@ float orc_lb_box_qenv_f32(const float *S, int64_t m, const float *T, int64_t n, 
  *       abandoning runs and the k best are kept.
  * Output as orc_knn_brute.  stats (nullable, 4 int64 per query):
  *   [pruned by the bound, DP started, DP completed (finite), cells visited]. */
-void orc_knn_scan(const float *db, const int64_t *db_off, int64_t N,
-                  const float *qs, const int64_t *q_off, int64_t nq, int d,
-                  int64_t k, int dist, int band_mode, int64_t band_r, float band_frac,
-                  int64_t *out_ids, float *out_keys, int64_t *stats)
+static void orc_knn_scan_impl(const float *db, const int64_t *db_off, int64_t N,
+                              const float *qs, const int64_t *q_off, int64_t nq, int d,
+                              int64_t k, int dist, int band_mode, int64_t band_r,
+                              float band_frac, int64_t *out_ids, float *out_keys,
+                              int64_t *stats, int keep_env)
 {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t q = 0; q < nq; ++q) {
         const float *S = qs + q_off[q] * d;
         int64_t m = q_off[q + 1] - q_off[q];
+        /* keep_env: the query's envelope for a candidate length, built on
+         * first use and kept (index = length) instead of rebuilt per pair */
+        float **env = keep_env ? calloc(ORC_MAX_LEN + 1, sizeof(float *)) : NULL;
         orc_kv *top = malloc(sizeof(orc_kv) * k);
         int64_t cnt = 0, pruned = 0, started = 0, completed = 0, cells = 0;
         float tau = ORC_INF;
@@ -798,7 +822,16 @@ void orc_knn_scan(const float *db, const int64_t *db_off, int64_t N,
                 int64_t n = db_off[c + 1] - db_off[c];
                 int64_t w = orc_pair_w(band_mode, band_r, band_frac, m, n);
                 const float *T = db + db_off[c] * d;
-                float lb = orc_lb_box_qenv_f32(S, m, T, n, d, w);
+                float lb;
+                if (env && n <= ORC_MAX_LEN) {
+                    if (!env[n]) {
+                        env[n] = malloc(sizeof(float) * 2 * n * d);
+                        orc_qenv(S, m, n, d, w, env[n], env[n] + n * d);
+                    }
+                    lb = orc_lb_box_qenv_sum_f32(T, n, d, env[n], env[n] + n * d);
+                } else {
+                    lb = orc_lb_box_qenv_f32(S, m, T, n, d, w);
+                }
                 if (lb > tau) { ++pruned; continue; }
                 ++started;
                 float v = orc_dtw_abandon_f32(S, m, T, n, d, w, tau, &cells);
@@ -819,11 +852,53 @@ void orc_knn_scan(const float *db, const int64_t *db_off, int64_t N,
             stats[q * 4 + 2] = completed; stats[q * 4 + 3] = cells;
         }
         free(top);
+        if (env) {
+            for (int64_t L = 0; L <= ORC_MAX_LEN; ++L) free(env[L]);
+            free(env);
+        }
+    }
+}
+
+void orc_knn_scan(const float *db, const int64_t *db_off, int64_t N,
+                  const float *qs, const int64_t *q_off, int64_t nq, int d,
+                  int64_t k, int dist, int band_mode, int64_t band_r, float band_frac,
+                  int64_t *out_ids, float *out_keys, int64_t *stats)
+{
+    orc_knn_scan_impl(db, db_off, N, qs, q_off, nq, d, k, dist, band_mode, band_r, band_frac,
+                      out_ids, out_keys, stats, 0);
+}
+
+/* The same scan with each query's envelope built once per candidate length
+ * (the DTW bound's values are unchanged: the same envelope, the same sums).
+ * Used to check full-size results, where rebuilding the envelope for every
+ * pair would take hours. */
+void orc_knn_verify(const float *db, const int64_t *db_off, int64_t N,
+                    const float *qs, const int64_t *q_off, int64_t nq, int d,
+                    int64_t k, int dist, int band_mode, int64_t band_r, float band_frac,
+                    int64_t *out_ids, float *out_keys, int64_t *stats)
+{
+    orc_knn_scan_impl(db, db_off, N, qs, q_off, nq, d, k, dist, band_mode, band_r, band_frac,
+                      out_ids, out_keys, stats, 1);
+}
+
+/* Full-DP keys of a list of (query, candidate) pairs: out[p] = key of
+ * (qi[p], ci[p]) (DTW sum or squared DK), in parallel over the list. */
+void orc_pair_list_keys(const float *db, const int64_t *db_off, const float *qs,
+                        const int64_t *q_off, int d, int64_t n_pairs, const int64_t *qi,
+                        const int64_t *ci, int dist, int band_mode, int64_t band_r,
+                        float band_frac, float *out)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const int64_t q = qi[p], c = ci[p];
+        int64_t m = q_off[q + 1] - q_off[q], n = db_off[c + 1] - db_off[c];
+        int64_t w = orc_pair_w(band_mode, band_r, band_frac, m, n);
+        out[p] = orc_pair_key(dist, qs + q_off[q] * d, m, db + db_off[c] * d, n, d, w);
     }
 }
 
 /* ================================================================ subsequence search
- * Sec. 4.2-4.3: a match may start and end anywhere in the long series T
+ * Sec. 4.1-4.2: a match may start and end anywhere in the long series T
  * (the query S is matched against a contiguous part T[a..b]).  The
  * subsequence DK of (S, T) is min over 0 <= a <= b < n of DK(S, T[a..b]);
  * its end is the first column b at which that minimum is reached, its start
@@ -1026,7 +1101,7 @@ void orc_subseq_knn(const float *ser, const int64_t *s_off, int64_t N, const flo
     }
 }
 
-/* The paper's pruned subsequence scan (Sec. 4.4 with the SUB variants):
+/* The paper's pruned subsequence scan (Sec. 4.3 with the SUB variants):
  * threshold = k-th smallest Alg. 2 bound over the series, then Alg. 3 with
  * SUB per series in id order, the threshold falling to the k-th best value
  * found.  Same outputs as orc_subseq_knn; stats[q] = visited cells. */

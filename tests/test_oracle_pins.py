@@ -368,7 +368,7 @@ def _db(rng, N, lens, d):
 @pytest.mark.parametrize("dist,band", [("dk", None), ("dtw", None), ("dtw", 3), ("dtw", 0.15),
                                        ("dk", 0.2)])
 def test_knn_scan_equals_brute(rng, dist, band):
-    """The paper's pruned scan (Sec. 4.4 / LB_Box + DTW) equals the plain
+    """The paper's pruned scan (Sec. 4.3 / LB_Box + DTW) equals the plain
     definition: full DP for every pair and a (distance, id) sort."""
     db, dbo = _db(rng, 300, (5, 40), 3)
     qs, qo = _db(rng, 7, (5, 40), 3)
@@ -379,6 +379,50 @@ def test_knn_scan_equals_brute(rng, dist, band):
         assert np.array_equal(keys_b, keys_s)
         if dist == "dtw" and band is not None:
             assert st[:, 0].sum() > 0  # LB_Box prunes something
+
+
+@pytest.mark.parametrize("dist,band", [("dk", None), ("dtw", None), ("dtw", 3), ("dtw", 0.15),
+                                       ("dk", 0.2)])
+def test_knn_verify_equals_brute(rng, dist, band):
+    """The full-size check (the pruned scan with each query's envelope kept
+    per candidate length) equals the plain definition, on uneven lengths
+    (many envelope lengths) and equal lengths (one)."""
+    for lens in ((5, 40), (24, 24)):
+        db, dbo = _db(rng, 300, lens, 3)
+        qs, qo = _db(rng, 7, lens, 3)
+        for k in (1, 5, 17):
+            ids_b, keys_b = O.knn_brute(db, dbo, qs, qo, k, dist, band)
+            ids_v, keys_v, _ = O.knn_verify(db, dbo, qs, qo, k, dist, band)
+            assert np.array_equal(ids_b, ids_v)
+            assert np.array_equal(keys_b, keys_v)
+
+
+def test_query_envelope_bruteforce(rng):
+    """orc_qenv: for column j of a candidate of length n, the per-dimension
+    min / max of the query rows the band lets j align with."""
+    for _ in range(20):
+        n = int(rng.integers(1, 30))
+        m = int(rng.integers(1, 30))
+        w = int(rng.integers(-1, 5))
+        S = rng.normal(size=(m, 2)).astype(np.float32)
+        lo, hi = O.qenv(S, n, w)
+        for j in range(n):
+            rows = [i for i in range(m) if O.band_ok(i, j, m, n, w)]
+            if rows:
+                assert np.array_equal(lo[j], S[rows].min(0)) and np.array_equal(hi[j], S[rows].max(0))
+            else:
+                assert np.all(lo[j] == INF) and np.all(hi[j] == -INF)
+
+
+def test_pair_list_keys_equal_all_pairs(rng):
+    db, dbo = _db(rng, 40, (3, 30), 2)
+    qs, qo = _db(rng, 5, (3, 30), 2)
+    for dist, band in (("dk", None), ("dtw", 0.2), ("dtw", 2)):
+        allk = O.pair_keys(db, dbo, qs, qo, dist, band)
+        qi = rng.integers(0, 5, size=64)
+        ci = rng.integers(0, 40, size=64)
+        got = O.pair_list_keys(db, dbo, qs, qo, qi, ci, dist, band)
+        assert np.array_equal(got, allk[qi, ci])
 
 
 def test_knn_ties_and_padding():
