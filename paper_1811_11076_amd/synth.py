@@ -73,9 +73,16 @@ def _interp(protos: np.ndarray, cls: np.ndarray, pos: np.ndarray) -> np.ndarray:
     p0 = np.clip(np.floor(pos).astype(np.int64), 0, proto_len - 1)
     p1 = np.minimum(p0 + 1, proto_len - 1)
     f = (pos - p0)[..., None]
-    a = protos[cls[:, None], p0]
-    b = protos[cls[:, None], p1]
+    flat = protos.reshape(-1, protos.shape[2])
+    base = (np.asarray(cls, np.int64) * proto_len)[:, None]
+    a = np.take(flat, base + p0, axis=0)
+    b = np.take(flat, base + p1, axis=0)
     return a + (b - a) * f
+
+
+def _workers() -> int:
+    import os
+    return max(1, min(16, os.cpu_count() or 1))
 
 
 class ClassWarp:
@@ -90,6 +97,22 @@ class ClassWarp:
         steps = rng.standard_normal((n_classes, proto_len, d))
         self.protos = np.cumsum(steps, axis=1)  # float64
 
+    def _chunk_draws(self, ch: int, stream: str, length, class_mode: str):
+        """The chunk's draws in their fixed order: lengths, classes, warp
+        slopes, then the seed of its noise stream."""
+        rng = _rng(self.cfg_id, stream, ch)
+        if isinstance(length, tuple):
+            lens = rng.integers(length[0], length[1] + 1, size=CHUNK)
+        else:
+            lens = np.full(CHUNK, int(length))
+        if class_mode == "uniform":
+            cls = rng.integers(0, self.n_classes, size=CHUNK)
+        else:
+            cls = np.arange(ch * CHUNK, (ch + 1) * CHUNK) % self.n_classes
+        slopes = rng.uniform(SLOPE_LO, SLOPE_HI, size=(CHUNK, N_SEGMENTS))
+        noise_seed = rng.integers(0, 2**63 - 1)
+        return lens, cls, slopes, noise_seed
+
     def members(self, n: int, stream: str, start: int = 0,
                 length: int | tuple[int, int] = 256, class_mode: str = "mod"):
         """Members start..start+n-1 of a stream.
@@ -97,28 +120,37 @@ class ClassWarp:
         length: an int (all equal) or (lo, hi) for lengths uniform in {lo..hi}.
         class_mode: "mod" (class = index mod C) or "uniform" (drawn).
         Returns (values float32 [sum(len), d], offsets int64 [n+1], labels int64 [n]).
+        Chunks are generated in worker threads (numpy releases the GIL); every
+        value depends only on its chunk's seed, so the result is the same for
+        any number of workers.
         """
-        chunks = []
-        lens_all = []
-        labels_all = []
+        from concurrent.futures import ThreadPoolExecutor
         first_chunk = start // CHUNK
         last_chunk = (start + n - 1) // CHUNK if n > 0 else first_chunk - 1
-        for ch in range(first_chunk, last_chunk + 1):
-            rng = _rng(self.cfg_id, stream, ch)
-            idx = np.arange(ch * CHUNK, (ch + 1) * CHUNK)
-            if isinstance(length, tuple):
-                lens = rng.integers(length[0], length[1] + 1, size=CHUNK)
-            else:
-                lens = np.full(CHUNK, int(length))
-            if class_mode == "uniform":
-                cls = rng.integers(0, self.n_classes, size=CHUNK)
-            else:
-                cls = idx % self.n_classes
-            slopes = rng.uniform(SLOPE_LO, SLOPE_HI, size=(CHUNK, N_SEGMENTS))
-            noise_seed = rng.integers(0, 2**63 - 1)
+        chunks = list(range(first_chunk, last_chunk + 1))
+
+        def span(ch):
             lo = max(start, ch * CHUNK)
             hi = min(start + n, (ch + 1) * CHUNK)
-            sel = slice(lo - ch * CHUNK, hi - ch * CHUNK)
+            return slice(lo - ch * CHUNK, hi - ch * CHUNK), lo - start
+
+        # pass 1: lengths and classes of every member (cheap draws)
+        lens_all, labels_all = [], []
+        for ch in chunks:
+            lens, cls, _, _ = self._chunk_draws(ch, stream, length, class_mode)
+            sel, _ = span(ch)
+            lens_all.append(lens[sel])
+            labels_all.append(cls[sel])
+        lens_all = np.concatenate(lens_all) if lens_all else np.zeros(0, np.int64)
+        labels = np.concatenate(labels_all) if labels_all else np.zeros(0, np.int64)
+        offsets = np.zeros(n + 1, dtype=np.int64)
+        offsets[1:] = np.cumsum(lens_all)
+        values = np.empty((int(offsets[-1]), self.d), dtype=np.float32)
+
+        # pass 2: each chunk's values, written in place
+        def fill(ch):
+            lens, cls, slopes, noise_seed = self._chunk_draws(ch, stream, length, class_mode)
+            sel, out0 = span(ch)
             nrng = np.random.Generator(np.random.PCG64(noise_seed))
             lens_c, cls_c, slopes_c = lens[sel], cls[sel], slopes[sel]
             # noise for the whole chunk is drawn in one fixed order, then sliced
@@ -131,19 +163,16 @@ class ClassWarp:
                 vals = _interp(self.protos, cls_c[rows], pos)
                 r_chunk = rows + sel.start
                 gather = noff[r_chunk][:, None] + np.arange(int(ulen))[None, :]
-                vals += noise[gather]
-                chunks.append((rows + (lo - start), vals))
-            lens_all.append(lens_c)
-            labels_all.append(cls_c)
-        lens_all = np.concatenate(lens_all) if lens_all else np.zeros(0, np.int64)
-        labels = np.concatenate(labels_all) if labels_all else np.zeros(0, np.int64)
-        offsets = np.zeros(n + 1, dtype=np.int64)
-        offsets[1:] = np.cumsum(lens_all)
-        values = np.empty((int(offsets[-1]), self.d), dtype=np.float32)
-        for rows, vals in chunks:
-            ulen = vals.shape[1]
-            gather = offsets[rows][:, None] + np.arange(ulen)[None, :]
-            values[gather] = vals
+                vals += np.take(noise, gather, axis=0)
+                dst = offsets[rows + out0][:, None] + np.arange(int(ulen))[None, :]
+                values[dst] = vals
+
+        if len(chunks) > 1:
+            with ThreadPoolExecutor(max_workers=min(_workers(), len(chunks))) as ex:
+                list(ex.map(fill, chunks))
+        else:
+            for ch in chunks:
+                fill(ch)
         return values, offsets, labels.astype(np.int64)
 
 
@@ -155,7 +184,7 @@ def flat_equal(arr: np.ndarray):
 
 
 # ---------------------------------------------------------------- long series and planted queries
-# Subsequence search (Sec. 4.2-4.3 and the long-series experiment of Sec. 5)
+# Subsequence search (Sec. 4.1-4.2 and the long-series experiment of Sec. 5)
 # queries short series against long ones; these stand in for the long ECG
 # recording.
 
