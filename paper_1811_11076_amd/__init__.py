@@ -108,7 +108,8 @@ class Index:
             walk_pass: int = -1, task_size: int = 0, tube_rows: int = 0, model=None,
             lb_qgroup: int = 0, use_graph: bool = False, tune: bool = False, out=None,
             dk_band_slots: int = 0, surv_order: int = 0, dp_rows: int = 0,
-            dp_waves_per_cu: int = 0, dk_seed: int = 0, cancel=None, lb_both: bool = False):
+            dp_waves_per_cu: int = 0, dk_seed: int = 0, cancel=None, lb_both: bool = False,
+            raw_keys: bool = False):
         """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
         float32 [nq, k], stats dict or None); DK distances are unsquared.
         order: None (plain), a CUDA int32 [nq, n] permutation per query, or
@@ -119,7 +120,8 @@ class Index:
         set non-zero (e.g. by another thread), stops the call before its next
         chunk of queries (TskError with code TSK_ERR_CANCELLED); lb_both:
         DTW on an equal-length index also bounds the survivors with the
-        candidate-envelope LB_Box and keeps the larger bound."""
+        candidate-envelope LB_Box and keeps the larger bound; raw_keys: dist
+        receives the ranking keys (DK squared), for exact merges of shards."""
         torch = _torch()
         qv = _values(queries, self.dim)
         qo = _offsets(q_offsets)
@@ -130,6 +132,9 @@ class Index:
                     tuple(ids.shape) != (nq, k) or tuple(dist.shape) != (nq, k) or
                     not ids.is_contiguous() or not dist.is_contiguous()):
                 raise ValueError("out must be contiguous (int64 [nq, k], float32 [nq, k])")
+            if not (ids.is_cuda and dist.is_cuda and ids.device == qv.device and
+                    dist.device == qv.device):
+                raise ValueError("out tensors must be on the queries' CUDA device")
         else:
             ids = torch.empty((nq, k), dtype=torch.int64, device=qv.device)
             dist = torch.empty((nq, k), dtype=torch.float32, device=qv.device)
@@ -147,6 +152,7 @@ class Index:
         opts.dp_waves_per_cu = int(dp_waves_per_cu)
         opts.dk_seed = int(dk_seed)
         opts.lb_both = 1 if lb_both else 0
+        opts.raw_keys = 1 if raw_keys else 0
         opts.use_graph = 1 if use_graph else 0
         opts.tune = _lib.TSK_TUNE_CACHED if tune else _lib.TSK_TUNE_OFF
         if cancel is not None:

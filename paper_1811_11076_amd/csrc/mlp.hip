@@ -624,6 +624,8 @@ extern "C" int tsk_model_embed(tsk_model *m, const float *values_dev, const int6
     if (!values_dev || !out_dev)
         return set_err(TSK_ERR_INVALID_ARG, "NULL device pointer");
     TSK_TRY(check_offsets(offsets_host, n_series));
+    TSK_TRY(check_dev_ptr(values_dev, m->device, "values_dev"));
+    TSK_TRY(check_dev_ptr(out_dev, m->device, "out_dev"));
     std::lock_guard<std::mutex> lock(m->mu);
     hipStream_t s = (hipStream_t)hip_stream;
     TSK_TRY(upload_offsets(m, offsets_host, n_series, s));
@@ -645,6 +647,7 @@ extern "C" int tsk_model_batch_grad(tsk_model *m, const float *values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "values_dev is NULL");
     TSK_TRY(check_offsets(offsets_host, n_series));
     TSK_TRY(check_pairs(a_host, b_host, target_host, n_pairs, n_series));
+    TSK_TRY(check_dev_ptr(values_dev, m->device, "values_dev"));
     if (n_pairs > 65536)
         return set_err(TSK_ERR_UNSUPPORTED, "at most 65536 pairs per batch");
     std::lock_guard<std::mutex> lock(m->mu);
@@ -688,6 +691,7 @@ extern "C" int tsk_model_train(tsk_model *m, const float *values_dev, const int6
         return set_err(TSK_ERR_INVALID_ARG, "epochs >= 1, batch in [1, 65536], lr > 0");
     TSK_TRY(check_offsets(offsets_host, n_series));
     TSK_TRY(check_pairs(a_host, b_host, target_host, n_pairs, n_series));
+    TSK_TRY(check_dev_ptr(values_dev, m->device, "values_dev"));
     const float b1 = opts->beta1 > 0.0f ? opts->beta1 : 0.9f;
     const float b2 = opts->beta2 > 0.0f ? opts->beta2 : 0.999f;
     const float eps = opts->eps > 0.0f ? opts->eps : 1e-8f;

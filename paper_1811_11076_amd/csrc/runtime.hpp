@@ -38,6 +38,33 @@ int set_err(int code, const char *fmt, ...);
     } while (0)
 
 namespace tsk {
+// A "_dev" argument must be device memory (or managed memory) visible to
+// `device` (< 0: any device): a kernel that reads or writes through a host
+// address faults the GPU, so such a pointer is an argument error.  NULL is
+// left to the caller's own checks.
+inline int check_dev_ptr(const void *p, int device, const char *what)
+{
+    if (!p)
+        return TSK_OK;
+    hipPointerAttribute_t a;
+    a.type = hipMemoryTypeUnregistered;
+    a.device = -1;
+    const hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return tsk::set_err(TSK_ERR_INVALID_ARG, "%s is not device memory (%s)", what,
+                            hipGetErrorString(e));
+    }
+    if (a.type == hipMemoryTypeManaged)
+        return TSK_OK;
+    if (a.type != hipMemoryTypeDevice)
+        return tsk::set_err(TSK_ERR_INVALID_ARG, "%s is not device memory", what);
+    if (device >= 0 && a.device != device)
+        return tsk::set_err(TSK_ERR_INVALID_ARG, "%s is on device %d, not on device %d", what,
+                            a.device, device);
+    return TSK_OK;
+}
+
 // ------------------------------------------------------------------ device buffers
 template <typename T> struct DevBuf {
     T *p = nullptr;

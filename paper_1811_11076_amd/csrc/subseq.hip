@@ -196,6 +196,12 @@ extern "C" int tsk_subseq_query(const float *series_dev, const int64_t *s_offset
         return set_err(TSK_ERR_INVALID_ARG, "opts: chunk_cols >= 0, waves_per_cu in [0, 32], seed 0/1");
     int dev = -1, n_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
+    TSK_TRY(check_dev_ptr(series_dev, dev, "series_dev"));
+    TSK_TRY(check_dev_ptr(q_values_dev, dev, "q_values_dev"));
+    TSK_TRY(check_dev_ptr(out_ids_dev, dev, "out_ids_dev"));
+    TSK_TRY(check_dev_ptr(out_dist_dev, dev, "out_dist_dev"));
+    TSK_TRY(check_dev_ptr(out_end_dev, dev, "out_end_dev"));
+    TSK_TRY(check_dev_ptr(out_start_dev, dev, "out_start_dev"));
     HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     n_cu = std::max(1, n_cu);
     hipStream_t s = (hipStream_t)hip_stream;

@@ -196,3 +196,24 @@ def test_validate_values_arguments():
     assert bad.value == -1
     assert lib.tsk_validate_values(None, 3, ctypes.byref(bad), None) == _lib.TSK_ERR_INVALID_ARG
     assert lib.tsk_validate_values(ctypes.c_void_p(0x1000), -1, None, None) == _lib.TSK_ERR_INVALID_ARG
+
+
+def test_binding_rejects_host_outputs(monkeypatch):
+    """Index.knn refuses out tensors that are not on the queries' device
+    before any library call (a kernel writing to a host address faults)."""
+    import torch
+    import paper_1811_11076_amd as P
+
+    class FakeLib:
+        def tsk_knn_query(self, *a):
+            raise AssertionError("the library must not be called")
+
+    idx = P.Index.__new__(P.Index)
+    idx._lib = FakeLib()
+    idx._h = ctypes.c_void_p()
+    idx.n, idx.dim = 10, 3
+    monkeypatch.setattr(P, "_values", lambda v, dim=None: v)
+    q = torch.zeros((8, 3), dtype=torch.float32)
+    out = (torch.empty((1, 4), dtype=torch.int64), torch.empty((1, 4), dtype=torch.float32))
+    with pytest.raises(ValueError, match="CUDA device"):
+        idx.knn(q, np.array([0, 8]), 4, "dk", out=out)
