@@ -11,7 +11,7 @@
  *   - Sakoe-Chiba band (Sec. 2.2) optional for both.
  *   - k-NN query (Sec. 1): the k database series closest to each query.
  *   - Pruning: DTW uses LB_Box (Sec. 3, eq. (1)); DK uses the greedy upper
- *     bound of Alg. 1 to seed the threshold (Sec. 4.4) and the sparse-DK
+ *     bound of Alg. 1 to seed the threshold (Sec. 4.3) and the sparse-DK
  *     semantics of Alg. 3 (cells above the threshold are dead).
  *   Results are exact: identical to evaluating every pair with the full DP
  *   and sorting by (distance, id).
@@ -204,6 +204,13 @@ typedef struct {
                                       N x length x 2 x dim floats of
                                       workspace; 0 = off (default).  k-NN
                                       only (ignored by range queries) */
+    int32_t raw_keys;              /* 1: out_dist_dev receives each rank's
+                                      ranking key instead of its distance
+                                      (DK: the squared DK, whose correctly
+                                      rounded sqrt is the distance; DTW: the
+                                      distance itself), so that per-shard
+                                      rows can be merged by (key, id)
+                                      exactly; 0 = distances (default) */
 } tsk_query_opts;
 
 typedef struct {
@@ -306,7 +313,7 @@ typedef struct {
     int32_t reserved;
 } tsk_subseq_opts;
 
-/* Subsequence k-NN (Sec. 4.2-4.3; Alg. 2 and Alg. 3 with SUB): a match of a
+/* Subsequence k-NN (Sec. 4.1-4.2; Alg. 2 and Alg. 3 with SUB): a match of a
  * query may start and end anywhere in a series.  The subsequence DK of
  * (query S, series T) is min over a <= b of DK(S, T[a..b]) (squared point
  * costs, as for tsk_knn_query, reported as the correctly rounded sqrt).  For

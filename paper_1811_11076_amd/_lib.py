@@ -44,7 +44,8 @@ class QueryOpts(ctypes.Structure):
                 ("tune", ctypes.c_int32),
                 ("model", ctypes.c_void_p),
                 ("cancel_flag_host", ctypes.c_void_p),
-                ("lb_both", ctypes.c_int32)]
+                ("lb_both", ctypes.c_int32),
+                ("raw_keys", ctypes.c_int32)]
 
 
 class IndexOpts(ctypes.Structure):

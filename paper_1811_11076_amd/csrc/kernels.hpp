@@ -263,7 +263,7 @@ __device__ float greedy_walk(const float *__restrict__ q, int m, const float *__
 }
 
 // ------------------------------------------------------------------ seed pass
-// Threshold seed (Sec. 4.4, first loop, generalised to k): the greedy bound
+// Threshold seed (Sec. 4.3, first loop, generalised to k): the greedy bound
 // of the first S candidates of each query (in the query's candidate order)
 // is computed in full; the k-th smallest of them bounds the k-th smallest
 // distance from above and becomes the query's starting threshold.
@@ -307,7 +307,7 @@ __global__ void k_seed(const float *__restrict__ qv, const int64_t *__restrict__
 //   DK:  every path starts at (0,0) and ends at (m-1,n-1), so
 //        max(c(0,0), c(m-1,n-1)) <= squared DK; pairs passing it run the
 //        greedy walk of Alg. 1 with early return at the running threshold,
-//        and a completed walk lowers that threshold (Sec. 4.4).
+//        and a completed walk lowers that threshold (Sec. 4.3).
 // lbv[q][c] receives the bound if the pair survives (<= threshold), else
 // +inf.  DEBUG mode: no threshold, writes lb / greedy value / moves instead.
 struct BoundArgs {

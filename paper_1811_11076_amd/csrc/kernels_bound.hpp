@@ -472,7 +472,7 @@ __global__ __launch_bounds__(256) void k_corner(BoundArgs a)
     wave_count(a.ctr, C_PAIRS, (unsigned long long)nqg);
 }
 
-// DK greedy pass over the compacted survivors (Sec. 4.4, first loop): a wave
+// DK greedy pass over the compacted survivors (Sec. 4.3, first loop): a wave
 // takes 64 survivors of one query (query staged in LDS) and walks Alg. 1 on
 // each with early return at the running threshold; completed walks lower the
 // threshold through the query's upper-bound slots.

@@ -1,4 +1,4 @@
-// Subsequence search (Sec. 4.2-4.3): the DK of a query S against the best
+// Subsequence search (Sec. 4.1-4.2): the DK of a query S against the best
 // matching contiguous part T[a..b] of a long series T, a match starting and
 // ending anywhere (Alg. 2 and Alg. 3 with SUB).
 //

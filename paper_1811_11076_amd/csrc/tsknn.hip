@@ -369,6 +369,7 @@ extern "C" int tsk_validate_values(const float *values_dev, int64_t count, int64
         return TSK_OK;
     if (!values_dev)
         return set_err(TSK_ERR_INVALID_ARG, "values_dev is NULL");
+    TSK_TRY(check_dev_ptr(values_dev, -1, "values_dev"));
     hipStream_t s = (hipStream_t)hip_stream;
     DevBuf<unsigned long long> first;
     TSK_TRY(first.ensure(1));
@@ -524,6 +525,7 @@ extern "C" int tsk_index_build(const float *values_dev, const int64_t *offsets_h
         return set_err(TSK_ERR_DEVICE, "no HIP device available");
     }
     HIP_TRY(hipGetDevice(&dev));
+    TSK_TRY(check_dev_ptr(values_dev, dev, "values_dev"));
     tsk_index *ix = new (std::nothrow) tsk_index();
     if (!ix)
         return set_err(TSK_ERR_OOM, "host allocation failed");
@@ -772,6 +774,7 @@ static int check_queries(const tsk_index *ix, const float *qv, const int64_t *qo
         return set_err(TSK_ERR_INVALID_ARG, "dist %d is not TSK_DTW/TSK_DK", dist);
     TSK_TRY(check_band(band));
     TSK_TRY(check_device(ix));
+    TSK_TRY(check_dev_ptr(qv, ix->device, "q_values_dev"));
     return TSK_OK;
 }
 
@@ -888,6 +891,12 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_UNSUPPORTED, "k %d > %d", k, TSK_MAX_K);
     if (!rr && (!out_ids_dev || !out_dist_dev))
         return set_err(TSK_ERR_INVALID_ARG, "output pointers are NULL");
+    TSK_TRY(check_dev_ptr(out_ids_dev, cix->device, "out_ids_dev"));
+    TSK_TRY(check_dev_ptr(out_dist_dev, cix->device, "out_dist_dev"));
+    if (rr && rr->capacity > 0) {
+        TSK_TRY(check_dev_ptr(rr->ids, cix->device, "out_ids_dev"));
+        TSK_TRY(check_dev_ptr(rr->dist, cix->device, "out_dist_dev"));
+    }
     tsk_query_opts o;
     memset(&o, 0, sizeof(o));
     o.walk_pass = -1;
@@ -900,6 +909,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "opts->order %d unknown", o.order);
     if (o.order == TSK_ORDER_GIVEN && !o.order_dev)
         return set_err(TSK_ERR_INVALID_ARG, "TSK_ORDER_GIVEN needs order_dev");
+    if (o.order == TSK_ORDER_GIVEN)
+        TSK_TRY(check_dev_ptr(o.order_dev, cix->device, "opts->order_dev"));
     if (o.order == TSK_ORDER_LEARNED) {
         if (!o.model)
             return set_err(TSK_ERR_INVALID_ARG, "TSK_ORDER_LEARNED needs opts->model");
@@ -931,6 +942,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "lb_qgroup must be 0, 1, 2, 4, 8 or 16");
     if (o.lb_both != 0 && o.lb_both != 1)
         return set_err(TSK_ERR_INVALID_ARG, "lb_both must be 0 or 1");
+    if (o.raw_keys != 0 && o.raw_keys != 1)
+        return set_err(TSK_ERR_INVALID_ARG, "raw_keys must be 0 or 1");
     if (o.use_graph && (o.profile || o.order == TSK_ORDER_LEARNED))
         return set_err(TSK_ERR_UNSUPPORTED, "use_graph excludes profile and TSK_ORDER_LEARNED");
     if (rr) {
@@ -1175,7 +1188,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         if (rr)
             hipLaunchKernelGGL(k_range_count, dim3(nq), dim3(256), 0, s, W.rng.p, ix->n,
                                W.rcnt.p);
-        else if (dist == TSK_DK)
+        else if (dist == TSK_DK && !o.raw_keys)
             hipLaunchKernelGGL(k_finalize<DIST_DK>, dim3(nq), dim3(64), 0, s, W.resslots.p, nq, k,
                                out_ids_dev + c.q0 * k, out_dist_dev + c.q0 * k);
         else
@@ -1201,7 +1214,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                                     o.order, (int64_t)(uintptr_t)o.order_dev, o.seed_count,
                                     o.dp_kernel, o.walk_pass, o.task_size, o.tube_rows,
                                     o.lb_qgroup, o.dk_band_slots, o.surv_order, o.dp_rows,
-                                    o.dp_waves_per_cu, o.dk_seed, o.lb_both,
+                                    o.dp_waves_per_cu, o.dk_seed, o.lb_both, o.raw_keys,
                                     (int64_t)timed};
         // every workspace buffer the captured kernels address: a buffer
         // reallocated by another call changes the key
@@ -1432,6 +1445,7 @@ extern "C" int tsk_pair_distances(const tsk_index *cix, const float *q_values_de
     TSK_TRY(check_queries(cix, q_values_dev, q_offsets_host, n_queries, dist, band));
     if (!out_keys_dev)
         return set_err(TSK_ERR_INVALID_ARG, "out_keys_dev is NULL");
+    TSK_TRY(check_dev_ptr(out_keys_dev, cix->device, "out_keys_dev"));
     tsk_index *ix = const_cast<tsk_index *>(cix);
     std::lock_guard<std::mutex> lock(ix->mu);
     hipStream_t s = (hipStream_t)hip_stream;
@@ -1464,6 +1478,9 @@ extern "C" int tsk_pair_bounds(const tsk_index *cix, const float *q_values_dev,
 {
     g_err.clear();
     TSK_TRY(check_queries(cix, q_values_dev, q_offsets_host, n_queries, dist, band));
+    TSK_TRY(check_dev_ptr(out_lb_dev, cix->device, "out_lb_dev"));
+    TSK_TRY(check_dev_ptr(out_ub_dev, cix->device, "out_ub_dev"));
+    TSK_TRY(check_dev_ptr(out_steps_dev, cix->device, "out_steps_dev"));
     tsk_index *ix = const_cast<tsk_index *>(cix);
     std::lock_guard<std::mutex> lock(ix->mu);
     hipStream_t s = (hipStream_t)hip_stream;

@@ -1,9 +1,9 @@
 """One GPU standing in for a sharded database: the series split into S
 contiguous shards, one index per shard queried in turn (ids offset by the
-shard's first series), the per-shard top-k merged on the host by
-(distance, id).  The merged rows equal the unsharded index's and the
-oracle's plain definition: the merge is the only step a run over several
-GPUs would add to the single-GPU path."""
+shard's first series) for its ranking keys (DK: squared), the per-shard
+top-k merged on the host by (key, id).  The merged rows equal the unsharded
+index's and the oracle's plain definition bit for bit: the merge is the
+only step a run over several GPUs would add to the single-GPU path."""
 import numpy as np
 import pytest
 
@@ -21,35 +21,31 @@ def _gpu():
 
 
 def _merge(parts, k):
+    """Per query, the k smallest (key, id) over the shards' rows."""
     ids = np.concatenate([p[0] for p in parts], axis=1)
-    dist = np.concatenate([p[1] for p in parts], axis=1)
+    keys = np.concatenate([p[1] for p in parts], axis=1)
     out_i = np.full((ids.shape[0], k), -1, np.int64)
-    out_d = np.full((ids.shape[0], k), np.inf, np.float32)
+    out_k = np.full((ids.shape[0], k), np.inf, np.float32)
     for q in range(ids.shape[0]):
-        cand = sorted((float(dist[q, t]), int(ids[q, t])) for t in range(ids.shape[1])
+        cand = sorted((float(keys[q, t]), int(ids[q, t])) for t in range(ids.shape[1])
                       if ids[q, t] >= 0)[:k]
-        for r, (dd, ii) in enumerate(cand):
-            out_i[q, r], out_d[q, r] = ii, dd
-    return out_i, out_d
+        for r, (kk, ii) in enumerate(cand):
+            out_i[q, r], out_k[q, r] = ii, kk
+    return out_i, out_k
 
 
-def _check(mi, md, ref_ids, ref_keys, dist):
-    """Distances bit-exact per rank; ids exact, except that DK reports the
-    correctly rounded sqrt of its squared key, which can merge two adjacent
-    keys: inside a run of equal distances the ids are compared as sets."""
-    exp = np.sqrt(ref_keys.astype(np.float32)) if dist == "dk" else ref_keys.astype(np.float32)
-    assert np.array_equal(md.view(np.uint32), exp.view(np.uint32)), (md, exp)
-    if dist == "dtw":
-        assert np.array_equal(mi, ref_ids), (mi, ref_ids)
-        return
-    for q in range(mi.shape[0]):
-        r = 0
-        while r < mi.shape[1]:
-            e = r
-            while e + 1 < mi.shape[1] and md[q, e + 1] == md[q, r]:
-                e += 1
-            assert sorted(mi[q, r:e + 1]) == sorted(ref_ids[q, r:e + 1]), (q, mi[q], ref_ids[q])
-            r = e + 1
+def _check_keys(mi, mk, ref_ids, ref_keys):
+    """Merged (id, key) rows equal the oracle's bit for bit."""
+    assert np.array_equal(mi, ref_ids), (mi, ref_ids)
+    assert np.array_equal(mk.view(np.uint32), ref_keys.astype(np.float32).view(np.uint32))
+
+
+def _check(ids, dist, ref_ids, ref_keys, dist_name):
+    """Rows of one call: ids exact, distances bit-exact (DK: the correctly
+    rounded sqrt of the oracle's squared key)."""
+    exp = np.sqrt(ref_keys.astype(np.float32)) if dist_name == "dk" else ref_keys.astype(np.float32)
+    assert np.array_equal(ids, ref_ids), (ids, ref_ids)
+    assert np.array_equal(dist.view(np.uint32), exp.view(np.uint32)), (dist, exp)
 
 
 def _run_shards(db, dbo, qs, qo, k, dist, band, shards):
@@ -61,9 +57,9 @@ def _run_shards(db, dbo, qs, qo, k, dist, band, shards):
     for a, b in zip(cuts[:-1], cuts[1:]):
         sdo = (dbo[a:b + 1] - dbo[a]).astype(np.int64)
         idx = Index(to_dev(db[dbo[a]:dbo[b]]), sdo)
-        ids, d, _ = idx.knn(dq, qo, k, dist, band)
+        ids, key, _ = idx.knn(dq, qo, k, dist, band, raw_keys=True)
         ids = ids.cpu().numpy()
-        parts.append((np.where(ids >= 0, ids + a, -1), d.cpu().numpy()))
+        parts.append((np.where(ids >= 0, ids + a, -1), key.cpu().numpy()))
         idx.close()
     return _merge(parts, k)
 
@@ -74,8 +70,8 @@ def test_equal_length_shards(shards, dist, band):
     print(f"[case] shards={shards} {dist} equal lengths", flush=True)
     db, dbo, qs, qo = classwarp(2, 10, 128, 3, 1400, 6)
     ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, dist, band)
-    mi, md = _run_shards(db, dbo, qs, qo, 10, dist, band, shards)
-    _check(mi, md, ref_ids, ref_keys, dist)
+    mi, mk = _run_shards(db, dbo, qs, qo, 10, dist, band, shards)
+    _check_keys(mi, mk, ref_ids, ref_keys)
     from paper_1811_11076_amd import Index
     idx = Index(to_dev(db), dbo)
     ids, d, _ = idx.knn(to_dev(qs), qo, 10, dist, band)
@@ -98,11 +94,11 @@ def test_uneven_shards_and_padding(dist, band):
     for a, b in ((0, 102), (102, 204), (204, 205)):
         sdo = (dbo[a:b + 1] - dbo[a]).astype(np.int64)
         idx = Index(to_dev(db[dbo[a]:dbo[b]]), sdo)
-        ids, d, _ = idx.knn(dq, qo, 12, dist, band)
+        ids, key, _ = idx.knn(dq, qo, 12, dist, band, raw_keys=True)
         ids = ids.cpu().numpy()
         if b - a < 12:
-            assert (ids[:, b - a:] == -1).all() and np.isinf(d.cpu().numpy()[:, b - a:]).all()
-        parts.append((np.where(ids >= 0, ids + a, -1), d.cpu().numpy()))
+            assert (ids[:, b - a:] == -1).all() and np.isinf(key.cpu().numpy()[:, b - a:]).all()
+        parts.append((np.where(ids >= 0, ids + a, -1), key.cpu().numpy()))
         idx.close()
-    mi, md = _merge(parts, 12)
-    _check(mi, md, ref_ids, ref_keys, dist)
+    mi, mk = _merge(parts, 12)
+    _check_keys(mi, mk, ref_ids, ref_keys)

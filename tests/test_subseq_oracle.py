@@ -1,4 +1,4 @@
-"""Pins of the oracle's subsequence search (Sec. 4.2-4.3: Alg. 2 and Alg. 3
+"""Pins of the oracle's subsequence search (Sec. 4.1-4.2: Alg. 2 and Alg. 3
 with SUB) against what the definitions fix: hand-worked examples
 (tests/golden/subseq_examples.json), enumeration of every warping path that
 starts in row 0 and ends in the last row, the whole-match DK of every
