@@ -7,11 +7,17 @@ semantics; unbanded) followed by one exact k-NN batch under DTW with LB_Box
 resident in HBM.  value = (queries x series) / step time, i.e. pairs whose
 exact k-NN membership was decided under both distances per second.
 
+The default workload is the large one (4096 queries x 1 000 000 series,
+L = 512, d = 6, 12.3 GB resident), whose scan takes each query's candidates
+in the learned order (the encoder is trained first, untimed).  Smaller
+workloads run with --workload.
+
 Prints one JSON line.  Also reports each distance's own rate, the DK/DTW
-speed-up, the roofline of the dominant kernel (device time from HIP events
-recorded on the launch stream during the timed steps), and the CPU oracle's
-pruned scan timed on a bounded query sample (which also verifies the GPU
-results for those queries).
+and learned/plain speed-ups, the roofline of the dominant kernel (device
+time from HIP events recorded on the launch stream during the timed steps),
+the CPU oracle's pruned scan timed on a bounded sample, and a check of the
+GPU rows against the oracle at full size (a sample of queries against every
+series, and every returned (id, distance) recomputed).
 """
 from __future__ import annotations
 
@@ -42,7 +48,8 @@ WORKLOADS = {
                                                  N=100000, L=1024, lengths=(64, 1024), d=3,
                                                  k=10, dk_band=None, dtw_band=0.1),
 }
-DEFAULT = "classwarp-q100-n20000-L256-d3"
+DEFAULT = "classwarp-q4096-n1000000-L512-d6"
+SECONDARY = "classwarp-q100-n20000-L256-d3"
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz non-packed 32-bit VALU lane-ops
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
@@ -293,6 +300,8 @@ def order_controls(w, idx_dk, dev_q, qo, model, plain_dk, learned_prof, reps=3):
             ("learned_full_seed", dict(order="learned", model=model, **full)),
             ("plain_top_m_seed", {}),
             ("untrained_top_m_seed", dict(order="learned", model=untrained))]
+    if learned_prof is None:
+        runs.append(("learned_top_m_seed", dict(order="learned", model=model)))
     out = {}
     for name, kw in runs:
         ids, dist, _ = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], **kw)
@@ -306,7 +315,8 @@ def order_controls(w, idx_dk, dev_q, qo, model, plain_dk, learned_prof, reps=3):
         print(f"[bench] order control {name}: {out[name]['fraction_full_dps']:.5f} full DPs, "
               f"{out[name]['device_ms']:.3f} ms", file=sys.stderr, flush=True)
     untrained.close()
-    out["learned_top_m_seed"] = _control_row(learned_prof, pairs, True)
+    if learned_prof is not None:
+        out["learned_top_m_seed"] = _control_row(learned_prof, pairs, True)
     return out
 
 
@@ -480,58 +490,221 @@ def tightness_sweep():
     return {"queries": w["Q"], "series": w["N"], "k": w["k"], "band": w["band"], "rows": rows}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-queries", type=int, default=64)
-    ap.add_argument("--cpu-series", type=int, default=0,
-                    help="limit the CPU baseline sample to the first S series (0 = all)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--no-subseq", action="store_true",
-                    help="skip the subsequence-search measurement")
-    ap.add_argument("--tightness-sweep", action="store_true",
-                    help="run only the LB_Box tightness / pruning-power sweep (one JSON line)")
-    ap.add_argument("--subseq-only", action="store_true",
-                    help="run only the subsequence-search measurement (one JSON line)")
-    ap.add_argument("--eager", action="store_true",
-                    help="time the profiled eager step instead of the tuned graph step")
-    ap.add_argument("--per-query-sample", type=int, default=32)
-    ap.add_argument("--copy-calib-mib", type=int, default=0,
-                    help="first run one plain device copy of this many MiB (the reference "
-                         "dispatch that scales the HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "the scan runs on exactly one GPU; --gpus must be 1 "
-                                   "(sharding over several GPUs is not implemented)"}))
-        sys.exit(2)
-    if args.tightness_sweep:
-        print(json.dumps({"tightness_sweep": tightness_sweep()}), flush=True)
-        return
-    if args.subseq_only:
-        print(json.dumps({"subsequence": subsequence(args)}), flush=True)
-        return
+def full_size_check(db, dbo, qs, qo, w, res_dk, res_dtw, nq_dk=16, nq_dtw=8):
+    """Checks the GPU rows against the oracle at full size: the first nq_dk
+    (DK) and nq_dtw (DTW) queries against every series (the oracle's pruned
+    scan with its envelope kept per length, equal to the plain definition),
+    ids and distance bits; and every (id, distance) returned for every query
+    recomputed by the oracle's full DP."""
+    import numpy as np
+    import oracle as O
+    out = {}
+    t0 = time.perf_counter()
+    for name, (ids, dist), nsel, band in (("dk", res_dk, nq_dk, w["dk_band"]),
+                                         ("dtw", res_dtw, nq_dtw, w["dtw_band"])):
+        nsel = min(nsel, w["Q"])
+        t1 = time.perf_counter()
+        rids, rkeys, _ = O.knn_verify(db, dbo, qs[:qo[nsel]], qo[:nsel + 1], w["k"], name, band)
+        t2 = time.perf_counter()
+        g_ids = ids.cpu().numpy()
+        g_dist = dist.cpu().numpy()
+        exp = np.sqrt(rkeys.astype(np.float32)) if name == "dk" else rkeys.astype(np.float32)
+        rows_ok = (np.array_equal(g_ids[:nsel], rids)
+                   and np.array_equal(g_dist[:nsel].view(np.uint32), exp.view(np.uint32)))
+        # every returned pair of every query: the oracle's full DP of that pair
+        q_idx, r_idx = np.nonzero(g_ids >= 0)
+        keys = O.pair_list_keys(db, dbo, qs, qo, q_idx, g_ids[q_idx, r_idx], name, band)
+        got = g_dist[q_idx, r_idx]
+        want = np.sqrt(keys) if name == "dk" else keys
+        pairs_ok = bool(np.array_equal(got.view(np.uint32), want.astype(np.float32).view(np.uint32)))
+        # each row ascending by (distance, id), padding only at the end
+        order_ok = True
+        for q in range(g_ids.shape[0]):
+            row = [(g_dist[q, r], g_ids[q, r]) for r in range(g_ids.shape[1]) if g_ids[q, r] >= 0]
+            if row != sorted(row) or len(row) != len(set(x[1] for x in row)):
+                order_ok = False
+                break
+        t3 = time.perf_counter()
+        out[name] = {"queries_vs_all_series": nsel, "series": int(dbo.shape[0] - 1),
+                     "rows_equal_oracle": bool(rows_ok),
+                     "returned_pairs_rechecked": int(q_idx.size),
+                     "returned_pairs_equal_oracle": pairs_ok, "rows_sorted": order_ok,
+                     "oracle_seconds": t2 - t1, "recheck_seconds": t3 - t2}
+        print(f"[bench] full-size check {name}: {nsel} queries x all series "
+              f"{'equal' if rows_ok else 'DIFFER'}; {q_idx.size} returned pairs "
+              f"{'equal' if pairs_ok else 'DIFFER'} ({t3 - t1:.1f}s)", file=sys.stderr, flush=True)
+    out["verified_queries"] = bool(all(out[n]["rows_equal_oracle"] and
+                                       out[n]["returned_pairs_equal_oracle"] and
+                                       out[n]["rows_sorted"] for n in ("dk", "dtw")))
+    out["seconds"] = time.perf_counter() - t0
+    return out
 
+
+def roofline_of(prof_dk, prof_dtw, w, uneven, workload):
+    kern = {"dk": kernel_rooflines(prof_dk, "dk", w["d"], "k_dp_tube", uneven),
+            "dtw": kernel_rooflines(prof_dtw, "dtw", w["d"], "k_dp_band", uneven)}
+    if uneven:
+        kern["dtw"].pop("k_dp_band")  # uneven lengths: every DTW DP is a general one
+    dist_dom, kname = max(((dd, kk) for dd in kern for kk in kern[dd]),
+                          key=lambda x: kern[x[0]][x[1]]["ms"])
+    dom = kern[dist_dom][kname]
+    roof = {"bound": "alu", "kernel": f"{kname} ({dist_dom})",
+            "achieved": dom["tops"], "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+            "frac": dom["tops"] * 1e12 / VALU_PEAK_OPS,
+            "traffic": load_traffic(kname, workload),
+            "ms_per_launch": dom["ms"], "algorithmic_ops_per_launch": dom["ops"],
+            "per_unit_ops": dom["unit_ops"], "units_per_launch": dom["units"]}
+    return roof, kern
+
+
+def dist_summary(prof, kern, pairs):
+    c = max(1, prof["calls"])
+    ms = prof["ms_total"] / c
+    return {"pairs_per_s": pairs / (ms * 1e-3), "device_ms": ms,
+            "stages_ms": {"order": prof["ms_order"] / c, "seed": prof["ms_seed"] / c,
+                          "bound": prof["ms_bound"] / c, "dp": prof["ms_dp"] / c,
+                          "final": prof["ms_final"] / c},
+            "kernels": {k: {"ms": round(v["ms"], 4), "TOP/s": round(v["tops"], 3)}
+                        for k, v in kern.items()},
+            "dp_started": prof["dp_started"] / c, "dp_completed": prof["dp_completed"] / c,
+            "dp_valid_cells": prof["dp_valid_cells"] / c,
+            "fallback_pairs": prof["fallback_pairs"] / c}
+
+
+def train_encoder(w, seed=1):
+    import torch
+    from paper_1811_11076_amd import Model, synth
+    from paper_1811_11076_amd.learned import dk_training_set
+    t0 = time.perf_counter()
+    gen = synth.ClassWarp(w["cfg_id"], w["classes"], w["L"], w["d"])
+    # 200k pairs: 500 anchors x (200 same-class + 200 random) of a 2000-series pool
+    tv, to, ta, tb, ty = dk_training_set(gen, 2000, 500, 200, w.get("lengths", w["L"]), seed=1)
+    model = Model(w["d"], seed=seed)
+    losses = model.train(torch.from_numpy(tv).cuda(), to, ta, tb, ty, epochs=10, batch=1024,
+                         lr=1e-3, seed=1)
+    t_train = time.perf_counter() - t0
+    print(f"[bench] encoder trained on {ta.size} pairs in {t_train:.1f}s, loss "
+          f"{losses[0]:.3f} -> {losses[-1]:.3f}", file=sys.stderr, flush=True)
+    return model, {"pairs": int(ta.size), "epochs": 10, "batch": 1024, "seconds": t_train,
+                   "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])}
+
+
+def run_large(name, w, args):
+    """The large workload: the step is DK with each query's candidates in
+    the learned order plus DTW in the plain order, eager calls with
+    per-stage HIP events; the plain DK scan, the order / seed controls (on a
+    query subset), the full-size oracle check and the CPU baseline follow."""
+    import numpy as np
+    import torch
+    from paper_1811_11076_amd import Index, Model
+    t_gen = time.perf_counter()
+    db, dbo, qs, qo = make_data(w)
+    print(f"[bench] workload {name}: data in {time.perf_counter() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    dev_db = torch.from_numpy(db).cuda()
+    dev_q = torch.from_numpy(qs).cuda()
+    idx_dk = Index(dev_db, dbo)
+    idx_dtw = Index(dev_db, dbo)
+    del dev_db
+    torch.cuda.synchronize()
+    k, pairs = w["k"], w["Q"] * w["N"]
+    model, train_info = train_encoder(w)
+    dtw_kw = {}
+
+    def step(profile):
+        a = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], profile=profile, order="learned",
+                       model=model)
+        b = idx_dtw.knn(dev_q, qo, k, "dtw", w["dtw_band"], profile=profile, **dtw_kw)
+        return a, b
+
+    for _ in range(max(1, args.warmup)):
+        res = step(False)
+    torch.cuda.synchronize()
+    idx_dk.profile(reset=True)
+    idx_dtw.profile(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] {args.steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
+    prof_dk = idx_dk.profile(reset=True)
+    prof_dtw = idx_dtw.profile(reset=True)
+    ms_step = elapsed * 1e3 / args.steps
+    roof, kern = roofline_of(prof_dk, prof_dtw, w, False, name)
+
+    # the plain candidate order (the paper's scan order): same rows
+    plain_reps = max(1, args.plain_reps)
+    for _ in range(plain_reps):
+        pdk_res = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], profile=True)
+    torch.cuda.synchronize()
+    prof_plain = idx_dk.profile(reset=True)
+    plain_same = torch.equal(pdk_res[0], res[0][0]) and torch.equal(pdk_res[1], res[0][1])
+    kern_plain = kernel_rooflines(prof_plain, "dk", w["d"], "k_dp_tube")
+    print(f"[bench] plain-order DK: {prof_plain['ms_total'] / max(1, prof_plain['calls']):.1f} ms "
+          f"per call", file=sys.stderr, flush=True)
+    dk = dist_summary(prof_dk, kern["dk"], pairs)
+    dtw = dist_summary(prof_dtw, kern["dtw"], pairs)
+    dk_plain = dist_summary(prof_plain, kern_plain, pairs)
+
+    controls = None
+    if not args.no_controls:
+        sub = min(w["Q"], args.control_queries)
+        sq = dev_q[:int(qo[sub])]
+        so = qo[:sub + 1]
+        sw = dict(w, Q=sub)
+        plain_rows = (res[0][0][:sub].contiguous(), res[0][1][:sub].contiguous())
+        controls = order_controls(sw, idx_dk, sq, so, model, plain_rows, None, reps=1)
+        controls["queries"] = sub
+    out = {
+        "metric": METRIC, "value": pairs / (ms_step * 1e-3), "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": name, "queries": w["Q"], "series": w["N"], "length": w["L"],
+                   "dim": w["d"], "k": k, "dk_band": w["dk_band"], "dtw_band": w["dtw_band"],
+                   "order": "learned (DK), plain (DTW)"},
+        "roofline": roof,
+        "dk": dk, "dtw": dtw,
+        "dk_vs_dtw_speedup": dtw["device_ms"] / dk["device_ms"],
+        "step": "eager calls with per-stage HIP events: DK in the learned candidate order "
+                "(encoder trained beforehand, untimed), then DTW in the plain order",
+        "learned_order": {
+            "train": train_info,
+            "dk_plain_order": dk_plain,
+            "rows_equal_plain": bool(plain_same),
+            "dk_speedup_vs_plain": dk_plain["device_ms"] / dk["device_ms"],
+            "step_speedup_vs_plain": (dk_plain["device_ms"] + dtw["device_ms"]) /
+                                     (dk["device_ms"] + dtw["device_ms"]),
+            "dk_fraction_full_dps": dk["dp_completed"] / pairs,
+            "dk_fraction_full_dps_plain": dk_plain["dp_completed"] / pairs,
+            "dk_vs_dtw_speedup_plain_order": dtw["device_ms"] / dk_plain["device_ms"],
+            "dk_controls": controls,
+        },
+    }
+    model.close()
+    if not args.no_verify:
+        out["full_size_check"] = full_size_check(db, dbo, qs, qo, w, res[0][:2], res[1][:2])
+        out["verified_queries"] = out["full_size_check"]["verified_queries"]
+    if not args.no_cpu_baseline:
+        cb, _ = cpu_baseline(db, dbo, qs, qo, w, args.cpu_queries, args.cpu_series or 20000)
+        out["cpu_baseline"] = cb
+    idx_dk.close()
+    idx_dtw.close()
+    return out
+
+
+def run_standard(name, w, args, secondary=False):
+    """Workloads that fit a query call in one chunk: eager profiled steps,
+    then the tuned graph step (the faster of the two is the step), the
+    learned order and its controls, the CPU baseline with a row check."""
     import numpy as np
     import torch
     from paper_1811_11076_amd import Index
 
-    if args.copy_calib_mib > 0:
-        n = args.copy_calib_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    w = WORKLOADS[args.workload]
     t_gen = time.perf_counter()
     db, dbo, qs, qo = make_data(w)
-    print(f"[bench] workload {args.workload}: data in {time.perf_counter() - t_gen:.1f}s",
+    print(f"[bench] workload {name}: data in {time.perf_counter() - t_gen:.1f}s",
           file=sys.stderr, flush=True)
     dev_db = torch.from_numpy(db).cuda()
     dev_q = torch.from_numpy(qs).cuda()
@@ -572,50 +745,27 @@ def main():
                     "on concurrent streams")
 
     learned = None
-    if not args.no_learned and w["gen"] == "classwarp":
+    if not args.no_learned and w["gen"] == "classwarp" and not secondary:
         learned = learned_order(w, args, db, dbo, dev_db, dev_q, qo, idx_dk, idx_dtw, res)
 
     pairs = w["Q"] * w["N"]
     ms_step = elapsed * 1e3 / args.steps
     value = pairs / (ms_step * 1e-3)
     eager["pairs_per_s"] = pairs / (eager["ms_per_step"] * 1e-3)
-    dk_ms = prof_dk["ms_total"] / max(1, prof_dk["calls"])
-    dtw_ms = prof_dtw["ms_total"] / max(1, prof_dtw["calls"])
-
     uneven = "lengths" in w
-    kern = {"dk": kernel_rooflines(prof_dk, "dk", w["d"], "k_dp_tube", uneven),
-            "dtw": kernel_rooflines(prof_dtw, "dtw", w["d"], "k_dp_band", uneven)}
-    if uneven:
-        kern["dtw"].pop("k_dp_band")  # uneven lengths: every DTW DP is a general one
-    dist_dom, kname = max(((dd, kk) for dd in kern for kk in kern[dd]),
-                          key=lambda x: kern[x[0]][x[1]]["ms"])
-    dom = kern[dist_dom][kname]
-    roof = {"bound": "alu", "kernel": f"{kname} ({dist_dom})",
-            "achieved": dom["tops"], "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
-            "frac": dom["tops"] * 1e12 / VALU_PEAK_OPS,
-            "traffic": load_traffic(kname, args.workload),
-            "ms_per_launch": dom["ms"], "algorithmic_ops_per_launch": dom["ops"],
-            "per_unit_ops": dom["unit_ops"], "units_per_launch": dom["units"]}
-
+    roof, kern = roofline_of(prof_dk, prof_dtw, w, uneven, name)
+    dk = dist_summary(prof_dk, kern["dk"], pairs)
+    dtw = dist_summary(prof_dtw, kern["dtw"], pairs)
     out = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": args.workload, "queries": w["Q"], "series": w["N"],
+        "config": {"workload": name, "queries": w["Q"], "series": w["N"],
                    "length": w["L"], "dim": w["d"], "k": k, "dk_band": w["dk_band"],
                    "dtw_band": w["dtw_band"], "order": "plain"},
         "roofline": roof,
-        "dk": {"pairs_per_s": pairs / (dk_ms * 1e-3), "device_ms": dk_ms,
-               "kernels": {k: {"ms": round(v["ms"], 4), "TOP/s": round(v["tops"], 3)}
-                           for k, v in kern["dk"].items()},
-               "dp_started": prof_dk["dp_started"] / max(1, prof_dk["calls"]),
-               "dp_valid_cells": prof_dk["dp_valid_cells"] / max(1, prof_dk["calls"])},
-        "dtw": {"pairs_per_s": pairs / (dtw_ms * 1e-3), "device_ms": dtw_ms,
-                "kernels": {k: {"ms": round(v["ms"], 4), "TOP/s": round(v["tops"], 3)}
-                            for k, v in kern["dtw"].items()},
-                "dp_started": prof_dtw["dp_started"] / max(1, prof_dtw["calls"]),
-                "dp_valid_cells": prof_dtw["dp_valid_cells"] / max(1, prof_dtw["calls"])},
-        "dk_vs_dtw_speedup": dtw_ms / dk_ms if dk_ms > 0 else None,
+        "dk": dk, "dtw": dtw,
+        "dk_vs_dtw_speedup": dtw["device_ms"] / dk["device_ms"],
         "step": mode,
         "eager_profiled": eager,
     }
@@ -624,23 +774,19 @@ def main():
     if learned is not None:
         # both legs eager and sequential: the learned order's effect alone
         learned["step_speedup_vs_plain"] = eager["ms_per_step"] / learned["ms_per_step"]
-        learned["dk_speedup_vs_plain"] = dk_ms / learned["dk"]["device_ms"]
-        if w.get("step_order") == "learned" and learned["rows_equal_plain"] and \
-                learned["ms_per_step"] < ms_step:
-            # this configuration's scan is defined with the learned order
-            ms_step = learned["ms_per_step"]
-            value = pairs / (ms_step * 1e-3)
-            out["config"]["order"] = "learned (DK), plain (DTW)"
-            out.update({"value": value, "ms_per_step": ms_step,
-                        "step": "eager calls; DK candidates in learned order (encoder trained "
-                                "beforehand, untimed), DTW plain"})
+        learned["dk_speedup_vs_plain"] = dk["device_ms"] / learned["dk"]["device_ms"]
         learned["dk_fraction_full_dps_plain"] = prof_dk["dp_completed"] / max(1, prof_dk["calls"]) / pairs
         out["learned_order"] = learned
-    if not args.no_subseq:
-        out["subsequence"] = subsequence(args)
-        print(f"[bench] subsequence search: {out['subsequence']['ms_per_call']:.3f} ms per call",
-              file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline:
+    if secondary:
+        # rows of a query sample against the oracle's plain definition
+        import oracle as O
+        sel = min(w["Q"], 16)
+        ok = {}
+        for dist, r, band in (("dk", res[0], w["dk_band"]), ("dtw", res[1], w["dtw_band"])):
+            rids, _, _ = O.knn_verify(db, dbo, qs[:qo[sel]], qo[:sel + 1], k, dist, band)
+            ok[dist] = bool(np.array_equal(r[0][:sel].cpu().numpy(), rids))
+        out["verified_queries"] = {"count": sel, "dk_ids_equal": ok["dk"], "dtw_ids_equal": ok["dtw"]}
+    elif not args.no_cpu_baseline:
         cb, (sel, dk_ref, dtw_ref) = cpu_baseline(db, dbo, qs, qo, w, args.cpu_queries,
                                                   args.cpu_series)
         out["cpu_baseline"] = cb
@@ -650,6 +796,89 @@ def main():
             ok_dtw = np.array_equal(ids_dtw[:sel].cpu().numpy(), dtw_ref[0])
             out["verified_queries"] = {"count": sel, "dk_ids_equal": bool(ok_dk),
                                        "dtw_ids_equal": bool(ok_dtw)}
+    idx_dk.close()
+    idx_dtw.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-queries", type=int, default=0,
+                    help="queries of the CPU baseline sample (0 = 64, or 16 on the large workload)")
+    ap.add_argument("--cpu-series", type=int, default=0,
+                    help="limit the CPU baseline sample to the first S series (0 = all, or "
+                         "20000 on the large workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-verify", action="store_true",
+                    help="skip the full-size oracle check of the large workload")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-controls", action="store_true",
+                    help="skip the order / seed controls of the large workload")
+    ap.add_argument("--control-queries", type=int, default=512,
+                    help="queries of the large workload's order / seed controls")
+    ap.add_argument("--plain-reps", type=int, default=2,
+                    help="plain-order DK calls timed on the large workload")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 100 x 20 000 workload that the large one reports beside it")
+    ap.add_argument("--no-subseq", action="store_true",
+                    help="skip the subsequence-search measurement")
+    ap.add_argument("--tightness-sweep", action="store_true",
+                    help="run only the LB_Box tightness / pruning-power sweep (one JSON line)")
+    ap.add_argument("--subseq-only", action="store_true",
+                    help="run only the subsequence-search measurement (one JSON line)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time the profiled eager step instead of the tuned graph step")
+    ap.add_argument("--per-query-sample", type=int, default=32)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (the reference "
+                         "dispatch that scales the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "the scan runs on exactly one GPU; --gpus must be 1 "
+                                   "(sharding over several GPUs is not implemented)"}))
+        sys.exit(2)
+    if args.tightness_sweep:
+        print(json.dumps({"tightness_sweep": tightness_sweep()}), flush=True)
+        return
+    if args.subseq_only:
+        print(json.dumps({"subsequence": subsequence(args)}), flush=True)
+        return
+
+    import torch
+
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    w = WORKLOADS[args.workload]
+    large = w.get("step_order") == "learned"
+    if args.cpu_queries <= 0:
+        args.cpu_queries = 16 if large else 64
+    if large:
+        out = run_large(args.workload, w, args)
+    else:
+        out = run_standard(args.workload, w, args)
+    if large and not args.no_secondary:
+        t0 = time.perf_counter()
+        sec = run_standard(SECONDARY, WORKLOADS[SECONDARY], args, secondary=True)
+        keep = ("value", "unit", "ms_per_step", "config", "roofline", "dk", "dtw",
+                "dk_vs_dtw_speedup", "step", "verified_queries")
+        out["secondary"] = {key: sec[key] for key in keep if key in sec}
+        print(f"[bench] secondary workload {SECONDARY} in {time.perf_counter() - t0:.1f}s",
+              file=sys.stderr, flush=True)
+    if not args.no_subseq:
+        out["subsequence"] = subsequence(args)
+        print(f"[bench] subsequence search: {out['subsequence']['ms_per_call']:.3f} ms per call",
+              file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
