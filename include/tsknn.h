@@ -273,6 +273,31 @@ int tsk_knn_query(const tsk_index *index, const float *q_values_dev, const int64
                   const tsk_query_opts *opts, int64_t *out_ids_dev, float *out_dist_dev,
                   tsk_stats *stats_host, void *hip_stream);
 
+/* Size of the fixed device workspace of tsk_knn_query_noalloc (bytes). */
+#define TSK_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * exact k-NN query as tsk_knn_query, with the same arguments, outputs and
+ * errors, except that its workspace is a fixed device array of
+ * TSK_NOALLOC_SCRATCH_BYTES inside the library (one per device, held from
+ * the first such call on that device until the process ends) and the call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ * The caller still passes the queries and the outputs (device memory).
+ * Queries are split into chunks whose workspace fits the array (the
+ * workspace per query grows with the database: about 20 bytes per series,
+ * plus the staged query); a call whose single query does not fit returns
+ * TSK_ERR_INVALID_ARG before any device work.  No statistics.  Excluded
+ * (TSK_ERR_UNSUPPORTED): use_graph, profile, TSK_ORDER_LEARNED, lb_both.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents (each call clears what must start at zero): calls that overlap
+ * in time on one device race, so the caller serialises them, on one stream
+ * or by synchronising. */
+int tsk_knn_query_noalloc(const tsk_index *index, const float *q_values_dev,
+                          const int64_t *q_offsets_host, int64_t n_queries, int32_t k,
+                          int32_t dist, tsk_band band, const tsk_query_opts *opts,
+                          int64_t *out_ids_dev, float *out_dist_dev, void *hip_stream);
+
 /* Range query (Sec. 1: all database series within a distance of the
  * query, the paper's second query type beside k-NN), through the same
  * bound and DP kernels with the threshold fixed at the radius (no seeding,

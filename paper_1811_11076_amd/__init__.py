@@ -109,7 +109,7 @@ class Index:
             lb_qgroup: int = 0, use_graph: bool = False, tune: bool = False, out=None,
             dk_band_slots: int = 0, surv_order: int = 0, dp_rows: int = 0,
             dp_waves_per_cu: int = 0, dk_seed: int = 0, cancel=None, lb_both: bool = False,
-            raw_keys: bool = False):
+            raw_keys: bool = False, no_alloc: bool = False):
         """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
         float32 [nq, k], stats dict or None); DK distances are unsquared.
         order: None (plain), a CUDA int32 [nq, n] permutation per query, or
@@ -121,7 +121,10 @@ class Index:
         chunk of queries (TskError with code TSK_ERR_CANCELLED); lb_both:
         DTW on an equal-length index also bounds the survivors with the
         candidate-envelope LB_Box and keeps the larger bound; raw_keys: dist
-        receives the ranking keys (DK squared), for exact merges of shards."""
+        receives the ranking keys (DK squared), for exact merges of shards;
+        no_alloc: the call allocates no device memory (C:
+        tsk_knn_query_noalloc, the library's fixed workspace; pass `out`
+        to keep the binding from allocating the outputs; no stats)."""
         torch = _torch()
         qv = _values(queries, self.dim)
         qo = _offsets(q_offsets)
@@ -170,6 +173,14 @@ class Index:
             order = order.contiguous()
             opts.order = _lib.TSK_ORDER_GIVEN
             opts.order_dev = order.data_ptr()
+        if no_alloc:
+            if stats:
+                raise ValueError("no_alloc calls report no stats")
+            _lib.check(self._lib.tsk_knn_query_noalloc(
+                self._h, ctypes.c_void_p(qv.data_ptr()), qo.ctypes.data_as(ctypes.c_void_p), nq,
+                int(k), _DIST[distance], _lib.band_struct(band), ctypes.byref(opts),
+                ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dist.data_ptr()), _stream()))
+            return ids, dist, None
         st = _lib.Stats() if stats else None
         _lib.check(self._lib.tsk_knn_query(
             self._h, ctypes.c_void_p(qv.data_ptr()), qo.ctypes.data_as(ctypes.c_void_p), nq, int(k),

@@ -103,6 +103,8 @@ SIGNATURES = {
     "tsk_index_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
     "tsk_knn_query": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, Band, _vp, _vp, _vp, _vp,
                                      _vp]),
+    "tsk_knn_query_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, Band, _vp, _vp,
+                                             _vp, _vp]),
     "tsk_index_profile": (ctypes.c_int, [_vp, _vp, _i32]),
     "tsk_pair_distances": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp]),
     "tsk_pair_bounds": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp, _vp, _vp]),

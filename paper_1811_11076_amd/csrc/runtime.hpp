@@ -69,10 +69,24 @@ inline int check_dev_ptr(const void *p, int device, const char *what)
 template <typename T> struct DevBuf {
     T *p = nullptr;
     size_t cap = 0; // elements
+    // borrowed: p points into memory the buffer does not own (a carved
+    // region of a fixed array); it is never freed, and a request beyond cap
+    // is an error instead of a reallocation
+    bool borrowed = false;
+    void borrow(T *q, size_t n)
+    {
+        p = q;
+        cap = n;
+        borrowed = true;
+    }
     int ensure(size_t n)
     {
         if (n <= cap && p)
             return TSK_OK;
+        if (borrowed)
+            return tsk::set_err(TSK_ERR_INVALID_ARG,
+                                "workspace of %zu elements exceeds its fixed region of %zu", n,
+                                cap);
         if (p) {
             (void)hipFree(p);
             p = nullptr;
@@ -91,10 +105,11 @@ template <typename T> struct DevBuf {
     }
     void release()
     {
-        if (p)
+        if (p && !borrowed)
             (void)hipFree(p);
         p = nullptr;
         cap = 0;
+        borrowed = false;
     }
 };
 

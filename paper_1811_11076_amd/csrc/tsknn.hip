@@ -13,6 +13,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "launch.hpp"
@@ -877,11 +878,93 @@ struct RangeReq {
     int64_t *offsets_host; // [n_queries + 1]
 };
 
+// The workspace of one chunk of nq queries laid out in one region of
+// memory, each buffer 256-byte aligned (the same buffers and sizes that
+// ensure_ws and a chunk's preparation request).  With base == nullptr only
+// the size is computed; otherwise the workspace's buffers borrow the region.
+struct WsShape {
+    int64_t nq;
+    int k;
+    bool env, qpad, qtab;
+    int qrows;               // staged rows per query (longest query + padding)
+    int64_t qtab_floats_q;   // sparse-table floats of the longest query
+};
+static size_t carve_ws(const tsk_index *ix, const WsShape &sh, char *base, Workspace *w)
+{
+    size_t off = 0;
+    auto take = [&](auto &buf, size_t n) {
+        using T = std::remove_pointer_t<decltype(buf.p)>;
+        off = (off + 255) & ~(size_t)255;
+        if (base)
+            buf.borrow(reinterpret_cast<T *>(base + off), n);
+        off += std::max<size_t>(n, 1) * sizeof(T);
+    };
+    const int64_t N = ix->n, nq = sh.nq;
+    take(w->tau, nq);
+    take(w->seedslots, nq * sh.k);
+    take(w->ubslots, nq * sh.k);
+    take(w->resslots, nq * sh.k);
+    take(w->lbv, nq * N);
+    take(w->surv, nq * N);
+    take(w->surv_cnt, nq);
+    take(w->max_cnt, 1);
+    take(w->qcur, nq);
+    take(w->rcnt, nq);
+    take(w->ctr, C_NUM);
+    take(w->work, 8);
+    take(w->qoff, nq + 1);
+    if (sh.env)
+        take(w->env, nq * (int64_t)ix->max_len * 2 * ix->dim);
+    take(w->tbuf, (size_t)dp_blocks(ix) * 4 * 2 * ix->max_len);
+    take(w->fb, nq * N);
+    if (sh.qpad)
+        take(w->qpad, (size_t)nq * sh.qrows * (ix->dim <= 4 ? 4 : 8));
+    if (sh.qtab) {
+        take(w->qtab, nq * sh.qtab_floats_q);
+        take(w->qtab_off, nq + 1);
+    }
+    return off;
+}
+
+// Fixed device workspace of tsk_knn_query_noalloc.  Host code never uses
+// the array's name as an address (it is a host-side stand-in there): the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[TSK_NOALLOC_SCRATCH_BYTES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// The calling thread's current device's copy of the array (the device is
+// the index's: callers check that first).
+static int scratch_address(int device, char **out)
+{
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES)
+        return set_err(TSK_ERR_UNSUPPORTED, "device %d outside the fixed workspace's table",
+                       device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr)
+            return set_err(TSK_ERR_DEVICE, "hipGetSymbolAddress gave a null fixed workspace");
+        g_scratch_ptr[device] = (char *)ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return TSK_OK;
+}
+
+// A call whose workspace is carved from a fixed region instead of the
+// index's growable buffers (nothing allocated on the device).
+struct FixedWs {
+    char *base;
+    size_t bytes;
+};
+
 static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                      const int64_t *q_offsets_host, int64_t n_queries, int32_t k, int32_t dist,
                      tsk_band band, const tsk_query_opts *opts, int64_t *out_ids_dev,
                      float *out_dist_dev, tsk_stats *stats_host, void *hip_stream,
-                     const RangeReq *rr)
+                     const RangeReq *rr, const FixedWs *fx = nullptr)
 {
     g_err.clear();
     TSK_TRY(check_queries(cix, q_values_dev, q_offsets_host, n_queries, dist, band));
@@ -946,6 +1029,10 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "raw_keys must be 0 or 1");
     if (o.use_graph && (o.profile || o.order == TSK_ORDER_LEARNED))
         return set_err(TSK_ERR_UNSUPPORTED, "use_graph excludes profile and TSK_ORDER_LEARNED");
+    if (fx && (o.use_graph || o.profile || o.order == TSK_ORDER_LEARNED || o.lb_both || rr ||
+               stats_host))
+        return set_err(TSK_ERR_UNSUPPORTED, "the fixed-workspace call excludes use_graph, "
+                                            "profile, TSK_ORDER_LEARNED and lb_both");
     if (rr) {
         if (o.use_graph)
             return set_err(TSK_ERR_UNSUPPORTED, "a range query cannot run as a graph");
@@ -984,6 +1071,58 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
 
     // the candidate-envelope bound: DTW on an equal-length index
     const bool lb_rev = o.lb_both && dist == TSK_DTW && P.env_ok && o.dp_kernel != 1 && !rr;
+    // fixed workspace: the largest chunk whose workspace fits the region,
+    // carved for the call's longest query and lent to the index for the
+    // call (the index's own buffers are put back on every return)
+    Workspace fixed_ws;
+    struct Lend {
+        tsk_index *ix;
+        Workspace *w;
+        bool on = false;
+        ~Lend()
+        {
+            if (!on)
+                return;
+            std::swap(ix->ws, *w);
+            ix->ws.h_qoff.swap(w->h_qoff);
+            ix->ws.h_qtab.swap(w->h_qtab);
+        }
+    } lend{ix, &fixed_ws};
+    if (fx) {
+        int32_t qmax = 0;
+        for (int64_t i = 0; i < n_queries; ++i)
+            qmax = std::max<int32_t>(qmax, (int32_t)(q_offsets_host[i + 1] - q_offsets_host[i]));
+        WsShape sh;
+        sh.k = k;
+        sh.env = P.env_ok;
+        sh.qpad = o.dp_kernel != 1;
+        sh.qrows = qmax + 2 * QPAD;
+        sh.qtab = dist == TSK_DTW && !P.env_ok && ix->bucketed && o.dp_kernel != 1;
+        sh.qtab_floats_q = qtable_floats(qmax, ix->dim <= 4 ? 4 : 8);
+        int64_t lo = 0, hi = P.chunk; // largest nq in [1, P.chunk] that fits
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            sh.nq = mid;
+            if (carve_ws(ix, sh, nullptr, &fixed_ws) <= fx->bytes)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        if (lo < 1) {
+            sh.nq = 1;
+            return set_err(TSK_ERR_INVALID_ARG,
+                           "one query's workspace (%zu bytes for %lld series) exceeds the fixed "
+                           "workspace of %zu bytes",
+                           carve_ws(ix, sh, nullptr, &fixed_ws), (long long)ix->n, fx->bytes);
+        }
+        sh.nq = lo;
+        P.chunk = lo;
+        carve_ws(ix, sh, fx->base, &fixed_ws);
+        fixed_ws.h_qoff.swap(ix->ws.h_qoff);
+        fixed_ws.h_qtab.swap(ix->ws.h_qtab);
+        std::swap(ix->ws, fixed_ws);
+        lend.on = true;
+    }
     TSK_TRY(ensure_ws(ix, P.chunk, k, P.env_ok, lb_rev));
     Workspace &W = ix->ws;
     if (rr)
@@ -1338,6 +1477,22 @@ extern "C" int tsk_knn_query(const tsk_index *cix, const float *q_values_dev,
 {
     return scan_impl(cix, q_values_dev, q_offsets_host, n_queries, k, dist, band, opts,
                      out_ids_dev, out_dist_dev, stats_host, hip_stream, nullptr);
+}
+
+extern "C" int tsk_knn_query_noalloc(const tsk_index *cix, const float *q_values_dev,
+                                     const int64_t *q_offsets_host, int64_t n_queries, int32_t k,
+                                     int32_t dist, tsk_band band, const tsk_query_opts *opts,
+                                     int64_t *out_ids_dev, float *out_dist_dev, void *hip_stream)
+{
+    g_err.clear();
+    if (!cix)
+        return set_err(TSK_ERR_INVALID_ARG, "index is NULL");
+    TSK_TRY(check_device(cix));
+    FixedWs fx;
+    TSK_TRY(scratch_address(cix->device, &fx.base));
+    fx.bytes = (size_t)TSK_NOALLOC_SCRATCH_BYTES;
+    return scan_impl(cix, q_values_dev, q_offsets_host, n_queries, k, dist, band, opts,
+                     out_ids_dev, out_dist_dev, nullptr, hip_stream, nullptr, &fx);
 }
 
 // Largest fp32 key whose reported distance is within the radius: DTW keys
