@@ -379,6 +379,14 @@ int tsk_pair_distances(const tsk_index *index, const float *q_values_dev,
                        const int64_t *q_offsets_host, int64_t n_queries, int32_t dist,
                        tsk_band band, float *out_keys_dev, void *hip_stream);
 
+/* DK distances from squared DK keys (as tsk_pair_distances writes them):
+ * out_dev[i] = the correctly rounded fp32 square root of keys_dev[i] (Sec.
+ * 2.1: DK is the largest Euclidean point distance on the best path, the keys
+ * hold its square), the same rounding as the k-NN outputs; +inf stays +inf.
+ * Both device arrays of n floats on the current device; out_dev may equal
+ * keys_dev (in place).  Asynchronous on the stream.  Errors: INVALID_ARG. */
+int tsk_dk_distances(const float *keys_dev, float *out_dev, int64_t n, void *hip_stream);
+
 /* Per-pair bounds through the same kernels as the k-NN path, with no
  * threshold (no early return):
  *   out_lb_dev[q*N + c]  = LB_Box with the query's band envelope and the

@@ -246,9 +246,11 @@ class Index:
         _lib.check(self._lib.tsk_index_profile(self._h, ctypes.byref(st), 1 if reset else 0))
         return st.as_dict()
 
-    def pair_distances(self, queries, q_offsets, distance: str = "dk", band=None):
+    def pair_distances(self, queries, q_offsets, distance: str = "dk", band=None,
+                       dk_sqrt: bool = False):
         """Full-DP key of every (query, series) pair (C: tsk_pair_distances);
-        DK keys are squared."""
+        DK keys are squared, or with dk_sqrt the DK distances themselves
+        (C: tsk_dk_distances on the keys, in place)."""
         torch = _torch()
         qv = _values(queries, self.dim)
         qo = _offsets(q_offsets)
@@ -257,6 +259,10 @@ class Index:
         _lib.check(self._lib.tsk_pair_distances(
             self._h, ctypes.c_void_p(qv.data_ptr()), qo.ctypes.data_as(ctypes.c_void_p), nq,
             _DIST[distance], _lib.band_struct(band), ctypes.c_void_p(out.data_ptr()), _stream()))
+        if dk_sqrt and distance == "dk":
+            _lib.check(self._lib.tsk_dk_distances(ctypes.c_void_p(out.data_ptr()),
+                                                  ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                                  _stream()))
         return out
 
     def pair_bounds(self, queries, q_offsets, distance: str = "dk", band=None):
@@ -317,6 +323,9 @@ class Model:
 
     def __init__(self, dim: int, points: int = 32, hidden: int = 256, embed: int = 64,
                  seed: int = 0, _handle=None):
+        # torch's HIP context first: the encoder's memory lives on torch's
+        # current device and later calls run on torch's streams
+        _torch().cuda.init()
         self._lib = _lib.load()
         self._h = ctypes.c_void_p()
         if _handle is not None:
@@ -333,6 +342,7 @@ class Model:
 
     @classmethod
     def load(cls, path: str) -> "Model":
+        _torch().cuda.init()
         h = ctypes.c_void_p()
         _lib.check(_lib.load().tsk_model_load(path.encode(), ctypes.byref(h)))
         return cls(0, _handle=h)

@@ -107,6 +107,7 @@ SIGNATURES = {
                                              _vp, _vp]),
     "tsk_index_profile": (ctypes.c_int, [_vp, _vp, _i32]),
     "tsk_pair_distances": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp]),
+    "tsk_dk_distances": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
     "tsk_pair_bounds": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp, _vp, _vp]),
     "tsk_tune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, Band, _vp, _vp, _vp, _vp, _vp]),
     # band by pointer: libffi misplaces a float scalar next to a by-value

@@ -1592,6 +1592,34 @@ extern "C" int tsk_index_profile(tsk_index *ix, tsk_stats *out, int32_t reset)
     return TSK_OK;
 }
 
+// DK distances from squared DK keys (the output rounding of k_finalize).
+static __global__ void k_sqrt_keys(const float *__restrict__ keys, float *__restrict__ out,
+                                   int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = sqrt_rn_f32(keys[i]);
+}
+
+extern "C" int tsk_dk_distances(const float *keys_dev, float *out_dev, int64_t n,
+                                void *hip_stream)
+{
+    g_err.clear();
+    if (n < 0 || (n > 0 && (!keys_dev || !out_dev)))
+        return set_err(TSK_ERR_INVALID_ARG, "n must be >= 0 and the pointers non-NULL");
+    if (n == 0)
+        return TSK_OK;
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    TSK_TRY(check_dev_ptr(keys_dev, dev, "keys_dev"));
+    TSK_TRY(check_dev_ptr(out_dev, dev, "out_dev"));
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_sqrt_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, keys_dev,
+                       out_dev, n);
+    HIP_TRY(hipGetLastError());
+    return TSK_OK;
+}
+
 extern "C" int tsk_pair_distances(const tsk_index *cix, const float *q_values_dev,
                                   const int64_t *q_offsets_host, int64_t n_queries, int32_t dist,
                                   tsk_band band, float *out_keys_dev, void *hip_stream)

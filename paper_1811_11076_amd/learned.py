@@ -25,8 +25,8 @@ def dk_training_set(gen: "synth.ClassWarp", n_pool: int, n_anchor: int, per_clas
     pv, po, pl = gen.members(n_pool, stream, start=0, length=length)
     av, ao, al = gen.members(n_anchor, stream, start=n_pool, length=length)
     idx = Index(torch.from_numpy(pv).cuda(), po)
-    keys = idx.pair_distances(torch.from_numpy(av).cuda(), ao, "dk", None)
-    dist = torch.sqrt(keys).cpu().numpy()
+    dist = idx.pair_distances(torch.from_numpy(av).cuda(), ao, "dk", None,
+                              dk_sqrt=True).cpu().numpy()
     idx.close()
     rng = np.random.default_rng([int(seed), n_pool, n_anchor])
     a, b, y = [], [], []
