@@ -8,9 +8,10 @@ resident in HBM.  value = (queries x series) / step time, i.e. pairs whose
 exact k-NN membership was decided under both distances per second.
 
 The default workload is the large one (4096 queries x 1 000 000 series,
-L = 512, d = 6, 12.3 GB resident), whose scan takes each query's candidates
-in the learned order (the encoder is trained first, untimed).  Smaller
-workloads run with --workload.
+L = 512, d = 6, 12.3 GB resident), scanned in the library's default
+configuration; the learned candidate order (encoder trained first, untimed)
+is timed beside it at identical rows.  Smaller workloads run with
+--workload.
 
 Prints one JSON line.  Also reports each distance's own rate, the DK/DTW
 and learned/plain speed-ups, the roofline of the dominant kernel (device
@@ -285,8 +286,10 @@ def order_controls(w, idx_dk, dev_q, qo, model, plain_dk, learned_prof, reps=3):
     """DK work under the order and seeding controls: the plain order with
     Alg. 1 over every candidate (the paper's own first pass), the learned
     order with that full seed, the learned order with the library's top-M
-    seed (its first 512 candidates), the plain order with the top-M seed,
-    and an untrained (random-init) encoder with the top-M seed.  Each row
+    seed (its first 512 candidates), the plain order with the top-M seed
+    (the 512 candidates of smallest corner bound, the library default), the
+    plain order with the first 512 candidates as the seed set, and an
+    untrained (random-init) encoder with the top-M seed.  Each row
     gives the fraction of (query, series) pairs whose DP ran to
     completion, DPs started, DP cells and device time per call; every
     control's rows must equal the plain scan's."""
@@ -299,6 +302,7 @@ def order_controls(w, idx_dk, dev_q, qo, model, plain_dk, learned_prof, reps=3):
     runs = [("plain_full_seed", full),
             ("learned_full_seed", dict(order="learned", model=model, **full)),
             ("plain_top_m_seed", {}),
+            ("plain_head_seed", {"bound_seed": 2}),
             ("untrained_top_m_seed", dict(order="learned", model=untrained))]
     if learned_prof is None:
         runs.append(("learned_top_m_seed", dict(order="learned", model=model)))
@@ -590,10 +594,13 @@ def train_encoder(w, seed=1):
 
 
 def run_large(name, w, args):
-    """The large workload: the step is DK with each query's candidates in
-    the learned order plus DTW in the plain order, eager calls with
-    per-stage HIP events; the plain DK scan, the order / seed controls (on a
-    query subset), the full-size oracle check and the CPU baseline follow."""
+    """The large workload: the step is DK plus DTW over all queries in the
+    library's default configuration (plain candidate order; the threshold
+    seeded from the candidates of smallest corner bound; DTW prunes by the
+    corner bound before LB_Box), eager calls with per-stage HIP events; the
+    learned candidate order, DTW with LB_Box on every pair, the order / seed
+    controls (on a query subset), the full-size oracle check and the CPU
+    baseline follow."""
     import numpy as np
     import torch
     from paper_1811_11076_amd import Index, Model
@@ -612,8 +619,7 @@ def run_large(name, w, args):
     dtw_kw = {}
 
     def step(profile):
-        a = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], profile=profile, order="learned",
-                       model=model)
+        a = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], profile=profile)
         b = idx_dtw.knn(dev_q, qo, k, "dtw", w["dtw_band"], profile=profile, **dtw_kw)
         return a, b
 
@@ -633,19 +639,38 @@ def run_large(name, w, args):
     ms_step = elapsed * 1e3 / args.steps
     roof, kern = roofline_of(prof_dk, prof_dtw, w, False, name)
 
-    # the plain candidate order (the paper's scan order): same rows
+    # the learned candidate order (trained encoder): same rows
     plain_reps = max(1, args.plain_reps)
     for _ in range(plain_reps):
-        pdk_res = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], profile=True)
+        ldk_res = idx_dk.knn(dev_q, qo, k, "dk", w["dk_band"], profile=True, order="learned",
+                             model=model)
     torch.cuda.synchronize()
-    prof_plain = idx_dk.profile(reset=True)
-    plain_same = torch.equal(pdk_res[0], res[0][0]) and torch.equal(pdk_res[1], res[0][1])
-    kern_plain = kernel_rooflines(prof_plain, "dk", w["d"], "k_dp_tube")
-    print(f"[bench] plain-order DK: {prof_plain['ms_total'] / max(1, prof_plain['calls']):.1f} ms "
-          f"per call", file=sys.stderr, flush=True)
+    prof_learned = idx_dk.profile(reset=True)
+    learned_same = torch.equal(ldk_res[0], res[0][0]) and torch.equal(ldk_res[1], res[0][1])
+    kern_learned = kernel_rooflines(prof_learned, "dk", w["d"], "k_dp_tube")
+    print(f"[bench] learned-order DK: "
+          f"{prof_learned['ms_total'] / max(1, prof_learned['calls']):.1f} ms per call",
+          file=sys.stderr, flush=True)
     dk = dist_summary(prof_dk, kern["dk"], pairs)
     dtw = dist_summary(prof_dtw, kern["dtw"], pairs)
-    dk_plain = dist_summary(prof_plain, kern_plain, pairs)
+    dk_learned = dist_summary(prof_learned, kern_learned, pairs)
+
+    # DTW without the corner-bound cascade (LB_Box of every pair, threshold
+    # from the diagonal paths of the first candidates): same rows, timed
+    # beside the default cascade
+    dtw_lb_all = None
+    if not args.no_controls:
+        for _ in range(plain_reps):
+            cres = idx_dtw.knn(dev_q, qo, k, "dtw", w["dtw_band"], profile=True, dtw_cascade=2,
+                               bound_seed=2)
+        torch.cuda.synchronize()
+        prof_all = idx_dtw.profile(reset=True)
+        kern_all = kernel_rooflines(prof_all, "dtw", w["d"], "k_dp_band")
+        dtw_lb_all = dist_summary(prof_all, kern_all, pairs)
+        dtw_lb_all["rows_equal_default"] = bool(torch.equal(cres[0], res[1][0]) and
+                                                torch.equal(cres[1], res[1][1]))
+        print(f"[bench] DTW with LB_Box on every pair: {dtw_lb_all['device_ms']:.1f} ms per "
+              f"call", file=sys.stderr, flush=True)
 
     controls = None
     if not args.no_controls:
@@ -663,22 +688,23 @@ def run_large(name, w, args):
         "data": "synthetic",
         "config": {"workload": name, "queries": w["Q"], "series": w["N"], "length": w["L"],
                    "dim": w["d"], "k": k, "dk_band": w["dk_band"], "dtw_band": w["dtw_band"],
-                   "order": "learned (DK), plain (DTW)"},
+                   "order": "plain (threshold seeded from the smallest corner bounds)"},
         "roofline": roof,
         "dk": dk, "dtw": dtw,
         "dk_vs_dtw_speedup": dtw["device_ms"] / dk["device_ms"],
-        "step": "eager calls with per-stage HIP events: DK in the learned candidate order "
-                "(encoder trained beforehand, untimed), then DTW in the plain order",
+        "dtw_lb_box_every_pair": dtw_lb_all,
+        "dtw_cascade_speedup": (dtw_lb_all["device_ms"] / dtw["device_ms"]) if dtw_lb_all else None,
+        "step": "eager calls with per-stage HIP events: DK, then DTW, each over all queries "
+                "in the library's default configuration",
         "learned_order": {
             "train": train_info,
-            "dk_plain_order": dk_plain,
-            "rows_equal_plain": bool(plain_same),
-            "dk_speedup_vs_plain": dk_plain["device_ms"] / dk["device_ms"],
-            "step_speedup_vs_plain": (dk_plain["device_ms"] + dtw["device_ms"]) /
-                                     (dk["device_ms"] + dtw["device_ms"]),
-            "dk_fraction_full_dps": dk["dp_completed"] / pairs,
-            "dk_fraction_full_dps_plain": dk_plain["dp_completed"] / pairs,
-            "dk_vs_dtw_speedup_plain_order": dtw["device_ms"] / dk_plain["device_ms"],
+            "dk_learned_order": dk_learned,
+            "rows_equal_plain": bool(learned_same),
+            "dk_speedup_vs_plain": dk["device_ms"] / dk_learned["device_ms"],
+            "step_speedup_vs_plain": (dk["device_ms"] + dtw["device_ms"]) /
+                                     (dk_learned["device_ms"] + dtw["device_ms"]),
+            "dk_fraction_full_dps": dk_learned["dp_completed"] / pairs,
+            "dk_fraction_full_dps_plain": dk["dp_completed"] / pairs,
             "dk_controls": controls,
         },
     }

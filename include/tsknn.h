@@ -178,7 +178,8 @@ typedef struct {
     int32_t tune;                  /* TSK_TUNE_CACHED: take seed_count,
                                       tube_rows, task_size, walk_pass,
                                       lb_qgroup, dk_band_slots, surv_order,
-                                      dp_rows, dp_waves_per_cu and dk_seed
+                                      dp_rows, dp_waves_per_cu, dk_seed,
+                                      bound_seed and dtw_cascade
                                       from the index's tuning cache
                                       for this (distance, band, k), if
                                       tsk_tune filled it; TSK_TUNE_OFF: as
@@ -211,6 +212,31 @@ typedef struct {
                                       distance itself), so that per-shard
                                       rows can be merged by (key, id)
                                       exactly; 0 = distances (default) */
+    int32_t bound_seed;            /* threshold seed set: 1 = each query's
+                                      seed_count candidates of smallest
+                                      corner bound (every path's first and
+                                      last cells: max of their costs for DK,
+                                      sum for DTW; computed for every pair
+                                      first), 2 = the first seed_count
+                                      candidates of the query's order;
+                                      0 = library default (DK: 1 for the
+                                      plain order, 2 for given and learned
+                                      orders; DTW: as the cascade).  DK on
+                                      LDS-sized queries and DTW on equal
+                                      lengths (where the seed is the
+                                      diagonal path's cost sum unless the
+                                      cascade runs); k-NN only */
+    int32_t dtw_cascade;           /* DTW on equal lengths: 1 = the corner
+                                      bound prunes first, with the threshold
+                                      seeded by greedy walks (Alg. 1, summing
+                                      costs) over the candidates of smallest
+                                      corner bound; LB_Box (eq. (1)) is
+                                      computed only for its survivors, which
+                                      then run in ascending LB_Box; 2 =
+                                      LB_Box for every pair; 0 = library
+                                      default (1 for the plain order unless
+                                      bound_seed is 2 or lb_qgroup names an
+                                      LB_Box kernel, else 2) */
 } tsk_query_opts;
 
 typedef struct {

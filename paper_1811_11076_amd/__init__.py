@@ -109,7 +109,8 @@ class Index:
             lb_qgroup: int = 0, use_graph: bool = False, tune: bool = False, out=None,
             dk_band_slots: int = 0, surv_order: int = 0, dp_rows: int = 0,
             dp_waves_per_cu: int = 0, dk_seed: int = 0, cancel=None, lb_both: bool = False,
-            raw_keys: bool = False, no_alloc: bool = False):
+            raw_keys: bool = False, no_alloc: bool = False, bound_seed: int = 0,
+            dtw_cascade: int = 0):
         """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
         float32 [nq, k], stats dict or None); DK distances are unsquared.
         order: None (plain), a CUDA int32 [nq, n] permutation per query, or
@@ -122,6 +123,11 @@ class Index:
         DTW on an equal-length index also bounds the survivors with the
         candidate-envelope LB_Box and keeps the larger bound; raw_keys: dist
         receives the ranking keys (DK squared), for exact merges of shards;
+        bound_seed: 1 = seed the threshold from each query's candidates of
+        smallest corner bound, 2 = from the head of its order, 0 = default
+        (1 for the plain order); dtw_cascade: 1 = DTW prunes by the corner
+        bound first and computes LB_Box for its survivors only, 2 = LB_Box
+        for every pair, 0 = default (1 for the plain order);
         no_alloc: the call allocates no device memory (C:
         tsk_knn_query_noalloc, the library's fixed workspace; pass `out`
         to keep the binding from allocating the outputs; no stats)."""
@@ -156,6 +162,8 @@ class Index:
         opts.dk_seed = int(dk_seed)
         opts.lb_both = 1 if lb_both else 0
         opts.raw_keys = 1 if raw_keys else 0
+        opts.bound_seed = int(bound_seed)
+        opts.dtw_cascade = int(dtw_cascade)
         opts.use_graph = 1 if use_graph else 0
         opts.tune = _lib.TSK_TUNE_CACHED if tune else _lib.TSK_TUNE_OFF
         if cancel is not None:

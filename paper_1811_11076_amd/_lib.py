@@ -45,7 +45,9 @@ class QueryOpts(ctypes.Structure):
                 ("model", ctypes.c_void_p),
                 ("cancel_flag_host", ctypes.c_void_p),
                 ("lb_both", ctypes.c_int32),
-                ("raw_keys", ctypes.c_int32)]
+                ("raw_keys", ctypes.c_int32),
+                ("bound_seed", ctypes.c_int32),
+                ("dtw_cascade", ctypes.c_int32)]
 
 
 class IndexOpts(ctypes.Structure):

@@ -56,11 +56,22 @@ template <int D> void seed_diag_d(int dist, const SeedRingArgs &r, hipStream_t s
                            r.aos, r.off, r.len, r.N, r.order, r.S, r.k, r.seedslots, r.tau, r.ctr);
 }
 
-template <int D> void corner_d(const BoundArgs &a, hipStream_t s)
+template <int D> void corner_d(int dist, const BoundArgs &a, hipStream_t s)
 {
     constexpr int QG = 8;
     dim3 grid((unsigned)((a.N + 255) / 256), (unsigned)((a.nq + QG - 1) / QG));
-    hipLaunchKernelGGL((k_corner<D, QG>), grid, dim3(256), 0, s, a);
+    if (dist == DIST_DK)
+        hipLaunchKernelGGL((k_corner<D, QG, DIST_DK>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_corner<D, QG, DIST_DTW>), grid, dim3(256), 0, s, a);
+}
+
+template <int D>
+void bound_lb_surv_d(const BoundArgs &a, const int32_t *surv, const int32_t *surv_cnt,
+                     const int32_t *max_cnt, unsigned long long *work, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_bound_lb_surv<D>), dim3(blocks), dim3(256), 0, s, a, surv, surv_cnt,
+                       max_cnt, work);
 }
 
 template <int D>
@@ -129,9 +140,18 @@ void launch_seed_diag(int D, int dist, const SeedRingArgs &r, hipStream_t s)
 #undef CALL
 }
 
-void launch_corner(int D, const BoundArgs &a, hipStream_t s)
+void launch_corner(int D, int dist, const BoundArgs &a, hipStream_t s)
 {
-#define CALL(d) corner_d<d>(a, s)
+#define CALL(d) corner_d<d>(dist, a, s)
+    TSK_SWITCH_D(D, CALL)
+#undef CALL
+}
+
+void launch_bound_lb_surv(int D, const BoundArgs &a, const int32_t *surv, const int32_t *surv_cnt,
+                          const int32_t *max_cnt, unsigned long long *work, int blocks,
+                          hipStream_t s)
+{
+#define CALL(d) bound_lb_surv_d<d>(a, surv, surv_cnt, max_cnt, work, blocks, s)
     TSK_SWITCH_D(D, CALL)
 #undef CALL
 }

@@ -23,6 +23,19 @@ enum {
     C_VALID_GEN, // valid cells of the general DP (also counted in C_VALID_CELLS)
     C_NUM
 };
+constexpr int CTR_STRIPES = 64;
+constexpr int CTR_WORDS = C_NUM * CTR_STRIPES; // device words of the counters
+
+// Host: the counters from their striped device words.
+inline void ctr_sum(const unsigned long long *words, unsigned long long *out)
+{
+    for (int i = 0; i < C_NUM; ++i) {
+        unsigned long long t = 0;
+        for (int j = 0; j < CTR_STRIPES; ++j)
+            t += words[i * CTR_STRIPES + j];
+        out[i] = t;
+    }
+}
 
 struct BandArgs {
     int mode, r;
@@ -38,6 +51,15 @@ __device__ __forceinline__ Band pair_band(const BandArgs &ba, int m, int n)
 // Statistics counters (ctr[C_...]): a null base turns counting off (calls
 // that ask for neither stats nor a profile), sparing every wave its atomics
 // on the few shared counter words.
+// Each counter is CTR_STRIPES words (ctr[idx * CTR_STRIPES + stripe]) that
+// the host sums: a kernel of millions of waves would otherwise serialise on
+// one word's atomics.  A wave adds to the stripe of its block.
+__device__ __forceinline__ unsigned long long *ctr_word(unsigned long long *ctr, int idx)
+{
+    const unsigned b = blockIdx.x + 7u * blockIdx.y + 13u * blockIdx.z + (threadIdx.x >> 6);
+    return ctr + idx * CTR_STRIPES + (b & (CTR_STRIPES - 1));
+}
+
 __device__ __forceinline__ void wave_count(unsigned long long *ctr, int idx, unsigned long long v)
 {
     if (ctr == nullptr)
@@ -46,13 +68,23 @@ __device__ __forceinline__ void wave_count(unsigned long long *ctr, int idx, uns
     for (int o = 32; o > 0; o >>= 1)
         v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0 && v)
-        atomicAdd(ctr + idx, v);
+        atomicAdd(ctr_word(ctr, idx), v);
 }
 
 __device__ __forceinline__ void ctr_add(unsigned long long *ctr, int idx, unsigned long long v)
 {
     if (ctr != nullptr)
-        atomicAdd(ctr + idx, v);
+        atomicAdd(ctr_word(ctr, idx), v);
+}
+
+// Sum over the wave's 64 lanes (xor butterfly: both lanes of every pair add
+// the same two values, so every lane ends with the same bits).
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 __device__ __forceinline__ float wave_min(float v)
@@ -81,8 +113,7 @@ static __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, i
 
 static __global__ void k_add_u64(unsigned long long *dst, const unsigned long long *src, int n)
 {
-    const int i = threadIdx.x;
-    if (i < n)
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
         dst[i] += src[i];
 }
 
@@ -457,65 +488,87 @@ __global__ __launch_bounds__(256) void k_bounds(BoundArgs a)
 
 // ------------------------------------------------------------------ compaction
 // Survivors of one query, in the query's candidate order, re-checked against
-// the current threshold: surv[q][0..cnt).  One block of 256 per query.
+// the current threshold: surv[q][0..cnt).  One block of 1024 per query; each
+// pass takes 4096 positions, 4 consecutive ones per thread (so the survivors
+// of a thread precede those of the next), ranks them by a block-wide prefix
+// sum of the per-thread counts and writes them in order.
 // Candidate order: order[q][p] if given, else perm[p] (length-sorted
 // positions) if given, else p.  lbv is indexed by candidate id, except after
 // the length-bucket bound pass, which writes it by position (then perm maps
 // positions to ids and inv ids to positions).
-static __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ lbv, int64_t N,
-                                                 const int32_t *__restrict__ order,
-                                                 const int32_t *__restrict__ perm,
-                                                 const int32_t *__restrict__ inv,
-                                                 const uint32_t *__restrict__ tau,
-                                                 int32_t *__restrict__ surv, int32_t *__restrict__ cnt,
-                                                 int32_t *__restrict__ max_cnt,
-                                                 unsigned long long *ctr)
+constexpr int COMPACT_PER = 4;
+static __global__ __launch_bounds__(1024) void k_compact(const float *__restrict__ lbv, int64_t N,
+                                                  const int32_t *__restrict__ order,
+                                                  const int32_t *__restrict__ perm,
+                                                  const int32_t *__restrict__ inv,
+                                                  const uint32_t *__restrict__ tau,
+                                                  int32_t *__restrict__ surv, int32_t *__restrict__ cnt,
+                                                  int32_t *__restrict__ max_cnt,
+                                                  unsigned long long *ctr)
 {
     const int q = blockIdx.x;
-    __shared__ int wave_tot[4];
-    __shared__ int base_s;
+    __shared__ int wave_tot[2][16];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const float tq = bits_f(tau[q]);
-    if (threadIdx.x == 0)
-        base_s = 0;
-    __syncthreads();
+    const float *L = lbv + (int64_t)q * N;
+    int32_t *out = surv + (int64_t)q * N;
+    int base = 0;
     unsigned long long late = 0;
-    for (int64_t p0 = 0; p0 < N; p0 += 256) {
-        const int64_t p = p0 + threadIdx.x;
-        int c = -1;
-        bool keep = false;
-        if (p < N) {
-            int64_t li;
-            if (order) {
-                c = order[(int64_t)q * N + p];
-                li = inv ? inv[c] : c;
-            } else {
-                c = perm ? perm[p] : (int)p;
-                li = p;
+    int buf = 0;
+    for (int64_t p0 = 0; p0 < N; p0 += 1024 * COMPACT_PER, buf ^= 1) {
+        const int64_t pb = p0 + (int64_t)threadIdx.x * COMPACT_PER;
+        int cs[COMPACT_PER];
+        bool keep[COMPACT_PER];
+        int mine = 0;
+#pragma unroll
+        for (int u = 0; u < COMPACT_PER; ++u) {
+            const int64_t p = pb + u;
+            cs[u] = -1;
+            keep[u] = false;
+            if (p < N) {
+                int64_t li;
+                int c;
+                if (order) {
+                    c = order[(int64_t)q * N + p];
+                    li = inv ? inv[c] : c;
+                } else {
+                    c = perm ? perm[p] : (int)p;
+                    li = p;
+                }
+                const float lb = L[li];
+                cs[u] = c;
+                keep[u] = lb <= tq;
+                late += (lb != tsk_inf() && !keep[u]) ? 1 : 0;
+                mine += keep[u] ? 1 : 0;
             }
-            const float lb = lbv[(int64_t)q * N + li];
-            keep = lb <= tq;
-            late += (lb != tsk_inf() && !keep) ? 1 : 0;
         }
-        const unsigned long long bal = __ballot(keep);
-        const int rank = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0)
-            wave_tot[wv] = __popcll(bal);
-        __syncthreads();
-        int off = base_s;
-        for (int w = 0; w < wv; ++w)
-            off += wave_tot[w];
-        if (keep)
-            surv[(int64_t)q * N + off + rank] = c;
-        __syncthreads();
-        if (threadIdx.x == 0)
-            base_s += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
-        __syncthreads();
+        // inclusive prefix sum of the counts over the wave, then over waves
+        int inc = mine;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o, 64);
+            if (lane >= o)
+                inc += t;
+        }
+        if (lane == 63)
+            wave_tot[buf][wv] = inc;
+        __syncthreads(); // (the other buffer is free: read before this barrier)
+        int off = base + inc - mine, all = 0;
+        for (int w = 0; w < 16; ++w) {
+            const int t = wave_tot[buf][w];
+            off += w < wv ? t : 0;
+            all += t;
+        }
+#pragma unroll
+        for (int u = 0; u < COMPACT_PER; ++u)
+            if (keep[u])
+                out[off++] = cs[u];
+        base += all;
     }
     wave_count(ctr, C_BOUND_PRUNED, late);
     if (threadIdx.x == 0) {
-        cnt[q] = base_s;
-        atomicMax(max_cnt, base_s);
+        cnt[q] = base;
+        atomicMax(max_cnt, base);
     }
 }
 
@@ -525,6 +578,8 @@ static __global__ __launch_bounds__(256) void k_compact(const float *__restrict_
 // pairs most likely to be neighbours run first, so the threshold falls
 // early, and pairs of similar bound share a wave.  Same survivors as
 // k_compact (tau is fixed while it runs: no DP of this chunk has started).
+// cap < N keeps only the first cap survivors of that order (the cap
+// smallest bounds, up to the order inside the last bucket they reach).
 // One block of 1024 per query; SURV_BUCKETS counters in dynamic LDS.
 constexpr int SURV_BUCKETS = 8192;
 constexpr int SURV_SHIFT = 18;
@@ -532,7 +587,7 @@ static __global__ __launch_bounds__(1024) void k_compact_sorted(
     const float *__restrict__ lbv, int64_t N, const int32_t *__restrict__ order,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ inv,
     const uint32_t *__restrict__ tau, int32_t *__restrict__ surv, int32_t *__restrict__ cnt,
-    int32_t *__restrict__ max_cnt, unsigned long long *ctr)
+    int32_t *__restrict__ max_cnt, unsigned long long *ctr, int64_t cap)
 {
     extern __shared__ int32_t hist[];
     __shared__ int32_t wsum[16];
@@ -599,7 +654,8 @@ static __global__ __launch_bounds__(1024) void k_compact_sorted(
         if (lb <= tq) {
             const int pos =
                 atomicAdd(&hist[min(__float_as_uint(lb) >> SURV_SHIFT, (uint32_t)SURV_BUCKETS - 1)], 1);
-            surv[(int64_t)q * N + pos] = c;
+            if (pos < cap)
+                surv[(int64_t)q * N + pos] = c;
         }
     }
     wave_count(ctr, C_BOUND_PRUNED, late);
@@ -607,6 +663,7 @@ static __global__ __launch_bounds__(1024) void k_compact_sorted(
         int all = 0;
         for (int w = 0; w < 16; ++w)
             all += wsum[w];
+        all = (int)min((int64_t)all, cap);
         cnt[q] = all;
         atomicMax(max_cnt, all);
     }

@@ -422,11 +422,15 @@ __global__ __launch_bounds__(256) void k_bound_lb_pp(BoundArgs a)
 inline size_t lb_pp_lds_bytes(int D, int n) { return (size_t)n * 2 * D * sizeof(float); }
 constexpr size_t LB_PP_MAX_LDS = 64 * 1024;
 
-// DK corner pass: every warping path starts at (0,0) and ends at (m-1,n-1),
-// so max(c(0,0), c(m-1,n-1)) <= squared DK.  One lane per candidate, a
-// group of QG queries per block (their end points via scalar loads); lbv gets
-// the bound if it does not exceed the running threshold, else +inf.
-template <int D, int QG>
+// Corner pass: every warping path starts at (0,0) and ends at (m-1,n-1),
+// and both cells lie in any band, so for DK max(c(0,0), c(m-1,n-1)) <= the
+// squared DK, and for DTW c(0,0) + c(m-1,n-1) <= DTW (two distinct cells of
+// every path unless m = n = 1; in fp32 the DP's last value is
+// fl(c(m-1,n-1) + p) with p >= c(0,0), so by monotone rounding it is >=
+// fl(c(0,0) + c(m-1,n-1))).  One lane per candidate, a group of QG queries
+// per block (their end points via scalar loads); lbv gets the bound if it
+// does not exceed the running threshold, else +inf.
+template <int D, int QG, int DIST>
 __global__ __launch_bounds__(256) void k_corner(BoundArgs a)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -463,7 +467,12 @@ __global__ __launch_bounds__(256) void k_corner(BoundArgs a)
             qa[e] = Q[o0 * D + e];
             qz[e] = Q[(o1 - 1) * D + e];
         }
-        const float lb = fmaxf(point_cost<D>(qa, c0), point_cost<D>(qz, cl));
+        const float ca = point_cost<D>(qa, c0), cz = point_cost<D>(qz, cl);
+        float lb;
+        if (DIST == DIST_DK)
+            lb = fmaxf(ca, cz);
+        else
+            lb = (o1 - o0 > 1 || n > 1) ? ca + cz : ca;
         const bool keep = lb <= tq[g];
         a.lbv[(int64_t)q * a.N + c] = keep ? lb : tsk_inf();
         pruned += keep ? 0 : 1;
@@ -702,6 +711,87 @@ __global__ __launch_bounds__(256) void k_bound_lb_rev(const float *__restrict__ 
     }
     float *p = lbv + (int64_t)q * N + c;
     *p = fmaxf(*p, acc);
+}
+
+// LB_Box of the survivors of a first-stage bound (equal lengths, the query
+// envelope of k_env), only for the pairs left in surv: a wave per pair, its
+// 64 lanes on 64 consecutive candidate points at a time (coalesced loads of
+// the candidate and of the envelope), the same per-point terms as k_bound_lb,
+// summed in parallel.  The sum of any order of n <= 4096 non-negative fp32
+// terms is within (n-1) 2^-24 (relative) of the exact sum, so the sum scaled
+// by (1 - 2^-9) (rounding included) is <= the sequential sum of k_bound_lb,
+// hence <= the fp32 DTW; that scaled value is the pair's bound.  A partial
+// sum above the query's threshold stops the pair (every term is >= 0) and
+// it leaves with +inf; otherwise lbv gets the bound, which the DP stage
+// compares with the threshold again.  Waves take tasks of LBS_TASK survivors
+// of one query from a work counter, queries interleaved.
+constexpr int LBS_TASK = 16;
+
+template <int D>
+__global__ __launch_bounds__(256) void k_bound_lb_surv(BoundArgs a, const int32_t *__restrict__ surv,
+                                                       const int32_t *__restrict__ surv_cnt,
+                                                       const int32_t *__restrict__ max_cnt,
+                                                       unsigned long long *__restrict__ work)
+{
+    const int lane = threadIdx.x & 63;
+    const int n = a.env_n;
+    const int64_t per_q = (*max_cnt + LBS_TASK - 1) / LBS_TASK;
+    const int64_t total = (int64_t)a.nq * per_q;
+    const float scale = 1.0f - 0x1.0p-9f;
+    unsigned long long terms = 0;
+    for (;;) {
+        unsigned long long t = 0;
+        if (lane == 0)
+            t = atomicAdd(work, 1ull);
+        t = uniform_u64(t);
+        if (t >= (unsigned long long)total)
+            break;
+        const int q = __builtin_amdgcn_readfirstlane((int)(t % (unsigned long long)a.nq));
+        const int r0 = (int)(t / (unsigned long long)a.nq) * LBS_TASK;
+        const int cnt = surv_cnt[q];
+        if (r0 >= cnt)
+            continue;
+        const int r1 = min(r0 + LBS_TASK, cnt);
+        const float *E = a.env + (int64_t)q * n * 2 * D;
+        for (int r = r0; r < r1; ++r) {
+            const float tau = bits_f(load_relaxed_u32(a.tau + q));
+            const int c = __builtin_amdgcn_readfirstlane(surv[(int64_t)q * a.N + r]);
+            const float *cp = a.aos + a.off[c] * D;
+            float acc = 0.0f;
+            bool over = false;
+            int j0 = 0;
+            for (; j0 < n; j0 += 64) {
+                const int j = j0 + lane;
+                if (j < n) {
+                    float x[D];
+                    load_point<D>(cp + (int64_t)j * D, x);
+                    const float *e = E + (int64_t)j * 2 * D;
+                    float tt = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const float d = fmaxf(fmaxf(e[k] - x[k], x[k] - e[D + k]), 0.0f);
+                        tt = (k == 0) ? d * d : __builtin_fmaf(d, d, tt);
+                    }
+                    acc += tt;
+                }
+                if ((j0 & 255) == 192 && j0 + 64 < n) {
+                    // every 256 points: stop once the partial bound exceeds tau
+                    if (wave_sum(acc) * scale > tau) {
+                        over = true;
+                        j0 += 64;
+                        break;
+                    }
+                }
+            }
+            terms += (unsigned long long)min(j0, n);
+            const float lb = wave_sum(acc) * scale;
+            if (lane == 0)
+                a.lbv[(int64_t)q * a.N + c] = (over || lb > tau) ? tsk_inf() : lb;
+        }
+    }
+    if (lane != 0)
+        terms = 0;
+    wave_count(a.ctr, C_BOUND_STEPS, terms);
 }
 
 } // namespace tsk

@@ -240,7 +240,7 @@ extern "C" int tsk_subseq_query(const float *series_dev, const int64_t *s_offset
     TSK_TRY(b.seedslots.ensure(G * k));
     TSK_TRY(b.resslots.ensure(G * k));
     TSK_TRY(b.work.ensure(1));
-    TSK_TRY(b.ctr.ensure(C_NUM));
+    TSK_TRY(b.ctr.ensure(CTR_WORDS));
     TSK_TRY(b.clb.ensure(G * chunks));
     TSK_TRY(b.cj.ensure(G * chunks));
     TSK_TRY(b.pclb.ensure(G * N));
@@ -253,7 +253,7 @@ extern "C" int tsk_subseq_query(const float *series_dev, const int64_t *s_offset
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(b.coff.p, coff.data(), (N + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
-    fill64(b.ctr.p, 0ull, C_NUM, s);
+    fill64(b.ctr.p, 0ull, CTR_WORDS, s);
     const int waves = o.waves_per_cu ? o.waves_per_cu : 16;
     const int dp_blocks = std::max(1, n_cu * waves / 4);
     float t_seed = 0, t_dp = 0, t_fin = 0, t_all = 0;
@@ -337,9 +337,10 @@ extern "C" int tsk_subseq_query(const float *series_dev, const int64_t *s_offset
         t_all += x;
     }
     if (stats_host) {
-        unsigned long long c[C_NUM];
-        HIP_TRY(hipMemcpyAsync(c, b.ctr.p, sizeof(c), hipMemcpyDeviceToHost, s));
+        unsigned long long words[CTR_WORDS], c[C_NUM];
+        HIP_TRY(hipMemcpyAsync(words, b.ctr.p, sizeof(words), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        ctr_sum(words, c);
         memset(stats_host, 0, sizeof(*stats_host));
         stats_host->pairs = n_queries * N;
         stats_host->seed_pairs = (int64_t)c[C_SEED_PAIRS];

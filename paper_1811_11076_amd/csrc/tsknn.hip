@@ -794,7 +794,7 @@ static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env, bool need_
     TSK_TRY(w.max_cnt.ensure(1));
     TSK_TRY(w.qcur.ensure(nq));
     TSK_TRY(w.rcnt.ensure(nq));
-    TSK_TRY(w.ctr.ensure(C_NUM));
+    TSK_TRY(w.ctr.ensure(CTR_WORDS));
     TSK_TRY(w.work.ensure(8));
     TSK_TRY(w.qoff.ensure(nq + 1));
     if (need_env)
@@ -866,6 +866,8 @@ static void apply_tuned(tsk_query_opts *o, const tsk_query_opts &t)
     o->dp_rows = t.dp_rows;
     o->dp_waves_per_cu = t.dp_waves_per_cu;
     o->dk_seed = t.dk_seed;
+    o->bound_seed = t.bound_seed;
+    o->dtw_cascade = t.dtw_cascade;
 }
 
 // A range query (fixed threshold, every hit reported) riding on the k-NN
@@ -910,7 +912,7 @@ static size_t carve_ws(const tsk_index *ix, const WsShape &sh, char *base, Works
     take(w->max_cnt, 1);
     take(w->qcur, nq);
     take(w->rcnt, nq);
-    take(w->ctr, C_NUM);
+    take(w->ctr, CTR_WORDS);
     take(w->work, 8);
     take(w->qoff, nq + 1);
     if (sh.env)
@@ -1027,6 +1029,10 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "lb_both must be 0 or 1");
     if (o.raw_keys != 0 && o.raw_keys != 1)
         return set_err(TSK_ERR_INVALID_ARG, "raw_keys must be 0 or 1");
+    if (o.bound_seed < 0 || o.bound_seed > 2)
+        return set_err(TSK_ERR_INVALID_ARG, "bound_seed must be 0, 1 or 2");
+    if (o.dtw_cascade < 0 || o.dtw_cascade > 2)
+        return set_err(TSK_ERR_INVALID_ARG, "dtw_cascade must be 0, 1 or 2");
     if (o.use_graph && (o.profile || o.order == TSK_ORDER_LEARNED))
         return set_err(TSK_ERR_UNSUPPORTED, "use_graph excludes profile and TSK_ORDER_LEARNED");
     if (fx && (o.use_graph || o.profile || o.order == TSK_ORDER_LEARNED || o.lb_both || rr ||
@@ -1133,7 +1139,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
     // statistics counters only when a call reports them
     unsigned long long *const ctr = timed ? W.ctr.p : nullptr;
     if (profile)
-        TSK_TRY(ix->prof_ctr.ensure(C_NUM));
+        TSK_TRY(ix->prof_ctr.ensure(CTR_WORDS));
     const size_t ev_first = ix->ev_used;
 
     tsk_model *model = const_cast<tsk_model *>(o.model);
@@ -1158,7 +1164,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         int nq;
         int32_t qmin, qmax;
         const int32_t *order;
-        bool lds_query, dk_split, lbu, diag_seed;
+        bool lds_query, dk_split, lbu, diag_seed, dk_cascade, dtw_cascade, dtw_bseed;
         int fast, wsel, qrows;
     };
     auto plan_chunk = [&](int64_t q0) {
@@ -1182,6 +1188,21 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         // equal lengths: the diagonal path seeds DTW, and DK on request
         c.diag_seed = P.seed > 0 && (dist == TSK_DTW || o.dk_seed == 1) && c.qmin == c.qmax &&
                       ix->min_len == ix->max_len && ix->min_len == c.qmin && o.dp_kernel != 1;
+        // threshold seed from the candidates of smallest corner bound (plain
+        // order; the learned and given orders seed from their own head)
+        // (DK by default in the plain order; DTW on request, or with the
+        // cascade below)
+        const bool seedable = !rr && P.seed > 0;
+        c.dk_cascade = seedable && c.dk_split &&
+                       (o.bound_seed == 1 || (o.bound_seed == 0 && o.order == TSK_ORDER_PLAIN));
+        // DTW on equal lengths (by default in the plain order): the corner
+        // bound first, LB_Box only for its survivors
+        const bool dtw_eq = seedable && c.diag_seed && dist == TSK_DTW && P.env_ok;
+        c.dtw_cascade = dtw_eq && o.lb_qgroup != 1 && !lb_rev &&
+                        (o.dtw_cascade == 1 ||
+                         (o.dtw_cascade == 0 && o.bound_seed != 2 && o.order == TSK_ORDER_PLAIN &&
+                          o.lb_qgroup == 0));
+        c.dtw_bseed = dtw_eq && (o.bound_seed == 1 || c.dtw_cascade);
         c.fast = pick_fast(ix, dist, band, c.qmin, c.qmax, o.dp_kernel, o.dk_band_slots, &c.wsel);
         c.qrows = c.qmax + 2 * QPAD;
         return c;
@@ -1228,23 +1249,65 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         SeedRingArgs seed_args{qv, W.qoff.p, nq, c.qmax, ix->aos, ix->off, ix->len, ix->n,
                                c.order, 0, P.seed, k, P.ba, W.seedslots.p, W.tau.p, ctr,
                                nullptr, nullptr};
-        if (c.diag_seed) {
+        const bool cascade = c.dk_cascade || c.dtw_bseed;
+        if (cascade) {
+            // corner bound of every pair (the threshold is still +inf: none
+            // pruned), then each query's seed set = its P.seed candidates of
+            // smallest corner bound, in ascending bound
+            BoundArgs cb = bound_args(ix, qv, nq, P);
+            // it counts the pairs unless LB_Box still runs on all of them
+            cb.ctr = (c.dk_cascade || c.dtw_cascade) ? ctr : nullptr;
+            launch_corner(P.D, dist, cb, s);
+            hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
+                               SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,
+                               nullptr, nullptr, W.tau.p, W.surv.p, W.surv_cnt.p, W.max_cnt.p,
+                               nullptr, (int64_t)P.seed);
+            seed_args.order = W.surv.p;
+        }
+        if (c.diag_seed && !(c.dtw_cascade && c.lds_query)) {
             // equal lengths: diagonal-path sums seed the DTW threshold
             launch_seed_diag(P.D, dist, seed_args, s);
         } else if (P.seed > 0 && c.lds_query) {
+            // (the DTW cascade: greedy walks of Alg. 1 summing their costs;
+            // they follow a warped neighbour where the diagonal does not, so
+            // their threshold lets the corner bound prune)
             // the first 64 candidates walk to the end and set a threshold;
             // the rest of the seed set returns early against it
             launch_seed_ring(P.D, dist, seed_args, s);
         } else {
             dispatch_d<SeedLaunch>(P.D, ix, qv, nq, P, c.order, s);
         }
+        if (cascade)
+            fill_u32((uint32_t *)W.max_cnt.p, 0u, 1, s); // the seed list's count
+        // survivors by ascending bound by default for DTW (measured faster
+        // on every class-warp workload), candidate order for DK (mixed)
+        const int so = o.surv_order != 0 ? o.surv_order : (dist == TSK_DTW ? 1 : 2);
+        auto compact = [&]() {
+            if (so == 1)
+                hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
+                                   SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,
+                                   c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr,
+                                   W.tau.p, W.surv.p, W.surv_cnt.p, W.max_cnt.p, ctr, ix->n);
+            else
+                hipLaunchKernelGGL(k_compact, dim3(nq), dim3(1024), 0, s, W.lbv.p, ix->n, c.order,
+                                   c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr,
+                                   W.tau.p, W.surv.p, W.surv_cnt.p, W.max_cnt.p, ctr);
+        };
+        if (c.dtw_cascade)
+            compact(); // the corner survivors, before LB_Box
         TSK_MARK(2);
         BoundArgs ba = bound_args(ix, qv, nq, P);
         ba.ctr = ctr;
         if (rr)
             ba.ubslots = nullptr;
-        if (c.dk_split) {
-            launch_corner(P.D, ba, s);
+        if (c.dtw_cascade) {
+            // LB_Box of the corner survivors only (lbv: their LB_Box or +inf)
+            launch_bound_lb_surv(P.D, ba, W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.work.p + 6,
+                                 ix->n_cu * 8, s);
+        } else if (c.dk_cascade) {
+            // the corner bounds are in lbv already
+        } else if (c.dk_split) {
+            launch_corner(P.D, dist, ba, s);
         } else if (dist == TSK_DTW && P.env_ok && o.dp_kernel != 1) {
             if (o.lb_qgroup == 1 && lb_pp_lds_bytes(P.D, ba.env_n) <= LB_PP_MAX_LDS) {
                 launch_bound_lb_pp(P.D, ba, s); // per pair, early abandoning
@@ -1263,18 +1326,9 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
         }
         TSK_MARK(3);
-        // survivors by ascending bound by default for DTW (measured faster
-        // on every class-warp workload), candidate order for DK (mixed)
-        const int so = o.surv_order != 0 ? o.surv_order : (dist == TSK_DTW ? 1 : 2);
-        if (so == 1)
-            hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
-                               SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,
-                               c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr, W.tau.p,
-                               W.surv.p, W.surv_cnt.p, W.max_cnt.p, ctr);
-        else
-            hipLaunchKernelGGL(k_compact, dim3(nq), dim3(256), 0, s, W.lbv.p, ix->n, c.order,
-                               c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr, W.tau.p,
-                               W.surv.p, W.surv_cnt.p, W.max_cnt.p, ctr);
+        if (c.dtw_cascade)
+            fill_u32((uint32_t *)W.max_cnt.p, 0u, 1, s); // re-ranked by LB_Box below
+        compact();
         if (lb_rev) {
             // LB_Box in both orientations: the survivors' bounds become the
             // larger one (queries of another length keep theirs)
@@ -1354,7 +1408,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                                     o.dp_kernel, o.walk_pass, o.task_size, o.tube_rows,
                                     o.lb_qgroup, o.dk_band_slots, o.surv_order, o.dp_rows,
                                     o.dp_waves_per_cu, o.dk_seed, o.lb_both, o.raw_keys,
-                                    (int64_t)timed};
+                                    o.bound_seed, o.dtw_cascade, (int64_t)timed};
         // every workspace buffer the captured kernels address: a buffer
         // reallocated by another call changes the key
         for (const void *ptr :
@@ -1385,7 +1439,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             hipStream_t cs = ix->cap_stream;
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            fill_u64(W.ctr.p, 0ull, C_NUM, cs);
+            fill_u64(W.ctr.p, 0ull, CTR_WORDS, cs);
             const int rc = enqueue_chunk(c, nullptr, cs);
             const hipError_t ec = hipStreamEndCapture(cs, &g);
             if (rc != TSK_OK) {
@@ -1404,7 +1458,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         if (stats_host)
             HIP_TRY(hipEventRecord(ix->gev[1], s));
     } else {
-        fill_u64(W.ctr.p, 0ull, C_NUM, s);
+        fill_u64(W.ctr.p, 0ull, CTR_WORDS, s);
         for (int64_t q0 = 0; q0 < n_queries; q0 += P.chunk) {
             if (o.cancel_flag_host && *o.cancel_flag_host != 0)
                 return set_err(TSK_ERR_CANCELLED, "cancelled before query %lld", (long long)q0);
@@ -1445,13 +1499,15 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
     }
     HIP_TRY(hipGetLastError());
     if (profile) {
-        hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, s, ix->prof_ctr.p, W.ctr.p, (int)C_NUM);
+        hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(256), 0, s, ix->prof_ctr.p, W.ctr.p,
+                           (int)CTR_WORDS);
         ix->prof_calls += 1;
     }
     if (stats_host) {
-        unsigned long long c[C_NUM];
-        HIP_TRY(hipMemcpyAsync(c, W.ctr.p, sizeof(c), hipMemcpyDeviceToHost, s));
+        unsigned long long words[CTR_WORDS], c[C_NUM];
+        HIP_TRY(hipMemcpyAsync(words, W.ctr.p, sizeof(words), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        ctr_sum(words, c);
         memset(stats_host, 0, sizeof(*stats_host));
         stats_from(stats_host, c);
         stats_host->calls = 1;
@@ -1574,9 +1630,10 @@ extern "C" int tsk_index_profile(tsk_index *ix, tsk_stats *out, int32_t reset)
     float t[NEV - 1];
     TSK_TRY(sum_events(ix, 0, ix->ev_used, t));
     if (ix->prof_ctr.p) {
-        unsigned long long c[C_NUM];
+        unsigned long long words[CTR_WORDS], c[C_NUM];
         HIP_TRY(hipDeviceSynchronize());
-        HIP_TRY(hipMemcpy(c, ix->prof_ctr.p, sizeof(c), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(words, ix->prof_ctr.p, sizeof(words), hipMemcpyDeviceToHost));
+        ctr_sum(words, c);
         stats_from(out, c);
     }
     out->calls = ix->prof_calls;
@@ -1585,7 +1642,7 @@ extern "C" int tsk_index_profile(tsk_index *ix, tsk_stats *out, int32_t reset)
         ix->ev_used = 0;
         ix->prof_calls = 0;
         if (ix->prof_ctr.p) {
-            fill_u64(ix->prof_ctr.p, 0ull, C_NUM, nullptr);
+            fill_u64(ix->prof_ctr.p, 0ull, CTR_WORDS, nullptr);
             HIP_TRY(hipDeviceSynchronize());
         }
     }
@@ -1644,7 +1701,7 @@ extern "C" int tsk_pair_distances(const tsk_index *cix, const float *q_values_de
         const int nq = (int)std::min<int64_t>(chunk, n_queries - q0);
         TSK_TRY(upload_qoff(ix, q_offsets_host, q0, nq, s));
         fill_u64(ix->ws.work.p, 0ull, 8, s);
-        fill_u64(ix->ws.ctr.p, 0ull, C_NUM, s);
+        fill_u64(ix->ws.ctr.p, 0ull, CTR_WORDS, s);
         DpArgs da = dp_args(ix, q_values_dev, nq, P);
         da.out_all = out_keys_dev + q0 * ix->n;
         launch_dp_wave(P.D, dist, DPW_ALLPAIRS, da, dp_blocks(ix), s);
@@ -1679,7 +1736,7 @@ extern "C" int tsk_pair_bounds(const tsk_index *cix, const float *q_values_dev,
     for (int64_t q0 = 0; q0 < n_queries; q0 += chunk) {
         const int nq = (int)std::min<int64_t>(chunk, n_queries - q0);
         TSK_TRY(upload_qoff(ix, q_offsets_host, q0, nq, s));
-        fill_u64(ix->ws.ctr.p, 0ull, C_NUM, s);
+        fill_u64(ix->ws.ctr.p, 0ull, CTR_WORDS, s);
         if (P.env_ok)
             dispatch_d<EnvLaunch>(P.D, ix, q_values_dev, nq, P.ba, s);
         BoundArgs ba = bound_args(ix, q_values_dev, nq, P);
@@ -1793,8 +1850,12 @@ extern "C" int tsk_tune(tsk_index *ix, const float *q_values_dev, const int64_t 
         }
         if (lbu)
             knobs.push_back({&tsk_query_opts::lb_qgroup, {2, 4, 8}});
-        else if (dist == TSK_DTW)
+        else if (dist == TSK_DTW) {
+            knobs.push_back({&tsk_query_opts::dtw_cascade, {1, 2}}); // corner first or not
             knobs.push_back({&tsk_query_opts::lb_qgroup, {1, 8, 16}}); // LB kernel and query group
+        }
+        if (dk_free)
+            knobs.push_back({&tsk_query_opts::bound_seed, {1, 2}});
         knobs.push_back({&tsk_query_opts::surv_order, {1, 2}});
         knobs.push_back({&tsk_query_opts::dp_rows, {1, 2, 4}});
         knobs.push_back({&tsk_query_opts::dp_waves_per_cu, {8, 16, 32}});

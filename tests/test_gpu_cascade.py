@@ -1,0 +1,116 @@
+"""The corner-bound cascade and the bound-ordered threshold seed, through
+the C-ABI, against the oracle's plain k-NN definition.
+
+Every warping path contains the first and the last cell, so the corner
+bound (DK: the larger of their costs, DTW: their sum) never exceeds the
+distance; seeding the threshold from the candidates of smallest corner
+bound and computing LB_Box (eq. (1)) only for the corner survivors change
+which pairs are pruned, never the rows: ids and distance bits equal the
+oracle's, the other settings' rows, and graph replays of the call."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_cases import assert_same_knn, classwarp, ragged_walks, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _index(vals, off):
+    from paper_1811_11076_amd import Index
+    return Index(to_dev(vals), off)
+
+
+SETTINGS = [
+    # (bound_seed, dtw_cascade)
+    (0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (2, 1),
+]
+
+
+@pytest.mark.parametrize("d", [1, 3, 6, 8])
+@pytest.mark.parametrize("band", [None, 0, 4, 0.1])
+def test_cascade_random_walks(d, band):
+    """Random walks of one length (L = 97: ragged steps), an exact copy of a
+    query (distance 0 at both corners) and a copy with its end point moved
+    (same first cell, a larger corner bound), k = 7 of 500."""
+    print(f"[case] cascade walks d={d} band={band}", flush=True)
+    db, dbo = ragged_walks(900 + d, 500, (97, 97), d)
+    qs, qo = ragged_walks(901 + d, 6, (97, 97), d)
+    db[dbo[40]:dbo[41]] = qs[qo[2]:qo[3]]
+    db[dbo[41]:dbo[42]] = qs[qo[2]:qo[3]]
+    db[dbo[42] - 1] += 0.5
+    idx = _index(db, dbo)
+    dq = to_dev(qs)
+    for distance in ("dk", "dtw"):
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 7, distance, band)
+        for bs, cas in SETTINGS:
+            ids, dst, st = idx.knn(dq, qo, 7, distance, band, stats=True, bound_seed=bs,
+                                   dtw_cascade=cas)
+            assert_same_knn(ids, dst, ref_ids, ref_keys, distance)
+            assert st["pairs"] == 6 * 500
+    idx.close()
+
+
+@pytest.mark.parametrize("seed_count", [1, 10, 512, 3000])
+def test_cascade_classwarp(seed_count):
+    """Class-warp series (10 classes, L = 256, d = 3), k = 10: DK unbanded
+    and DTW in the 10 % band, seed sets from one candidate to all of them,
+    every setting of the seed and the cascade."""
+    print(f"[case] cascade classwarp seed_count={seed_count}", flush=True)
+    db, dbo, qs, qo = classwarp(2, 10, 256, 3, 3000, 12)
+    idx = _index(db, dbo)
+    dq = to_dev(qs)
+    for distance, band in (("dk", None), ("dtw", 0.1)):
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, distance, band)
+        st = {}
+        for bs, cas in SETTINGS:
+            ids, dst, st[(bs, cas)] = idx.knn(dq, qo, 10, distance, band, stats=True,
+                                              seed_count=seed_count, bound_seed=bs,
+                                              dtw_cascade=cas)
+            assert_same_knn(ids, dst, ref_ids, ref_keys, distance)
+        print(f"  {distance}: completed DPs bound-ordered {st[(1, 0)]['dp_completed']} "
+              f"head {st[(2, 0)]['dp_completed']}; seed+bound steps cascade "
+              f"{st[(0, 1)]['bound_steps']} all-pairs LB_Box {st[(0, 0)]['bound_steps']}",
+              flush=True)
+    idx.close()
+
+
+def test_cascade_graph_replay_and_chunks_cascade_on():
+    _graph_and_chunks(dict(dtw_cascade=1))
+
+
+def test_cascade_graph_replay_and_chunks():
+    _graph_and_chunks({})
+
+
+def _graph_and_chunks(kw):
+    """The cascade inside a captured graph (three replays, eager work and a
+    synchronisation between them) and over several query chunks (a small
+    workspace bound) gives the eager single-chunk rows."""
+    import torch
+    from paper_1811_11076_amd import Index
+    db, dbo, qs, qo = classwarp(2, 10, 128, 3, 2000, 16)
+    dq = to_dev(qs)
+    idx = _index(db, dbo)
+    small = Index(to_dev(db), dbo, workspace_limit_bytes=2000 * 20 * 3 + 128 * 64 * 3)
+    for distance, band in (("dk", None), ("dtw", 0.1)):
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, distance, band)
+        ids, dst, _ = small.knn(dq, qo, 10, distance, band, **kw)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, distance)
+        out = (torch.empty((16, 10), dtype=torch.int64, device="cuda"),
+               torch.empty((16, 10), dtype=torch.float32, device="cuda"))
+        for rep in range(3):
+            idx.knn(dq, qo, 10, distance, band, use_graph=True, out=out, **kw)
+            torch.cuda.synchronize()
+            assert_same_knn(out[0], out[1], ref_ids, ref_keys, distance)
+            idx.knn(dq[:int(qo[3])], qo[:4], 10, "dtw", 3)
+            torch.cuda.synchronize()
+    small.close()
+    idx.close()

@@ -53,6 +53,29 @@ def _check(db, dbo, qs, qo, ids, dist, distance, band):
         assert row == sorted(row) and len(set(ids[q].tolist())) == K
 
 
+def _same_or_report(db, dbo, qs, qo, runs, distance, band):
+    """Rows of two runs equal; if not, the differing rows are checked
+    against the oracle so that the failure names the wrong side."""
+    (na, (ia, da)), (nb, (ib, dbb)) = runs.items()
+    ia, da, ib, dbb = (t.cpu().numpy() for t in (ia, da, ib, dbb))
+    rows = np.nonzero((ia != ib).any(1) | (da.view(np.uint32) != dbb.view(np.uint32)).any(1))[0]
+    if rows.size == 0:
+        return
+    report = [f"{rows.size} rows differ: {rows[:16].tolist()}"]
+    for q in rows[:4]:
+        one = qs[qo[q]:qo[q + 1]]
+        rids, rkeys, _ = O.knn_verify(db, dbo, one, np.array([0, len(one)], np.int64), K,
+                                      distance, band)
+        exp = np.sqrt(rkeys.astype(np.float32)) if distance == "dk" else rkeys.astype(np.float32)
+        for name, ids, dist in ((na, ia, da), (nb, ib, dbb)):
+            ok = np.array_equal(ids[q], rids[0]) and \
+                np.array_equal(dist[q].view(np.uint32), exp[0].view(np.uint32))
+            report.append(f"query {q} {name} {'equals' if ok else 'differs from'} the oracle: "
+                          f"{ids[q].tolist()} {dist[q].tolist()} vs {rids[0].tolist()} "
+                          f"{exp[0].tolist()}")
+    raise AssertionError("\n".join(report))
+
+
 @pytest.mark.parametrize("distance,band", [("dk", None), ("dtw", BAND)])
 def test_uneven_full_size(workload, distance, band):
     db, dbo, qs, qo, idx = workload
@@ -76,8 +99,8 @@ def test_uneven_full_size_graph_replay(workload):
             print(f"[case] full-size uneven graph replay {rep} {dist}", flush=True)
             idx.knn(dq, qo, K, dist, band, use_graph=True, out=out[dist])
             torch.cuda.synchronize()
-            assert torch.equal(out[dist][0], ref[dist][0][0])
-            assert torch.equal(out[dist][1], ref[dist][0][1])
+            _same_or_report(db, dbo, qs, qo, {"eager": ref[dist][:2], "graph": out[dist]},
+                            dist, band)
             # eager work between replays
             idx.knn(dq[:int(qo[4])], qo[:5], K, "dtw", BAND)
             torch.cuda.synchronize()

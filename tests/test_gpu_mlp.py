@@ -148,9 +148,13 @@ def test_learned_order_exact_and_gain():
     ref_ids, ref_keys, _ = O.knn_scan(db, dbo, qs, qo, 10, "dk", None)
     res = {}
     full = dict(seed_count=len(dbo) - 1)   # Alg. 1 over every candidate
-    for name, kw in (("plain", {}), ("untrained", dict(order="learned", model=untrained)),
+    # "plain": the first candidates of the plain order seed the threshold;
+    # "plain_bound_seed": the library default for the plain order, the
+    # candidates of smallest corner bound
+    for name, kw in (("plain", dict(bound_seed=2)), ("plain_bound_seed", {}),
+                     ("untrained", dict(order="learned", model=untrained)),
                      ("trained", dict(order="learned", model=trained)),
-                     ("plain_full_seed", full),
+                     ("plain_full_seed", dict(bound_seed=2, **full)),
                      ("trained_full_seed", dict(order="learned", model=trained, **full))):
         ids, dst, st = idx.knn(to_dev(qs), qo, 10, "dk", None, stats=True, **kw)
         assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
