@@ -43,7 +43,7 @@ WORKLOADS = {
     # the large configuration: 200 classes, two independent 3-D tracks per series
     "classwarp-q4096-n1000000-L512-d6": dict(cfg_id=5, gen="classwarp", classes=200, Q=4096,
                                              N=1000000, L=512, d=6, k=10, dk_band=None,
-                                             dtw_band=0.1, step_order="learned"),
+                                             dtw_band=0.1, large=True),
     # uneven lengths: members of length U{64..1024} from 50 prototypes of length 1024
     "classwarp-q1024-n100000-L64to1024-d3": dict(cfg_id=3, gen="classwarp", classes=50, Q=1024,
                                                  N=100000, L=1024, lengths=(64, 1024), d=3,
@@ -93,34 +93,36 @@ def make_data(w):
     return db, dbo, qs, qo
 
 
-def kernel_rooflines(prof, dist, d, fast_kernel, uneven=False):
-    """Per-kernel device time (HIP events around each kernel on its launch
-    stream, averaged per call) and algorithmic work of one distance's
-    profile.  Work units: DP = in-band in-matrix cells of live pairs, 2d+2
-    ops each; LB_Box = terms, 4d+1 ops each; corner bound = 2 point costs per
-    pair (4d+1 ops); greedy seed = moves (~6d+4 ops)."""
-    calls = max(1, prof["calls"])
+def kernel_rooflines(prof, dist, d, fast_kernel, uneven=False, cascade=None):
+    """Per-kernel device time and algorithmic work of one distance's
+    profile, per launch: HIP events around each stage on its launch stream,
+    summed over the profiled calls and divided by the launches (one per
+    query chunk).  Work units: DP = in-band in-matrix cells of live pairs,
+    2d+2 ops each; LB_Box = terms, 4d+1 ops each; corner bound = 2 point
+    costs per pair (4d+1 ops); greedy seed = moves (~6d+4 ops).  cascade:
+    the corner bound runs inside the seed stage (DK by default; DTW on
+    equal lengths in the plain order by default), and DTW's LB_Box kernel is
+    the survivors' one (k_bound_lb_surv)."""
+    if cascade is None:
+        cascade = dist == "dk" or not uneven
+    n = max(1, prof["chunks"])
     cell_ops = 2 * d + 2
     fast_cells = prof["dp_valid_cells"] - prof["dp_valid_cells_general"]
     out = {
-        fast_kernel: dict(ms=prof["ms_dp_fast"] / calls, units=fast_cells / calls,
-                          unit_ops=cell_ops),
-        "k_dp_wave": dict(ms=prof["ms_dp_general"] / calls,
-                          units=prof["dp_valid_cells_general"] / calls, unit_ops=cell_ops),
+        fast_kernel: dict(ms=prof["ms_dp_fast"] / n, units=fast_cells / n, unit_ops=cell_ops),
+        "k_dp_wave": dict(ms=prof["ms_dp_general"] / n,
+                          units=prof["dp_valid_cells_general"] / n, unit_ops=cell_ops),
     }
+    seed_name = ("seed stage (k_corner, k_compact_sorted, k_seed_ring)" if cascade
+                 else ("k_seed_ring" if (uneven or dist == "dk") else "k_seed_diag"))
+    out[seed_name] = dict(ms=prof["ms_seed"] / n, units=prof["seed_steps"] / n, unit_ops=6 * d + 4)
     if dist == "dtw":
-        out["k_bound_lbu" if uneven else "k_bound_lb"] = dict(
-            ms=prof["ms_bound_kernel"] / calls, units=prof["bound_steps"] / calls,
-            unit_ops=4 * d + 1)
-        if uneven:
-            out["k_seed_ring"] = dict(ms=prof["ms_seed"] / calls, units=0, unit_ops=0)
-        else:
-            out["k_seed_diag"] = dict(ms=prof["ms_seed"] / calls, units=0, unit_ops=0)
-    else:
-        out["k_corner"] = dict(ms=prof["ms_bound_kernel"] / calls, units=prof["pairs"] / calls,
+        name = "k_bound_lbu" if uneven else ("k_bound_lb_surv" if cascade else "k_bound_lb")
+        out[name] = dict(ms=prof["ms_bound_kernel"] / n, units=prof["bound_steps"] / n,
+                         unit_ops=4 * d + 1)
+    elif not cascade:
+        out["k_corner"] = dict(ms=prof["ms_bound_kernel"] / n, units=prof["pairs"] / n,
                                unit_ops=4 * d + 1)
-        out["k_seed_ring"] = dict(ms=prof["ms_seed"] / calls, units=prof["bound_steps"] / calls,
-                                  unit_ops=6 * d + 4)
     for v in out.values():
         v["ops"] = v["units"] * v["unit_ops"]
         v["tops"] = v["ops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0
@@ -549,7 +551,7 @@ def roofline_of(prof_dk, prof_dtw, w, uneven, workload):
             "dtw": kernel_rooflines(prof_dtw, "dtw", w["d"], "k_dp_band", uneven)}
     if uneven:
         kern["dtw"].pop("k_dp_band")  # uneven lengths: every DTW DP is a general one
-    dist_dom, kname = max(((dd, kk) for dd in kern for kk in kern[dd]),
+    dist_dom, kname = max(((dd, kk) for dd in kern for kk in kern[dd] if "stage" not in kk),
                           key=lambda x: kern[x[0]][x[1]]["ms"])
     dom = kern[dist_dom][kname]
     roof = {"bound": "alu", "kernel": f"{kname} ({dist_dom})",
@@ -568,8 +570,9 @@ def dist_summary(prof, kern, pairs):
             "stages_ms": {"order": prof["ms_order"] / c, "seed": prof["ms_seed"] / c,
                           "bound": prof["ms_bound"] / c, "dp": prof["ms_dp"] / c,
                           "final": prof["ms_final"] / c},
-            "kernels": {k: {"ms": round(v["ms"], 4), "TOP/s": round(v["tops"], 3)}
-                        for k, v in kern.items()},
+            "launches_per_call": prof["chunks"] / c,
+            "kernels_per_launch": {k: {"ms": round(v["ms"], 4), "TOP/s": round(v["tops"], 3)}
+                                   for k, v in kern.items()},
             "dp_started": prof["dp_started"] / c, "dp_completed": prof["dp_completed"] / c,
             "dp_valid_cells": prof["dp_valid_cells"] / c,
             "fallback_pairs": prof["fallback_pairs"] / c}
@@ -647,7 +650,7 @@ def run_large(name, w, args):
     torch.cuda.synchronize()
     prof_learned = idx_dk.profile(reset=True)
     learned_same = torch.equal(ldk_res[0], res[0][0]) and torch.equal(ldk_res[1], res[0][1])
-    kern_learned = kernel_rooflines(prof_learned, "dk", w["d"], "k_dp_tube")
+    kern_learned = kernel_rooflines(prof_learned, "dk", w["d"], "k_dp_tube", cascade=False)
     print(f"[bench] learned-order DK: "
           f"{prof_learned['ms_total'] / max(1, prof_learned['calls']):.1f} ms per call",
           file=sys.stderr, flush=True)
@@ -665,7 +668,7 @@ def run_large(name, w, args):
                                bound_seed=2)
         torch.cuda.synchronize()
         prof_all = idx_dtw.profile(reset=True)
-        kern_all = kernel_rooflines(prof_all, "dtw", w["d"], "k_dp_band")
+        kern_all = kernel_rooflines(prof_all, "dtw", w["d"], "k_dp_band", cascade=False)
         dtw_lb_all = dist_summary(prof_all, kern_all, pairs)
         dtw_lb_all["rows_equal_default"] = bool(torch.equal(cres[0], res[1][0]) and
                                                 torch.equal(cres[1], res[1][1]))
@@ -886,7 +889,7 @@ def main():
         del src, dst
 
     w = WORKLOADS[args.workload]
-    large = w.get("step_order") == "learned"
+    large = bool(w.get("large"))
     if args.cpu_queries <= 0:
         args.cpu_queries = 16 if large else 64
     if large:

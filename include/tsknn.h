@@ -95,7 +95,8 @@ typedef struct {
     int64_t dp_completed;   /* DPs that ended with a value <= threshold */
     int64_t dp_abandoned;   /* DPs stopped early (value > threshold) */
     int64_t dp_cells;       /* DP cells evaluated (lane-cells, dead ones too) */
-    int64_t bound_steps;    /* greedy-bound moves + LB_Box terms */
+    int64_t bound_steps;    /* LB_Box terms + greedy moves of the optional
+                               pass over the survivors */
     int64_t fallback_pairs; /* pairs that left the fast DP for the general one */
     int64_t dp_valid_cells; /* DP cells inside the matrix and the band */
     int64_t calls;          /* calls accumulated (tsk_index_profile) */
@@ -110,13 +111,18 @@ typedef struct {
     int64_t dp_valid_cells_general; /* of dp_valid_cells: general DP's share */
     float ms_order;         /* TSK_ORDER_LEARNED: query embedding, scores and
                                per-query candidate order */
+    int64_t seed_steps;     /* greedy moves of the threshold-seeding walks
+                               (bound_steps counts the other bound work) */
+    int64_t chunks;         /* query chunks: launches of each per-chunk kernel */
 } tsk_stats;
 
 typedef struct {
     int64_t size;                  /* sizeof(tsk_query_opts) */
     int32_t order;                 /* TSK_ORDER_PLAIN, _GIVEN or _LEARNED */
     int32_t seed_count;            /* candidates per query used to seed the
-                                      threshold (0 = library default) */
+                                      threshold (0 = library default: 128
+                                      with the corner-bound seed, else 512
+                                      for DK and 1024 for DTW) */
     const int32_t *order_dev;      /* TSK_ORDER_GIVEN: [n_queries][n_series]
                                       candidate ids, each row a permutation;
                                       the first seed_count entries form the
@@ -140,7 +146,8 @@ typedef struct {
                                       survivors of the corner bound before
                                       the DP: -1 auto, 0 off, 1 on */
     int32_t task_size;             /* survivors per wave task of the sparse-DK
-                                      kernel (0 = library default) */
+                                      kernel (0 = library default: 64, 128
+                                      or 256 from 2^16 / 2^19 series up) */
     int32_t tube_rows;             /* rows per lane window of the sparse-DK
                                       kernel: 8, 16 or 32 (0 = library
                                       default, 16);
@@ -311,7 +318,7 @@ int tsk_knn_query(const tsk_index *index, const float *q_values_dev, const int64
  * allocates nothing: no hipMalloc, hipFree or allocating library routine.
  * The caller still passes the queries and the outputs (device memory).
  * Queries are split into chunks whose workspace fits the array (the
- * workspace per query grows with the database: about 20 bytes per series,
+ * workspace per query grows with the database: about 20-24 bytes per series,
  * plus the staged query); a call whose single query does not fit returns
  * TSK_ERR_INVALID_ARG before any device work.  No statistics.  Excluded
  * (TSK_ERR_UNSUPPORTED): use_graph, profile, TSK_ORDER_LEARNED, lb_both.

@@ -65,7 +65,8 @@ class Stats(ctypes.Structure):
                 ("ms_dp", ctypes.c_float), ("ms_final", ctypes.c_float),
                 ("ms_bound_kernel", ctypes.c_float), ("ms_dp_fast", ctypes.c_float),
                 ("ms_dp_general", ctypes.c_float), ("dp_valid_cells_general", ctypes.c_int64),
-                ("ms_order", ctypes.c_float)]
+                ("ms_order", ctypes.c_float), ("seed_steps", ctypes.c_int64),
+                ("chunks", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -58,7 +58,8 @@ template <int D> void seed_diag_d(int dist, const SeedRingArgs &r, hipStream_t s
 
 template <int D> void corner_d(int dist, const BoundArgs &a, hipStream_t s)
 {
-    constexpr int QG = 8;
+    // 16 queries per block: each candidate's end points are read once per 16
+    constexpr int QG = 16;
     dim3 grid((unsigned)((a.N + 255) / 256), (unsigned)((a.nq + QG - 1) / QG));
     if (dist == DIST_DK)
         hipLaunchKernelGGL((k_corner<D, QG, DIST_DK>), grid, dim3(256), 0, s, a);
@@ -70,8 +71,13 @@ template <int D>
 void bound_lb_surv_d(const BoundArgs &a, const int32_t *surv, const int32_t *surv_cnt,
                      const int32_t *max_cnt, unsigned long long *work, int blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_bound_lb_surv<D>), dim3(blocks), dim3(256), 0, s, a, surv, surv_cnt,
-                       max_cnt, work);
+    const size_t lds = (size_t)a.env_n * 2 * D * sizeof(float);
+    if (lds <= 64 * 1024)
+        hipLaunchKernelGGL((k_bound_lb_surv<D, true>), dim3(blocks), dim3(256), lds, s, a, surv,
+                           surv_cnt, max_cnt, work);
+    else
+        hipLaunchKernelGGL((k_bound_lb_surv<D, false>), dim3(blocks), dim3(256), 0, s, a, surv,
+                           surv_cnt, max_cnt, work);
 }
 
 template <int D>

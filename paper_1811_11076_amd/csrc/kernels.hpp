@@ -21,6 +21,7 @@ enum {
     C_LATE_PRUNED,
     C_VALID_CELLS,
     C_VALID_GEN, // valid cells of the general DP (also counted in C_VALID_CELLS)
+    C_SEED_STEPS, // greedy moves of the threshold-seeding walks
     C_NUM
 };
 constexpr int CTR_STRIPES = 64;
@@ -324,7 +325,7 @@ __global__ void k_seed(const float *__restrict__ qv, const int64_t *__restrict__
         steps_cnt = steps;
         pairs = 1;
     }
-    wave_count(ctr, C_BOUND_STEPS, steps_cnt);
+    wave_count(ctr, C_SEED_STEPS, steps_cnt);
     wave_count(ctr, C_SEED_PAIRS, pairs);
 }
 
@@ -580,6 +581,8 @@ static __global__ __launch_bounds__(1024) void k_compact(const float *__restrict
 // k_compact (tau is fixed while it runs: no DP of this chunk has started).
 // cap < N keeps only the first cap survivors of that order (the cap
 // smallest bounds, up to the order inside the last bucket they reach).
+// With cnt_in the candidates are a survivor list (order, its counts cnt_in;
+// the output surv must be another buffer), re-ranked by their bounds.
 // One block of 1024 per query; SURV_BUCKETS counters in dynamic LDS.
 constexpr int SURV_BUCKETS = 8192;
 constexpr int SURV_SHIFT = 18;
@@ -587,7 +590,8 @@ static __global__ __launch_bounds__(1024) void k_compact_sorted(
     const float *__restrict__ lbv, int64_t N, const int32_t *__restrict__ order,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ inv,
     const uint32_t *__restrict__ tau, int32_t *__restrict__ surv, int32_t *__restrict__ cnt,
-    int32_t *__restrict__ max_cnt, unsigned long long *ctr, int64_t cap)
+    int32_t *__restrict__ max_cnt, unsigned long long *ctr, int64_t cap,
+    const int32_t *__restrict__ cnt_in)
 {
     extern __shared__ int32_t hist[];
     __shared__ int32_t wsum[16];
@@ -609,7 +613,10 @@ static __global__ __launch_bounds__(1024) void k_compact_sorted(
         }
         lb = lbv[(int64_t)q * N + li];
     };
-    for (int64_t p = tid; p < N; p += 1024) {
+    // cnt_in: re-rank a survivor list (order[q][0 .. cnt_in[q])) instead of
+    // every candidate
+    const int64_t P = cnt_in ? (int64_t)cnt_in[q] : N;
+    for (int64_t p = tid; p < P; p += 1024) {
         int c;
         float lb;
         cand(p, c, lb);
@@ -647,7 +654,7 @@ static __global__ __launch_bounds__(1024) void k_compact_sorted(
     for (int i = 0; i < PER; ++i)
         hist[tid * PER + i] = excl + loc[i];
     __syncthreads();
-    for (int64_t p = tid; p < N; p += 1024) {
+    for (int64_t p = tid; p < P; p += 1024) {
         int c;
         float lb;
         cand(p, c, lb);

@@ -629,7 +629,7 @@ __global__ __launch_bounds__(64) void k_seed_ring(const float *__restrict__ qv,
     if (dbg_ub)
         return;
     wave_topk_insert(seedslots + (int64_t)q * k, k, want, make_key(g, (uint32_t)c), tau + q);
-    wave_count(ctr, C_BOUND_STEPS, steps_cnt);
+    wave_count(ctr, C_SEED_STEPS, steps_cnt);
     wave_count(ctr, C_SEED_PAIRS, pairs);
 }
 
@@ -716,44 +716,60 @@ __global__ __launch_bounds__(256) void k_bound_lb_rev(const float *__restrict__ 
 // LB_Box of the survivors of a first-stage bound (equal lengths, the query
 // envelope of k_env), only for the pairs left in surv: a wave per pair, its
 // 64 lanes on 64 consecutive candidate points at a time (coalesced loads of
-// the candidate and of the envelope), the same per-point terms as k_bound_lb,
-// summed in parallel.  The sum of any order of n <= 4096 non-negative fp32
-// terms is within (n-1) 2^-24 (relative) of the exact sum, so the sum scaled
-// by (1 - 2^-9) (rounding included) is <= the sequential sum of k_bound_lb,
+// the candidate), the same per-point terms as k_bound_lb, summed in
+// parallel.  The sum of any order of n <= 4096 non-negative fp32 terms is
+// within (n-1) 2^-24 (relative) of the exact sum, so the sum scaled by
+// (1 - 2^-9) (rounding included) is <= the sequential sum of k_bound_lb,
 // hence <= the fp32 DTW; that scaled value is the pair's bound.  A partial
 // sum above the query's threshold stops the pair (every term is >= 0) and
 // it leaves with +inf; otherwise lbv gets the bound, which the DP stage
-// compares with the threshold again.  Waves take tasks of LBS_TASK survivors
-// of one query from a work counter, queries interleaved.
-constexpr int LBS_TASK = 16;
+// compares with the threshold again.  A block takes tasks of LBS_TASK
+// survivors of one query from a work counter (queries interleaved), its
+// waves a quarter each; with ENV_LDS the query's envelope is staged in LDS
+// once per task instead of being read by every pair.
+constexpr int LBS_TASK = 64;
 
-template <int D>
+template <int D, bool ENV_LDS>
 __global__ __launch_bounds__(256) void k_bound_lb_surv(BoundArgs a, const int32_t *__restrict__ surv,
                                                        const int32_t *__restrict__ surv_cnt,
                                                        const int32_t *__restrict__ max_cnt,
                                                        unsigned long long *__restrict__ work)
 {
-    const int lane = threadIdx.x & 63;
+    extern __shared__ float senv[]; // [n][2][D] of the task's query (ENV_LDS)
+    __shared__ unsigned long long task_s;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int n = a.env_n;
     const int64_t per_q = (*max_cnt + LBS_TASK - 1) / LBS_TASK;
     const int64_t total = (int64_t)a.nq * per_q;
     const float scale = 1.0f - 0x1.0p-9f;
     unsigned long long terms = 0;
+    int staged = -1;
     for (;;) {
-        unsigned long long t = 0;
-        if (lane == 0)
-            t = atomicAdd(work, 1ull);
-        t = uniform_u64(t);
+        __syncthreads(); // the previous task (and its envelope) is done with
+        if (threadIdx.x == 0)
+            task_s = atomicAdd(work, 1ull);
+        __syncthreads();
+        const unsigned long long t = task_s;
         if (t >= (unsigned long long)total)
             break;
-        const int q = __builtin_amdgcn_readfirstlane((int)(t % (unsigned long long)a.nq));
+        const int q = (int)(t % (unsigned long long)a.nq);
         const int r0 = (int)(t / (unsigned long long)a.nq) * LBS_TASK;
         const int cnt = surv_cnt[q];
         if (r0 >= cnt)
             continue;
-        const int r1 = min(r0 + LBS_TASK, cnt);
         const float *E = a.env + (int64_t)q * n * 2 * D;
-        for (int r = r0; r < r1; ++r) {
+        if (ENV_LDS) {
+            if (q != staged) {
+                for (int i = threadIdx.x; i < n * 2 * D; i += blockDim.x)
+                    senv[i] = E[i];
+                __syncthreads();
+                staged = q;
+            }
+            E = senv;
+        }
+        const int per_w = LBS_TASK / 4;
+        const int r1 = min(r0 + (wv + 1) * per_w, cnt);
+        for (int r = r0 + wv * per_w; r < r1; ++r) {
             const float tau = bits_f(load_relaxed_u32(a.tau + q));
             const int c = __builtin_amdgcn_readfirstlane(surv[(int64_t)q * a.N + r]);
             const float *cp = a.aos + a.off[c] * D;
@@ -765,7 +781,7 @@ __global__ __launch_bounds__(256) void k_bound_lb_surv(BoundArgs a, const int32_
                 if (j < n) {
                     float x[D];
                     load_point<D>(cp + (int64_t)j * D, x);
-                    const float *e = E + (int64_t)j * 2 * D;
+                    const float *e = E + j * 2 * D;
                     float tt = 0.0f;
 #pragma unroll
                     for (int k = 0; k < D; ++k) {

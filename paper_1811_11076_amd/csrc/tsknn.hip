@@ -44,6 +44,7 @@ struct Workspace {
     DevBuf<unsigned long long> seedslots, ubslots, resslots;
     DevBuf<float> lbv;
     DevBuf<int32_t> surv, surv_cnt, max_cnt, qcur;
+    DevBuf<int32_t> surv2;    // survivors re-ranked by LB_Box (DTW cascade)
     DevBuf<float> rng;            // range query hit map [q][N]
     DevBuf<int64_t> rcnt, rqoff;  // its per-query counts and output offsets
     DevBuf<unsigned long long> ctr, work;
@@ -64,6 +65,7 @@ struct Workspace {
         resslots.release();
         lbv.release();
         surv.release();
+        surv2.release();
         surv_cnt.release();
         max_cnt.release();
         qcur.release();
@@ -136,6 +138,7 @@ struct tsk_index {
     size_t ev_used = 0;
     DevBuf<unsigned long long> prof_ctr;
     int64_t prof_calls = 0;
+    int64_t prof_chunks = 0;
 };
 
 static int take_events(tsk_index *ix, hipEvent_t **out)
@@ -163,6 +166,7 @@ static void stats_from(tsk_stats *st, const unsigned long long *c)
     st->fallback_pairs = (int64_t)c[C_FALLBACK];
     st->dp_valid_cells = (int64_t)c[C_VALID_CELLS];
     st->dp_valid_cells_general = (int64_t)c[C_VALID_GEN];
+    st->seed_steps = (int64_t)c[C_SEED_STEPS];
 }
 
 // Stage times of event sets [from, to) of the pool (synchronising):
@@ -780,7 +784,8 @@ static int check_queries(const tsk_index *ix, const float *qv, const int64_t *qo
 }
 
 // Workspace for a chunk of nq queries; sizes follow the index.
-static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env, bool need_cenv = false)
+static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env, bool need_cenv = false,
+                     bool need_surv2 = false)
 {
     Workspace &w = ix->ws;
     const int64_t N = ix->n;
@@ -790,6 +795,8 @@ static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env, bool need_
     TSK_TRY(w.resslots.ensure(nq * k));
     TSK_TRY(w.lbv.ensure(nq * N));
     TSK_TRY(w.surv.ensure(nq * N));
+    if (need_surv2)
+        TSK_TRY(w.surv2.ensure(nq * N));
     TSK_TRY(w.surv_cnt.ensure(nq));
     TSK_TRY(w.max_cnt.ensure(1));
     TSK_TRY(w.qcur.ensure(nq));
@@ -840,9 +847,10 @@ static int64_t chunk_queries(const tsk_index *ix, int64_t nq)
     // grid's y dimension
     int64_t q = std::min<int64_t>(budget / std::max<int64_t>(1, ix->n), 65535);
     if (ix->ws_limit > 0) {
-        // per query: bounds, survivors, fallback pairs and range hits per
-        // series (20 bytes), the envelope and staged rows per point
-        const int64_t per_q = ix->n * 20 + (int64_t)ix->max_len * (8 * ix->dim + 32) + 1024;
+        // per query: bounds, survivors (two lists on equal lengths),
+        // fallback pairs and range hits per series (24 bytes), the envelope
+        // and staged rows per point
+        const int64_t per_q = ix->n * 24 + (int64_t)ix->max_len * (8 * ix->dim + 32) + 1024;
         q = std::min<int64_t>(q, ix->ws_limit / per_q);
     }
     return std::max<int64_t>(1, std::min<int64_t>(nq, q));
@@ -887,7 +895,7 @@ struct RangeReq {
 struct WsShape {
     int64_t nq;
     int k;
-    bool env, qpad, qtab;
+    bool env, qpad, qtab, surv2;
     int qrows;               // staged rows per query (longest query + padding)
     int64_t qtab_floats_q;   // sparse-table floats of the longest query
 };
@@ -908,6 +916,8 @@ static size_t carve_ws(const tsk_index *ix, const WsShape &sh, char *base, Works
     take(w->resslots, nq * sh.k);
     take(w->lbv, nq * N);
     take(w->surv, nq * N);
+    if (sh.surv2)
+        take(w->surv2, nq * N);
     take(w->surv_cnt, nq);
     take(w->max_cnt, 1);
     take(w->qcur, nq);
@@ -1066,14 +1076,22 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
     if (o.use_graph && P.chunk < n_queries)
         return set_err(TSK_ERR_UNSUPPORTED, "use_graph needs the queries to fit one chunk "
                                             "(%lld here)", (long long)P.chunk);
+    P.env_ok = (dist == TSK_DTW) && ix->min_len == ix->max_len;
     // seed sizes: the greedy DK seed is a latency-bound walk (a few hundred
     // candidates give a tight threshold); the diagonal DTW seed is a cheap
-    // parallel sum, so it takes more candidates
-    const int default_seed = dist == TSK_DK ? 512 : 1024;
+    // parallel sum, so it takes more candidates.  Seeds of smallest corner
+    // bound (the cascade) are likely neighbours already: 128 suffice
+    // (measured on 4096 x 1M x 512 x 6: the threshold they give leaves the
+    // DP work unchanged down to 128, while the walks' time halves)
+    const bool plain_seedable = o.order == TSK_ORDER_PLAIN && o.bound_seed != 2;
+    const bool corner_seeded =
+        o.bound_seed == 1 ||
+        (plain_seedable && (dist == TSK_DK || (P.env_ok && o.dtw_cascade != 2 &&
+                                               o.lb_qgroup == 0 && !o.lb_both)));
+    const int default_seed = corner_seeded ? 128 : (dist == TSK_DK ? 512 : 1024);
     P.seed = (int)std::min<int64_t>(ix->n, o.seed_count > 0 ? o.seed_count : default_seed);
     if (rr)
         P.seed = 0; // no threshold seeding: the radius is the threshold
-    P.env_ok = (dist == TSK_DTW) && ix->min_len == ix->max_len;
 
     // the candidate-envelope bound: DTW on an equal-length index
     const bool lb_rev = o.lb_both && dist == TSK_DTW && P.env_ok && o.dp_kernel != 1 && !rr;
@@ -1101,6 +1119,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         WsShape sh;
         sh.k = k;
         sh.env = P.env_ok;
+        sh.surv2 = P.env_ok; // DTW on equal lengths: the cascade may run
         sh.qpad = o.dp_kernel != 1;
         sh.qrows = qmax + 2 * QPAD;
         sh.qtab = dist == TSK_DTW && !P.env_ok && ix->bucketed && o.dp_kernel != 1;
@@ -1129,7 +1148,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         std::swap(ix->ws, fixed_ws);
         lend.on = true;
     }
-    TSK_TRY(ensure_ws(ix, P.chunk, k, P.env_ok, lb_rev));
+    TSK_TRY(ensure_ws(ix, P.chunk, k, P.env_ok, lb_rev, P.env_ok));
     Workspace &W = ix->ws;
     if (rr)
         TSK_TRY(W.rng.ensure((size_t)P.chunk * ix->n));
@@ -1138,8 +1157,13 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
     const bool timed = stats_host != nullptr || profile;
     // statistics counters only when a call reports them
     unsigned long long *const ctr = timed ? W.ctr.p : nullptr;
-    if (profile)
+    if (profile) {
+        // a new profile buffer starts at zero (its memory may hold anything)
+        const bool fresh = ix->prof_ctr.p == nullptr;
         TSK_TRY(ix->prof_ctr.ensure(CTR_WORDS));
+        if (fresh)
+            fill_u64(ix->prof_ctr.p, 0ull, CTR_WORDS, s);
+    }
     const size_t ev_first = ix->ev_used;
 
     tsk_model *model = const_cast<tsk_model *>(o.model);
@@ -1261,7 +1285,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
                                SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,
                                nullptr, nullptr, W.tau.p, W.surv.p, W.surv_cnt.p, W.max_cnt.p,
-                               nullptr, (int64_t)P.seed);
+                               nullptr, (int64_t)P.seed, nullptr);
             seed_args.order = W.surv.p;
         }
         if (c.diag_seed && !(c.dtw_cascade && c.lds_query)) {
@@ -1287,7 +1311,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                 hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
                                    SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,
                                    c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr,
-                                   W.tau.p, W.surv.p, W.surv_cnt.p, W.max_cnt.p, ctr, ix->n);
+                                   W.tau.p, W.surv.p, W.surv_cnt.p, W.max_cnt.p, ctr, ix->n,
+                                   nullptr);
             else
                 hipLaunchKernelGGL(k_compact, dim3(nq), dim3(1024), 0, s, W.lbv.p, ix->n, c.order,
                                    c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr,
@@ -1326,9 +1351,17 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
         }
         TSK_MARK(3);
-        if (c.dtw_cascade)
-            fill_u32((uint32_t *)W.max_cnt.p, 0u, 1, s); // re-ranked by LB_Box below
-        compact();
+        if (c.dtw_cascade) {
+            // the corner survivors re-ranked by their LB_Box (into surv2)
+            fill_u32((uint32_t *)W.max_cnt.p, 0u, 1, s);
+            hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
+                               SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, W.surv.p,
+                               nullptr, nullptr, W.tau.p, W.surv2.p, W.surv_cnt.p, W.max_cnt.p,
+                               ctr, ix->n, W.surv_cnt.p);
+        } else {
+            compact();
+        }
+        int32_t *const surv_dp = c.dtw_cascade ? W.surv2.p : W.surv.p;
         if (lb_rev) {
             // LB_Box in both orientations: the survivors' bounds become the
             // larger one (queries of another length keep theirs)
@@ -1348,6 +1381,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         TSK_MARK(4);
         DpArgs da = dp_args(ix, qv, nq, P);
         da.ctr = ctr;
+        da.surv = surv_dp;
         da.lb_inv = c.lbu ? ix->inv : nullptr;
         da.range_out = rr ? W.rng.p : nullptr;
         if (o.dp_rows != 0)
@@ -1357,10 +1391,16 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             TSK_MARK(5);
             FastArgs fa = fast_args(ix, nq, P, c.qrows);
             fa.ctr = ctr;
+            fa.surv = surv_dp;
             fa.lb_inv = c.lbu ? ix->inv : nullptr;
             fa.range_out = rr ? W.rng.p : nullptr;
             if (c.fast == FAST_TUBE32) {
-                fa.task = o.task_size > 0 ? o.task_size : 64;
+                // survivors per wave task: larger databases leave more
+                // survivors per query, and larger tasks then cut the lanes'
+                // idle tails at task ends (measured: 256 best on 1M series,
+                // 64 on 20 000)
+                fa.task = o.task_size > 0 ? o.task_size
+                                          : (ix->n >= (1 << 19) ? 256 : ix->n >= (1 << 16) ? 128 : 64);
                 // 16-row windows: the live tube of near neighbours is a few
                 // rows wide; the rare wider ones finish in the general DP
                 launch_tube(P.D, fa, o.tube_rows == 0 ? 16 : o.tube_rows, ix->n_cu * fast_waves, c.qmax,
@@ -1418,7 +1458,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
               (const void *)W.qcur.p,
               (const void *)W.work.p, (const void *)W.qoff.p, (const void *)W.env.p,
               (const void *)W.tbuf.p, (const void *)W.qpad.p, (const void *)W.fb.p,
-              (const void *)W.qtab.p, (const void *)W.qtab_off.p, (const void *)W.cenv.p})
+              (const void *)W.qtab.p, (const void *)W.qtab_off.p, (const void *)W.cenv.p,
+              (const void *)W.surv2.p})
             key.push_back((int64_t)(uintptr_t)ptr);
         key.insert(key.end(), q_offsets_host, q_offsets_host + n_queries + 1);
         if (stats_host) {
@@ -1502,6 +1543,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(256), 0, s, ix->prof_ctr.p, W.ctr.p,
                            (int)CTR_WORDS);
         ix->prof_calls += 1;
+        ix->prof_chunks += (n_queries + P.chunk - 1) / P.chunk;
     }
     if (stats_host) {
         unsigned long long words[CTR_WORDS], c[C_NUM];
@@ -1511,6 +1553,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         memset(stats_host, 0, sizeof(*stats_host));
         stats_from(stats_host, c);
         stats_host->calls = 1;
+        stats_host->chunks = (n_queries + P.chunk - 1) / P.chunk;
         if (o.use_graph) {
             // a replayed graph is timed as one interval (no stage marks)
             HIP_TRY(hipEventElapsedTime(&stats_host->ms_total, ix->gev[0], ix->gev[1]));
@@ -1637,10 +1680,12 @@ extern "C" int tsk_index_profile(tsk_index *ix, tsk_stats *out, int32_t reset)
         stats_from(out, c);
     }
     out->calls = ix->prof_calls;
+    out->chunks = ix->prof_chunks;
     stats_times(out, t);
     if (reset) {
         ix->ev_used = 0;
         ix->prof_calls = 0;
+        ix->prof_chunks = 0;
         if (ix->prof_ctr.p) {
             fill_u64(ix->prof_ctr.p, 0ull, CTR_WORDS, nullptr);
             HIP_TRY(hipDeviceSynchronize());

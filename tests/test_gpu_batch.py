@@ -90,3 +90,25 @@ def test_tuner_keeps_rows_and_caches():
         assert np.array_equal(ids.cpu().numpy(), base_ids.cpu().numpy())
         assert np.array_equal(dst.cpu().numpy(), base_d.cpu().numpy())
     idx.close()
+
+
+def test_profile_counters_start_at_zero():
+    """A new index's profile starts from zero even where its buffer reuses
+    the memory of an earlier index's profile: the pair count of two profiled
+    calls is exactly twice the queries x series, for both distances."""
+    import torch
+    from paper_1811_11076_amd import Index
+    db, dbo, qs, qo = classwarp(2, 10, 128, 3, 3000, 8)
+    dq = to_dev(qs)
+    for rep in range(3):
+        idx = Index(to_dev(db), dbo)
+        idx.profile(reset=True)
+        for distance, band in (("dk", None), ("dtw", 0.1)):
+            for _ in range(2):
+                idx.knn(dq, qo, 10, distance, band, profile=True)
+            p = idx.profile(reset=True)
+            assert p["calls"] == 2 and p["chunks"] == 2
+            assert p["pairs"] == 2 * 8 * 3000, (rep, distance, p["pairs"])
+            assert p["dp_started"] <= p["pairs"] and p["fallback_pairs"] <= p["dp_started"]
+        idx.close()
+        torch.cuda.synchronize()
