@@ -128,15 +128,17 @@ typedef struct {
                                       the first seed_count entries form the
                                       seed set, and with surv_order 2
                                       survivors are processed in this order */
-    int32_t use_graph;             /* 1: the call (one chunk of queries:
-                                      up to min(2^28 / n_series, 65535)
-                                      of them) runs as
-                                      one captured HIP graph, cached on the
-                                      index and replayed while the call
-                                      repeats (same pointers, offsets, k,
-                                      distance, band and options); excludes
-                                      profile and TSK_ORDER_LEARNED; with
-                                      stats_host only ms_total is timed */
+    int32_t use_graph;             /* 1: the call (all its chunks of
+                                      queries) runs as one captured HIP
+                                      graph, cached on the index and
+                                      replayed while the call repeats (same
+                                      pointers, offsets, k, distance, band,
+                                      options and encoder); excludes
+                                      profile; uneven-length DTW needs its
+                                      queries to fit one chunk (up to
+                                      min(2^28 / n_series, 65535) of them);
+                                      with stats_host only ms_total is
+                                      timed */
     int32_t dp_kernel;             /* 0 auto, 1 force the general DP */
     int32_t profile;               /* 1: record per-stage HIP events on the
                                       stream and add this call's counters to
@@ -254,8 +256,7 @@ typedef struct {
                                       queries); calls
                                       split their queries into chunks whose
                                       workspace fits (at least one query per
-                                      chunk).  use_graph calls need one
-                                      chunk for all their queries */
+                                      chunk) */
 } tsk_index_opts;
 
 /* Library version. */

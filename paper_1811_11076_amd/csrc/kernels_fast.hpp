@@ -647,7 +647,8 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
                 vmin = fminf(vmin, v);
             }
             cells += W;
-            valid += __popcll(__ballot(running)) * (unsigned long long)W;
+            // cells of the window inside the matrix (rows past m-1 are padding)
+            valid += running ? (unsigned long long)max(0, min(W, m - lo)) : 0ull;
             if (running) {
                 if (j == n - 1) {
                     const int slot = m - 1 - lo;
@@ -687,10 +688,9 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
     wave_count(a.ctr, C_DP_ABANDONED, abandoned);
     wave_count(a.ctr, C_BOUND_PRUNED, late);
     wave_count(a.ctr, C_FALLBACK, fallback);
-    if (threadIdx.x == 0) {
+    wave_count(a.ctr, C_VALID_CELLS, valid);
+    if (threadIdx.x == 0)
         ctr_add(a.ctr, C_DP_CELLS, cells * 64ull);
-        ctr_add(a.ctr, C_VALID_CELLS, valid);
-    }
 }
 
 } // namespace tsk

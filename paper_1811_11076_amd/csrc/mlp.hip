@@ -328,7 +328,6 @@ int ensure_batch(tsk_model *mdl, int64_t rows)
     return TSK_OK;
 }
 
-constexpr int64_t EMBED_CHUNK = 65536;
 
 uint64_t splitmix64(uint64_t &x)
 {
@@ -493,6 +492,8 @@ int prepare_pool(tsk_model *m, const float *vals, const int64_t *off, int64_t n,
 }
 
 } // namespace
+
+int model_reserve_rows(tsk_model *m, int64_t rows) { return ensure_batch(m, rows); }
 
 int model_embed_dev(tsk_model *m, const float *vals, const int64_t *off_dev, int64_t n, float *out,
                     hipStream_t s)

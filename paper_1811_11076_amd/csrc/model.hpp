@@ -26,6 +26,13 @@ struct tsk_model {
 
 namespace tsk {
 
+// Rows of series embedded per pass of model_embed_dev.
+constexpr int64_t EMBED_CHUNK = 65536;
+
+// Sizes the encoder's scratch for passes of `rows` series (allocates only if
+// it grows; a captured embedding pass needs it sized beforehand).
+int model_reserve_rows(tsk_model *mdl, int64_t rows);
+
 // Embeddings of n series (AoS values, device offsets) into out [n][embed],
 // in chunks of rows; asynchronous on s.
 int model_embed_dev(tsk_model *mdl, const float *vals, const int64_t *off_dev, int64_t n,

@@ -49,6 +49,9 @@ struct Workspace {
     DevBuf<int64_t> rcnt, rqoff;  // its per-query counts and output offsets
     DevBuf<unsigned long long> ctr, work;
     DevBuf<int64_t> qoff;
+    // the offsets of the chunk being enqueued (qoff + its first query): the
+    // k-NN call uploads every query's offsets once
+    int64_t *qoff_cur = nullptr;
     DevBuf<float> env;
     DevBuf<float> cenv;       // candidate envelopes [N][n][2][D] (option lb_both)
     DevBuf<float> tbuf;
@@ -575,7 +578,7 @@ template <int D> struct EnvLaunch {
     static void run(tsk_index *ix, const float *qv, int nq, BandArgs ba, hipStream_t s)
     {
         const int n = ix->max_len;
-        hipLaunchKernelGGL(k_env<D>, dim3((n + 63) / 64, nq), dim3(64), 0, s, qv, ix->ws.qoff.p, nq,
+        hipLaunchKernelGGL(k_env<D>, dim3((n + 63) / 64, nq), dim3(64), 0, s, qv, ix->ws.qoff_cur, nq,
                            n, ba, ix->ws.env.p);
     }
 };
@@ -588,11 +591,11 @@ template <int D> struct SeedLaunch {
             return;
         dim3 grid((P.seed + 63) / 64, nq);
         if (P.dist == DIST_DK)
-            hipLaunchKernelGGL((k_seed<D, DIST_DK>), grid, dim3(64), 0, s, qv, ix->ws.qoff.p, nq,
+            hipLaunchKernelGGL((k_seed<D, DIST_DK>), grid, dim3(64), 0, s, qv, ix->ws.qoff_cur, nq,
                                ix->aos, ix->off, ix->len, ix->n, order, P.seed, P.k, P.ba,
                                ix->ws.seedslots.p, ix->ws.tau.p, ix->ws.ctr.p);
         else
-            hipLaunchKernelGGL((k_seed<D, DIST_DTW>), grid, dim3(64), 0, s, qv, ix->ws.qoff.p, nq,
+            hipLaunchKernelGGL((k_seed<D, DIST_DTW>), grid, dim3(64), 0, s, qv, ix->ws.qoff_cur, nq,
                                ix->aos, ix->off, ix->len, ix->n, order, P.seed, P.k, P.ba,
                                ix->ws.seedslots.p, ix->ws.tau.p, ix->ws.ctr.p);
     }
@@ -602,7 +605,7 @@ static BoundArgs bound_args(tsk_index *ix, const float *qv, int nq, const QueryP
 {
     BoundArgs a;
     a.qv = qv;
-    a.qoff = ix->ws.qoff.p;
+    a.qoff = ix->ws.qoff_cur;
     a.nq = nq;
     a.qgroup = 4;
     a.soa = ix->soa;
@@ -647,7 +650,7 @@ static DpArgs dp_args(tsk_index *ix, const float *qv, int nq, const QueryPlan &P
 {
     DpArgs a;
     a.qv = qv;
-    a.qoff = ix->ws.qoff.p;
+    a.qoff = ix->ws.qoff_cur;
     a.nq = nq;
     a.aos = ix->aos;
     a.off = ix->off;
@@ -685,7 +688,7 @@ enum { FAST_NONE = 0, FAST_BAND, FAST_TUBE32, FAST_BAND_DKV };
 static FastArgs fast_args(tsk_index *ix, int nq, const QueryPlan &P, int qrows)
 {
     FastArgs a;
-    a.qoff = ix->ws.qoff.p;
+    a.qoff = ix->ws.qoff_cur;
     a.nq = nq;
     a.aos = ix->aos;
     a.off = ix->off;
@@ -819,6 +822,7 @@ static int upload_qoff(tsk_index *ix, const int64_t *qoff, int64_t q0, int64_t n
     ix->ws.h_qoff.assign(qoff + q0, qoff + q0 + nq + 1);
     HIP_TRY(hipMemcpyAsync(ix->ws.qoff.p, ix->ws.h_qoff.data(), (nq + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
+    ix->ws.qoff_cur = ix->ws.qoff.p;
     return TSK_OK;
 }
 
@@ -894,6 +898,7 @@ struct RangeReq {
 // the size is computed; otherwise the workspace's buffers borrow the region.
 struct WsShape {
     int64_t nq;
+    int64_t nq_total;        // queries of the call (their offsets are uploaded at once)
     int k;
     bool env, qpad, qtab, surv2;
     int qrows;               // staged rows per query (longest query + padding)
@@ -924,7 +929,7 @@ static size_t carve_ws(const tsk_index *ix, const WsShape &sh, char *base, Works
     take(w->rcnt, nq);
     take(w->ctr, CTR_WORDS);
     take(w->work, 8);
-    take(w->qoff, nq + 1);
+    take(w->qoff, sh.nq_total + 1);
     if (sh.env)
         take(w->env, nq * (int64_t)ix->max_len * 2 * ix->dim);
     take(w->tbuf, (size_t)dp_blocks(ix) * 4 * 2 * ix->max_len);
@@ -1043,8 +1048,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "bound_seed must be 0, 1 or 2");
     if (o.dtw_cascade < 0 || o.dtw_cascade > 2)
         return set_err(TSK_ERR_INVALID_ARG, "dtw_cascade must be 0, 1 or 2");
-    if (o.use_graph && (o.profile || o.order == TSK_ORDER_LEARNED))
-        return set_err(TSK_ERR_UNSUPPORTED, "use_graph excludes profile and TSK_ORDER_LEARNED");
+    if (o.use_graph && o.profile)
+        return set_err(TSK_ERR_UNSUPPORTED, "use_graph excludes profile");
     if (fx && (o.use_graph || o.profile || o.order == TSK_ORDER_LEARNED || o.lb_both || rr ||
                stats_host))
         return set_err(TSK_ERR_UNSUPPORTED, "the fixed-workspace call excludes use_graph, "
@@ -1073,9 +1078,12 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
     P.nq = n_queries;
     P.N = ix->n;
     P.chunk = chunk_queries(ix, n_queries);
-    if (o.use_graph && P.chunk < n_queries)
-        return set_err(TSK_ERR_UNSUPPORTED, "use_graph needs the queries to fit one chunk "
-                                            "(%lld here)", (long long)P.chunk);
+    // several chunks in one graph need the per-chunk uploads of the
+    // length-bucket bound (uneven-length DTW) outside it
+    if (o.use_graph && P.chunk < n_queries && dist == TSK_DTW && ix->bucketed &&
+        ix->min_len != ix->max_len && o.dp_kernel != 1)
+        return set_err(TSK_ERR_UNSUPPORTED, "use_graph on uneven-length DTW needs the queries to "
+                                            "fit one chunk (%lld here)", (long long)P.chunk);
     P.env_ok = (dist == TSK_DTW) && ix->min_len == ix->max_len;
     // seed sizes: the greedy DK seed is a latency-bound walk (a few hundred
     // candidates give a tight threshold); the diagonal DTW seed is a cheap
@@ -1117,6 +1125,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         for (int64_t i = 0; i < n_queries; ++i)
             qmax = std::max<int32_t>(qmax, (int32_t)(q_offsets_host[i + 1] - q_offsets_host[i]));
         WsShape sh;
+        sh.nq_total = n_queries;
         sh.k = k;
         sh.env = P.env_ok;
         sh.surv2 = P.env_ok; // DTW on equal lengths: the cascade may run
@@ -1232,7 +1241,6 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return c;
     };
     auto prepare_chunk = [&](const Chunk &c) -> int {
-        TSK_TRY(upload_qoff(ix, q_offsets_host, c.q0, c.nq, s));
         if (c.lbu)
             TSK_TRY(prepare_qtables(ix, q_offsets_host, c.q0, c.nq, s));
         if (c.fast != FAST_NONE)
@@ -1250,6 +1258,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
     } while (0)
         const int nq = c.nq;
         const float *qv = q_values_dev; // offsets are absolute into q_values_dev
+        W.qoff_cur = W.qoff.p + c.q0;   // every query's offsets are on the device
         TSK_MARK(0);
         fill_u32(W.tau.p, rr ? f_bits_host(rr->tau_key) : TSK_INF_BITS, nq, s);
         if (rr)
@@ -1263,14 +1272,14 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         if (o.order == TSK_ORDER_LEARNED) {
             // embed the chunk's queries, score every candidate, bucket-sort;
             // the bound pass overwrites lbv (the scores' scratch) later
-            TSK_TRY(model_embed_dev(model, qv, W.qoff.p, nq, ix->qemb.p, s));
+            TSK_TRY(model_embed_dev(model, qv, W.qoff_cur, nq, ix->qemb.p, s));
             launch_embed_score(ix->qemb.p, nq, ix->emb.p, ix->n, model->embed, W.lbv.p, s);
             launch_bucket_order(W.lbv.p, nq, ix->n, ix->lorder.p, s);
         }
         TSK_MARK(1);
         if (P.env_ok)
             dispatch_d<EnvLaunch>(P.D, ix, qv, nq, P.ba, s);
-        SeedRingArgs seed_args{qv, W.qoff.p, nq, c.qmax, ix->aos, ix->off, ix->len, ix->n,
+        SeedRingArgs seed_args{qv, W.qoff_cur, nq, c.qmax, ix->aos, ix->off, ix->len, ix->n,
                                c.order, 0, P.seed, k, P.ba, W.seedslots.p, W.tau.p, ctr,
                                nullptr, nullptr};
         const bool cascade = c.dk_cascade || c.dtw_bseed;
@@ -1344,7 +1353,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                 launch_bound_lb(P.D, ba, false, s);
             }
         } else if (c.lbu) {
-            launch_qtable(P.D, qv, W.qoff.p, nq, W.qtab_off.p, W.qtab.p, s);
+            launch_qtable(P.D, qv, W.qoff_cur, nq, W.qtab_off.p, W.qtab.p, s);
             launch_bound_lbu(P.D, ba, bucket_args(ix), W.qtab.p, W.qtab_off.p,
                              o.lb_qgroup > 1 ? std::min(o.lb_qgroup, 8) : 4, false, s);
         } else {
@@ -1366,7 +1375,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             // LB_Box in both orientations: the survivors' bounds become the
             // larger one (queries of another length keep theirs)
             launch_bound_lb_rev(P.D, ix->aos, ix->off, ix->n, ix->max_len, P.ba, W.cenv.p, qv,
-                                W.qoff.p, nq, W.surv.p, W.surv_cnt.p, W.lbv.p, s);
+                                W.qoff_cur, nq, W.surv.p, W.surv_cnt.p, W.lbv.p, s);
         }
         // the greedy pass over the corner survivors costs more than the DP
         // work its tighter threshold saves on the class-warp workloads, so
@@ -1387,7 +1396,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         if (o.dp_rows != 0)
             da.rows_per_lane = o.dp_rows;
         if (c.fast != FAST_NONE) {
-            dispatch_d<QpadLaunch>(P.D, qv, W.qoff.p, nq, c.qrows, W.qpad.p, s);
+            dispatch_d<QpadLaunch>(P.D, qv, W.qoff_cur, nq, c.qrows, W.qpad.p, s);
             TSK_MARK(5);
             FastArgs fa = fast_args(ix, nq, P, c.qrows);
             fa.ctr = ctr;
@@ -1435,11 +1444,26 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
 
     if (o.cancel_flag_host && *o.cancel_flag_host != 0)
         return set_err(TSK_ERR_CANCELLED, "cancelled before any device work");
+    // every query's offsets to the device once (the chunks index into them)
+    TSK_TRY(W.qoff.ensure(n_queries + 1));
+    TSK_TRY(upload_qoff(ix, q_offsets_host, 0, n_queries, s));
     if (o.use_graph) {
-        // one chunk, replayed from a cached executable graph when the call
-        // repeats (same inputs, outputs, shape and options)
-        const Chunk c = plan_chunk(0);
-        TSK_TRY(prepare_chunk(c));
+        // every chunk of the call in one graph, replayed from a cached
+        // executable graph when the call repeats (same inputs, outputs,
+        // shape and options).  Buffers are sized for the largest chunk first,
+        // so no chunk's preparation reallocates one the capture addressed.
+        std::vector<Chunk> chunks;
+        for (int64_t q0 = 0; q0 < n_queries; q0 += P.chunk)
+            chunks.push_back(plan_chunk(q0));
+        int qrows_max = 0;
+        for (const Chunk &c : chunks)
+            qrows_max = std::max(qrows_max, c.fast != FAST_NONE ? c.qrows : 0);
+        if (qrows_max > 0)
+            TSK_TRY(W.qpad.ensure((size_t)P.chunk * qrows_max * (P.D <= 4 ? 4 : 8)));
+        for (const Chunk &c : chunks)
+            TSK_TRY(prepare_chunk(c));
+        if (o.order == TSK_ORDER_LEARNED)
+            TSK_TRY(model_reserve_rows(model, std::min<int64_t>(P.chunk, EMBED_CHUNK)));
         std::vector<int64_t> key = {(int64_t)(uintptr_t)q_values_dev, n_queries, k, dist,
                                     band.mode, band.r, (int64_t)f_bits_host(band.frac),
                                     (int64_t)(uintptr_t)out_ids_dev,
@@ -1459,7 +1483,12 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
               (const void *)W.work.p, (const void *)W.qoff.p, (const void *)W.env.p,
               (const void *)W.tbuf.p, (const void *)W.qpad.p, (const void *)W.fb.p,
               (const void *)W.qtab.p, (const void *)W.qtab_off.p, (const void *)W.cenv.p,
-              (const void *)W.surv2.p})
+              (const void *)W.surv2.p, (const void *)o.model, (const void *)ix->emb.p,
+              (const void *)ix->qemb.p, (const void *)ix->lorder.p,
+              (const void *)(model ? model->x.p : nullptr),
+              (const void *)(model ? model->a1.p : nullptr),
+              (const void *)(model ? model->a2.p : nullptr),
+              (const void *)(model ? model->params.p : nullptr)})
             key.push_back((int64_t)(uintptr_t)ptr);
         key.insert(key.end(), q_offsets_host, q_offsets_host + n_queries + 1);
         if (stats_host) {
@@ -1481,7 +1510,10 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             fill_u64(W.ctr.p, 0ull, CTR_WORDS, cs);
-            const int rc = enqueue_chunk(c, nullptr, cs);
+            int rc = TSK_OK;
+            for (const Chunk &c : chunks)
+                if (rc == TSK_OK)
+                    rc = enqueue_chunk(c, nullptr, cs);
             const hipError_t ec = hipStreamEndCapture(cs, &g);
             if (rc != TSK_OK) {
                 if (g)

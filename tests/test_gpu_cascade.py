@@ -93,7 +93,8 @@ def test_cascade_graph_replay_and_chunks():
 def _graph_and_chunks(kw):
     """The cascade inside a captured graph (three replays, eager work and a
     synchronisation between them) and over several query chunks (a small
-    workspace bound) gives the eager single-chunk rows."""
+    workspace bound: six chunks, eager and as one graph) gives the oracle's
+    rows."""
     import torch
     from paper_1811_11076_amd import Index
     db, dbo, qs, qo = classwarp(2, 10, 128, 3, 2000, 16)
@@ -111,6 +112,12 @@ def _graph_and_chunks(kw):
             torch.cuda.synchronize()
             assert_same_knn(out[0], out[1], ref_ids, ref_keys, distance)
             idx.knn(dq[:int(qo[3])], qo[:4], 10, "dtw", 3)
+            torch.cuda.synchronize()
+            # all six chunks of the small-workspace index in one graph
+            small.knn(dq, qo, 10, distance, band, use_graph=True, out=out, **kw)
+            torch.cuda.synchronize()
+            assert_same_knn(out[0], out[1], ref_ids, ref_keys, distance)
+            small.knn(dq[:int(qo[5])], qo[:6], 10, distance, band)
             torch.cuda.synchronize()
     small.close()
     idx.close()

@@ -244,3 +244,37 @@ def test_dk_distances_correctly_rounded():
     _lib.check(lib.tsk_dk_distances(ctypes.c_void_p(dk.data_ptr()), ctypes.c_void_p(dk.data_ptr()),
                                     keys.size, None))
     assert np.array_equal(dk.cpu().numpy().view(np.uint32), want.view(np.uint32))
+
+
+def test_learned_order_graph_replays():
+    """The learned candidate order inside a captured graph: the embedding,
+    scoring and ordering kernels run in the graph, the candidates'
+    embeddings are recomputed outside it when the encoder changes; rows
+    equal the oracle's on every replay, also after more training and over
+    several query chunks."""
+    print("[case] learned order graph", flush=True)
+    import torch
+    from paper_1811_11076_amd import Index, Model
+    db, dbo, qs, qo = classwarp(2, 10, 128, 3, 2000, 12)
+    dq = to_dev(qs)
+    ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, "dk", None)
+    m, _ = _model(3, 8)
+    vals, off = ragged_walks(95, 100, (64, 128), 3)
+    r = np.random.default_rng(1)
+    a = r.integers(0, 100, 500).astype(np.int32)
+    b = r.integers(0, 100, 500).astype(np.int32)
+    y = r.uniform(1.0, 10.0, 500).astype(np.float32)
+    for ws in (0, 2000 * 24 * 4 + 128 * 64 * 4):   # one chunk; three chunks
+        idx = Index(to_dev(db), dbo, workspace_limit_bytes=ws)
+        out = (torch.empty((12, 10), dtype=torch.int64, device="cuda"),
+               torch.empty((12, 10), dtype=torch.float32, device="cuda"))
+        for rep in range(3):
+            idx.knn(dq, qo, 10, "dk", None, order="learned", model=m, use_graph=True, out=out)
+            torch.cuda.synchronize()
+            assert_same_knn(out[0], out[1], ref_ids, ref_keys, "dk")
+            if rep == 1:
+                m.train(to_dev(vals), off, a, b, y, epochs=1, batch=100, lr=1e-3, seed=rep)
+            idx.knn(dq[:int(qo[2])], qo[:3], 10, "dtw", 0.1)
+            torch.cuda.synchronize()
+        idx.close()
+    m.close()
