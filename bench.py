@@ -454,7 +454,7 @@ def subsequence(args):
 # theorem's own assumption)
 SWEEP = dict(cfg_id=7, classes=10, Q=16, N=2000, k=10, band=0.1,
              gens=("classwarp", "randomwalk", "iid"),
-             dims=(1, 2, 3, 4, 5, 6, 7, 8), lengths=(32, 64, 128, 256, 512))
+             dims=(1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 20, 24, 27), lengths=(32, 64, 128, 256, 512))
 
 
 def tightness_sweep():
@@ -497,6 +497,50 @@ def tightness_sweep():
                 print(f"[sweep] {gen} d={d} L={L} tightness {rows[-1]['tightness']:.4f} "
                       f"pruning {rows[-1]['pruning_power']:.4f}", file=sys.stderr, flush=True)
     return {"queries": w["Q"], "series": w["N"], "k": w["k"], "band": w["band"], "rows": rows}
+
+
+# DK against DTW + LB_Box as the dimension grows (Sec. 5.2, Table 1 spans
+# d = 1 .. 27), class-warp series of one length, library defaults
+DIM_SWEEP = dict(cfg_id=8, classes=50, Q=256, N=100000, L=128, k=10,
+                 dims=(1, 2, 3, 6, 8, 13, 22, 27), reps=3)
+
+
+def dim_sweep():
+    """Per d: device time of one k-NN call (all queries) for DK (no band),
+    DTW with a 10 % band and unbanded DTW, the DTW / DK time ratio, and the
+    share of pairs that reached a DP (tsk_knn_query counters)."""
+    import torch
+    from paper_1811_11076_amd import Index, synth
+    w = DIM_SWEEP
+    rows = []
+    for d in w["dims"]:
+        t0 = time.perf_counter()
+        g = synth.ClassWarp(w["cfg_id"] * 100 + d, w["classes"], w["L"], d)
+        db, dbo, _ = g.members(w["N"], "db", length=w["L"])
+        qs, qo, _ = g.members(w["Q"], "query", length=w["L"], class_mode="uniform")
+        idx = Index(torch.from_numpy(db).cuda(), dbo)
+        dq = torch.from_numpy(qs).cuda()
+        row = {"d": d}
+        for name, dist, band in (("dk", "dk", None), ("dtw_band10", "dtw", 0.1),
+                                 ("dtw_full", "dtw", None)):
+            _, _, st = idx.knn(dq, qo, w["k"], dist, band, stats=True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(w["reps"]):
+                idx.knn(dq, qo, w["k"], dist, band)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t1) * 1e3 / w["reps"]
+            row[name] = {"ms": ms, "pairs_per_s": w["Q"] * w["N"] / (ms * 1e-3),
+                         "dp_share": st["dp_started"] / max(1, st["pairs"])}
+        row["dtw_band10_over_dk"] = row["dtw_band10"]["ms"] / row["dk"]["ms"]
+        row["dtw_full_over_dk"] = row["dtw_full"]["ms"] / row["dk"]["ms"]
+        idx.close()
+        del dq
+        rows.append(row)
+        print(f"[dims] d={d} dk {row['dk']['ms']:.1f} ms, dtw 10% {row['dtw_band10']['ms']:.1f} ms, "
+              f"dtw full {row['dtw_full']['ms']:.1f} ms ({time.perf_counter() - t0:.1f}s)",
+              file=sys.stderr, flush=True)
+    return {"queries": w["Q"], "series": w["N"], "length": w["L"], "k": w["k"], "rows": rows}
 
 
 def full_size_check(db, dbo, qs, qo, w, res_dk, res_dtw, nq_dk=16, nq_dtw=8):
@@ -936,6 +980,8 @@ def main():
                     help="skip the subsequence-search measurement")
     ap.add_argument("--tightness-sweep", action="store_true",
                     help="run only the LB_Box tightness / pruning-power sweep (one JSON line)")
+    ap.add_argument("--dim-sweep", action="store_true",
+                    help="run only the DK / DTW time over the dimension d (one JSON line)")
     ap.add_argument("--subseq-only", action="store_true",
                     help="run only the subsequence-search measurement (one JSON line)")
     ap.add_argument("--eager", action="store_true",
@@ -954,6 +1000,9 @@ def main():
         return
     if args.subseq_only:
         print(json.dumps({"subsequence": subsequence(args)}), flush=True)
+        return
+    if args.dim_sweep:
+        print(json.dumps({"dim_sweep": dim_sweep()}), flush=True)
         return
 
     import torch

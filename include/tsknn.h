@@ -43,7 +43,12 @@ extern "C" {
 #define TSK_VERSION_MAJOR 0
 #define TSK_VERSION_MINOR 1
 
-#define TSK_MAX_DIM 8
+#define TSK_MAX_DIM 32      /* k-NN and range queries; above 8 dimensions the
+                               series are stored and scanned padded with zero
+                               coordinates to 12, 16, 24 or 32 (same costs and
+                               bounds, bit for bit) by the general kernels */
+#define TSK_SUB_MAX_DIM 8   /* subsequence search */
+#define TSK_MLP_MAX_DIM 8   /* the learned order's encoder */
 #define TSK_MAX_LEN 4096
 #define TSK_MAX_K 64
 
@@ -391,8 +396,9 @@ typedef struct {
  * items swept / with a value <= threshold / without), dp_cells, dp_valid_cells,
  * bound_steps (greedy moves + row-0 costs scanned), ms_total / ms_seed /
  * ms_dp / ms_final.  The call allocates its working memory and is
- * synchronous.  Errors: INVALID_ARG, UNSUPPORTED (dim, k > TSK_MAX_K, query
- * longer than TSK_SUB_MAX_QLEN), OOM, DEVICE. */
+ * synchronous.  Errors: INVALID_ARG, UNSUPPORTED (dim outside
+ * [1, TSK_SUB_MAX_DIM], k > TSK_MAX_K, query longer than TSK_SUB_MAX_QLEN),
+ * OOM, DEVICE. */
 int tsk_subseq_query(const float *series_dev, const int64_t *s_offsets_host, int64_t n_series,
                      int32_t dim, const float *q_values_dev, const int64_t *q_offsets_host,
                      int64_t n_queries, int32_t k, const tsk_subseq_opts *opts,
@@ -472,7 +478,7 @@ int tsk_tune(tsk_index *index, const float *q_values_dev, const int64_t *q_offse
  * ------------------------------------------------------------------------ */
 typedef struct {
     int64_t size;    /* sizeof(tsk_mlp_shape) */
-    int32_t dim;     /* series dimensionality (1..TSK_MAX_DIM) */
+    int32_t dim;     /* series dimensionality (1..TSK_MLP_MAX_DIM) */
     int32_t points;  /* resampled points (2..256; 32 by default if 0) */
     int32_t hidden;  /* hidden width (multiple of 32, <= 1024; 256 if 0) */
     int32_t embed;   /* embedding width (multiple of 32, <= 256; 64 if 0) */

@@ -99,6 +99,10 @@ void walk_d(const FastArgs &a, const float *qv, unsigned long long *ubslots, int
     case 6: CALL(6); break;                                                                        \
     case 7: CALL(7); break;                                                                        \
     case 8: CALL(8); break;                                                                        \
+    case 12: CALL(12); break;                                                                      \
+    case 16: CALL(16); break;                                                                      \
+    case 24: CALL(24); break;                                                                      \
+    case 32: CALL(32); break;                                                                      \
     default: break;                                                                                \
     }
 

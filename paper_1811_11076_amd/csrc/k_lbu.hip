@@ -26,11 +26,20 @@ void bound_lbu_d(const BoundArgs &a, const BucketArgs &bk, const float *tab,
             hipLaunchKernelGGL((k_bound_lbu<D, QG, false>), grid, dim3(64), 0, s, a, bk, tab,      \
                                tab_off);                                                           \
     } while (0)
-    if (qg <= 2)
+    // the group's envelopes stay within 32 KB of LDS: up to 8 queries for
+    // 8 dimensions, 4 for 12 and 16, 2 for 24 and 32
+    constexpr int QG_MAX = D <= 8 ? 8 : (D <= 16 ? 4 : 2);
+    if (qg <= 2 || QG_MAX == 2) {
         TSK_LBU(2);
-    else if (qg <= 4)
-        TSK_LBU(4);
-    else
+        return;
+    }
+    if constexpr (QG_MAX >= 4) {
+        if (qg <= 4 || QG_MAX == 4) {
+            TSK_LBU(4);
+            return;
+        }
+    }
+    if constexpr (QG_MAX >= 8)
         TSK_LBU(8);
 #undef TSK_LBU
 }
@@ -53,6 +62,10 @@ template <int D> void pack_bucket_d(const float *aos, const int64_t *off, const 
     case 6: CALL(6); break;                                                                        \
     case 7: CALL(7); break;                                                                        \
     case 8: CALL(8); break;                                                                        \
+    case 12: CALL(12); break;                                                                      \
+    case 16: CALL(16); break;                                                                      \
+    case 24: CALL(24); break;                                                                      \
+    case 32: CALL(32); break;                                                                      \
     default: break;                                                                                \
     }
 

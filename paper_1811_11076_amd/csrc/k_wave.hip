@@ -22,7 +22,11 @@ template <int D, int R> void wave_r(int dist, int mode, const DpArgs &a, int blo
 
 template <int D> void wave_d(int dist, int mode, const DpArgs &a, int blocks, hipStream_t s)
 {
-    if (a.rows_per_lane == 1)
+    // above 8 dimensions one row per lane (a lane holds its rows' points in
+    // registers: 4 rows of 32 floats would crowd out the rest)
+    if constexpr (D > 8)
+        wave_r<D, 1>(dist, mode, a, blocks, s);
+    else if (a.rows_per_lane == 1)
         wave_r<D, 1>(dist, mode, a, blocks, s);
     else if (a.rows_per_lane == 2)
         wave_r<D, 2>(dist, mode, a, blocks, s);
@@ -42,6 +46,10 @@ void launch_dp_wave(int D, int dist, int mode, const DpArgs &a, int blocks, hipS
     case 6: wave_d<6>(dist, mode, a, blocks, s); break;
     case 7: wave_d<7>(dist, mode, a, blocks, s); break;
     case 8: wave_d<8>(dist, mode, a, blocks, s); break;
+    case 12: wave_d<12>(dist, mode, a, blocks, s); break;
+    case 16: wave_d<16>(dist, mode, a, blocks, s); break;
+    case 24: wave_d<24>(dist, mode, a, blocks, s); break;
+    case 32: wave_d<32>(dist, mode, a, blocks, s); break;
     default: break;
     }
 }

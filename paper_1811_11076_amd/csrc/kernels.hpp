@@ -38,6 +38,31 @@ inline void ctr_sum(const unsigned long long *words, unsigned long long *out)
     }
 }
 
+// Dimensions the kernels are built for: 1..8, and 12, 16, 24, 32, to which
+// larger dimensionalities are padded with zero coordinates (a zero
+// coordinate on both sides adds fl(0*0 + acc) = acc to a point cost and 0 to
+// a box term, so every cost and bound keeps its bits).
+__host__ __device__ constexpr int kernel_dim(int d)
+{
+    return d <= 8 ? d : (d <= 12 ? 12 : (d <= 16 ? 16 : (d <= 24 ? 24 : 32)));
+}
+// Floats per staged point: 4 up to 4 dimensions, 8 up to 8, else the
+// dimension itself (a multiple of 4 above 8).
+__host__ __device__ constexpr int pad_dim(int D) { return D <= 4 ? 4 : (D <= 8 ? 8 : D); }
+
+// Point rows [rows][d] -> [rows][kd] with zero coordinates d..kd-1.
+static __global__ void k_pad_dims(const float *__restrict__ src, int64_t rows, int d, int kd,
+                                  float *__restrict__ dst)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = rows * kd;
+    for (int64_t i = t; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / kd;
+        const int k = (int)(i % kd);
+        dst[i] = k < d ? src[r * d + k] : 0.0f;
+    }
+}
+
 struct BandArgs {
     int mode, r;
     float frac;
@@ -979,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_dp_wave(DpArgs a)
             if (lane == 0)
                 a.out_all[t] = res;
         } else {
-            started += MODE == DPW_SURV ? 1 : 0; // fallback pairs were counted when started
+            ++started; // (the fast kernels do not count the pairs they hand over)
             if (res != tsk_inf()) {
                 ++completed;
                 if (lane == 0 && res <= bits_f(load_relaxed_u32(a.tau + q))) {

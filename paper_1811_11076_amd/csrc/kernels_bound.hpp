@@ -17,7 +17,8 @@ constexpr int WALK_RING_STRIDE = WALK_RING_FLOATS + 1;
 // greedy_walk().  Latency layout for gfx950: the query comes from LDS (row
 // stride DP floats); the candidate goes through a lane-private LDS ring of
 // RN = 4B points (slot = point mod RN; B = 8 points per block for DP = 4, 4
-// for DP = 8, so a ring is 128 floats either way).  Every B moves, on the
+// for DP = 8, 2 for DP = 12 and 16, 1 for DP = 24 and 32, so a ring is at
+// most 128 floats).  Every B moves, on the
 // same moves for every lane still walking (lanes advance j at their own
 // pace, and a refill taken by some lanes only would wait on loads that
 // others had just issued into the same registers), each lane writes the B
@@ -39,7 +40,7 @@ __device__ float greedy_walk_ring(const float *qs, int m, const float *__restric
     constexpr int DP = PadDim<D>::value;
     constexpr int B = WALK_RING_FLOATS / (4 * DP); // points per block
     constexpr int RN = 4 * B;                       // ring points
-    static_assert((B & (B - 1)) == 0 && B >= 2, "block of points: a power of two >= 2");
+    static_assert((B & (B - 1)) == 0 && B >= 1, "block of points: a power of two");
     float q0[D], q1[D], q2[D];
     float r0[D], r1[D], r2[D];
     float pf[B][D];
@@ -742,7 +743,7 @@ __global__ __launch_bounds__(256) void k_bound_lb_surv(BoundArgs a, const int32_
     const int64_t per_q = (*max_cnt + LBS_TASK - 1) / LBS_TASK;
     const int64_t total = (int64_t)a.nq * per_q;
     const float scale = 1.0f - 0x1.0p-9f;
-    unsigned long long terms = 0;
+    unsigned long long terms = 0, pruned = 0;
     int staged = -1;
     for (;;) {
         __syncthreads(); // the previous task (and its envelope) is done with
@@ -801,13 +802,18 @@ __global__ __launch_bounds__(256) void k_bound_lb_surv(BoundArgs a, const int32_
             }
             terms += (unsigned long long)min(j0, n);
             const float lb = wave_sum(acc) * scale;
+            const bool drop = over || lb > tau;
+            pruned += drop ? 1 : 0;
             if (lane == 0)
-                a.lbv[(int64_t)q * a.N + c] = (over || lb > tau) ? tsk_inf() : lb;
+                a.lbv[(int64_t)q * a.N + c] = drop ? tsk_inf() : lb;
         }
     }
-    if (lane != 0)
+    if (lane != 0) {
         terms = 0;
+        pruned = 0;
+    }
     wave_count(a.ctr, C_BOUND_STEPS, terms);
+    wave_count(a.ctr, C_BOUND_PRUNED, pruned);
 }
 
 } // namespace tsk

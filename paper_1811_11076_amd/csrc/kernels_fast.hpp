@@ -19,7 +19,7 @@ constexpr int QPAD = 128;
 typedef __attribute__((address_space(4))) const float cfloat;
 
 template <int D> struct PadDim {
-    static constexpr int value = D <= 4 ? 4 : 8;
+    static constexpr int value = pad_dim(D);
 };
 
 struct FastArgs {
@@ -667,6 +667,7 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
                 } else if (Dv[W - 1] <= tau) {
                     push_fallback(a, q, c);
                     ++fallback;
+                    --started; // the general DP counts it
                     running = false;
                 }
             }

@@ -39,7 +39,7 @@ struct SeedRingArgs {
 // per lane, WALK_RING_STRIDE floats apart.
 inline size_t walk_lds_bytes(int D, int maxm)
 {
-    const int DP = D <= 4 ? 4 : 8;
+    const int DP = pad_dim(D);
     return ((size_t)maxm * DP + 64 * WALK_RING_STRIDE) * sizeof(float);
 }
 

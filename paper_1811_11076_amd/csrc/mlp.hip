@@ -425,8 +425,8 @@ int resolve_shape(const tsk_mlp_shape *in, tsk_mlp_shape *sh)
         sh->hidden = 256;
     if (sh->embed == 0)
         sh->embed = 64;
-    if (sh->dim < 1 || sh->dim > TSK_MAX_DIM)
-        return set_err(TSK_ERR_UNSUPPORTED, "dim %d outside [1, %d]", sh->dim, TSK_MAX_DIM);
+    if (sh->dim < 1 || sh->dim > TSK_MLP_MAX_DIM)
+        return set_err(TSK_ERR_UNSUPPORTED, "dim %d outside [1, %d]", sh->dim, TSK_MLP_MAX_DIM);
     if (sh->points < 2 || sh->points > 256)
         return set_err(TSK_ERR_UNSUPPORTED, "points %d outside [2, 256]", sh->points);
     if (sh->hidden < 32 || sh->hidden > 1024 || sh->hidden % 32)

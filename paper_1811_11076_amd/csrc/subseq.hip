@@ -171,8 +171,8 @@ extern "C" int tsk_subseq_query(const float *series_dev, const int64_t *s_offset
     // ---- validation, before any device work
     if (!series_dev || !q_values_dev)
         return set_err(TSK_ERR_INVALID_ARG, "series_dev / q_values_dev is NULL");
-    if (dim < 1 || dim > TSK_MAX_DIM)
-        return set_err(TSK_ERR_UNSUPPORTED, "dim %d outside [1, %d]", dim, TSK_MAX_DIM);
+    if (dim < 1 || dim > TSK_SUB_MAX_DIM)
+        return set_err(TSK_ERR_UNSUPPORTED, "dim %d outside [1, %d]", dim, TSK_SUB_MAX_DIM);
     if (k < 1)
         return set_err(TSK_ERR_INVALID_ARG, "k must be >= 1");
     if (k > TSK_MAX_K)

@@ -53,6 +53,7 @@ struct Workspace {
     // k-NN call uploads every query's offsets once
     int64_t *qoff_cur = nullptr;
     DevBuf<float> env;
+    DevBuf<float> qdims;      // the queries padded to the kernels' dimension
     DevBuf<float> cenv;       // candidate envelopes [N][n][2][D] (option lb_both)
     DevBuf<float> tbuf;
     DevBuf<float> qpad;
@@ -79,6 +80,7 @@ struct Workspace {
         work.release();
         qoff.release();
         env.release();
+        qdims.release();
         cenv.release();
         tbuf.release();
         qpad.release();
@@ -97,7 +99,8 @@ constexpr int NEV = 9;
 struct tsk_index {
     int device = 0;
     int64_t ws_limit = 0; // workspace bound of a query call (0 = none)
-    int dim = 0;
+    int dim = 0;  // the kernels' dimension (kernel_dim of udim: padded above 8)
+    int udim = 0; // the caller's dimension
     int64_t n = 0;
     int64_t total = 0;
     int32_t min_len = 0, max_len = 0;
@@ -222,6 +225,10 @@ template <template <int> class F, typename... A> static void dispatch_d(int d, A
     case 6: F<6>::run(args...); break;
     case 7: F<7>::run(args...); break;
     case 8: F<8>::run(args...); break;
+    case 12: F<12>::run(args...); break;
+    case 16: F<16>::run(args...); break;
+    case 24: F<24>::run(args...); break;
+    case 32: F<32>::run(args...); break;
     default: break;
     }
 }
@@ -321,7 +328,7 @@ extern "C" int tsk_index_info(const tsk_index *ix, int64_t *n_series, int32_t *d
     if (n_series)
         *n_series = ix->n;
     if (dim)
-        *dim = ix->dim;
+        *dim = ix->udim;
     return TSK_OK;
 }
 
@@ -429,8 +436,13 @@ static int index_build_impl(tsk_index *ix, const float *values_dev, hipStream_t 
     HIP_TRY(hipMalloc((void **)&ix->aos, std::max<int64_t>(1, ix->total * D) * sizeof(float)));
     HIP_TRY(hipMalloc((void **)&ix->off, (ix->n + 1) * sizeof(int64_t)));
     HIP_TRY(hipMalloc((void **)&ix->len, ix->n * sizeof(int32_t)));
-    HIP_TRY(hipMemcpyAsync(ix->aos, values_dev, ix->total * D * sizeof(float),
-                           hipMemcpyDeviceToDevice, s));
+    if (ix->udim == D) {
+        HIP_TRY(hipMemcpyAsync(ix->aos, values_dev, ix->total * D * sizeof(float),
+                               hipMemcpyDeviceToDevice, s));
+    } else {
+        hipLaunchKernelGGL(k_pad_dims, dim3(grid_for(ix->total * D, 256, 8192)), dim3(256), 0, s,
+                           values_dev, ix->total, ix->udim, D, ix->aos);
+    }
     HIP_TRY(hipMemcpyAsync(ix->off, ix->h_off.data(), (ix->n + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(ix->len, ix->h_len.data(), ix->n * sizeof(int32_t),
@@ -539,7 +551,8 @@ extern "C" int tsk_index_build(const float *values_dev, const int64_t *offsets_h
         return set_err(TSK_ERR_OOM, "host allocation failed");
     ix->device = dev;
     ix->ws_limit = opts ? opts->workspace_limit_bytes : 0;
-    ix->dim = dim;
+    ix->udim = dim;
+    ix->dim = kernel_dim(dim);
     ix->n = n_series;
     ix->total = offsets_host[n_series];
     ix->min_len = mn;
@@ -734,9 +747,10 @@ static int pick_fast(const tsk_index *ix, int dist, const tsk_band &band, int32_
                      int dp_kernel, int dk_band_slots, int *wsel)
 {
     *wsel = -1;
-    if (dp_kernel == 1)
+    // the lane-per-pair kernels are built for up to 8 dimensions
+    if (dp_kernel == 1 || ix->dim > 8)
         return FAST_NONE;
-    const int DP = ix->dim <= 4 ? 4 : 8;
+    const int DP = pad_dim(ix->dim);
     if (dist == TSK_DK && band.mode == TSK_BAND_NONE && dk_band_slots > 0 && qmin == qmax &&
         ix->min_len == ix->max_len && ix->min_len == qmin) {
         for (int i = 0; i < N_BAND_WS; ++i)
@@ -786,6 +800,23 @@ static int check_queries(const tsk_index *ix, const float *qv, const int64_t *qo
     return TSK_OK;
 }
 
+// The queries as the kernels read them: the caller's values, or above 8
+// dimensions a copy padded with zero coordinates (in the workspace).
+static int kernel_queries(tsk_index *ix, const float *qv, const int64_t *qoff_host, int64_t nq,
+                          hipStream_t s, const float **out)
+{
+    *out = qv;
+    if (ix->udim == ix->dim)
+        return TSK_OK;
+    const int64_t rows = qoff_host[nq];
+    TSK_TRY(ix->ws.qdims.ensure((size_t)rows * ix->dim));
+    hipLaunchKernelGGL(k_pad_dims, dim3(grid_for(rows * ix->dim, 256, 8192)), dim3(256), 0, s, qv,
+                       rows, ix->udim, ix->dim, ix->ws.qdims.p);
+    HIP_TRY(hipGetLastError());
+    *out = ix->ws.qdims.p;
+    return TSK_OK;
+}
+
 // Workspace for a chunk of nq queries; sizes follow the index.
 static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env, bool need_cenv = false,
                      bool need_surv2 = false)
@@ -832,7 +863,7 @@ static int upload_qoff(tsk_index *ix, const int64_t *qoff, int64_t q0, int64_t n
 static int prepare_qtables(tsk_index *ix, const int64_t *qoff_host, int64_t q0, int nq,
                            hipStream_t s)
 {
-    const int DP = ix->dim <= 4 ? 4 : 8;
+    const int DP = pad_dim(ix->dim);
     std::vector<int64_t> &h = ix->ws.h_qtab;
     h.assign(nq + 1, 0);
     for (int i = 0; i < nq; ++i)
@@ -903,6 +934,7 @@ struct WsShape {
     bool env, qpad, qtab, surv2;
     int qrows;               // staged rows per query (longest query + padding)
     int64_t qtab_floats_q;   // sparse-table floats of the longest query
+    int64_t qdims_floats;    // the call's queries padded to the kernels' dimension
 };
 static size_t carve_ws(const tsk_index *ix, const WsShape &sh, char *base, Workspace *w)
 {
@@ -935,7 +967,9 @@ static size_t carve_ws(const tsk_index *ix, const WsShape &sh, char *base, Works
     take(w->tbuf, (size_t)dp_blocks(ix) * 4 * 2 * ix->max_len);
     take(w->fb, nq * N);
     if (sh.qpad)
-        take(w->qpad, (size_t)nq * sh.qrows * (ix->dim <= 4 ? 4 : 8));
+        take(w->qpad, (size_t)nq * sh.qrows * pad_dim(ix->dim));
+    if (sh.qdims_floats > 0)
+        take(w->qdims, sh.qdims_floats);
     if (sh.qtab) {
         take(w->qtab, nq * sh.qtab_floats_q);
         take(w->qtab_off, nq + 1);
@@ -1014,7 +1048,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
     if (o.order == TSK_ORDER_LEARNED) {
         if (!o.model)
             return set_err(TSK_ERR_INVALID_ARG, "TSK_ORDER_LEARNED needs opts->model");
-        if (o.model->dim != cix->dim || o.model->device != cix->device)
+        if (o.model->dim != cix->udim || o.model->device != cix->device)
             return set_err(TSK_ERR_INVALID_ARG, "the model's dim/device differ from the index's");
     }
     if (o.seed_count < 0)
@@ -1132,7 +1166,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         sh.qpad = o.dp_kernel != 1;
         sh.qrows = qmax + 2 * QPAD;
         sh.qtab = dist == TSK_DTW && !P.env_ok && ix->bucketed && o.dp_kernel != 1;
-        sh.qtab_floats_q = qtable_floats(qmax, ix->dim <= 4 ? 4 : 8);
+        sh.qtab_floats_q = qtable_floats(qmax, pad_dim(ix->dim));
+        sh.qdims_floats = ix->udim == ix->dim ? 0 : q_offsets_host[n_queries] * ix->dim;
         int64_t lo = 0, hi = P.chunk; // largest nq in [1, P.chunk] that fits
         while (lo < hi) {
             const int64_t mid = (lo + hi + 1) / 2;
@@ -1158,6 +1193,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         lend.on = true;
     }
     TSK_TRY(ensure_ws(ix, P.chunk, k, P.env_ok, lb_rev, P.env_ok));
+    const float *qvals = q_values_dev;
+    TSK_TRY(kernel_queries(ix, q_values_dev, q_offsets_host, n_queries, s, &qvals));
     Workspace &W = ix->ws;
     if (rr)
         TSK_TRY(W.rng.ensure((size_t)P.chunk * ix->n));
@@ -1244,7 +1281,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         if (c.lbu)
             TSK_TRY(prepare_qtables(ix, q_offsets_host, c.q0, c.nq, s));
         if (c.fast != FAST_NONE)
-            TSK_TRY(W.qpad.ensure((size_t)c.nq * c.qrows * (P.D <= 4 ? 4 : 8)));
+            TSK_TRY(W.qpad.ensure((size_t)c.nq * c.qrows * pad_dim(P.D)));
         return TSK_OK;
     };
     // 16 persistent waves per CU (4 per SIMD) hide the DP loops' load latency
@@ -1257,7 +1294,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             HIP_TRY(hipEventRecord(ev[i], s));                                                     \
     } while (0)
         const int nq = c.nq;
-        const float *qv = q_values_dev; // offsets are absolute into q_values_dev
+        const float *qv = qvals; // offsets are absolute into the query values
         W.qoff_cur = W.qoff.p + c.q0;   // every query's offsets are on the device
         TSK_MARK(0);
         fill_u32(W.tau.p, rr ? f_bits_host(rr->tau_key) : TSK_INF_BITS, nq, s);
@@ -1459,7 +1496,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         for (const Chunk &c : chunks)
             qrows_max = std::max(qrows_max, c.fast != FAST_NONE ? c.qrows : 0);
         if (qrows_max > 0)
-            TSK_TRY(W.qpad.ensure((size_t)P.chunk * qrows_max * (P.D <= 4 ? 4 : 8)));
+            TSK_TRY(W.qpad.ensure((size_t)P.chunk * qrows_max * pad_dim(P.D)));
         for (const Chunk &c : chunks)
             TSK_TRY(prepare_chunk(c));
         if (o.order == TSK_ORDER_LEARNED)
@@ -1483,7 +1520,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
               (const void *)W.work.p, (const void *)W.qoff.p, (const void *)W.env.p,
               (const void *)W.tbuf.p, (const void *)W.qpad.p, (const void *)W.fb.p,
               (const void *)W.qtab.p, (const void *)W.qtab_off.p, (const void *)W.cenv.p,
-              (const void *)W.surv2.p, (const void *)o.model, (const void *)ix->emb.p,
+              (const void *)W.surv2.p, (const void *)qvals, (const void *)o.model,
+              (const void *)ix->emb.p,
               (const void *)ix->qemb.p, (const void *)ix->lorder.p,
               (const void *)(model ? model->x.p : nullptr),
               (const void *)(model ? model->a1.p : nullptr),
@@ -1774,12 +1812,14 @@ extern "C" int tsk_pair_distances(const tsk_index *cix, const float *q_values_de
     P.ba = BandArgs{band.mode, band.r, band.frac};
     const int64_t chunk = chunk_queries(ix, n_queries);
     TSK_TRY(ensure_ws(ix, chunk, 1, false));
+    const float *qvals = q_values_dev;
+    TSK_TRY(kernel_queries(ix, q_values_dev, q_offsets_host, n_queries, s, &qvals));
     for (int64_t q0 = 0; q0 < n_queries; q0 += chunk) {
         const int nq = (int)std::min<int64_t>(chunk, n_queries - q0);
         TSK_TRY(upload_qoff(ix, q_offsets_host, q0, nq, s));
         fill_u64(ix->ws.work.p, 0ull, 8, s);
         fill_u64(ix->ws.ctr.p, 0ull, CTR_WORDS, s);
-        DpArgs da = dp_args(ix, q_values_dev, nq, P);
+        DpArgs da = dp_args(ix, qvals, nq, P);
         da.out_all = out_keys_dev + q0 * ix->n;
         launch_dp_wave(P.D, dist, DPW_ALLPAIRS, da, dp_blocks(ix), s);
         HIP_TRY(hipGetLastError());
@@ -1810,13 +1850,15 @@ extern "C" int tsk_pair_bounds(const tsk_index *cix, const float *q_values_dev,
     P.env_ok = (dist == TSK_DTW) && ix->min_len == ix->max_len;
     const int64_t chunk = chunk_queries(ix, n_queries);
     TSK_TRY(ensure_ws(ix, chunk, 1, P.env_ok));
+    const float *qvals = q_values_dev;
+    TSK_TRY(kernel_queries(ix, q_values_dev, q_offsets_host, n_queries, s, &qvals));
     for (int64_t q0 = 0; q0 < n_queries; q0 += chunk) {
         const int nq = (int)std::min<int64_t>(chunk, n_queries - q0);
         TSK_TRY(upload_qoff(ix, q_offsets_host, q0, nq, s));
         fill_u64(ix->ws.ctr.p, 0ull, CTR_WORDS, s);
         if (P.env_ok)
-            dispatch_d<EnvLaunch>(P.D, ix, q_values_dev, nq, P.ba, s);
-        BoundArgs ba = bound_args(ix, q_values_dev, nq, P);
+            dispatch_d<EnvLaunch>(P.D, ix, qvals, nq, P.ba, s);
+        BoundArgs ba = bound_args(ix, qvals, nq, P);
         ba.dbg_lb = out_lb_dev ? out_lb_dev + q0 * ix->n : nullptr;
         ba.dbg_ub = out_ub_dev ? out_ub_dev + q0 * ix->n : nullptr;
         ba.dbg_steps = out_steps_dev ? out_steps_dev + q0 * ix->n : nullptr;
@@ -1827,14 +1869,14 @@ extern "C" int tsk_pair_bounds(const tsk_index *cix, const float *q_values_dev,
             launch_bound_lb(P.D, ba, true, s);
         if (dist == TSK_DTW && !P.env_ok && ix->bucketed && ba.dbg_lb) {
             TSK_TRY(prepare_qtables(ix, q_offsets_host, q0, nq, s));
-            launch_qtable(P.D, q_values_dev, ix->ws.qoff.p, nq, ix->ws.qtab_off.p, ix->ws.qtab.p, s);
+            launch_qtable(P.D, qvals, ix->ws.qoff.p, nq, ix->ws.qtab_off.p, ix->ws.qtab.p, s);
             launch_bound_lbu(P.D, ba, bucket_args(ix), ix->ws.qtab.p, ix->ws.qtab_off.p, 4, true, s);
         }
         int32_t qmax = 0;
         for (int i = 0; i < nq; ++i)
             qmax = std::max<int32_t>(qmax, (int32_t)(q_offsets_host[q0 + i + 1] - q_offsets_host[q0 + i]));
         if (ba.dbg_ub && ba.dbg_steps && walk_lds_bytes(P.D, qmax) <= 64 * 1024) {
-            SeedRingArgs r{q_values_dev, ix->ws.qoff.p, nq, qmax, ix->aos, ix->off, ix->len, ix->n,
+            SeedRingArgs r{qvals, ix->ws.qoff.p, nq, qmax, ix->aos, ix->off, ix->len, ix->n,
                            nullptr, 0, (int)std::min<int64_t>(ix->n, INT32_MAX), 1, P.ba,
                            ix->ws.seedslots.p, ix->ws.tau.p, ix->ws.ctr.p, ba.dbg_ub, ba.dbg_steps};
             launch_seed_ring(P.D, dist, r, s);

@@ -56,7 +56,7 @@ def test_build_rejects_bad_arguments_before_device_work():
     assert lib.tsk_index_build(None, offp, 2, 3, None, None, ctypes.byref(out)) == _lib.TSK_ERR_INVALID_ARG
     # unsupported dimension
     assert lib.tsk_index_build(fake, offp, 2, 0, None, None, ctypes.byref(out)) == _lib.TSK_ERR_UNSUPPORTED
-    assert lib.tsk_index_build(fake, offp, 2, 9, None, None, ctypes.byref(out)) == _lib.TSK_ERR_UNSUPPORTED
+    assert lib.tsk_index_build(fake, offp, 2, 33, None, None, ctypes.byref(out)) == _lib.TSK_ERR_UNSUPPORTED
     # zero-length series
     bad = np.array([0, 4, 4], np.int64)
     assert lib.tsk_index_build(fake, bad.ctypes.data_as(ctypes.c_void_p), 2, 3, None, None,

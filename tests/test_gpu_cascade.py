@@ -55,6 +55,8 @@ def test_cascade_random_walks(d, band):
                                    dtw_cascade=cas)
             assert_same_knn(ids, dst, ref_ids, ref_keys, distance)
             assert st["pairs"] == 6 * 500
+            # every pair is either discarded by a bound or reaches a DP
+            assert st["bound_pruned"] + st["dp_started"] == st["pairs"], (bs, cas, st)
     idx.close()
 
 
@@ -75,6 +77,8 @@ def test_cascade_classwarp(seed_count):
                                               seed_count=seed_count, bound_seed=bs,
                                               dtw_cascade=cas)
             assert_same_knn(ids, dst, ref_ids, ref_keys, distance)
+            s_ = st[(bs, cas)]
+            assert s_["bound_pruned"] + s_["dp_started"] == s_["pairs"], (bs, cas, s_)
         print(f"  {distance}: completed DPs bound-ordered {st[(1, 0)]['dp_completed']} "
               f"head {st[(2, 0)]['dp_completed']}; seed+bound steps cascade "
               f"{st[(0, 1)]['bound_steps']} all-pairs LB_Box {st[(0, 0)]['bound_steps']}",

@@ -170,6 +170,8 @@ def test_knn_small(case, band):
         ids, dst, st = idx.knn(to_dev(qs), qo, k, dist, band, stats=True)
         assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
         assert st["pairs"] == Q * N
+        # every pair is counted once: discarded by a bound, or a DP began
+        assert st["bound_pruned"] + st["dp_started"] == st["pairs"], st
     idx.close()
 
 
@@ -270,6 +272,9 @@ def test_knn_tube_overflow_goes_to_general_dp(rows):
     ids, dst, st = idx.knn(to_dev(qs), qo, 40, "dk", None, stats=True, tube_rows=rows)
     assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
     assert st["fallback_pairs"] > 0
+    # a handed-over pair counts once, in the general DP
+    assert st["bound_pruned"] + st["dp_started"] == st["pairs"], st
+    assert st["dp_completed"] + st["dp_abandoned"] == st["dp_started"], st
     # queries no taller than the window never overflow it
     db2, dbo2 = ragged_walks(53, 40, (5, 40), 2)
     qs2, qo2 = ragged_walks(54, 2, (5, rows), 2)
