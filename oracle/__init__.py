@@ -51,6 +51,8 @@ def _load():
         "orc_lb_box_f32": (ctypes.c_float, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64]),
         "orc_lb_box_f64": (ctypes.c_double, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64]),
         "orc_lb_box_qenv_f32": (ctypes.c_float, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64]),
+        "orc_lb_dk_box_f32": (ctypes.c_float, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64]),
+        "orc_lb_dk_box_qenv_f32": (ctypes.c_float, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64]),
         "orc_lb_keogh_f64": (ctypes.c_double, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64, ctypes.c_int]),
         "orc_lb_sigmamin_f64": (ctypes.c_double, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64]),
         "orc_gdk_sq_f32": (ctypes.c_float, [_f32p, _i64, _f32p, _i64, ctypes.c_int, _i64,
@@ -206,6 +208,18 @@ def lb_box_f64(S, T, w=-1) -> float:
 def lb_box_qenv_f32(S, T, w=-1) -> float:
     """Boxes over the query S, summed over the points of the candidate T."""
     return float(_pair_call("orc_lb_box_qenv_f32", S, T, w))
+
+
+def lb_dk_box_f32(S, T, w=-1) -> float:
+    """DK box bound: the largest squared distance of a row of S to its box
+    of T (Sec. 3's boxes, the maximum in place of eq. (1)'s sum); <= DK^2."""
+    return float(_pair_call("orc_lb_dk_box_f32", S, T, w))
+
+
+def lb_dk_box_qenv_f32(S, T, w=-1) -> float:
+    """The DK box bound with boxes over the query S, the largest over the
+    points of the candidate T."""
+    return float(_pair_call("orc_lb_dk_box_qenv_f32", S, T, w))
 
 
 def lb_keogh_f64(S, T, w=-1, dim=0) -> float:

@@ -761,6 +761,44 @@ float orc_lb_box_qenv_f32(const float *S, int64_t m, const float *T, int64_t n, 
     return acc;
 }
 
+/* DK lower bound from the boxes of Sec. 3.  DK^2 is the largest point cost
+ * on the best warping path (Sec. 2.1), and every path aligns each row i of S
+ * with some column of its band window, at a cost no smaller than the squared
+ * distance of s_i to the box B_i of T over that window.  So the largest of
+ * these box distances bounds DK^2 from below: eq. (1)'s construction with a
+ * maximum in place of the sum.  fp32 box terms in the point cost's order
+ * (each at most the fp32 cost of any cell of its window, by monotone
+ * rounding); a maximum rounds nothing.  An empty window gives +inf. */
+float orc_lb_dk_box_f32(const float *S, int64_t m, const float *T, int64_t n, int d, int64_t w)
+{
+    float *lo = malloc(sizeof(float) * m * d), *hi = malloc(sizeof(float) * m * d);
+    orc_envelope(T, n, m, d, w, lo, hi);
+    float best = 0.0f;
+    for (int64_t i = 0; i < m; ++i) {
+        float t = orc_box_term_f32(S + i * d, lo + i * d, hi + i * d, d);
+        if (t > best) best = t;
+    }
+    free(lo); free(hi);
+    return best;
+}
+
+/* The same bound with the roles of the series exchanged: boxes of the query
+ * S over the rows each column j of T may align with (orc_qenv), the largest
+ * box distance over the candidate's points t_j. */
+float orc_lb_dk_box_qenv_f32(const float *S, int64_t m, const float *T, int64_t n, int d,
+                             int64_t w)
+{
+    float *lo = malloc(sizeof(float) * n * d), *hi = malloc(sizeof(float) * n * d);
+    orc_qenv(S, m, n, d, w, lo, hi);
+    float best = 0.0f;
+    for (int64_t j = 0; j < n; ++j) {
+        float t = orc_box_term_f32(T + j * d, lo + j * d, hi + j * d, d);
+        if (t > best) best = t;
+    }
+    free(lo); free(hi);
+    return best;
+}
+
 /* Paper-faithful pruned scan, one query at a time in candidate-id order.
  *   DK  (Sec. 4.3): a first pass computes the greedy bound (Alg. 1) of every
  *       candidate with early return against the running k-th smallest bound;

@@ -295,6 +295,73 @@ def test_wider_window_lowers_lb_box(rng):
             prev = lb
 
 
+def test_dk_box_bound_below_dk(rng):
+    """The DK box bound (Sec. 3's boxes, the largest box distance) never
+    exceeds the fp32 DK^2 of the same band, in either orientation; it is
+    never below the box distance of any single row; exchanging the series
+    exchanges the orientations."""
+    for band in (None, 0, 1, 3, 0.25):
+        for _ in range(50):
+            m = int(rng.integers(1, 25))
+            n = m if band is not None and not isinstance(band, float) else int(rng.integers(1, 25))
+            d = int(rng.integers(1, 5))
+            S = rng.normal(size=(m, d)).astype(np.float32)
+            T = rng.normal(size=(n, d)).astype(np.float32)
+            w = O.band_w(band, m, n)
+            dk = O.dk_sq_f32(S, T, w)
+            lb = O.lb_dk_box_f32(S, T, w)
+            lbq = O.lb_dk_box_qenv_f32(S, T, w)
+            assert lb <= dk and lbq <= dk, (band, m, n, lb, lbq, dk)
+            assert lbq == O.lb_dk_box_f32(T, S, w)
+            lo, hi = O.envelope(T, m, w)
+            i = int(rng.integers(0, m))
+            assert lb >= O.box_term_f32(S[i], lo[i], hi[i])
+
+
+def test_dk_box_bound_closed_forms(rng):
+    """Closed forms, bit for bit: with w = 0 and m = n every box is one
+    point and only the diagonal path remains, so both orientations equal
+    DK^2 (the largest diagonal cost); with m = 1 every column's query box is
+    the one query point and the only path visits all of T, so the
+    query-box orientation equals DK^2 (and with n = 1 the other one)."""
+    for _ in range(40):
+        L = int(rng.integers(1, 40))
+        d = int(rng.integers(1, 5))
+        S = rng.normal(size=(L, d)).astype(np.float32)
+        T = rng.normal(size=(L, d)).astype(np.float32)
+        dk = O.dk_sq_f32(S, T, 0)
+        assert O.lb_dk_box_f32(S, T, 0) == dk
+        assert O.lb_dk_box_qenv_f32(S, T, 0) == dk
+        assert dk == max(O.cost_f32(S[i], T[i]) for i in range(L))
+        n = int(rng.integers(1, 30))
+        P = rng.normal(size=(1, d)).astype(np.float32)
+        U = rng.normal(size=(n, d)).astype(np.float32)
+        assert O.lb_dk_box_qenv_f32(P, U) == O.dk_sq_f32(P, U)
+        assert O.lb_dk_box_f32(U, P) == O.dk_sq_f32(U, P)
+        # a point inside every box contributes nothing: a series against
+        # itself, unbanded, has bound 0 = DK^2
+        assert O.lb_dk_box_f32(S, S) == 0.0 == O.dk_sq_f32(S, S)
+
+
+def test_dk_box_bound_wider_window_lower(rng):
+    """A superset window widens each box: the bound over a wider band is
+    never larger, and each band's bound stays below that band's DK^2."""
+    for _ in range(40):
+        m = int(rng.integers(1, 30))
+        n = int(rng.integers(1, 30))
+        d = int(rng.integers(1, 4))
+        S = rng.normal(size=(m, d)).astype(np.float32)
+        T = rng.normal(size=(n, d)).astype(np.float32)
+        prev = prevq = None
+        for w in (0, 1, 3, 7, 30, -1):
+            lb, lbq = O.lb_dk_box_f32(S, T, w), O.lb_dk_box_qenv_f32(S, T, w)
+            if prev is not None:
+                assert lb <= prev and lbq <= prevq
+            dk = O.dk_sq_f32(S, T, w)
+            assert lb <= dk and lbq <= dk
+            prev, prevq = lb, lbq
+
+
 # ------------------------------------------------------------------ greedy bounds
 def test_greedy_upper_bounds(rng):
     """Alg. 1 returns an upper bound of DK (Sec. 4.1) in at most m+n-2 moves;
