@@ -251,6 +251,13 @@ typedef struct {
                                       default (1 for the plain order unless
                                       bound_seed is 2 or lb_qgroup names an
                                       LB_Box kernel, else 2) */
+    int32_t dk_box;                /* DK on an equal-length index with the
+                                      corner cascade (the plain order's
+                                      default, or bound_seed = 1): 1 = the
+                                      corner survivors are also bounded by
+                                      the DK box bound (tsk_pair_dk_box) and
+                                      the DP runs on those it keeps, in
+                                      ascending bound; 0 or 2 = off */
 } tsk_query_opts;
 
 typedef struct {
@@ -426,6 +433,21 @@ int tsk_pair_distances(const tsk_index *index, const float *q_values_dev,
  * Both device arrays of n floats on the current device; out_dev may equal
  * keys_dev (in place).  Asynchronous on the stream.  Errors: INVALID_ARG. */
 int tsk_dk_distances(const float *keys_dev, float *out_dev, int64_t n, void *hip_stream);
+
+/* DK box bound of every pair (Sec. 3's boxes with the maximum in place of
+ * eq. (1)'s sum; Sec. 2.1: DK is the largest point distance on the best
+ * warping path): out_dev[q * n_series + c] = the largest, over the points
+ * t_j of series c, of the squared distance of t_j to the box (per-dimension
+ * [min, max]) of the query rows that the band lets column j align with,
+ * float32 terms in the point cost's order; it never exceeds the squared DK
+ * of the pair (tsk_pair_distances), and +inf where a column's window is
+ * empty.  The same kernel as the k-NN option dk_box, with no threshold.
+ * Needs an index of equal-length series (queries of any length).
+ * out_dev: device float [n_queries * n_series].  Synchronous.  Errors:
+ * INVALID_ARG, UNSUPPORTED (series of unequal length), OOM, DEVICE. */
+int tsk_pair_dk_box(const tsk_index *index, const float *q_values_dev,
+                    const int64_t *q_offsets_host, int64_t n_queries, tsk_band band,
+                    float *out_dev, void *hip_stream);
 
 /* Per-pair bounds through the same kernels as the k-NN path, with no
  * threshold (no early return):

@@ -110,7 +110,7 @@ class Index:
             dk_band_slots: int = 0, surv_order: int = 0, dp_rows: int = 0,
             dp_waves_per_cu: int = 0, dk_seed: int = 0, cancel=None, lb_both: bool = False,
             raw_keys: bool = False, no_alloc: bool = False, bound_seed: int = 0,
-            dtw_cascade: int = 0):
+            dtw_cascade: int = 0, dk_box: int = 0):
         """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
         float32 [nq, k], stats dict or None); DK distances are unsquared.
         order: None (plain), a CUDA int32 [nq, n] permutation per query, or
@@ -127,7 +127,9 @@ class Index:
         smallest corner bound, 2 = from the head of its order, 0 = default
         (1 for the plain order); dtw_cascade: 1 = DTW prunes by the corner
         bound first and computes LB_Box for its survivors only, 2 = LB_Box
-        for every pair, 0 = default (1 for the plain order);
+        for every pair, 0 = default (1 for the plain order); dk_box: 1 = DK
+        on an equal-length index also bounds the corner survivors by the
+        DK box bound (see pair_dk_box), 0 / 2 = off;
         no_alloc: the call allocates no device memory (C:
         tsk_knn_query_noalloc, the library's fixed workspace; pass `out`
         to keep the binding from allocating the outputs; no stats)."""
@@ -164,6 +166,7 @@ class Index:
         opts.raw_keys = 1 if raw_keys else 0
         opts.bound_seed = int(bound_seed)
         opts.dtw_cascade = int(dtw_cascade)
+        opts.dk_box = int(dk_box)
         opts.use_graph = 1 if use_graph else 0
         opts.tune = _lib.TSK_TUNE_CACHED if tune else _lib.TSK_TUNE_OFF
         if cancel is not None:
@@ -287,6 +290,19 @@ class Index:
             _DIST[distance], _lib.band_struct(band), ctypes.c_void_p(lb.data_ptr()),
             ctypes.c_void_p(ub.data_ptr()), ctypes.c_void_p(steps.data_ptr()), _stream()))
         return lb, ub, steps
+
+    def pair_dk_box(self, queries, q_offsets, band=None):
+        """DK box bound of every pair, squared (C: tsk_pair_dk_box); the
+        index's series must share one length."""
+        torch = _torch()
+        qv = _values(queries, self.dim)
+        qo = _offsets(q_offsets)
+        nq = int(qo.shape[0] - 1)
+        out = torch.empty((nq, self.n), dtype=torch.float32, device=qv.device)
+        _lib.check(self._lib.tsk_pair_dk_box(
+            self._h, ctypes.c_void_p(qv.data_ptr()), qo.ctypes.data_as(ctypes.c_void_p), nq,
+            _lib.band_struct(band), ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
 
 
 def subseq_query(series, s_offsets, queries, q_offsets, k: int = 1, chunk_cols: int = 0,

@@ -47,7 +47,7 @@ class QueryOpts(ctypes.Structure):
                 ("lb_both", ctypes.c_int32),
                 ("raw_keys", ctypes.c_int32),
                 ("bound_seed", ctypes.c_int32),
-                ("dtw_cascade", ctypes.c_int32)]
+                ("dtw_cascade", ctypes.c_int32), ("dk_box", ctypes.c_int32)]
 
 
 class IndexOpts(ctypes.Structure):
@@ -112,6 +112,7 @@ SIGNATURES = {
     "tsk_pair_distances": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp]),
     "tsk_dk_distances": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
     "tsk_pair_bounds": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Band, _vp, _vp, _vp, _vp]),
+    "tsk_pair_dk_box": (ctypes.c_int, [_vp, _vp, _vp, _i64, Band, _vp, _vp]),
     "tsk_tune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, Band, _vp, _vp, _vp, _vp, _vp]),
     # band by pointer: libffi misplaces a float scalar next to a by-value
     # struct with a float member, so this entry point takes neither

@@ -67,17 +67,27 @@ template <int D> void corner_d(int dist, const BoundArgs &a, hipStream_t s)
         hipLaunchKernelGGL((k_corner<D, QG, DIST_DTW>), grid, dim3(256), 0, s, a);
 }
 
-template <int D>
-void bound_lb_surv_d(const BoundArgs &a, const int32_t *surv, const int32_t *surv_cnt,
-                     const int32_t *max_cnt, unsigned long long *work, int blocks, hipStream_t s)
+template <int D, int DIST>
+void bound_lb_surv_dd(const BoundArgs &a, const int32_t *surv, const int32_t *surv_cnt,
+                      const int32_t *max_cnt, unsigned long long *work, int blocks, hipStream_t s)
 {
     const size_t lds = (size_t)a.env_n * 2 * D * sizeof(float);
     if (lds <= 64 * 1024)
-        hipLaunchKernelGGL((k_bound_lb_surv<D, true>), dim3(blocks), dim3(256), lds, s, a, surv,
-                           surv_cnt, max_cnt, work);
+        hipLaunchKernelGGL((k_bound_lb_surv<D, true, DIST>), dim3(blocks), dim3(256), lds, s, a,
+                           surv, surv_cnt, max_cnt, work);
     else
-        hipLaunchKernelGGL((k_bound_lb_surv<D, false>), dim3(blocks), dim3(256), 0, s, a, surv,
-                           surv_cnt, max_cnt, work);
+        hipLaunchKernelGGL((k_bound_lb_surv<D, false, DIST>), dim3(blocks), dim3(256), 0, s, a,
+                           surv, surv_cnt, max_cnt, work);
+}
+
+template <int D>
+void bound_lb_surv_d(int dist, const BoundArgs &a, const int32_t *surv, const int32_t *surv_cnt,
+                     const int32_t *max_cnt, unsigned long long *work, int blocks, hipStream_t s)
+{
+    if (dist == DIST_DK)
+        bound_lb_surv_dd<D, DIST_DK>(a, surv, surv_cnt, max_cnt, work, blocks, s);
+    else
+        bound_lb_surv_dd<D, DIST_DTW>(a, surv, surv_cnt, max_cnt, work, blocks, s);
 }
 
 template <int D>
@@ -157,11 +167,11 @@ void launch_corner(int D, int dist, const BoundArgs &a, hipStream_t s)
 #undef CALL
 }
 
-void launch_bound_lb_surv(int D, const BoundArgs &a, const int32_t *surv, const int32_t *surv_cnt,
-                          const int32_t *max_cnt, unsigned long long *work, int blocks,
-                          hipStream_t s)
+void launch_bound_lb_surv(int D, int dist, const BoundArgs &a, const int32_t *surv,
+                          const int32_t *surv_cnt, const int32_t *max_cnt,
+                          unsigned long long *work, int blocks, hipStream_t s)
 {
-#define CALL(d) bound_lb_surv_d<d>(a, surv, surv_cnt, max_cnt, work, blocks, s)
+#define CALL(d) bound_lb_surv_d<d>(dist, a, surv, surv_cnt, max_cnt, work, blocks, s)
     TSK_SWITCH_D(D, CALL)
 #undef CALL
 }

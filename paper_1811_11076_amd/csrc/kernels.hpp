@@ -113,6 +113,14 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 __device__ __forceinline__ float wave_min(float v)
 {
 #pragma unroll
@@ -128,6 +136,14 @@ static __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+// rows of 0 .. N-1: a survivor list holding every candidate of each query
+static __global__ void k_iota_rows(int32_t *p, int64_t rows, int64_t N)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < rows * N; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)(i % N);
 }
 
 static __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n)

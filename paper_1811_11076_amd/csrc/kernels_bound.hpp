@@ -728,9 +728,15 @@ __global__ __launch_bounds__(256) void k_bound_lb_rev(const float *__restrict__ 
 // survivors of one query from a work counter (queries interleaved), its
 // waves a quarter each; with ENV_LDS the query's envelope is staged in LDS
 // once per task instead of being read by every pair.
+// DIST_DK: the DK box bound instead, the largest term (Sec. 3's boxes; the
+// squared DK is the largest cost on the best path, which aligns each
+// candidate point with a query row of its window, at a cost no smaller than
+// the term), compared with the squared-DK threshold.  A maximum rounds
+// nothing and each term is at most the fp32 cost of any cell of its window
+// (same operation order, monotone rounding), so no scaling.
 constexpr int LBS_TASK = 64;
 
-template <int D, bool ENV_LDS>
+template <int D, bool ENV_LDS, int DIST>
 __global__ __launch_bounds__(256) void k_bound_lb_surv(BoundArgs a, const int32_t *__restrict__ surv,
                                                        const int32_t *__restrict__ surv_cnt,
                                                        const int32_t *__restrict__ max_cnt,
@@ -789,11 +795,12 @@ __global__ __launch_bounds__(256) void k_bound_lb_surv(BoundArgs a, const int32_
                         const float d = fmaxf(fmaxf(e[k] - x[k], x[k] - e[D + k]), 0.0f);
                         tt = (k == 0) ? d * d : __builtin_fmaf(d, d, tt);
                     }
-                    acc += tt;
+                    acc = DIST == DIST_DK ? fmaxf(acc, tt) : acc + tt;
                 }
                 if ((j0 & 255) == 192 && j0 + 64 < n) {
                     // every 256 points: stop once the partial bound exceeds tau
-                    if (wave_sum(acc) * scale > tau) {
+                    const float part = DIST == DIST_DK ? wave_max(acc) : wave_sum(acc) * scale;
+                    if (part > tau) {
                         over = true;
                         j0 += 64;
                         break;
@@ -801,7 +808,7 @@ __global__ __launch_bounds__(256) void k_bound_lb_surv(BoundArgs a, const int32_
                 }
             }
             terms += (unsigned long long)min(j0, n);
-            const float lb = wave_sum(acc) * scale;
+            const float lb = DIST == DIST_DK ? wave_max(acc) : wave_sum(acc) * scale;
             const bool drop = over || lb > tau;
             pruned += drop ? 1 : 0;
             if (lane == 0)

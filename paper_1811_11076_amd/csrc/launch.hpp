@@ -52,10 +52,11 @@ void launch_bound_lb_rev(int D, const float *aos, const int64_t *off, int64_t N,
 void launch_bound_lb_pp(int D, const BoundArgs &a, hipStream_t s);
 void launch_seed_ring(int D, int dist, const SeedRingArgs &r, hipStream_t s);
 void launch_corner(int D, int dist, const BoundArgs &a, hipStream_t s);
-// LB_Box of the compacted survivors (query envelope in a.env), lbv updated
-void launch_bound_lb_surv(int D, const BoundArgs &a, const int32_t *surv, const int32_t *surv_cnt,
-                          const int32_t *max_cnt, unsigned long long *work, int blocks,
-                          hipStream_t s);
+// LB_Box (DTW) or the DK box bound (DK) of the compacted survivors (query
+// envelope in a.env), lbv updated
+void launch_bound_lb_surv(int D, int dist, const BoundArgs &a, const int32_t *surv,
+                          const int32_t *surv_cnt, const int32_t *max_cnt,
+                          unsigned long long *work, int blocks, hipStream_t s);
 void launch_seed_diag(int D, int dist, const SeedRingArgs &r, hipStream_t s);
 void launch_walk_dk(int D, const FastArgs &a, const float *qv, unsigned long long *ubslots,
                     int blocks, int maxm, hipStream_t s);

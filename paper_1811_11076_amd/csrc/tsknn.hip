@@ -911,6 +911,7 @@ static void apply_tuned(tsk_query_opts *o, const tsk_query_opts &t)
     o->dk_seed = t.dk_seed;
     o->bound_seed = t.bound_seed;
     o->dtw_cascade = t.dtw_cascade;
+    o->dk_box = t.dk_box;
 }
 
 // A range query (fixed threshold, every hit reported) riding on the k-NN
@@ -1082,6 +1083,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "bound_seed must be 0, 1 or 2");
     if (o.dtw_cascade < 0 || o.dtw_cascade > 2)
         return set_err(TSK_ERR_INVALID_ARG, "dtw_cascade must be 0, 1 or 2");
+    if (o.dk_box < 0 || o.dk_box > 2)
+        return set_err(TSK_ERR_INVALID_ARG, "dk_box must be 0, 1 or 2");
     if (o.use_graph && o.profile)
         return set_err(TSK_ERR_UNSUPPORTED, "use_graph excludes profile");
     if (fx && (o.use_graph || o.profile || o.order == TSK_ORDER_LEARNED || o.lb_both || rr ||
@@ -1118,7 +1121,9 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         ix->min_len != ix->max_len && o.dp_kernel != 1)
         return set_err(TSK_ERR_UNSUPPORTED, "use_graph on uneven-length DTW needs the queries to "
                                             "fit one chunk (%lld here)", (long long)P.chunk);
-    P.env_ok = (dist == TSK_DTW) && ix->min_len == ix->max_len;
+    // the query envelope: DTW on an equal-length index, and DK there when the
+    // box bound is asked for
+    P.env_ok = (dist == TSK_DTW || (o.dk_box == 1 && !rr)) && ix->min_len == ix->max_len;
     // seed sizes: the greedy DK seed is a latency-bound walk (a few hundred
     // candidates give a tight threshold); the diagonal DTW seed is a cheap
     // parallel sum, so it takes more candidates.  Seeds of smallest corner
@@ -1234,7 +1239,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         int nq;
         int32_t qmin, qmax;
         const int32_t *order;
-        bool lds_query, dk_split, lbu, diag_seed, dk_cascade, dtw_cascade, dtw_bseed;
+        bool lds_query, dk_split, lbu, diag_seed, dk_cascade, dtw_cascade, dtw_bseed, dk_box;
+        bool surv_lb; // a second bound over the first one's survivors (surv -> surv2)
         int fast, wsel, qrows;
     };
     auto plan_chunk = [&](int64_t q0) {
@@ -1273,6 +1279,9 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                          (o.dtw_cascade == 0 && o.bound_seed != 2 && o.order == TSK_ORDER_PLAIN &&
                           o.lb_qgroup == 0));
         c.dtw_bseed = dtw_eq && (o.bound_seed == 1 || c.dtw_cascade);
+        // DK on equal lengths, on request: the box bound of the corner survivors
+        c.dk_box = c.dk_cascade && dist == TSK_DK && P.env_ok;
+        c.surv_lb = c.dtw_cascade || c.dk_box;
         c.fast = pick_fast(ix, dist, band, c.qmin, c.qmax, o.dp_kernel, o.dk_band_slots, &c.wsel);
         c.qrows = c.qmax + 2 * QPAD;
         return c;
@@ -1364,17 +1373,18 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                                    c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr,
                                    W.tau.p, W.surv.p, W.surv_cnt.p, W.max_cnt.p, ctr);
         };
-        if (c.dtw_cascade)
-            compact(); // the corner survivors, before LB_Box
+        if (c.surv_lb)
+            compact(); // the corner survivors, before LB_Box or the DK box bound
         TSK_MARK(2);
         BoundArgs ba = bound_args(ix, qv, nq, P);
         ba.ctr = ctr;
         if (rr)
             ba.ubslots = nullptr;
-        if (c.dtw_cascade) {
-            // LB_Box of the corner survivors only (lbv: their LB_Box or +inf)
-            launch_bound_lb_surv(P.D, ba, W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.work.p + 6,
-                                 ix->n_cu * 8, s);
+        if (c.surv_lb) {
+            // LB_Box (DTW) or the DK box bound of the corner survivors only
+            // (lbv: their bound or +inf)
+            launch_bound_lb_surv(P.D, dist, ba, W.surv.p, W.surv_cnt.p, W.max_cnt.p,
+                                 W.work.p + 6, ix->n_cu * 8, s);
         } else if (c.dk_cascade) {
             // the corner bounds are in lbv already
         } else if (c.dk_split) {
@@ -1397,8 +1407,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             dispatch_d<BoundLaunch>(P.D, ba, dist, false, s);
         }
         TSK_MARK(3);
-        if (c.dtw_cascade) {
-            // the corner survivors re-ranked by their LB_Box (into surv2)
+        if (c.surv_lb) {
+            // the corner survivors re-ranked by their second bound (into surv2)
             fill_u32((uint32_t *)W.max_cnt.p, 0u, 1, s);
             hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
                                SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, W.surv.p,
@@ -1407,7 +1417,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         } else {
             compact();
         }
-        int32_t *const surv_dp = c.dtw_cascade ? W.surv2.p : W.surv.p;
+        int32_t *const surv_dp = c.surv_lb ? W.surv2.p : W.surv.p;
         if (lb_rev) {
             // LB_Box in both orientations: the survivors' bounds become the
             // larger one (queries of another length keep theirs)
@@ -1509,7 +1519,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                                     o.dp_kernel, o.walk_pass, o.task_size, o.tube_rows,
                                     o.lb_qgroup, o.dk_band_slots, o.surv_order, o.dp_rows,
                                     o.dp_waves_per_cu, o.dk_seed, o.lb_both, o.raw_keys,
-                                    o.bound_seed, o.dtw_cascade, (int64_t)timed};
+                                    o.bound_seed, o.dtw_cascade, o.dk_box, (int64_t)timed};
         // every workspace buffer the captured kernels address: a buffer
         // reallocated by another call changes the key
         for (const void *ptr :
@@ -1881,6 +1891,56 @@ extern "C" int tsk_pair_bounds(const tsk_index *cix, const float *q_values_dev,
                            ix->ws.seedslots.p, ix->ws.tau.p, ix->ws.ctr.p, ba.dbg_ub, ba.dbg_steps};
             launch_seed_ring(P.D, dist, r, s);
         }
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return TSK_OK;
+}
+
+extern "C" int tsk_pair_dk_box(const tsk_index *cix, const float *q_values_dev,
+                               const int64_t *q_offsets_host, int64_t n_queries, tsk_band band,
+                               float *out_dev, void *hip_stream)
+{
+    g_err.clear();
+    TSK_TRY(check_queries(cix, q_values_dev, q_offsets_host, n_queries, TSK_DK, band));
+    if (!out_dev)
+        return set_err(TSK_ERR_INVALID_ARG, "out_dev is NULL");
+    TSK_TRY(check_dev_ptr(out_dev, cix->device, "out_dev"));
+    if (cix->min_len != cix->max_len)
+        return set_err(TSK_ERR_UNSUPPORTED, "the DK box bound needs series of one length "
+                                            "(index lengths %d .. %d)", cix->min_len, cix->max_len);
+    tsk_index *ix = const_cast<tsk_index *>(cix);
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    QueryPlan P;
+    memset(&P, 0, sizeof(P));
+    P.D = ix->dim;
+    P.dist = TSK_DK;
+    P.k = 1;
+    P.ba = BandArgs{band.mode, band.r, band.frac};
+    P.env_ok = true;
+    const int64_t chunk = chunk_queries(ix, n_queries);
+    TSK_TRY(ensure_ws(ix, chunk, 1, true));
+    const float *qvals = q_values_dev;
+    TSK_TRY(kernel_queries(ix, q_values_dev, q_offsets_host, n_queries, s, &qvals));
+    Workspace &W = ix->ws;
+    const int64_t N = ix->n;
+    for (int64_t q0 = 0; q0 < n_queries; q0 += chunk) {
+        const int nq = (int)std::min<int64_t>(chunk, n_queries - q0);
+        TSK_TRY(upload_qoff(ix, q_offsets_host, q0, nq, s));
+        fill_u64(W.ctr.p, 0ull, CTR_WORDS, s);
+        dispatch_d<EnvLaunch>(P.D, ix, qvals, nq, P.ba, s);
+        // every candidate is a survivor; no threshold
+        hipLaunchKernelGGL(k_iota_rows, dim3(grid_for(nq * N, 256, 8192)), dim3(256), 0, s,
+                           W.surv.p, (int64_t)nq, N);
+        fill_u32((uint32_t *)W.surv_cnt.p, (uint32_t)N, nq, s);
+        fill_u32((uint32_t *)W.max_cnt.p, (uint32_t)N, 1, s);
+        fill_u32(W.tau.p, TSK_INF_BITS, nq, s);
+        fill_u64(W.work.p, 0ull, 8, s);
+        BoundArgs ba = bound_args(ix, qvals, nq, P);
+        ba.lbv = out_dev + q0 * N;
+        launch_bound_lb_surv(P.D, TSK_DK, ba, W.surv.p, W.surv_cnt.p, W.max_cnt.p, W.work.p + 6,
+                             ix->n_cu * 8, s);
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(s));
