@@ -247,10 +247,13 @@ typedef struct {
                                       corner bound; LB_Box (eq. (1)) is
                                       computed only for its survivors, which
                                       then run in ascending LB_Box; 2 =
-                                      LB_Box for every pair; 0 = library
-                                      default (1 for the plain order unless
-                                      bound_seed is 2 or lb_qgroup names an
-                                      LB_Box kernel, else 2) */
+                                      LB_Box for every pair; 3 = the corner
+                                      bound and seed of 1 without LB_Box
+                                      (its survivors run in ascending corner
+                                      bound); 0 = library default (1 for the
+                                      plain order unless bound_seed is 2 or
+                                      lb_qgroup names an LB_Box kernel,
+                                      else 2) */
     int32_t dk_box;                /* DK on an equal-length index with the
                                       corner cascade (the plain order's
                                       default, or bound_seed = 1): 1 = the

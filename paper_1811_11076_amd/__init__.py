@@ -127,7 +127,8 @@ class Index:
         smallest corner bound, 2 = from the head of its order, 0 = default
         (1 for the plain order); dtw_cascade: 1 = DTW prunes by the corner
         bound first and computes LB_Box for its survivors only, 2 = LB_Box
-        for every pair, 0 = default (1 for the plain order); dk_box: 1 = DK
+        for every pair, 3 = the corner bound alone (no LB_Box), 0 = default
+        (1 for the plain order); dk_box: 1 = DK
         on an equal-length index also bounds the corner survivors by the
         DK box bound (see pair_dk_box), 0 / 2 = off;
         no_alloc: the call allocates no device memory (C:

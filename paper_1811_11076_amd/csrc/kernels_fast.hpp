@@ -220,6 +220,23 @@ __device__ __forceinline__ void finish_lane(const FastArgs &a, int q, int c, flo
 // lane's pair (checked every 8 columns).
 constexpr int BAND_NC = 2; // columns per iteration of k_dp_band
 
+// Cells inside the band (slot < wact) and the matrix (row 0 .. m-1) among
+// the G steps from k0 of an NC-column iteration at column j: column j + r
+// takes slots k0 - r .. k0 + G - 1 - r, slot s being row j + r - w + s.
+template <int G, int NC>
+__device__ __forceinline__ int band_group_cells(int k0, int j, int w, int wact, int m)
+{
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+        const int c = j + r;
+        const int lo = max(max(k0 - r, 0), w - c);
+        const int hi = min(min(k0 + G - 1 - r, wact - 1), m - 1 - c + w);
+        n += max(0, hi - lo + 1);
+    }
+    return n;
+}
+
 template <int D, int DIST, int W, int KMASK>
 __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restrict__ qpad)
 {
@@ -296,6 +313,30 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
             auto combine = [](float cst, float pred) -> float {
                 return DIST == DIST_DK ? fmaxf(cst, pred) : cst + pred;
             };
+            // Dead groups of G steps: a group's cells take their
+            // predecessors from inside the group, from Dv[gG .. gG+G]
+            // (column j-1, not yet overwritten when the group starts) and
+            // from prv[] (the step before the group).  If all of those
+            // exceed tau on every live lane, so does every cell of the group
+            // (a cell is its cost, >= 0, combined with its smallest
+            // predecessor), and no path through them ends within tau: the
+            // group is skipped, its cells +inf.  Group g writes back slots
+            // gG-1 .. gG+G-2 of column j+NC-1; with gw and gl the first and
+            // last groups that wrote a value within tau (on some live lane),
+            // the next sweep's live predecessors in Dv lie in groups
+            // gw-1 .. gl (gw-1 only if slot gwG-1 or gwG is live), so it
+            // runs groups gs .. gl, then on while the group just done
+            // leaves a live value in prv[].  Its first query rows are
+            // loaded at the end of the sweep before.
+            constexpr int NG = KSG / G;
+            int gs = max(0, w / G - 1);      // Dv holds one finite slot, w
+            int g_last = min(NG - 1, w / G);
+            float qc[G][D], qn[G][D];
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+#pragma unroll
+                for (int e = 0; e < D; ++e)
+                    qc[u][e] = qbase[(int64_t)(gs * G + u) * DP + e];
             for (; j + NC - 1 < m; j += NC) {
                 float nx[NC][D];
 #pragma unroll
@@ -311,15 +352,22 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                     e0[r] = tsk_inf();
                     eT[r] = tsk_inf();
                 }
-                float qc[G][D], qn[G][D];
+                int hs = 0;    // in-band, in-matrix cells of the computed groups
+                int ncomp = 0; // computed groups (G steps of NC cells each)
+                int gw = NG, gl = -1, glo = NG;
+                bool run = gs < NG;
 #pragma unroll
-                for (int u = 0; u < G; ++u)
+                for (int g = 0; g < NG; ++g) {
+                    if (g < gs || !run) {
 #pragma unroll
-                    for (int e = 0; e < D; ++e)
-                        qc[u][e] = qrow[u * DP + e];
-#pragma unroll
-                for (int g = 0; g < KSG / G; ++g) {
-                    if (g + 1 < KSG / G) {
+                        for (int u = 0; u < G; ++u) {
+                            const int sl = g * G + u - (NC - 1);
+                            if (g * G + u < KS && sl >= 0 && sl < W)
+                                Dv[sl] = tsk_inf();
+                        }
+                        continue;
+                    }
+                    if (g + 1 < NG) {
 #pragma unroll
                         for (int u = 0; u < G; ++u)
 #pragma unroll
@@ -327,6 +375,10 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                                 qn[u][e] = qrow[((g + 1) * G + u) * DP + e];
                     }
                     __builtin_amdgcn_sched_barrier(0);
+                    ++ncomp;
+                    hs += band_group_cells<G, NC>(g * G, j, w, wact, m);
+                    float wmin = tsk_inf(); // values this group writes back
+                    float lmin = tsk_inf(); // of them, slots gG-1 and gG
 #pragma unroll
                     for (int u = 0; u < G; ++u) {
                         const int k = g * G + u;
@@ -352,8 +404,12 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                                         e0[r] = v;
                                     if (sl == TOP)
                                         eT[r] = v;
-                                    if (r == NC - 1)
+                                    if (r == NC - 1) {
                                         Dv[sl] = v;
+                                        wmin = fminf(wmin, v);
+                                        if (sl <= g * G)
+                                            lmin = fminf(lmin, v);
+                                    }
                                 } else {
                                     cur[r] = tsk_inf();
                                 }
@@ -364,23 +420,45 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                         }
                     }
                     __builtin_amdgcn_sched_barrier(0);
+                    if (__ballot(alive && wmin <= tau) != 0ull) {
+                        if (gw == NG) {
+                            gw = g;
+                            // group g-1 reads slot gG-1 and gG
+                            glo = __ballot(alive && lmin <= tau) != 0ull ? g - 1 : g;
+                        }
+                        gl = g;
+                    }
+                    if (g >= g_last) {
+                        float pmin = prv[0];
+#pragma unroll
+                        for (int r = 1; r < NC; ++r)
+                            pmin = fminf(pmin, prv[r]);
+                        run = __ballot(alive && pmin <= tau) != 0ull;
+                    }
 #pragma unroll
                     for (int u = 0; u < G; ++u)
 #pragma unroll
                         for (int e = 0; e < D; ++e)
                             qc[u][e] = qn[u][e];
                 }
+                // the next sweep's range, and its first query rows
+                gs = gw < NG ? max(0, glo) : NG;
+                g_last = gl;
+                {
+                    cfloat *qnext = qrow + (int64_t)NC * DP + (int64_t)min(gs, NG - 1) * G * DP;
+#pragma unroll
+                    for (int u = 0; u < G; ++u)
+#pragma unroll
+                        for (int e = 0; e < D; ++e)
+                            qc[u][e] = qnext[u * DP + e];
+                }
 #pragma unroll
                 for (int r = 0; r < NC; ++r)
 #pragma unroll
                     for (int e = 0; e < D; ++e)
                         cc[r][e] = nx[r][e];
-                int hs = 0;
-#pragma unroll
-                for (int r = 0; r < NC; ++r)
-                    hs += min(j + r + w, m - 1) - max(j + r - w, 0) + 1;
                 valid += (unsigned long long)hs * __popcll(__ballot(alive));
-                cells += NC * W;
+                cells += (unsigned long long)ncomp * G * NC;
                 if (vband) {
                     bool edge = false;
 #pragma unroll

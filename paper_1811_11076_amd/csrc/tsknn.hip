@@ -1081,8 +1081,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         return set_err(TSK_ERR_INVALID_ARG, "raw_keys must be 0 or 1");
     if (o.bound_seed < 0 || o.bound_seed > 2)
         return set_err(TSK_ERR_INVALID_ARG, "bound_seed must be 0, 1 or 2");
-    if (o.dtw_cascade < 0 || o.dtw_cascade > 2)
-        return set_err(TSK_ERR_INVALID_ARG, "dtw_cascade must be 0, 1 or 2");
+    if (o.dtw_cascade < 0 || o.dtw_cascade > 3)
+        return set_err(TSK_ERR_INVALID_ARG, "dtw_cascade must be 0, 1, 2 or 3");
     if (o.dk_box < 0 || o.dk_box > 2)
         return set_err(TSK_ERR_INVALID_ARG, "dk_box must be 0, 1 or 2");
     if (o.use_graph && o.profile)
@@ -1275,13 +1275,14 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         // bound first, LB_Box only for its survivors
         const bool dtw_eq = seedable && c.diag_seed && dist == TSK_DTW && P.env_ok;
         c.dtw_cascade = dtw_eq && o.lb_qgroup != 1 && !lb_rev &&
-                        (o.dtw_cascade == 1 ||
+                        (o.dtw_cascade == 1 || o.dtw_cascade == 3 ||
                          (o.dtw_cascade == 0 && o.bound_seed != 2 && o.order == TSK_ORDER_PLAIN &&
                           o.lb_qgroup == 0));
         c.dtw_bseed = dtw_eq && (o.bound_seed == 1 || c.dtw_cascade);
         // DK on equal lengths, on request: the box bound of the corner survivors
         c.dk_box = c.dk_cascade && dist == TSK_DK && P.env_ok;
-        c.surv_lb = c.dtw_cascade || c.dk_box;
+        // (dtw_cascade 3: the corner bound alone, no LB_Box)
+        c.surv_lb = (c.dtw_cascade && o.dtw_cascade != 3) || c.dk_box;
         c.fast = pick_fast(ix, dist, band, c.qmin, c.qmax, o.dp_kernel, o.dk_band_slots, &c.wsel);
         c.qrows = c.qmax + 2 * QPAD;
         return c;
@@ -1385,7 +1386,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             // (lbv: their bound or +inf)
             launch_bound_lb_surv(P.D, dist, ba, W.surv.p, W.surv_cnt.p, W.max_cnt.p,
                                  W.work.p + 6, ix->n_cu * 8, s);
-        } else if (c.dk_cascade) {
+        } else if (c.dk_cascade || c.dtw_cascade) {
             // the corner bounds are in lbv already
         } else if (c.dk_split) {
             launch_corner(P.D, dist, ba, s);

@@ -29,8 +29,8 @@ def _index(vals, off):
 
 
 SETTINGS = [
-    # (bound_seed, dtw_cascade)
-    (0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (2, 1),
+    # (bound_seed, dtw_cascade); dtw_cascade 3 = the corner bound alone
+    (0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (2, 1), (0, 3), (2, 3),
 ]
 
 

@@ -260,6 +260,39 @@ def test_knn_band_kernel_widths(w):
     idx.close()
 
 
+@pytest.mark.parametrize("w", [12, 45, 60])
+def test_knn_band_dead_groups(w):
+    """The band kernel skips groups of slots whose predecessors all exceed
+    the threshold.  Series that put the live cells far from the diagonal
+    (copies of a query shifted by up to most of the band, forwards and
+    back) and long zero-cost runs (a constant stretch shared by query and
+    copy: live cells climb a whole column through the upward chain) must
+    still give the oracle's rows, for both distances and for k from 1 to
+    beyond the planted copies."""
+    print(f"[case] knn band dead groups w={w}", flush=True)
+    L, d = 160, 3
+    db, dbo = ragged_walks(700 + w, 300, (L, L), d)
+    qs, qo = ragged_walks(710 + w, 3, (L, L), d)
+    q0 = qs[qo[0]:qo[1]].copy()
+    q0[50:90] = q0[50]  # a constant stretch
+    qs[qo[0]:qo[1]] = q0
+    for i, sh in enumerate((w * 3 // 4, -(w * 3 // 4), w // 3, -1, 0)):
+        c = 20 + 7 * i
+        src = np.roll(q0, sh, axis=0)
+        src[:max(sh, 0)] = q0[0]
+        if sh < 0:
+            src[sh:] = q0[-1]
+        db[dbo[c]:dbo[c + 1]] = src + np.float32(0.01 * i)
+    idx = _index(db, dbo)
+    for dist in ("dk", "dtw"):
+        for k in (1, 4, 9):
+            ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, k, dist, w)
+            ids, dst, st = idx.knn(to_dev(qs), qo, k, dist, w, stats=True)
+            assert_same_knn(ids, dst, ref_ids, ref_keys, dist)
+            assert st["bound_pruned"] + st["dp_started"] == st["pairs"], st
+    idx.close()
+
+
 @pytest.mark.parametrize("rows", [8, 16, 32])
 def test_knn_tube_overflow_goes_to_general_dp(rows):
     """k = N keeps every DK cell alive, so every tube outgrows its window and
