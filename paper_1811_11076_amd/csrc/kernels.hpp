@@ -717,6 +717,228 @@ static __global__ __launch_bounds__(1024) void k_compact_sorted(
     }
 }
 
+// ------------------------------------------------------------------ compaction, many blocks per query
+// The same survivors as k_compact / k_compact_sorted in the plain candidate
+// order (lbv indexed by id, position = id), for long candidate lists: each
+// wave owns a segment of SEG_LEN consecutive positions of one query, so a
+// chunk of queries spreads over nq * ceil(N / SEG_LEN) waves instead of nq
+// blocks (one block per query leaves most CUs idle and each block bound by
+// the latency of its sequential loads).  tau is fixed while they run.
+constexpr int SEG_LEN = 4096;   // positions per wave
+constexpr int SEG_WAVES = 4;    // waves per block
+
+// The lbv values of positions p .. p+3 of a row (+inf past the end, which
+// every caller masks out by position: a threshold of +inf keeps +inf).
+__device__ __forceinline__ void load_lbv4(const float *__restrict__ L, int64_t p, int64_t end,
+                                          bool vec, float (&v)[4])
+{
+    if (vec && p + 3 < end) {
+        const float4 x = *reinterpret_cast<const float4 *>(L + p);
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            v[i] = p + i < end ? L[p + i] : tsk_inf();
+    }
+}
+
+// Pass 1: each wave counts the survivors (lb <= tau) of its segment into
+// segcnt[q][seg]; SORTED also counts them by bound bucket into hist[q][b]
+// (global atomics: survivors are few).  Pairs above tau are counted pruned.
+template <bool SORTED>
+__global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_count(
+    const float *__restrict__ lbv, int64_t N, const uint32_t *__restrict__ tau,
+    int32_t *__restrict__ segcnt, int32_t *__restrict__ hist, unsigned long long *ctr)
+{
+    const int q = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int64_t nseg = (N + SEG_LEN - 1) / SEG_LEN;
+    const int64_t seg = (int64_t)blockIdx.x * SEG_WAVES + (threadIdx.x >> 6);
+    if (seg >= nseg)
+        return;
+    const float tq = bits_f(tau[q]);
+    const float *L = lbv + (int64_t)q * N;
+    const bool vec = ((uint64_t)L & 15u) == 0;
+    const int64_t p0 = seg * SEG_LEN, p1 = min(N, p0 + SEG_LEN);
+    int mine = 0;
+    unsigned long long late = 0;
+    for (int64_t p = p0 + lane * 4; p < p1; p += 256) {
+        float v[4];
+        load_lbv4(L, p, p1, vec, v);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (p + i >= p1)
+                continue;
+            if (v[i] <= tq) {
+                ++mine;
+                if (SORTED)
+                    atomicAdd(&hist[(int64_t)q * SURV_BUCKETS +
+                                    min(__float_as_uint(v[i]) >> SURV_SHIFT, (uint32_t)SURV_BUCKETS - 1)],
+                              1);
+            } else if (v[i] != tsk_inf()) {
+                ++late;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        mine += __shfl_xor(mine, o, 64);
+    if (lane == 0)
+        segcnt[(int64_t)q * nseg + seg] = mine;
+    wave_count(ctr, C_BOUND_PRUNED, late);
+}
+
+// Sum of segcnt[q][0 .. seg) over the wave (every lane gets it).
+__device__ __forceinline__ int seg_prefix(const int32_t *__restrict__ segcnt, int64_t nseg, int q,
+                                          int64_t seg, int lane)
+{
+    int s = 0;
+    for (int64_t i = lane; i < seg; i += 64)
+        s += segcnt[(int64_t)q * nseg + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        s += __shfl_xor(s, o, 64);
+    return s;
+}
+
+// Pass 2, candidate order: each wave writes its segment's survivors at the
+// offset of the segments before it, in position order (4 consecutive
+// positions per lane, ranked by a wave prefix sum); the query's last
+// segment writes its count.
+static __global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_scatter(
+    const float *__restrict__ lbv, int64_t N, const uint32_t *__restrict__ tau,
+    const int32_t *__restrict__ segcnt, int32_t *__restrict__ surv, int32_t *__restrict__ cnt,
+    int32_t *__restrict__ max_cnt)
+{
+    const int q = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int64_t nseg = (N + SEG_LEN - 1) / SEG_LEN;
+    const int64_t seg = (int64_t)blockIdx.x * SEG_WAVES + (threadIdx.x >> 6);
+    if (seg >= nseg)
+        return;
+    const float tq = bits_f(tau[q]);
+    const float *L = lbv + (int64_t)q * N;
+    const bool vec = ((uint64_t)L & 15u) == 0;
+    int32_t *out = surv + (int64_t)q * N;
+    const int64_t p0 = seg * SEG_LEN, p1 = min(N, p0 + SEG_LEN);
+    int base = seg_prefix(segcnt, nseg, q, seg, lane);
+    if (seg == nseg - 1 && lane == 0) {
+        const int all = base + segcnt[(int64_t)q * nseg + seg];
+        cnt[q] = all;
+        atomicMax(max_cnt, all);
+    }
+    if (segcnt[(int64_t)q * nseg + seg] == 0)
+        return;
+    for (int64_t p = p0 + lane * 4; p - lane * 4 < p1; p += 256) {
+        float v[4];
+        load_lbv4(L, p, p1, vec, v);
+        bool keep[4];
+        int mine = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            keep[i] = p + i < p1 && v[i] <= tq;
+            mine += keep[i] ? 1 : 0;
+        }
+        int inc = mine;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o, 64);
+            if (lane >= o)
+                inc += t;
+        }
+        int at = base + inc - mine;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (keep[i])
+                out[at++] = (int32_t)(p + i);
+        base += __shfl(inc, 63, 64);
+    }
+}
+
+// Sorted pass 2: exclusive prefix of each query's bucket counts, in place
+// (one block of 1024 per query, 8 buckets per thread); count = min(total,
+// cap).
+static __global__ __launch_bounds__(1024) void k_seg_bucket_scan(int32_t *__restrict__ hist,
+                                                                 int64_t cap, int32_t *__restrict__ cnt,
+                                                                 int32_t *__restrict__ max_cnt)
+{
+    __shared__ int32_t wsum[16];
+    const int q = blockIdx.x;
+    const int tid = threadIdx.x;
+    int32_t *h = hist + (int64_t)q * SURV_BUCKETS;
+    constexpr int PER = SURV_BUCKETS / 1024;
+    int loc[PER];
+    int tot = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        loc[i] = tot;
+        tot += h[tid * PER + i];
+    }
+    const int lane = tid & 63, wv = tid >> 6;
+    int inc = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o)
+            inc += t;
+    }
+    if (lane == 63)
+        wsum[wv] = inc;
+    __syncthreads();
+    int base = 0, all = 0;
+    for (int w = 0; w < 16; ++w) {
+        base += w < wv ? wsum[w] : 0;
+        all += wsum[w];
+    }
+    const int excl = base + inc - tot;
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        h[tid * PER + i] = excl + loc[i];
+    if (tid == 0) {
+        all = (int)min((int64_t)all, cap);
+        cnt[q] = all;
+        atomicMax(max_cnt, all);
+    }
+}
+
+// Sorted pass 3: each survivor takes the next slot of its bound bucket
+// (bucket-mates in arbitrary order, as in k_compact_sorted); slots from cap
+// on are dropped.
+static __global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_bucket_scatter(
+    const float *__restrict__ lbv, int64_t N, const uint32_t *__restrict__ tau,
+    const int32_t *__restrict__ segcnt, int32_t *__restrict__ hist, int64_t cap,
+    int32_t *__restrict__ surv)
+{
+    const int q = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int64_t nseg = (N + SEG_LEN - 1) / SEG_LEN;
+    const int64_t seg = (int64_t)blockIdx.x * SEG_WAVES + (threadIdx.x >> 6);
+    if (seg >= nseg || segcnt[(int64_t)q * nseg + seg] == 0)
+        return;
+    const float tq = bits_f(tau[q]);
+    const float *L = lbv + (int64_t)q * N;
+    const bool vec = ((uint64_t)L & 15u) == 0;
+    const int64_t p0 = seg * SEG_LEN, p1 = min(N, p0 + SEG_LEN);
+    for (int64_t p = p0 + lane * 4; p < p1; p += 256) {
+        float v[4];
+        load_lbv4(L, p, p1, vec, v);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (p + i < p1 && v[i] <= tq) {
+                const int pos = atomicAdd(
+                    &hist[(int64_t)q * SURV_BUCKETS +
+                          min(__float_as_uint(v[i]) >> SURV_SHIFT, (uint32_t)SURV_BUCKETS - 1)],
+                    1);
+                if (pos < cap)
+                    surv[(int64_t)q * N + pos] = (int32_t)(p + i);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ range query output
 // Hits of one query in ascending id order: cnt pass (one block per query),
 // then fill at the query's offset; DK keys leave as correctly rounded sqrt.

@@ -45,6 +45,8 @@ struct Workspace {
     DevBuf<float> lbv;
     DevBuf<int32_t> surv, surv_cnt, max_cnt, qcur;
     DevBuf<int32_t> surv2;    // survivors re-ranked by LB_Box (DTW cascade)
+    DevBuf<int32_t> segcnt;   // survivors per segment of SEG_LEN candidates [q][seg]
+    DevBuf<int32_t> hist;     // survivors per bound bucket [q][SURV_BUCKETS]
     DevBuf<float> rng;            // range query hit map [q][N]
     DevBuf<int64_t> rcnt, rqoff;  // its per-query counts and output offsets
     DevBuf<unsigned long long> ctr, work;
@@ -70,6 +72,8 @@ struct Workspace {
         lbv.release();
         surv.release();
         surv2.release();
+        segcnt.release();
+        hist.release();
         surv_cnt.release();
         max_cnt.release();
         qcur.release();
@@ -831,6 +835,8 @@ static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env, bool need_
     TSK_TRY(w.surv.ensure(nq * N));
     if (need_surv2)
         TSK_TRY(w.surv2.ensure(nq * N));
+    TSK_TRY(w.segcnt.ensure(nq * ((N + SEG_LEN - 1) / SEG_LEN)));
+    TSK_TRY(w.hist.ensure(nq * SURV_BUCKETS));
     TSK_TRY(w.surv_cnt.ensure(nq));
     TSK_TRY(w.max_cnt.ensure(1));
     TSK_TRY(w.qcur.ensure(nq));
@@ -956,6 +962,8 @@ static size_t carve_ws(const tsk_index *ix, const WsShape &sh, char *base, Works
     take(w->surv, nq * N);
     if (sh.surv2)
         take(w->surv2, nq * N);
+    take(w->segcnt, nq * ((N + SEG_LEN - 1) / SEG_LEN));
+    take(w->hist, nq * SURV_BUCKETS);
     take(w->surv_cnt, nq);
     take(w->max_cnt, 1);
     take(w->qcur, nq);
@@ -1326,6 +1334,28 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         TSK_MARK(1);
         if (P.env_ok)
             dispatch_d<EnvLaunch>(P.D, ix, qv, nq, P.ba, s);
+        // survivors (lbv <= tau) of the plain candidate order, many waves per
+        // query: in candidate order, or by ascending bound bucket (the first
+        // cap of them)
+        auto seg_compact = [&](int nqc, bool sorted, int64_t cap, unsigned long long *cctr) {
+            const int64_t N = ix->n;
+            const int64_t nseg = (N + SEG_LEN - 1) / SEG_LEN;
+            const dim3 grid((unsigned)((nseg + SEG_WAVES - 1) / SEG_WAVES), (unsigned)nqc);
+            if (sorted) {
+                fill_u32((uint32_t *)W.hist.p, 0u, (int64_t)nqc * SURV_BUCKETS, s);
+                hipLaunchKernelGGL(k_seg_count<true>, grid, dim3(64 * SEG_WAVES), 0, s, W.lbv.p, N,
+                                   W.tau.p, W.segcnt.p, W.hist.p, cctr);
+                hipLaunchKernelGGL(k_seg_bucket_scan, dim3(nqc), dim3(1024), 0, s, W.hist.p, cap,
+                                   W.surv_cnt.p, W.max_cnt.p);
+                hipLaunchKernelGGL(k_seg_bucket_scatter, grid, dim3(64 * SEG_WAVES), 0, s,
+                                   W.lbv.p, N, W.tau.p, W.segcnt.p, W.hist.p, cap, W.surv.p);
+            } else {
+                hipLaunchKernelGGL(k_seg_count<false>, grid, dim3(64 * SEG_WAVES), 0, s, W.lbv.p,
+                                   N, W.tau.p, W.segcnt.p, nullptr, cctr);
+                hipLaunchKernelGGL(k_seg_scatter, grid, dim3(64 * SEG_WAVES), 0, s, W.lbv.p, N,
+                                   W.tau.p, W.segcnt.p, W.surv.p, W.surv_cnt.p, W.max_cnt.p);
+            }
+        };
         SeedRingArgs seed_args{qv, W.qoff_cur, nq, c.qmax, ix->aos, ix->off, ix->len, ix->n,
                                c.order, 0, P.seed, k, P.ba, W.seedslots.p, W.tau.p, ctr,
                                nullptr, nullptr};
@@ -1338,6 +1368,8 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             // it counts the pairs unless LB_Box still runs on all of them
             cb.ctr = (c.dk_cascade || c.dtw_cascade) ? ctr : nullptr;
             launch_corner(P.D, dist, cb, s);
+            // (every candidate passes the +inf threshold here: one block per
+            // query counting buckets in LDS beats global bucket atomics)
             hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
                                SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,
                                nullptr, nullptr, W.tau.p, W.surv.p, W.surv_cnt.p, W.max_cnt.p,
@@ -1363,7 +1395,12 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         // on every class-warp workload), candidate order for DK (mixed)
         const int so = o.surv_order != 0 ? o.surv_order : (dist == TSK_DTW ? 1 : 2);
         auto compact = [&]() {
-            if (so == 1)
+            // many waves per query for long candidate lists (one block per
+            // query is latency-bound there; below 64 Ki candidates the single
+            // launch costs less)
+            if (c.order == nullptr && !c.lbu && ix->n >= (1 << 16))
+                seg_compact(nq, so == 1, ix->n, ctr);
+            else if (so == 1)
                 hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
                                    SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,
                                    c.lbu ? ix->perm : nullptr, c.lbu ? ix->inv : nullptr,
@@ -1526,6 +1563,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         for (const void *ptr :
              {(const void *)W.tau.p, (const void *)W.seedslots.p, (const void *)W.ubslots.p,
               (const void *)W.resslots.p, (const void *)W.lbv.p, (const void *)W.surv.p,
+              (const void *)W.segcnt.p, (const void *)W.hist.p,
               (const void *)W.surv_cnt.p, (const void *)W.max_cnt.p, (const void *)W.ctr.p,
               (const void *)W.qcur.p,
               (const void *)W.work.p, (const void *)W.qoff.p, (const void *)W.env.p,

@@ -125,3 +125,26 @@ def _graph_and_chunks(kw):
             torch.cuda.synchronize()
     small.close()
     idx.close()
+
+
+@pytest.mark.parametrize("N", [70001, 65536 + 4096 * 3])
+def test_compaction_long_lists(N):
+    """Candidate lists of 64 Ki and more are compacted by many waves per
+    query (segments of 4096 candidates): rows equal the oracle's for both
+    distances and both survivor orders, also when the threshold is still
+    +inf at compaction (one seed candidate for k = 10: every candidate
+    survives), with lists whose length is not a multiple of 4 (unaligned
+    rows of the bound matrix) or of the segment length."""
+    print(f"[case] long-list compaction N={N}", flush=True)
+    db, dbo = ragged_walks(960, N, (16, 16), 2)
+    qs, qo = ragged_walks(961, 5, (16, 16), 2)
+    idx = _index(db, dbo)
+    dq = to_dev(qs)
+    for distance, band in (("dk", None), ("dtw", 3)):
+        ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, distance, band)
+        for kw in ({}, {"seed_count": 1}, {"surv_order": 1}, {"surv_order": 2},
+                   {"dtw_cascade": 3}, {"bound_seed": 2, "dtw_cascade": 2}):
+            ids, dst, st = idx.knn(dq, qo, 10, distance, band, stats=True, **kw)
+            assert_same_knn(ids, dst, ref_ids, ref_keys, distance)
+            assert st["bound_pruned"] + st["dp_started"] == st["pairs"], (kw, st)
+    idx.close()
