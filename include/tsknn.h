@@ -231,7 +231,12 @@ typedef struct {
                                       corner bound (every path's first and
                                       last cells: max of their costs for DK,
                                       sum for DTW; computed for every pair
-                                      first), 2 = the first seed_count
+                                      first; in the plain order with
+                                      seed_count <= 512 and at least 32
+                                      candidates per seed, the smallest of
+                                      each of 2 * seed_count equal segments
+                                      of the candidates, and the seed_count
+                                      smallest of those), 2 = the first seed_count
                                       candidates of the query's order;
                                       0 = library default (DK: 1 for the
                                       plain order, 2 for given and learned

@@ -939,6 +939,85 @@ static __global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_bucket_scatter(
     }
 }
 
+// ------------------------------------------------------------------ seed set from segment minima
+// The threshold seed's candidate set for long lists: the 2*cap segments of
+// a query's candidates (plain order) each give the candidate of smallest
+// bound (ties to the lower id), and the cap smallest of those minima form
+// the seed set, in ascending bound.  Any seed set leaves the results exact
+// (the seed only sets a starting threshold that the k nearest never
+// exceed); this one costs one read of the bounds instead of a counting sort
+// of every candidate.  k_seg_min: a wave per segment.
+constexpr int SEEDSEG_MAX = 1024; // 2 * cap at most
+
+static __global__ __launch_bounds__(256) void k_seg_min(const float *__restrict__ lbv, int64_t N,
+                                                        int nseg, unsigned long long *__restrict__ keys)
+{
+    const int q = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int sg = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (sg >= nseg)
+        return;
+    const int64_t len = (N + nseg - 1) / nseg;
+    const int64_t p0 = (int64_t)sg * len, p1 = min(N, p0 + len);
+    const float *L = lbv + (int64_t)q * N;
+    unsigned long long best = ~0ull;
+    for (int64_t p = p0 + lane; p < p1; p += 64) {
+        const unsigned long long k =
+            ((unsigned long long)__float_as_uint(L[p]) << 32) | (unsigned long long)(uint32_t)p;
+        best = k < best ? k : best;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(best, o, 64);
+        best = other < best ? other : best;
+    }
+    if (lane == 0)
+        keys[(int64_t)q * SEEDSEG_MAX + sg] = best;
+}
+
+// One block of 1024 per query: bitonic sort of the nseg segment minima
+// (padded to a power of two with the largest key), the cap smallest ids
+// to surv[q][0 .. cap).
+static __global__ __launch_bounds__(1024) void k_seg_pick(const unsigned long long *__restrict__ keys,
+                                                          int nseg, int cap, int64_t N,
+                                                          int32_t *__restrict__ surv,
+                                                          int32_t *__restrict__ cnt,
+                                                          int32_t *__restrict__ max_cnt)
+{
+    __shared__ unsigned long long k[SEEDSEG_MAX];
+    const int q = blockIdx.x;
+    const int tid = threadIdx.x;
+    int P = 1;
+    while (P < nseg)
+        P <<= 1;
+    for (int i = tid; i < P; i += 1024)
+        k[i] = i < nseg ? keys[(int64_t)q * SEEDSEG_MAX + i] : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < P; i += 1024) {
+                const int jx = i ^ stride;
+                if (jx > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned long long a = k[i], b = k[jx];
+                    if ((a > b) == up) {
+                        k[i] = b;
+                        k[jx] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int take = min(cap, nseg);
+    for (int i = tid; i < take; i += 1024)
+        surv[(int64_t)q * N + i] = (int32_t)(uint32_t)(k[i] & 0xffffffffull);
+    if (tid == 0) {
+        cnt[q] = take;
+        atomicMax(max_cnt, take);
+    }
+}
+
 // ------------------------------------------------------------------ range query output
 // Hits of one query in ascending id order: cnt pass (one block per query),
 // then fill at the query's offset; DK keys leave as correctly rounded sqrt.

@@ -47,6 +47,7 @@ struct Workspace {
     DevBuf<int32_t> surv2;    // survivors re-ranked by LB_Box (DTW cascade)
     DevBuf<int32_t> segcnt;   // survivors per segment of SEG_LEN candidates [q][seg]
     DevBuf<int32_t> hist;     // survivors per bound bucket [q][SURV_BUCKETS]
+    DevBuf<unsigned long long> segkey; // seed-set segment minima [q][SEEDSEG_MAX]
     DevBuf<float> rng;            // range query hit map [q][N]
     DevBuf<int64_t> rcnt, rqoff;  // its per-query counts and output offsets
     DevBuf<unsigned long long> ctr, work;
@@ -74,6 +75,7 @@ struct Workspace {
         surv2.release();
         segcnt.release();
         hist.release();
+        segkey.release();
         surv_cnt.release();
         max_cnt.release();
         qcur.release();
@@ -837,6 +839,7 @@ static int ensure_ws(tsk_index *ix, int64_t nq, int k, bool need_env, bool need_
         TSK_TRY(w.surv2.ensure(nq * N));
     TSK_TRY(w.segcnt.ensure(nq * ((N + SEG_LEN - 1) / SEG_LEN)));
     TSK_TRY(w.hist.ensure(nq * SURV_BUCKETS));
+    TSK_TRY(w.segkey.ensure(nq * SEEDSEG_MAX));
     TSK_TRY(w.surv_cnt.ensure(nq));
     TSK_TRY(w.max_cnt.ensure(1));
     TSK_TRY(w.qcur.ensure(nq));
@@ -964,6 +967,7 @@ static size_t carve_ws(const tsk_index *ix, const WsShape &sh, char *base, Works
         take(w->surv2, nq * N);
     take(w->segcnt, nq * ((N + SEG_LEN - 1) / SEG_LEN));
     take(w->hist, nq * SURV_BUCKETS);
+    take(w->segkey, nq * SEEDSEG_MAX);
     take(w->surv_cnt, nq);
     take(w->max_cnt, 1);
     take(w->qcur, nq);
@@ -1362,18 +1366,30 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         const bool cascade = c.dk_cascade || c.dtw_bseed;
         if (cascade) {
             // corner bound of every pair (the threshold is still +inf: none
-            // pruned), then each query's seed set = its P.seed candidates of
-            // smallest corner bound, in ascending bound
+            // pruned), then each query's seed set = P.seed candidates of
+            // small corner bound, in ascending bound
             BoundArgs cb = bound_args(ix, qv, nq, P);
             // it counts the pairs unless LB_Box still runs on all of them
             cb.ctr = (c.dk_cascade || c.dtw_cascade) ? ctr : nullptr;
             launch_corner(P.D, dist, cb, s);
-            // (every candidate passes the +inf threshold here: one block per
-            // query counting buckets in LDS beats global bucket atomics)
-            hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
-                               SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,
-                               nullptr, nullptr, W.tau.p, W.surv.p, W.surv_cnt.p, W.max_cnt.p,
-                               nullptr, (int64_t)P.seed, nullptr);
+            if (c.order == nullptr && 2 * P.seed <= SEEDSEG_MAX && ix->n >= 32 * (int64_t)P.seed) {
+                // long lists: the smallest bound of each of 2 * seed segments,
+                // the seed smallest of those (segments of equal length, none
+                // empty)
+                const int64_t len = (ix->n + 2 * P.seed - 1) / (2 * P.seed);
+                const int nseg = (int)((ix->n + len - 1) / len);
+                hipLaunchKernelGGL(k_seg_min, dim3((nseg + 3) / 4, nq), dim3(256), 0, s, W.lbv.p,
+                                   ix->n, nseg, W.segkey.p);
+                hipLaunchKernelGGL(k_seg_pick, dim3(nq), dim3(1024), 0, s, W.segkey.p, nseg, P.seed,
+                                   ix->n, W.surv.p, W.surv_cnt.p, W.max_cnt.p);
+            } else {
+                // (every candidate passes the +inf threshold here: one block
+                // per query counting buckets in LDS beats global atomics)
+                hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
+                                   SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,
+                                   nullptr, nullptr, W.tau.p, W.surv.p, W.surv_cnt.p,
+                                   W.max_cnt.p, nullptr, (int64_t)P.seed, nullptr);
+            }
             seed_args.order = W.surv.p;
         }
         if (c.diag_seed && !(c.dtw_cascade && c.lds_query)) {
@@ -1563,7 +1579,7 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         for (const void *ptr :
              {(const void *)W.tau.p, (const void *)W.seedslots.p, (const void *)W.ubslots.p,
               (const void *)W.resslots.p, (const void *)W.lbv.p, (const void *)W.surv.p,
-              (const void *)W.segcnt.p, (const void *)W.hist.p,
+              (const void *)W.segcnt.p, (const void *)W.hist.p, (const void *)W.segkey.p,
               (const void *)W.surv_cnt.p, (const void *)W.max_cnt.p, (const void *)W.ctr.p,
               (const void *)W.qcur.p,
               (const void *)W.work.p, (const void *)W.qoff.p, (const void *)W.env.p,
