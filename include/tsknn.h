@@ -266,6 +266,14 @@ typedef struct {
                                       the DK box bound (tsk_pair_dk_box) and
                                       the DP runs on those it keeps, in
                                       ascending bound; 0 or 2 = off */
+    int32_t lb_prefix;             /* DTW cascade, LB_Box of the corner
+                                      survivors: after this many points of
+                                      the candidate (a multiple of 64), a
+                                      pair whose partial LB_Box scaled to all
+                                      its points stays below the threshold
+                                      keeps the partial sum (itself a lower
+                                      bound) and stops; -1 = every point;
+                                      0 = library default (64) */
 } tsk_query_opts;
 
 typedef struct {

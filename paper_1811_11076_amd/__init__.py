@@ -110,7 +110,7 @@ class Index:
             dk_band_slots: int = 0, surv_order: int = 0, dp_rows: int = 0,
             dp_waves_per_cu: int = 0, dk_seed: int = 0, cancel=None, lb_both: bool = False,
             raw_keys: bool = False, no_alloc: bool = False, bound_seed: int = 0,
-            dtw_cascade: int = 0, dk_box: int = 0):
+            dtw_cascade: int = 0, dk_box: int = 0, lb_prefix: int = 0):
         """Exact k-NN (C: tsk_knn_query).  Returns (ids int64 [nq, k], dist
         float32 [nq, k], stats dict or None); DK distances are unsquared.
         order: None (plain), a CUDA int32 [nq, n] permutation per query, or
@@ -130,7 +130,10 @@ class Index:
         for every pair, 3 = the corner bound alone (no LB_Box), 0 = default
         (1 for the plain order); dk_box: 1 = DK
         on an equal-length index also bounds the corner survivors by the
-        DK box bound (see pair_dk_box), 0 / 2 = off;
+        DK box bound (see pair_dk_box), 0 / 2 = off; lb_prefix: the corner
+        survivors' LB_Box gives up on a pair after this many points when its
+        partial sum scaled to all points stays below the threshold (-1 =
+        never, 0 = default 64);
         no_alloc: the call allocates no device memory (C:
         tsk_knn_query_noalloc, the library's fixed workspace; pass `out`
         to keep the binding from allocating the outputs; no stats)."""
@@ -168,6 +171,7 @@ class Index:
         opts.bound_seed = int(bound_seed)
         opts.dtw_cascade = int(dtw_cascade)
         opts.dk_box = int(dk_box)
+        opts.lb_prefix = int(lb_prefix)
         opts.use_graph = 1 if use_graph else 0
         opts.tune = _lib.TSK_TUNE_CACHED if tune else _lib.TSK_TUNE_OFF
         if cancel is not None:

@@ -47,7 +47,8 @@ class QueryOpts(ctypes.Structure):
                 ("lb_both", ctypes.c_int32),
                 ("raw_keys", ctypes.c_int32),
                 ("bound_seed", ctypes.c_int32),
-                ("dtw_cascade", ctypes.c_int32), ("dk_box", ctypes.c_int32)]
+                ("dtw_cascade", ctypes.c_int32), ("dk_box", ctypes.c_int32),
+                ("lb_prefix", ctypes.c_int32)]
 
 
 class IndexOpts(ctypes.Structure):

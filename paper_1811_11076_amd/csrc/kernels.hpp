@@ -398,6 +398,10 @@ struct BoundArgs {
     BandArgs ba;
     const float *env; // [nq][env_n][2][D] or null
     int env_n;
+    // k_bound_lb_surv (DTW): after this many candidate points (a multiple
+    // of 64), a pair whose partial sum extrapolated to all points stays
+    // below tau keeps the partial sum as its bound; 0 = every point
+    int lb_prefix;
     uint32_t *tau;
     unsigned long long *ubslots;
     float *lbv;

@@ -797,6 +797,23 @@ __global__ __launch_bounds__(256) void k_bound_lb_surv(BoundArgs a, const int32_
                     }
                     acc = DIST == DIST_DK ? fmaxf(acc, tt) : acc + tt;
                 }
+                if (DIST == DIST_DTW && a.lb_prefix > 0 && j0 + 64 == a.lb_prefix && j0 + 64 < n) {
+                    // after the prefix: stop once the partial bound exceeds
+                    // tau, or give up on a pair whose partial bound, scaled
+                    // to all n points, stays below tau (the partial sum of
+                    // non-negative terms is itself a lower bound, the one
+                    // the pair keeps)
+                    const float part = wave_sum(acc) * scale;
+                    if (part > tau) {
+                        over = true;
+                        j0 += 64;
+                        break;
+                    }
+                    if (part * ((float)n / (float)a.lb_prefix) < tau) {
+                        j0 += 64;
+                        break;
+                    }
+                }
                 if ((j0 & 255) == 192 && j0 + 64 < n) {
                     // every 256 points: stop once the partial bound exceeds tau
                     const float part = DIST == DIST_DK ? wave_max(acc) : wave_sum(acc) * scale;

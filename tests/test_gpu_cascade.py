@@ -148,3 +148,24 @@ def test_compaction_long_lists(N):
             assert_same_knn(ids, dst, ref_ids, ref_keys, distance)
             assert st["bound_pruned"] + st["dp_started"] == st["pairs"], (kw, st)
     idx.close()
+
+
+@pytest.mark.parametrize("prefix", [-1, 64, 128, 256])
+def test_lb_prefix_give_up(prefix):
+    """The corner survivors' LB_Box may stop after a prefix of the candidate
+    and keep the partial sum (a lower bound too): rows equal the oracle's
+    whatever the prefix, on class-warp series (LB_Box prunes the other
+    classes) and random walks, and each pair is counted once."""
+    print(f"[case] lb_prefix={prefix}", flush=True)
+    cw = classwarp(2, 10, 300, 3, 2000, 6)
+    rw_db, rw_dbo = ragged_walks(970, 700, (300, 300), 4)
+    rw_qs, rw_qo = ragged_walks(971, 4, (300, 300), 4)
+    for db, dbo, qs, qo in (cw, (rw_db, rw_dbo, rw_qs, rw_qo)):
+        idx = _index(db, dbo)
+        for band in (0.1, 4):
+            ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, "dtw", band)
+            ids, dst, st = idx.knn(to_dev(qs), qo, 10, "dtw", band, stats=True,
+                                   lb_prefix=prefix, dtw_cascade=1)
+            assert_same_knn(ids, dst, ref_ids, ref_keys, "dtw")
+            assert st["bound_pruned"] + st["dp_started"] == st["pairs"], st
+        idx.close()
