@@ -52,8 +52,11 @@ WORKLOADS = {
 DEFAULT = "classwarp-q4096-n1000000-L512-d6"
 SECONDARY = "classwarp-q100-n20000-L256-d3"
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz non-packed 32-bit VALU lane-ops
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X fp32 vector rate: 157.3 TFLOP/s with an FMA as two flops, i.e.
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 lane-ops per cycle (the
+# scan's non-packed VALU code issues above one op per lane-cycle: 46 T
+# lane-instructions/s measured in the LB_Box kernel)
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9 * 2
 HBM_PEAK_BPS = 8.0e12
 
 
