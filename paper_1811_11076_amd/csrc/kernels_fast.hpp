@@ -610,6 +610,17 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
 // LDS).  Lanes advance independently, each on its own pair and column; a
 // lane whose pair ends takes the chunk's next survivor, so the wave stays
 // busy until the chunk drains.
+// LDS slot of the 16-byte quarter i of the staged query rows: with 8-float
+// rows a row's two halves swap when bit 2 of the row is set, so the lanes'
+// rows (each at its own offset) spread over all eight 16-byte bank groups
+// of a 128-byte line instead of four.
+template <int DP> __device__ __forceinline__ int tube_slot(int i)
+{
+    if (DP != 8)
+        return i;
+    return i ^ ((i >> 3) & 1);
+}
+
 template <int D, int W>
 __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
 {
@@ -644,7 +655,7 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
             float4 *dst = reinterpret_cast<float4 *>(qs);
             const int n4 = (m + W) * DP / 4;
             for (int i = lane; i < n4; i += 64)
-                dst[i] = src[i];
+                dst[tube_slot<DP>(i)] = src[i];
             __syncthreads();
             staged = q;
         }
@@ -696,17 +707,17 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
             float vmin = tsk_inf();
 #pragma unroll
             for (int k = 0; k < W; ++k) {
-                const float *qr = qs + (lo + k) * DP;
+                const int row = lo + k;
                 float qq[D];
                 {
                     // whole rows with 16-byte LDS reads (rows are DP floats,
                     // 16-byte aligned); scattered rows conflict less that way
                     // than dword pairs that straddle rows
-                    const float4 *r4 = reinterpret_cast<const float4 *>(qr);
+                    const float4 *r4 = reinterpret_cast<const float4 *>(qs);
                     float rv[DP];
 #pragma unroll
                     for (int h = 0; h < DP / 4; ++h) {
-                        const float4 v = r4[h];
+                        const float4 v = r4[tube_slot<DP>(row * (DP / 4) + h)];
                         rv[4 * h] = v.x;
                         rv[4 * h + 1] = v.y;
                         rv[4 * h + 2] = v.z;
