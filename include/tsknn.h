@@ -273,7 +273,9 @@ typedef struct {
                                       its points stays below the threshold
                                       keeps the partial sum (itself a lower
                                       bound) and stops; -1 = every point;
-                                      0 = library default (64) */
+                                      0 = library default (64 when the
+                                      banded lane-per-pair DP follows, else
+                                      every point) */
 } tsk_query_opts;
 
 typedef struct {

@@ -133,7 +133,7 @@ class Index:
         DK box bound (see pair_dk_box), 0 / 2 = off; lb_prefix: the corner
         survivors' LB_Box gives up on a pair after this many points when its
         partial sum scaled to all points stays below the threshold (-1 =
-        never, 0 = default 64);
+        never, 0 = default: 64 before the banded DP, else never);
         no_alloc: the call allocates no device memory (C:
         tsk_knn_query_noalloc, the library's fixed workspace; pass `out`
         to keep the binding from allocating the outputs; no stats)."""

@@ -1442,10 +1442,16 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         if (c.surv_lb) {
             // LB_Box (DTW) or the DK box bound of the corner survivors only
             // (lbv: their bound or +inf)
-            // (default: a prefix of 64 points; measured on 1024 x 1M x 512 x 6
-            // the bound stage falls 13.4 -> 4.7 ms and the pairs it prunes
-            // 1.0188803e9 -> 1.018880e9, the DP work unchanged)
-            ba.lb_prefix = dist == TSK_DTW ? (o.lb_prefix == 0 ? 64 : std::max(0, o.lb_prefix)) : 0;
+            // (default: a prefix of 64 points when the banded lane-per-pair
+            // DP follows; measured on 1024 x 1M x 512 x 6 the bound stage
+            // falls 13.4 -> 4.7 ms and the pairs it prunes 1.0188803e9 ->
+            // 1.018880e9, the DP work unchanged.  Before the general DP the
+            // survivors' order by their full bound matters more: unbanded
+            // DTW on 256 x 100 000 x 128 x 3 took 13.5 ms with the prefix,
+            // 7.3 ms without)
+            const int def_prefix = c.fast == FAST_BAND ? 64 : 0;
+            ba.lb_prefix = dist == TSK_DTW ? (o.lb_prefix == 0 ? def_prefix : std::max(0, o.lb_prefix))
+                                           : 0;
             launch_bound_lb_surv(P.D, dist, ba, W.surv.p, W.surv_cnt.p, W.max_cnt.p,
                                  W.work.p + 6, ix->n_cu * 8, s);
         } else if (c.dk_cascade || c.dtw_cascade) {
