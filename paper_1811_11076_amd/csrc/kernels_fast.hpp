@@ -329,6 +329,10 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
             // leaves a live value in prv[].  Its first query rows are
             // loaded at the end of the sweep before.
             constexpr int NG = KSG / G;
+            static_assert(NG <= 32, "group mask");
+            // groups computed in the sweep before: only their slots can hold
+            // finite values, so only they need clearing when skipped
+            uint32_t comp_prev = ~0u;
             int gs = max(0, w / G - 1);      // Dv holds one finite slot, w
             int g_last = min(NG - 1, w / G);
             float qc[G][D], qn[G][D];
@@ -356,17 +360,22 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                 int ncomp = 0; // computed groups (G steps of NC cells each)
                 int gw = NG, gl = -1, glo = NG;
                 bool run = gs < NG;
+                uint32_t comp_now = 0;
+                float lmin_all = tsk_inf(); // the lane's smallest written value
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
                     if (g < gs || !run) {
+                        if ((comp_prev >> g) & 1u) {
 #pragma unroll
-                        for (int u = 0; u < G; ++u) {
-                            const int sl = g * G + u - (NC - 1);
-                            if (g * G + u < KS && sl >= 0 && sl < W)
-                                Dv[sl] = tsk_inf();
+                            for (int u = 0; u < G; ++u) {
+                                const int sl = g * G + u - (NC - 1);
+                                if (g * G + u < KS && sl >= 0 && sl < W)
+                                    Dv[sl] = tsk_inf();
+                            }
                         }
                         continue;
                     }
+                    comp_now |= 1u << g;
                     if (g + 1 < NG) {
 #pragma unroll
                         for (int u = 0; u < G; ++u)
@@ -420,6 +429,7 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                         }
                     }
                     __builtin_amdgcn_sched_barrier(0);
+                    lmin_all = fminf(lmin_all, wmin);
                     if (__ballot(alive && wmin <= tau) != 0ull) {
                         if (gw == NG) {
                             gw = g;
@@ -442,6 +452,7 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                             qc[u][e] = qn[u][e];
                 }
                 // the next sweep's range, and its first query rows
+                comp_prev = comp_now;
                 gs = gw < NG ? max(0, glo) : NG;
                 g_last = gl;
                 {
@@ -473,10 +484,9 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
                     }
                 }
                 if ((j + NC) / 8 != j / 8) { // about every 8 columns
-                    float cm = Dv[0];
-#pragma unroll
-                    for (int k = 1; k < W; ++k)
-                        cm = fminf(cm, Dv[k]);
+                    // the column's smallest value: every slot was written
+                    // by a computed group or holds +inf
+                    const float cm = lmin_all;
                     tau = bits_f(load_relaxed_u32(a.tau + q));
                     alive = alive && cm <= tau;
                     if (__ballot(alive) == 0ull) {
