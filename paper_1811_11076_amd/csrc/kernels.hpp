@@ -1099,9 +1099,26 @@ __global__ __launch_bounds__(256) void k_range_fill(const float *__restrict__ hi
 // the whole pair is > tau (abandoned).  Returns the value, or +inf if > tau.
 template <int D, int DIST, int R>
 __device__ float dp_wave_pair(const float *__restrict__ qp, int m, const float *__restrict__ cp, int n,
-                              const Band &band, const uint32_t *tau_ptr, float *__restrict__ tbuf,
+                              const Band &band_in, const uint32_t *tau_ptr, float *__restrict__ tbuf,
                               unsigned long long &cells, unsigned long long &valid)
 {
+    // Both distances are symmetric in the two series (the point cost is,
+    // bit for bit: fl(s - t) = -fl(t - s); so is the band), and every cell
+    // keeps its value when the matrix is transposed: the longer series runs
+    // down the strips, so a strip's 64R rows are filled and a slanted band
+    // crosses fewer of its columns.
+    Band band = band_in;
+    if (m < n) {
+        const float *t = qp;
+        qp = cp;
+        cp = t;
+        const int tm = m;
+        m = n;
+        n = tm;
+        const int64_t ta = band.A;
+        band.A = band.B;
+        band.B = ta;
+    }
     const int lane = threadIdx.x & 63;
     const float tau = tau_ptr ? bits_f(load_relaxed_u32(tau_ptr)) : tsk_inf();
     float result = tsk_inf();
