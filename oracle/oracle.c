@@ -512,14 +512,19 @@ float orc_greedy_sum_f32(const float *S, int64_t m, const float *T, int64_t n, i
 }
 
 /* ---------------------------------------------------------------- sparse DK (Alg. 3)
- * Sec. 4.2, Alg. 3, whole matching (SUB = false), squared domain, readings
- * R-sdk0 and R-sdkend.  Column by column over T; I holds the rows to visit
- * in the current column (kept sorted), J the rows for the next column.  A
- * visited cell whose cost is <= eps gets max(cost, min(lower, left,
- * lower-left)) and opens the cell above (same column) and the cells to the
- * right and upper-right (next column); a cell above eps stays +inf.
- * Returns squared DK if it is <= eps, else +inf.  *cells (nullable) receives
- * the number of visited cells.  The band, if any, restricts visited cells. */
+ * Sec. 4.2, Alg. 3, whole matching (SUB = false), squared domain, written as
+ * the thresholded recurrence the algorithm evaluates.  A cell (i, j) is live
+ * when its cost is <= eps and one of its predecessors (i-1, j), (i, j-1),
+ * (i-1, j-1) is live; the start (0, 0) has the virtual predecessor 0
+ * (R-sdk0).  A live cell holds max(cost, smallest live predecessor); every
+ * other cell counts as +inf.  With [lo, hi] the live rows of column j-1, a
+ * live cell of column j lies in rows lo .. hi+1 or is reached from the live
+ * cell below it in its own column, so each column is evaluated from row lo
+ * upward, through row hi+1 and on while the cell below is live.  A column
+ * with no live cell ends the scan (R-sdkend): squared DK > eps, +inf.
+ * Returns squared DK if it is <= eps, else +inf.  *cells (nullable)
+ * receives the number of evaluated in-band cells.  The band, if any,
+ * restricts the cells. */
 ORC_CLONES
 float orc_sparse_dk_sq_f32(const float *S, int64_t m, const float *T, int64_t n, int d,
                            int64_t w, float eps, int64_t *cells)
@@ -528,62 +533,55 @@ float orc_sparse_dk_sq_f32(const float *S, int64_t m, const float *T, int64_t n,
         if (cells) *cells = 0;
         return ORC_INF;
     }
-    float *D = malloc(sizeof(float) * m), *E = malloc(sizeof(float) * m);
-    int64_t *I = malloc(sizeof(int64_t) * (m + 1)), *J = malloc(sizeof(int64_t) * (m + 1));
-    /* rows holding a finite value in D (this column) and in E (last column) */
-    int64_t *setD = malloc(sizeof(int64_t) * (m + 1)), *setE = malloc(sizeof(int64_t) * (m + 1));
-    int64_t nI = 1, nJ = 0, nD = 0, nE = 0, visited = 0;
-    for (int64_t i = 0; i < m; ++i) D[i] = E[i] = ORC_INF;
-    I[0] = 0;
+    /* two columns; each remembers the rows it wrote, reset before reuse */
+    float *col[2] = {malloc(sizeof(float) * m), malloc(sizeof(float) * m)};
+    int64_t wlo[2] = {0, 0}, whi[2] = {m - 1, m - 1};
+    for (int64_t i = 0; i < m; ++i) col[0][i] = col[1][i] = ORC_INF;
+    int64_t lo = 0, hi = -1; /* live rows of the previous column (none yet) */
+    int64_t visited = 0;
     float result = ORC_INF;
     for (int64_t j = 0; j < n; ++j) {
-        int64_t pos = 0, carry = -1;
-        nJ = 0;
-        nD = 0;
-        for (;;) {
-            int64_t i;
-            if (carry >= 0 && (pos >= nI || carry <= I[pos])) {
-                i = carry;
-                if (pos < nI && I[pos] == carry) ++pos;
-                carry = -1;
-            } else if (pos < nI) {
-                i = I[pos++];
-            } else {
-                break;
+        float *prev = col[(j + 1) & 1], *cur = col[j & 1];
+        const int c = (int)(j & 1);
+        for (int64_t i = wlo[c]; i <= whi[c]; ++i) cur[i] = ORC_INF;
+        const int64_t first = j == 0 ? 0 : lo;
+        const int64_t reach = j == 0 ? 0 : hi + 1; /* last row fed by column j-1 */
+        int64_t nlo = -1, nhi = -1, last = first - 1;
+        for (int64_t i = first; i < m; ++i) {
+            const float below = i > 0 ? cur[i - 1] : ORC_INF;
+            if (i > reach && !(below <= eps))
+                break; /* no live predecessor above this row */
+            last = i;
+            float pred;
+            if (i == 0 && j == 0)
+                pred = 0.0f;
+            else
+                pred = fmin3f(below, prev[i], i > 0 ? prev[i - 1] : ORC_INF);
+            float v = ORC_INF;
+            if (orc_band_ok(i, j, m, n, w)) {
+                ++visited;
+                const float cost = orc_cost_f32(S + i * d, T + j * d, d);
+                if (cost <= eps && pred <= eps)
+                    v = cost > pred ? cost : pred;
             }
-            if (!orc_band_ok(i, j, m, n, w))
-                continue;
-            ++visited;
-            float c = orc_cost_f32(S + i * d, T + j * d, d);
-            if (c <= eps) {
-                float pred;
-                if (i == 0 && j == 0)
-                    pred = 0.0f;
-                else
-                    pred = fmin3f(i > 0 ? D[i - 1] : ORC_INF, E[i], i > 0 ? E[i - 1] : ORC_INF);
-                D[i] = c > pred ? c : pred;
-                setD[nD++] = i;
-                if (i + 1 < m) carry = i + 1;
-                if (nJ == 0 || J[nJ - 1] != i) J[nJ++] = i;
-                if (i + 1 < m) J[nJ++] = i + 1;
+            cur[i] = v;
+            if (v != ORC_INF) {
+                if (nlo < 0) nlo = i;
+                nhi = i;
             }
         }
+        wlo[c] = first;
+        whi[c] = last;
         if (j == n - 1) {
-            result = D[m - 1];
+            result = cur[m - 1];
             break;
         }
-        /* E = D, then D back to all +inf */
-        for (int64_t r = 0; r < nE; ++r) E[setE[r]] = ORC_INF;
-        for (int64_t r = 0; r < nD; ++r) { E[setD[r]] = D[setD[r]]; D[setD[r]] = ORC_INF; }
-        int64_t *tp = setE; setE = setD; setD = tp;
-        nE = nD;
-        int64_t *tmp = I; I = J; J = tmp;
-        nI = nJ;
-        if (nI == 0)
-            break; /* R-sdkend: nothing left alive -> DK > eps */
+        if (nlo < 0)
+            break; /* R-sdkend: no live cell left -> DK > eps */
+        lo = nlo;
+        hi = nhi;
     }
-    if (result > eps) result = ORC_INF;
-    free(D); free(E); free(I); free(J); free(setD); free(setE);
+    free(col[0]); free(col[1]);
     if (cells) *cells = visited;
     return result;
 }
