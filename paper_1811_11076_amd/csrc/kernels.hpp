@@ -749,13 +749,34 @@ __device__ __forceinline__ void load_lbv4(const float *__restrict__ L, int64_t p
     }
 }
 
+// The candidates at positions p .. p+3 of a query's order (O: its row of
+// the order array, or null for the plain order) and their bounds.
+__device__ __forceinline__ void load_cand4(const float *__restrict__ L, const int32_t *__restrict__ O,
+                                           int64_t p, int64_t end, bool vec, float (&v)[4],
+                                           int32_t (&id)[4])
+{
+    if (O == nullptr) {
+        load_lbv4(L, p, end, vec, v);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            id[i] = (int32_t)(p + i);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        id[i] = p + i < end ? O[p + i] : 0;
+        v[i] = p + i < end ? L[id[i]] : tsk_inf();
+    }
+}
+
 // Pass 1: each wave counts the survivors (lb <= tau) of its segment into
 // segcnt[q][seg]; SORTED also counts them by bound bucket into hist[q][b]
 // (global atomics: survivors are few).  Pairs above tau are counted pruned.
 template <bool SORTED>
 __global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_count(
-    const float *__restrict__ lbv, int64_t N, const uint32_t *__restrict__ tau,
-    int32_t *__restrict__ segcnt, int32_t *__restrict__ hist, unsigned long long *ctr)
+    const float *__restrict__ lbv, int64_t N, const int32_t *__restrict__ order,
+    const uint32_t *__restrict__ tau, int32_t *__restrict__ segcnt, int32_t *__restrict__ hist,
+    unsigned long long *ctr)
 {
     const int q = blockIdx.y;
     const int lane = threadIdx.x & 63;
@@ -767,11 +788,13 @@ __global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_count(
     const float *L = lbv + (int64_t)q * N;
     const bool vec = ((uint64_t)L & 15u) == 0;
     const int64_t p0 = seg * SEG_LEN, p1 = min(N, p0 + SEG_LEN);
+    const int32_t *O = order ? order + (int64_t)q * N : nullptr;
     int mine = 0;
     unsigned long long late = 0;
     for (int64_t p = p0 + lane * 4; p < p1; p += 256) {
         float v[4];
-        load_lbv4(L, p, p1, vec, v);
+        int32_t id[4];
+        load_cand4(L, O, p, p1, vec, v, id);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             if (p + i >= p1)
@@ -813,9 +836,9 @@ __device__ __forceinline__ int seg_prefix(const int32_t *__restrict__ segcnt, in
 // positions per lane, ranked by a wave prefix sum); the query's last
 // segment writes its count.
 static __global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_scatter(
-    const float *__restrict__ lbv, int64_t N, const uint32_t *__restrict__ tau,
-    const int32_t *__restrict__ segcnt, int32_t *__restrict__ surv, int32_t *__restrict__ cnt,
-    int32_t *__restrict__ max_cnt)
+    const float *__restrict__ lbv, int64_t N, const int32_t *__restrict__ order,
+    const uint32_t *__restrict__ tau, const int32_t *__restrict__ segcnt,
+    int32_t *__restrict__ surv, int32_t *__restrict__ cnt, int32_t *__restrict__ max_cnt)
 {
     const int q = blockIdx.y;
     const int lane = threadIdx.x & 63;
@@ -836,9 +859,11 @@ static __global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_scatter(
     }
     if (segcnt[(int64_t)q * nseg + seg] == 0)
         return;
+    const int32_t *O = order ? order + (int64_t)q * N : nullptr;
     for (int64_t p = p0 + lane * 4; p - lane * 4 < p1; p += 256) {
         float v[4];
-        load_lbv4(L, p, p1, vec, v);
+        int32_t id[4];
+        load_cand4(L, O, p, p1, vec, v, id);
         bool keep[4];
         int mine = 0;
 #pragma unroll
@@ -857,7 +882,7 @@ static __global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_scatter(
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             if (keep[i])
-                out[at++] = (int32_t)(p + i);
+                out[at++] = id[i];
         base += __shfl(inc, 63, 64);
     }
 }

@@ -1346,23 +1346,25 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
         // survivors (lbv <= tau) of the plain candidate order, many waves per
         // query: in candidate order, or by ascending bound bucket (the first
         // cap of them)
-        auto seg_compact = [&](int nqc, bool sorted, int64_t cap, unsigned long long *cctr) {
+        auto seg_compact = [&](int nqc, bool sorted, int64_t cap, unsigned long long *cctr,
+                               const int32_t *order) {
             const int64_t N = ix->n;
             const int64_t nseg = (N + SEG_LEN - 1) / SEG_LEN;
             const dim3 grid((unsigned)((nseg + SEG_WAVES - 1) / SEG_WAVES), (unsigned)nqc);
             if (sorted) {
                 fill_u32((uint32_t *)W.hist.p, 0u, (int64_t)nqc * SURV_BUCKETS, s);
                 hipLaunchKernelGGL(k_seg_count<true>, grid, dim3(64 * SEG_WAVES), 0, s, W.lbv.p, N,
-                                   W.tau.p, W.segcnt.p, W.hist.p, cctr);
+                                   nullptr, W.tau.p, W.segcnt.p, W.hist.p, cctr);
                 hipLaunchKernelGGL(k_seg_bucket_scan, dim3(nqc), dim3(1024), 0, s, W.hist.p, cap,
                                    W.surv_cnt.p, W.max_cnt.p);
                 hipLaunchKernelGGL(k_seg_bucket_scatter, grid, dim3(64 * SEG_WAVES), 0, s,
                                    W.lbv.p, N, W.tau.p, W.segcnt.p, W.hist.p, cap, W.surv.p);
             } else {
                 hipLaunchKernelGGL(k_seg_count<false>, grid, dim3(64 * SEG_WAVES), 0, s, W.lbv.p,
-                                   N, W.tau.p, W.segcnt.p, nullptr, cctr);
+                                   N, order, W.tau.p, W.segcnt.p, nullptr, cctr);
                 hipLaunchKernelGGL(k_seg_scatter, grid, dim3(64 * SEG_WAVES), 0, s, W.lbv.p, N,
-                                   W.tau.p, W.segcnt.p, W.surv.p, W.surv_cnt.p, W.max_cnt.p);
+                                   order, W.tau.p, W.segcnt.p, W.surv.p, W.surv_cnt.p,
+                                   W.max_cnt.p);
             }
         };
         SeedRingArgs seed_args{qv, W.qoff_cur, nq, c.qmax, ix->aos, ix->off, ix->len, ix->n,
@@ -1419,8 +1421,10 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
             // many waves per query for long candidate lists (one block per
             // query is latency-bound there; below 64 Ki candidates the single
             // launch costs less)
-            if (c.order == nullptr && !c.lbu && ix->n >= (1 << 16))
-                seg_compact(nq, so == 1, ix->n, ctr);
+            // (a given or learned order: the unsorted variant gathers the
+            // bounds through it)
+            if (!c.lbu && ix->n >= (1 << 16) && (c.order == nullptr || so != 1))
+                seg_compact(nq, so == 1, ix->n, ctr, c.order);
             else if (so == 1)
                 hipLaunchKernelGGL(k_compact_sorted, dim3(nq), dim3(1024),
                                    SURV_BUCKETS * sizeof(int32_t), s, W.lbv.p, ix->n, c.order,

@@ -136,14 +136,20 @@ def test_compaction_long_lists(N):
     survives), with lists whose length is not a multiple of 4 (unaligned
     rows of the bound matrix) or of the segment length."""
     print(f"[case] long-list compaction N={N}", flush=True)
+    import torch
     db, dbo = ragged_walks(960, N, (16, 16), 2)
     qs, qo = ragged_walks(961, 5, (16, 16), 2)
     idx = _index(db, dbo)
     dq = to_dev(qs)
+    # a given candidate order per query (the unsorted compaction gathers
+    # the bounds through it)
+    rng = np.random.default_rng(962)
+    perm = torch.from_numpy(np.stack([rng.permutation(N) for _ in range(5)]).astype(np.int32)).cuda()
     for distance, band in (("dk", None), ("dtw", 3)):
         ref_ids, ref_keys = O.knn_brute(db, dbo, qs, qo, 10, distance, band)
         for kw in ({}, {"seed_count": 1}, {"surv_order": 1}, {"surv_order": 2},
-                   {"dtw_cascade": 3}, {"bound_seed": 2, "dtw_cascade": 2}):
+                   {"dtw_cascade": 3}, {"bound_seed": 2, "dtw_cascade": 2},
+                   {"order": perm}, {"order": perm, "surv_order": 2, "seed_count": 1}):
             ids, dst, st = idx.knn(dq, qo, 10, distance, band, stats=True, **kw)
             assert_same_knn(ids, dst, ref_ids, ref_keys, distance)
             assert st["bound_pruned"] + st["dp_started"] == st["pairs"], (kw, st)
