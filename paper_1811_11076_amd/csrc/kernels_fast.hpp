@@ -615,7 +615,10 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
 // reached only through the window's top slot (same column, or the previous
 // column's top when lo did not move), so as long as the top slot stays dead
 // the window holds every live cell and the result is exact; a live top slot
-// sends the pair to the general DP.
+// sends the pair to the general DP.  In a pair's last column the end cell
+// is exact when its row is in the window (every row up to it is held); one
+// above the window is reached up that column through the top slot, so
+// there a live top slot sends the pair to the general DP too.
 // A wave takes a chunk of up to a.task survivors of one query (query rows in
 // LDS).  Lanes advance independently, each on its own pair and column; a
 // lane whose pair ends takes the chunk's next survivor, so the wave stays
@@ -749,7 +752,15 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
             // cells of the window inside the matrix (rows past m-1 are padding)
             valid += running ? (unsigned long long)max(0, min(W, m - lo)) : 0ull;
             if (running) {
-                if (j == n - 1) {
+                if (j == n - 1 && m - 1 - lo >= W && Dv[W - 1] <= tau) {
+                    // the end row lies above the window while the window's
+                    // top is live: the end cell may be reached up the last
+                    // column through rows the window does not hold
+                    push_fallback(a, q, c);
+                    ++fallback;
+                    --started; // the general DP counts it
+                    running = false;
+                } else if (j == n - 1) {
                     const int slot = m - 1 - lo;
                     float res = tsk_inf();
 #pragma unroll

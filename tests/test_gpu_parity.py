@@ -320,6 +320,42 @@ def test_knn_tube_overflow_goes_to_general_dp(rows):
     idx2.close()
 
 
+@pytest.mark.parametrize("rows", [8, 16, 32])
+def test_knn_tube_end_row_above_window(rows):
+    """A pair whose only path within tau runs along row 0 and then climbs
+    the whole last column (query 0, 1.5, 1.5, ...; candidate 0, ..., 0, e):
+    the window stays at rows 0 .. rows-1 and the end row (39) lies above it
+    while the window's top slot is live, so the pair must go to the general
+    DP; rows equal the oracle's (DK^2 = 0.5625 for e = 0.75)."""
+    import numpy as np
+    print(f"[case] knn tube end row above window rows={rows}", flush=True)
+    rng = np.random.default_rng(70 + rows)
+    m = 40
+    q = np.full((m, 1), 1.5, np.float32)
+    q[0] = 0.0
+    series = []
+    for e, n in ((0.75, 40), (0.7, 40), (0.8, 33), (0.75, 55)):
+        t = np.zeros((n, 1), np.float32)
+        t[-1] = e
+        series.append(t)
+    for _ in range(40):  # far from the query: pruned by their corner bounds
+        n = int(rng.integers(20, 60))
+        series.append((20.0 + np.cumsum(rng.standard_normal((n, 1)), 0)).astype(np.float32))
+    perm = rng.permutation(len(series))
+    series = [series[i] for i in perm]
+    db = np.concatenate(series)
+    dbo = np.concatenate([[0], np.cumsum([len(x) for x in series])]).astype(np.int64)
+    qo = np.array([0, m], np.int64)
+    idx = _index(db, dbo)
+    for k in (1, 3):
+        ref_ids, ref_keys = O.knn_brute(db, dbo, q, qo, k, "dk", None)
+        ids, dst, st = idx.knn(to_dev(q), qo, k, "dk", None, stats=True, tube_rows=rows)
+        assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
+        assert st["bound_pruned"] + st["dp_started"] == st["pairs"], st
+        print(f"  k={k} fallback {st['fallback_pairs']}", flush=True)
+    idx.close()
+
+
 @pytest.mark.parametrize("walk,task,seed", [(1, 128, 64), (0, 32, 0), (1, 256, 3000)])
 def test_knn_dk_pipeline_options(walk, task, seed):
     """The DK bound-stage options (greedy pass over survivors, task size,
