@@ -352,6 +352,9 @@ def test_knn_tube_end_row_above_window(rows):
         ids, dst, st = idx.knn(to_dev(q), qo, k, "dk", None, stats=True, tube_rows=rows)
         assert_same_knn(ids, dst, ref_ids, ref_keys, "dk")
         assert st["bound_pruned"] + st["dp_started"] == st["pairs"], st
+        # the pair with e = 0.8 (DK^2 = 0.49 <= every tau of the scan)
+        # reaches its last column with its end row above the window
+        assert st["fallback_pairs"] >= 1, st
         print(f"  k={k} fallback {st['fallback_pairs']}", flush=True)
     idx.close()
 
