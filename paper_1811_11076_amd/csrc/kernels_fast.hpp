@@ -608,17 +608,20 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
 // predecessors are all above tau is above tau too, so they never lower a
 // live cell, and liveness is tested against tau (which only falls) instead
 // of killing them.
-// Each lane keeps a window of W consecutive rows [lo, lo+W) of its current
-// column.  Cells below lo are dead (nothing below a dead prefix can come
-// back: every predecessor is lower or to the left), so after each column lo
-// moves up past up to two leading dead slots.  Cells above the window are
-// reached only through the window's top slot (same column, or the previous
-// column's top when lo did not move), so as long as the top slot stays dead
-// the window holds every live cell and the result is exact; a live top slot
-// sends the pair to the general DP.  In a pair's last column the end cell
-// is exact when its row is in the window (every row up to it is held); one
-// above the window is reached up that column through the top slot, so
-// there a live top slot sends the pair to the general DP too.
+// Each lane keeps a window of W consecutive rows [lo, lo+W) and computes
+// two columns over it per iteration, so each query row read from LDS serves
+// two cells.  Cells below lo are dead (nothing below a dead prefix can come
+// back: every predecessor is lower or to the left), so after each iteration
+// lo moves up past up to four leading dead slots of the second column.
+// Cells above the window are reached only through a top slot (of the same
+// column, or of an earlier column of the same window), so as long as both
+// columns' top slots stay dead the window holds every live cell and the
+// values in it are exact; a live top slot sends the pair to the general DP,
+// and only then is a window without live cells no proof that the pair is
+// above tau.  In the iteration holding a pair's last column the end cell is
+// exact when its row is in the window (every row up to it is held); one
+// above the window is reached through a top slot, so there a live top slot
+// sends the pair to the general DP too.
 // A wave takes a chunk of up to a.task survivors of one query (query rows in
 // LDS).  Lanes advance independently, each on its own pair and column; a
 // lane whose pair ends takes the chunk's next survivor, so the wave stays
@@ -713,11 +716,15 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
             }
             if ((it & 7) == 0)
                 tau = bits_f(load_relaxed_u32(a.tau + q));
-            float cv[D];
-            load_point<D>(cp + (int64_t)min(j, n - 1) * D, cv);
-            float down = tsk_inf();
-            float diag = (j == 0) ? 0.0f : tsk_inf(); // D(-1,-1) = 0 feeds (0,0)
-            float vmin = tsk_inf();
+            // two columns per iteration over the same window rows: each row
+            // read from LDS serves a cell of column j and one of column j+1
+            float cv0[D], cv1[D];
+            load_point<D>(cp + (int64_t)min(j, n - 1) * D, cv0);
+            load_point<D>(cp + (int64_t)min(j + 1, n - 1) * D, cv1);
+            float down0 = tsk_inf(), down1 = tsk_inf(), dg1 = tsk_inf();
+            float diag0 = (j == 0) ? 0.0f : tsk_inf(); // D(-1,-1) = 0 feeds (0,0)
+            float vmin1 = tsk_inf();
+            float V0[W]; // column j (Dv becomes column j+1)
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 const int row = lo + k;
@@ -740,58 +747,78 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
                     for (int e = 0; e < D; ++e)
                         qq[e] = rv[e];
                 }
-                const float cst = point_cost<D>(qq, cv);
+                const float c0 = point_cost<D>(qq, cv0);
+                const float c1 = point_cost<D>(qq, cv1);
                 const float old = Dv[k];
-                const float v = fmaxf(cst, min3f(down, old, diag));
-                diag = old;
-                Dv[k] = v;
-                down = v;
-                vmin = fminf(vmin, v);
+                const float v0 = fmaxf(c0, min3f(down0, old, diag0));
+                diag0 = old;
+                down0 = v0;
+                // column j+1: left is (row, j), lower-left (row-1, j)
+                const float v1 = fmaxf(c1, min3f(down1, v0, dg1));
+                dg1 = v0;
+                down1 = v1;
+                V0[k] = v0;
+                Dv[k] = v1;
+                vmin1 = fminf(vmin1, v1);
             }
-            cells += W;
+            const bool two = j + 1 <= n - 1; // column j+1 belongs to the pair
+            cells += 2 * W;
             // cells of the window inside the matrix (rows past m-1 are padding)
-            valid += running ? (unsigned long long)max(0, min(W, m - lo)) : 0ull;
+            valid += running ? (unsigned long long)((two ? 2 : 1) * max(0, min(W, m - lo))) : 0ull;
             if (running) {
-                if (j == n - 1 && m - 1 - lo >= W && Dv[W - 1] <= tau) {
-                    // the end row lies above the window while the window's
-                    // top is live: the end cell may be reached up the last
-                    // column through rows the window does not hold
-                    push_fallback(a, q, c);
-                    ++fallback;
-                    --started; // the general DP counts it
-                    running = false;
-                } else if (j == n - 1) {
-                    const int slot = m - 1 - lo;
-                    float res = tsk_inf();
+                const int slot = m - 1 - lo;
+                const bool top0 = V0[W - 1] <= tau;
+                const bool top1 = Dv[W - 1] <= tau;
+                if (j + 1 >= n - 1) {
+                    // the pair's last column is j (one column left) or j+1
+                    const bool top = two ? (top0 || top1) : top0;
+                    if (slot >= W && top) {
+                        // the end row lies above the window while a top slot
+                        // is live: the end cell may be reached up the last
+                        // columns through rows the window does not hold
+                        push_fallback(a, q, c);
+                        ++fallback;
+                        --started; // the general DP counts it
+                    } else {
+                        float res = tsk_inf();
 #pragma unroll
-                    for (int k = 0; k < W; ++k)
-                        res = (k == slot) ? Dv[k] : res;
-                    res = res <= tau ? res : tsk_inf();
-                    if (res == tsk_inf())
-                        ++abandoned;
-                    finish_lane(a, q, c, res, completed);
+                        for (int k = 0; k < W; ++k)
+                            res = (k == slot) ? (two ? Dv[k] : V0[k]) : res;
+                        res = res <= tau ? res : tsk_inf();
+                        if (res == tsk_inf())
+                            ++abandoned;
+                        finish_lane(a, q, c, res, completed);
+                    }
                     running = false;
-                } else if (!(vmin <= tau)) {
-                    ++abandoned;
-                    running = false;
-                } else if (Dv[W - 1] <= tau) {
+                } else if (top0 || top1) {
                     push_fallback(a, q, c);
                     ++fallback;
                     --started; // the general DP counts it
+                    running = false;
+                } else if (!(vmin1 <= tau)) {
+                    ++abandoned;
                     running = false;
                 }
             }
-            // drop up to two leading dead slots (idle lanes keep lo)
-            int sh = Dv[0] <= tau ? 0 : (Dv[1] <= tau ? 1 : 2);
+            // drop up to four leading dead slots of column j+1 (idle lanes
+            // keep lo), in steps of 1, 2 and 4
+            int sh = 0;
+#pragma unroll
+            for (int k = 3; k >= 0; --k)
+                sh = Dv[k] <= tau ? k : sh;
+            sh = (Dv[0] <= tau || Dv[1] <= tau || Dv[2] <= tau || Dv[3] <= tau) ? sh : 4;
             sh = running ? sh : 0;
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
-                const float d1 = (k + 1 < W) ? Dv[k + 1] : tsk_inf();
-                const float d2 = (k + 2 < W) ? Dv[k + 2] : tsk_inf();
-                Dv[k] = sh == 0 ? Dv[k] : (sh == 1 ? d1 : d2);
+            for (int step = 1; step <= 4; step *= 2) {
+                const bool mv = (sh & step) != 0;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const float d = (k + step < W) ? Dv[k + step] : tsk_inf();
+                    Dv[k] = mv ? d : Dv[k];
+                }
             }
             lo += sh;
-            j += running ? 1 : 0;
+            j += running ? 2 : 0;
         }
     }
     wave_count(a.ctr, C_DP_STARTED, started);
