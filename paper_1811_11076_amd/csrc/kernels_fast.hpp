@@ -609,13 +609,14 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
 // live cell, and liveness is tested against tau (which only falls) instead
 // of killing them.
 // Each lane keeps a window of W consecutive rows [lo, lo+W) and computes
-// two columns over it per iteration, so each query row read from LDS serves
-// two cells.  Cells below lo are dead (nothing below a dead prefix can come
-// back: every predecessor is lower or to the left), so after each iteration
-// lo moves up past up to four leading dead slots of the second column.
+// TUBE_NC columns over it per iteration, so each query row read from LDS
+// serves that many cells.  Cells below lo are dead (nothing below a dead
+// prefix can come back: every predecessor is lower or to the left), so after
+// each iteration lo moves up past up to 2 TUBE_NC - 1 (at most W - 1)
+// leading dead slots of the last column.
 // Cells above the window are reached only through a top slot (of the same
-// column, or of an earlier column of the same window), so as long as both
-// columns' top slots stay dead the window holds every live cell and the
+// column, or of an earlier column of the same window), so as long as all
+// the columns' top slots stay dead the window holds every live cell and the
 // values in it are exact; a live top slot sends the pair to the general DP,
 // and only then is a window without live cells no proof that the pair is
 // above tau.  In the iteration holding a pair's last column the end cell is
@@ -630,6 +631,13 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
 // rows a row's two halves swap when bit 2 of the row is set, so the lanes'
 // rows (each at its own offset) spread over all eight 16-byte bank groups
 // of a 128-byte line instead of four.
+// Columns per iteration of k_dp_tube: each LDS row read serves this many
+// cells; more columns keep the window in place longer, so more pairs
+// outgrow it (measured at d = 6, W = 16: 2, 4, 6, 8 columns took 3.1, 2.55,
+// 2.5, 2.3 ms per launch but handed 0, 24, 4 600 and 254 000 pairs per call
+// to the general DP, whose time made 4 the fastest).
+constexpr int TUBE_NC = 4;
+
 template <int DP> __device__ __forceinline__ int tube_slot(int i)
 {
     if (DP != 8)
@@ -641,6 +649,10 @@ template <int D, int W>
 __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
 {
     constexpr int DP = PadDim<D>::value;
+    constexpr int NT = TUBE_NC; // columns per iteration
+    // most slots the window moves per iteration
+    constexpr int SH = 2 * NT - 1 < W - 1 ? 2 * NT - 1 : W - 1;
+    static_assert(NT >= 2, "tube columns per iteration");
     extern __shared__ float qs[];
     unsigned long long started = 0, completed = 0, abandoned = 0, late = 0, fallback = 0;
     unsigned long long cells = 0, valid = 0;
@@ -716,15 +728,21 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
             }
             if ((it & 7) == 0)
                 tau = bits_f(load_relaxed_u32(a.tau + q));
-            // two columns per iteration over the same window rows: each row
-            // read from LDS serves a cell of column j and one of column j+1
-            float cv0[D], cv1[D];
-            load_point<D>(cp + (int64_t)min(j, n - 1) * D, cv0);
-            load_point<D>(cp + (int64_t)min(j + 1, n - 1) * D, cv1);
-            float down0 = tsk_inf(), down1 = tsk_inf(), dg1 = tsk_inf();
+            // NT columns per iteration over the same window rows: each row
+            // read from LDS serves a cell of each of columns j .. j+NT-1
+            float cv[NT][D];
+#pragma unroll
+            for (int r = 0; r < NT; ++r)
+                load_point<D>(cp + (int64_t)min(j + r, n - 1) * D, cv[r]);
+            float down[NT], dgp[NT];
+#pragma unroll
+            for (int r = 0; r < NT; ++r) {
+                down[r] = tsk_inf();
+                dgp[r] = tsk_inf();
+            }
             float diag0 = (j == 0) ? 0.0f : tsk_inf(); // D(-1,-1) = 0 feeds (0,0)
-            float vmin1 = tsk_inf();
-            float V0[W]; // column j (Dv becomes column j+1)
+            float vminl = tsk_inf();
+            float V[NT - 1][W]; // columns j .. j+NT-2 (Dv becomes column j+NT-1)
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 const int row = lo + k;
@@ -747,31 +765,44 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
                     for (int e = 0; e < D; ++e)
                         qq[e] = rv[e];
                 }
-                const float c0 = point_cost<D>(qq, cv0);
-                const float c1 = point_cost<D>(qq, cv1);
-                const float old = Dv[k];
-                const float v0 = fmaxf(c0, min3f(down0, old, diag0));
-                diag0 = old;
-                down0 = v0;
-                // column j+1: left is (row, j), lower-left (row-1, j)
-                const float v1 = fmaxf(c1, min3f(down1, v0, dg1));
-                dg1 = v0;
-                down1 = v1;
-                V0[k] = v0;
-                Dv[k] = v1;
-                vmin1 = fminf(vmin1, v1);
+                float prev = 0.0f; // column r-1's value in this row
+#pragma unroll
+                for (int r = 0; r < NT; ++r) {
+                    const float cst = point_cost<D>(qq, cv[r]);
+                    float v;
+                    if (r == 0) {
+                        const float old = Dv[k];
+                        v = fmaxf(cst, min3f(down[0], old, diag0));
+                        diag0 = old;
+                    } else {
+                        // left is (row, column r-1), lower-left (row-1, r-1)
+                        v = fmaxf(cst, min3f(down[r], prev, dgp[r]));
+                        dgp[r] = prev;
+                    }
+                    down[r] = v;
+                    if (r < NT - 1) {
+                        V[r < NT - 1 ? r : 0][k] = v;
+                    } else {
+                        Dv[k] = v;
+                        vminl = fminf(vminl, v);
+                    }
+                    prev = v;
+                }
             }
-            const bool two = j + 1 <= n - 1; // column j+1 belongs to the pair
-            cells += 2 * W;
-            // cells of the window inside the matrix (rows past m-1 are padding)
-            valid += running ? (unsigned long long)((two ? 2 : 1) * max(0, min(W, m - lo))) : 0ull;
+            cells += (unsigned long long)NT * W;
+            // cells of the window inside the matrix (rows past m-1 are
+            // padding), in the columns that belong to the pair
+            valid += running ? (unsigned long long)(min(NT, n - j) * max(0, min(W, m - lo))) : 0ull;
             if (running) {
                 const int slot = m - 1 - lo;
-                const bool top0 = V0[W - 1] <= tau;
-                const bool top1 = Dv[W - 1] <= tau;
-                if (j + 1 >= n - 1) {
-                    // the pair's last column is j (one column left) or j+1
-                    const bool top = two ? (top0 || top1) : top0;
+                const int rend = n - 1 - j; // the pair's last column, if < NT
+                bool top = false;           // a live top slot up to rend
+#pragma unroll
+                for (int r = 0; r < NT; ++r) {
+                    const float t = r < NT - 1 ? V[r < NT - 1 ? r : 0][W - 1] : Dv[W - 1];
+                    top = top || (r <= rend && t <= tau);
+                }
+                if (rend < NT) {
                     if (slot >= W && top) {
                         // the end row lies above the window while a top slot
                         // is live: the end cell may be reached up the last
@@ -782,34 +813,37 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
                     } else {
                         float res = tsk_inf();
 #pragma unroll
-                        for (int k = 0; k < W; ++k)
-                            res = (k == slot) ? (two ? Dv[k] : V0[k]) : res;
+                        for (int r = 0; r < NT; ++r)
+#pragma unroll
+                            for (int k = 0; k < W; ++k) {
+                                const float t = r < NT - 1 ? V[r < NT - 1 ? r : 0][k] : Dv[k];
+                                res = (r == rend && k == slot) ? t : res;
+                            }
                         res = res <= tau ? res : tsk_inf();
                         if (res == tsk_inf())
                             ++abandoned;
                         finish_lane(a, q, c, res, completed);
                     }
                     running = false;
-                } else if (top0 || top1) {
+                } else if (top) {
                     push_fallback(a, q, c);
                     ++fallback;
                     --started; // the general DP counts it
                     running = false;
-                } else if (!(vmin1 <= tau)) {
+                } else if (!(vminl <= tau)) {
                     ++abandoned;
                     running = false;
                 }
             }
-            // drop up to four leading dead slots of column j+1 (idle lanes
-            // keep lo), in steps of 1, 2 and 4
-            int sh = 0;
+            // drop up to SH leading dead slots of the last column (idle
+            // lanes keep lo), in steps of 1, 2, 4, ...
+            int sh = SH;
 #pragma unroll
-            for (int k = 3; k >= 0; --k)
+            for (int k = SH - 1; k >= 0; --k)
                 sh = Dv[k] <= tau ? k : sh;
-            sh = (Dv[0] <= tau || Dv[1] <= tau || Dv[2] <= tau || Dv[3] <= tau) ? sh : 4;
             sh = running ? sh : 0;
 #pragma unroll
-            for (int step = 1; step <= 4; step *= 2) {
+            for (int step = 1; step <= SH; step *= 2) {
                 const bool mv = (sh & step) != 0;
 #pragma unroll
                 for (int k = 0; k < W; ++k) {
@@ -818,7 +852,7 @@ __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
                 }
             }
             lo += sh;
-            j += running ? 2 : 0;
+            j += running ? NT : 0;
         }
     }
     wave_count(a.ctr, C_DP_STARTED, started);

@@ -5,8 +5,8 @@ The kernels drop cells whose value exceeds the threshold tau (Sec. 4.2:
 sparse DK keeps only cells <= tau; for DTW a path through such a cell ends
 above tau as well).  Two rules decide which cells they never compute:
 
-* the sparse-DK tube: a window of W rows, two columns per iteration, that
-  moves up past dead leading slots; a live top slot hands the pair over to
+* the sparse-DK tube: a window of W rows, several columns per iteration
+  over the same rows, that moves up past dead leading slots; a live top slot hands the pair over to
   the general DP, also in the last columns when the end row lies above the
   window;
 * the banded DP's dead-group skipping: groups of G slots whose
@@ -63,44 +63,48 @@ def planted(rng, m, n, w=None):
     return C
 
 
-def tube(C, tau, W):
-    """Sparse DK in a moving W-row window, two columns per iteration over
+def tube(C, tau, W, NT=4):
+    """Sparse DK in a moving W-row window, NT columns per iteration over
     the same rows: ('done', value) or ('fallback',)."""
     m, n = C.shape
+    SH = min(2 * NT - 1, W - 1)
     Dv = [INF] * W
     lo = j = 0
     while True:
         def cost(r, c):
             return C[r, c] if r < m else INF
-        V0, down, diag = [INF] * W, INF, (f32(0) if j == 0 else INF)
+        V = [[INF] * W for _ in range(NT)]
+        down, dgp = [INF] * NT, [INF] * NT
+        diag0 = f32(0) if j == 0 else INF
         for k in range(W):
-            old = Dv[k]
-            V0[k] = down = max(cost(lo + k, j), min(down, old, diag))
-            diag = old
-        j1 = min(j + 1, n - 1)
-        V1, down = [INF] * W, INF
-        for k in range(W):
-            dg = V0[k - 1] if k > 0 else INF
-            V1[k] = down = max(cost(lo + k, j1), min(down, V0[k], dg))
+            prev = None
+            for r in range(NT):
+                cst = cost(lo + k, min(j + r, n - 1))
+                if r == 0:
+                    old = Dv[k]
+                    v = max(cst, min(down[0], old, diag0))
+                    diag0 = old
+                else:
+                    v = max(cst, min(down[r], prev, dgp[r]))
+                    dgp[r] = prev
+                down[r] = V[r][k] = prev = v
         slot = m - 1 - lo
-        if j + 1 >= n - 1:
-            two = j + 1 == n - 1
-            top = V0[W - 1] <= tau or (two and V1[W - 1] <= tau)
-            if slot >= W and top:
+        if j + NT - 1 >= n - 1:
+            rend = n - 1 - j
+            if slot >= W and any(V[r][W - 1] <= tau for r in range(rend + 1)):
                 return ("fallback",)
-            last = V1 if two else V0
-            res = last[slot] if 0 <= slot < W else INF
+            res = V[rend][slot] if 0 <= slot < W else INF
             return ("done", res if res <= tau else INF)
-        if V0[W - 1] <= tau or V1[W - 1] <= tau:
+        if any(V[r][W - 1] <= tau for r in range(NT)):
             return ("fallback",)
-        if not min(V1) <= tau:
+        if not min(V[NT - 1]) <= tau:
             return ("done", INF)
         sh = 0
-        while sh < 4 and not V1[sh] <= tau:
+        while sh < SH and not V[NT - 1][sh] <= tau:
             sh += 1
-        Dv = V1[sh:] + [INF] * sh
+        Dv = V[NT - 1][sh:] + [INF] * sh
         lo += sh
-        j += 2
+        j += NT
 
 
 def band(C, w, W, G, NC, tau, dist):
@@ -178,8 +182,9 @@ def band(C, w, W, G, NC, tau, dist):
     return Dv[w] if Dv[w] <= tau else INF
 
 
-def test_tube_window_rules_exact():
-    rng = np.random.default_rng(7)
+@pytest.mark.parametrize("NT", [2, 4])
+def test_tube_window_rules_exact(NT):
+    rng = np.random.default_rng(7 + NT)
     handed = 0
     for _ in range(3000):
         m, n = int(rng.integers(1, 30)), int(rng.integers(1, 30))
@@ -187,7 +192,7 @@ def test_tube_window_rules_exact():
         C = planted(rng, m, n)
         tau = f32(rng.choice([0.3, 0.5, 0.7, 1.0, 1.5, np.inf]))
         ex = plain_dp(C, "dk")
-        r = tube(C, tau, W)
+        r = tube(C, tau, W, NT)
         if r[0] == "fallback":
             handed += 1
             continue
