@@ -609,11 +609,11 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
 // live cell, and liveness is tested against tau (which only falls) instead
 // of killing them.
 // Each lane keeps a window of W consecutive rows [lo, lo+W) and computes
-// TUBE_NC columns over it per iteration, so each query row read from LDS
-// serves that many cells.  Cells below lo are dead (nothing below a dead
-// prefix can come back: every predecessor is lower or to the left), so after
-// each iteration lo moves up past up to 2 TUBE_NC - 1 (at most W - 1)
-// leading dead slots of the last column.
+// NT columns over it per iteration, so each query row read from LDS serves
+// NT cells.  Cells below lo are dead (nothing below a dead prefix can come
+// back: every predecessor is lower or to the left), so after each iteration
+// lo moves up past up to 2 NT - 1 (at most W - 1) leading dead slots of the
+// last column.
 // Cells above the window are reached only through a top slot (of the same
 // column, or of an earlier column of the same window), so as long as all
 // the columns' top slots stay dead the window holds every live cell and the
@@ -631,12 +631,15 @@ __global__ __launch_bounds__(64) void k_dp_band(FastArgs a, const float *__restr
 // rows a row's two halves swap when bit 2 of the row is set, so the lanes'
 // rows (each at its own offset) spread over all eight 16-byte bank groups
 // of a 128-byte line instead of four.
-// Columns per iteration of k_dp_tube: each LDS row read serves this many
-// cells; more columns keep the window in place longer, so more pairs
-// outgrow it (measured at d = 6, W = 16: 2, 4, 6, 8 columns took 3.1, 2.55,
-// 2.5, 2.3 ms per launch but handed 0, 24, 4 600 and 254 000 pairs per call
-// to the general DP, whose time made 4 the fastest).
-constexpr int TUBE_NC = 4;
+// Columns per iteration of k_dp_tube: each LDS row read serves NT cells;
+// more columns keep the window in place longer, so more pairs outgrow it
+// (equal lengths, d = 6, W = 16: 2, 4, 6, 8 columns took 3.1, 2.55, 2.5,
+// 2.3 ms per launch but handed 0, 24, 4 600 and 254 000 pairs per call to
+// the general DP, whose time made 4 the fastest).  Pairs of different
+// lengths follow a slanted path that rises up to m/n rows per column, so
+// they take 2.
+constexpr int TUBE_NC_EQUAL = 4;
+constexpr int TUBE_NC_UNEVEN = 2;
 
 template <int DP> __device__ __forceinline__ int tube_slot(int i)
 {
@@ -645,11 +648,10 @@ template <int DP> __device__ __forceinline__ int tube_slot(int i)
     return i ^ ((i >> 3) & 1);
 }
 
-template <int D, int W>
+template <int D, int W, int NT>
 __global__ __launch_bounds__(64) void k_dp_tube(FastArgs a)
 {
     constexpr int DP = PadDim<D>::value;
-    constexpr int NT = TUBE_NC; // columns per iteration
     // most slots the window moves per iteration
     constexpr int SH = 2 * NT - 1 < W - 1 ? 2 * NT - 1 : W - 1;
     static_assert(NT >= 2, "tube columns per iteration");

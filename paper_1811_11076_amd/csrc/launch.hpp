@@ -61,7 +61,9 @@ void launch_seed_diag(int D, int dist, const SeedRingArgs &r, hipStream_t s);
 void launch_walk_dk(int D, const FastArgs &a, const float *qv, unsigned long long *ubslots,
                     int blocks, int maxm, hipStream_t s);
 void launch_band(int D, int dist, int wsel, const FastArgs &a, int blocks, hipStream_t s);
-void launch_tube(int D, const FastArgs &a, int rows, int blocks, int maxm, hipStream_t s);
+// equal: every query of the chunk and every series have one length (the
+// tube then computes more columns per iteration)
+void launch_tube(int D, const FastArgs &a, int rows, bool equal, int blocks, int maxm, hipStream_t s);
 void launch_dp_wave(int D, int dist, int mode, const DpArgs &a, int blocks, hipStream_t s);
 void launch_qtable(int D, const float *qv, const int64_t *qoff, int nq, const int64_t *tab_off,
                    float *tab, hipStream_t s);

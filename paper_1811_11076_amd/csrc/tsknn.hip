@@ -1532,8 +1532,9 @@ static int scan_impl(const tsk_index *cix, const float *q_values_dev,
                                           : (ix->n >= (1 << 19) ? 256 : ix->n >= (1 << 16) ? 128 : 64);
                 // 16-row windows: the live tube of near neighbours is a few
                 // rows wide; the rare wider ones finish in the general DP
-                launch_tube(P.D, fa, o.tube_rows == 0 ? 16 : o.tube_rows, ix->n_cu * fast_waves, c.qmax,
-                            s);
+                const bool equal = c.qmin == c.qmax && ix->min_len == ix->max_len && ix->min_len == c.qmin;
+                launch_tube(P.D, fa, o.tube_rows == 0 ? 16 : o.tube_rows, equal, ix->n_cu * fast_waves,
+                            c.qmax, s);
             } else {
                 fa.dk_virtual = c.fast == FAST_BAND_DKV ? 1 : 0;
                 launch_band(P.D, dist, c.wsel, fa, ix->n_cu * fast_waves, s);
