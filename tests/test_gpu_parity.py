@@ -320,26 +320,31 @@ def test_knn_tube_overflow_goes_to_general_dp(rows):
     idx2.close()
 
 
+@pytest.mark.parametrize("equal", [False, True], ids=["uneven", "equal"])
 @pytest.mark.parametrize("rows", [8, 16, 32])
-def test_knn_tube_end_row_above_window(rows):
+def test_knn_tube_end_row_above_window(rows, equal):
     """A pair whose only path within tau runs along row 0 and then climbs
     the whole last column (query 0, 1.5, 1.5, ...; candidate 0, ..., 0, e):
     the window stays at rows 0 .. rows-1 and the end row (39) lies above it
     while the window's top slot is live, so the pair must go to the general
-    DP; rows equal the oracle's (DK^2 = 0.5625 for e = 0.75)."""
+    DP; rows equal the oracle's (DK^2 = 0.5625 for e = 0.75).  With every
+    series as long as the query the tube runs its equal-length column
+    count, otherwise the other one."""
     import numpy as np
-    print(f"[case] knn tube end row above window rows={rows}", flush=True)
+    print(f"[case] knn tube end row above window rows={rows} equal={equal}", flush=True)
     rng = np.random.default_rng(70 + rows)
     m = 40
     q = np.full((m, 1), 1.5, np.float32)
     q[0] = 0.0
     series = []
-    for e, n in ((0.75, 40), (0.7, 40), (0.8, 33), (0.75, 55)):
+    near = ((0.75, 40), (0.7, 40), (0.8, 40), (0.65, 40)) if equal else \
+        ((0.75, 40), (0.7, 40), (0.8, 33), (0.75, 55))
+    for e, n in near:
         t = np.zeros((n, 1), np.float32)
         t[-1] = e
         series.append(t)
     for _ in range(40):  # far from the query: pruned by their corner bounds
-        n = int(rng.integers(20, 60))
+        n = m if equal else int(rng.integers(20, 60))
         series.append((20.0 + np.cumsum(rng.standard_normal((n, 1)), 0)).astype(np.float32))
     perm = rng.permutation(len(series))
     series = [series[i] for i in perm]
