@@ -141,7 +141,7 @@ typedef struct {
                                       options and encoder); excludes
                                       profile; uneven-length DTW needs its
                                       queries to fit one chunk (up to
-                                      min(2^28 / n_series, 65535) of them);
+                                      min(2^30 / n_series, 65535) of them);
                                       with stats_host only ms_total is
                                       timed */
     int32_t dp_kernel;             /* 0 auto, 1 force the general DP */
@@ -282,7 +282,7 @@ typedef struct {
     int64_t size;                  /* sizeof(tsk_index_opts) */
     int64_t workspace_limit_bytes; /* bound on the workspace of a query call
                                       (0 = library default: chunks of up to
-                                      2^28 (query, series) pairs and 65535
+                                      2^30 (query, series) pairs and 65535
                                       queries); calls
                                       split their queries into chunks whose
                                       workspace fits (at least one query per

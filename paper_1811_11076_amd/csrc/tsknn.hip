@@ -887,7 +887,12 @@ static int prepare_qtables(tsk_index *ix, const int64_t *qoff_host, int64_t q0, 
 
 static int64_t chunk_queries(const tsk_index *ix, int64_t nq)
 {
-    const int64_t budget = (int64_t)1 << 28; // (query, candidate) entries per chunk
+    // (query, candidate) entries per chunk: 2^30 (a workspace of about 24
+    // bytes per entry, 26 GB at 10^6 series, which HBM holds); fewer, larger
+    // chunks give the latency-bound seed walks and the DP launches more
+    // work each (4096 x 10^6 x 512 x 6: 4 chunks of 1073 queries, DK 77 -> 64
+    // and DTW 328 -> 318 ms per call against 16 chunks of 268)
+    const int64_t budget = (int64_t)1 << 30;
     // at most 65535 queries: several kernels put the chunk's queries on the
     // grid's y dimension
     int64_t q = std::min<int64_t>(budget / std::max<int64_t>(1, ix->n), 65535);
